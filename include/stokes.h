@@ -1,0 +1,214 @@
+/*
+ * stokes.h -- C ABI of the MI355X (gfx950) variable-coefficient MAC Stokes
+ * solver: GMRES / flexible GMRES preconditioned by the block preconditioners
+ * of Cai, Nonaka, Bell, Griffith and Donev, "Efficient Variable-Coefficient
+ * Finite-Volume Stokes Solvers" (arXiv:1308.4605), each built from one
+ * geometric-multigrid V-cycle for the velocity and one for the pressure.
+ *
+ * Problem (paper Sec. 2, eq. Saddle_sys, discretised as in Sec. 3.1):
+ *     M x = b,   M = [[A, G], [-D, 0]],   A = theta rho_f - L_mu,
+ * x = (face velocities u, cell pressure p), b = (b_u, b_p) with b_p = -g.
+ * D and G are the staggered divergence and gradient, rho_f the mean of the two
+ * cells sharing a face, L_mu the stress-form viscous operator
+ * div(mu (grad u + grad u^T)) with cell viscosity on the normal stresses and
+ * edge (3D) / node (2D) viscosity on the shear stresses.  theta = 0 is steady
+ * Stokes flow, theta ~ 1/dt unsteady (Sec. 2).
+ *
+ * ------------------------------------------------------------------------
+ * Array layout (all arrays C-ordered, x fastest; axes 0,1,2 = x,y,z):
+ *   cells (p, rho, mu, b_p, gradients w.r.t. cell fields): n[0]*n[1]*n[2]
+ *     entries (n[2] = 1 in 2D).
+ *   velocity: the d components stored back to back in one buffer.  Component
+ *     k lives on faces normal to axis k and has n[a] entries along a != k and
+ *     n[k] + bc[k] entries along k (bc = 1 for no-slip walls).  Wall faces
+ *     (index 0 and n[k] on a no-slip axis) are not unknowns: inputs may hold
+ *     anything there (they are read as 0); outputs hold 0 there.
+ *   edge viscosity: families m = 2, 1, 0 (3D) or m = 2 (2D, the grid nodes)
+ *     stored back to back.  Family m is parallel to axis m and carries the
+ *     viscosity of the shear stress between the two other axes; it has
+ *     n[a] + bc[a] entries along each a != m and n[m] along m.
+ * Every pointer passed to the functions below is a DEVICE pointer except the
+ * parameter/stat structs and `hip_stream`, unless stated otherwise.  Inputs
+ * are never modified.  All vectors are FP64.
+ *
+ * Ownership: the caller owns every buffer, including the workspace, which it
+ * allocates with at least stokes_workspace_bytes() bytes of device memory
+ * (256-byte aligned).  The context owns host metadata and a small pinned host
+ * buffer only; the library never allocates device memory.
+ *
+ * Streams: every call enqueues its kernels on the HIP stream given at
+ * creation.  stokes_apply, stokes_precond, stokes_vel_subsolve,
+ * stokes_p_subsolve and stokes_grad are asynchronous; stokes_solve and
+ * stokes_adjoint_solve read Arnoldi scalars back every iteration and return
+ * after the stream has drained.  A context is not thread-safe; two calls on
+ * one context must not overlap.
+ *
+ * Errors: every function returns a status code; validation happens on the
+ * host before any launch.  No exception crosses this boundary.
+ * ------------------------------------------------------------------------
+ */
+#ifndef STOKES_MI355X_H
+#define STOKES_MI355X_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+  STOKES_OK = 0,
+  STOKES_EINVAL = -1,      /* bad sizes/parameters/pointers; nothing launched */
+  STOKES_ENOMEM = -2,      /* workspace smaller than stokes_workspace_bytes */
+  STOKES_EDEVICE = -3,     /* a HIP runtime call failed */
+  STOKES_ENOCONV = -4,     /* max_iter reached; best iterate and stats written */
+  STOKES_EBREAKDOWN = -5,  /* Krylov breakdown with an unconverged residual */
+  STOKES_ENONFINITE = -6,  /* NaN/Inf in a residual */
+  STOKES_EINCOMPAT = -7    /* right-hand side not orthogonal to the null space */
+};
+
+/* boundary condition per axis (both ends) */
+enum { STOKES_PERIODIC = 0, STOKES_NOSLIP = 1 };
+
+/* block preconditioners of Sec. 2: projection (eq. P1_practical), lower
+   triangular (eq. CC_Pre_lower), upper triangular (eq. CC_Pre_upper),
+   block diagonal (eq. CC_Pre_diagonal), Uzawa-like (Sec. 2.4) */
+enum { STOKES_P1 = 1, STOKES_P2 = 2, STOKES_P3 = 3, STOKES_P4 = 4, STOKES_P5 = 5 };
+
+/* precision of the preconditioner (multigrid, transfers, coefficients and the
+   Schur/projection glue).  The Krylov solver, M, residuals and the solution
+   stay FP64.  STOKES_MG_FP32 requires STOKES_FGMRES. */
+enum { STOKES_FP64 = 0, STOKES_MG_FP32 = 1 };
+
+/* Krylov method: left-preconditioned GMRES(m) (Sec. 3.2, Sec. 4) or flexible
+   GMRES(m) (right preconditioning; named in Sec. 4) */
+enum { STOKES_GMRES_LEFT = 0, STOKES_FGMRES = 1 };
+
+/* edge/node viscosity: arithmetic mean of the neighbouring cells (Sec. 3.1),
+   harmonic mean, or caller-supplied values */
+enum { STOKES_EDGE_ARITH = 0, STOKES_EDGE_HARMONIC = 1, STOKES_EDGE_GIVEN = 2 };
+
+typedef struct {
+  int dim;          /* 2 or 3 */
+  int n[3];         /* cells per axis (n[2] ignored in 2D) */
+  double h;         /* grid spacing (> 0) */
+  int bc[3];        /* STOKES_PERIODIC or STOKES_NOSLIP per axis */
+  double theta;     /* >= 0 */
+  int precond;      /* STOKES_P1..STOKES_P5 */
+  int precision;    /* STOKES_FP64 or STOKES_MG_FP32 */
+  int krylov;       /* STOKES_GMRES_LEFT or STOKES_FGMRES */
+  int restart;      /* GMRES restart length m, 1..32 (the paper uses 10) */
+  int nu_pre;       /* Gauss-Seidel sweeps before coarsening (paper: 2) */
+  int nu_post;      /* sweeps after prolongation (paper: 2) */
+  int nu_coarse;    /* sweeps on the coarsest level (paper: 8 or more) */
+  int vcycles;      /* V-cycles per subsolver application (paper: 1) */
+  double rescale_c; /* rescaling c of eq. Stokes_rescaled; <= 0: c = h / mu_ref
+                       with mu_ref the geometric mean of the positive mu_cell */
+  int edge_avg;     /* STOKES_EDGE_* */
+} stokes_params;
+
+typedef struct {
+  int iters;            /* Arnoldi steps (applications of P^{-1} M or M P^{-1}) */
+  int restarts;         /* restart cycles started */
+  int precond_applies;  /* preconditioner applications */
+  int scalar_vcycles;   /* precond_applies * vcycles * (d * velocity cycles +
+                           pressure cycles): the paper's cost proxy (Sec. 4) */
+  double rel_res_true;  /* ||b' - M' x'|| / ||b'|| of the rescaled system at exit */
+  double rel_res_est;   /* last Givens estimate, as a true relative residual */
+} stokes_stats;
+
+typedef struct stokes_ctx stokes_ctx;
+
+/* Sizes of the ABI arrays for these parameters (host pointers; any may be
+   NULL).  Returns STOKES_EINVAL for invalid parameters.  The grid must halve
+   exactly until its smallest axis has two cells (Appendix C: coarsening by 2
+   down to two cells): the smallest n is a power of two >= 2, every n is
+   divisible by min(n)/2, and a periodic axis keeps an even cell count on the
+   coarsest level (n divisible by min(n)), which the red-black colouring needs. */
+int stokes_sizes(const stokes_params *p, size_t *nvel, size_t *ncell, size_t *nedge,
+                 int *nlevels);
+
+/* Device workspace bytes needed by stokes_create for these parameters; 0 for
+   invalid parameters. */
+size_t stokes_workspace_bytes(const stokes_params *p);
+
+/* Build the context: face density, rho-weighted coefficients, edge viscosity
+   (Sec. 3.1), the rescaling c ~ h/mu0 (Sec. 3.3) and the coarse-level
+   coefficients (Appendix C), all on the device.
+   rho_cell, mu_cell: cell fields (rho > 0, mu >= 0, finite);
+   mu_edges: edge viscosity for STOKES_EDGE_GIVEN, else NULL;
+   workspace: device buffer of ws_bytes >= stokes_workspace_bytes(p);
+   hip_stream: a hipStream_t (NULL = the default stream).
+   The coefficient fields are checked for sign and finiteness on the device
+   (one synchronisation); rho and mu are not retained. */
+int stokes_create(const stokes_params *p, const double *rho_cell, const double *mu_cell,
+                  const double *mu_edges, void *workspace, size_t ws_bytes, void *hip_stream,
+                  stokes_ctx **out);
+
+/* y = M x with the caller's (unscaled) coefficients (Sec. 2, eq. Saddle_sys;
+   direct evaluation of the stencils at every interior face and cell, Sec. 3.2). */
+int stokes_apply(stokes_ctx *ctx, const double *xu, const double *xp, double *yu, double *yp);
+
+/* z = P^{-1} b for the configured preconditioner and precision (Sec. 2), the
+   same operator the Krylov solver applies.  Output pressure has zero mean;
+   with a singular velocity operator (all axes periodic, theta = 0) the output
+   velocity components have zero mean (Sec. 3.2 null-space care). */
+int stokes_precond(stokes_ctx *ctx, const double *bu, const double *bp, double *zu, double *zp);
+
+/* The two multigrid subsolvers alone (Sec. 3.2, Appendix C): e = A~^{-1} r
+   (velocity, `vcycles` V-cycles from zero) and e = L~_rho^{-1} r (pressure,
+   L_rho = D rho_f^{-1} G; r must have zero mean; e has zero mean). */
+int stokes_vel_subsolve(stokes_ctx *ctx, const double *r, double *e);
+int stokes_p_subsolve(stokes_ctx *ctx, const double *r, double *e);
+
+/* Solve M x = b until the true relative residual of the rescaled system
+   ||b' - M' x'|| <= tol ||b'|| (Sec. 3.2 "true residual"), at most max_iter
+   Arnoldi steps.  use_x0 != 0 starts from the given x (a restart, Sec. 4.2.2),
+   else from 0.  x is the solution of the unscaled system with p of zero mean
+   (and zero-mean velocity components when the velocity operator is singular).
+   b_p must have zero mean (STOKES_EINCOMPAT otherwise), as must each velocity
+   component of b_u when all axes are periodic and theta = 0.  stats may be
+   NULL.  Synchronous. */
+int stokes_solve(stokes_ctx *ctx, const double *bu, const double *bp, double *xu, double *xp,
+                 double tol, int max_iter, int use_x0, stokes_stats *stats);
+
+/* Adjoint: with x the forward solution and g = dL/dx = (g_u, g_p), solve
+   M^T lambda = g (M = M^T, Sec. 2) with the same preconditioner and a fresh
+   Krylov space, then contract forward and adjoint strain rates:
+     dL/db        = lambda                              (lu, lp),
+     dL/dmu_cell  = -2 sum_k (D^k lambda_k)(D^k u_k)  + chain through the
+                    derived edge viscosity (EDGE_ARITH/HARMONIC),
+     dL/dmu_edge  = -w_e gamma_e(lambda) gamma_e(u),  w_e = 1/2 on no-slip
+                    wall edges, 1 elsewhere (partial derivative),
+     dL/drho_cell = -theta sum over the cell's faces of 1/2 lambda_f u_f.
+   Gradient outputs may be NULL.  Synchronous. */
+int stokes_adjoint_solve(stokes_ctx *ctx, const double *xu, const double *xp, const double *gu,
+                         const double *gp, double *lu, double *lp, double *dmu_cell,
+                         double *dmu_edge, double *drho_cell, double tol, int max_iter,
+                         stokes_stats *stats);
+
+/* The strain-contraction gradient alone, given forward velocity u and adjoint
+   velocity lambda (same formulas as above).  Asynchronous. */
+int stokes_grad(stokes_ctx *ctx, const double *xu, const double *lu, double *dmu_cell,
+                double *dmu_edge, double *drho_cell);
+
+/* Rescaling factor c in use (Sec. 3.3). */
+double stokes_rescale(const stokes_ctx *ctx);
+
+/* Per-kernel timing for the roofline report.  When enabled, every launch of
+   the finest-level velocity Gauss-Seidel colour pass is bracketed by HIP
+   events on the context stream; stokes_kernel_time returns the accumulated
+   milliseconds, the launch count and the algorithmic bytes of those launches
+   (each array the pass reads or writes counted once).  Reading the totals
+   synchronises the stream. */
+int stokes_set_timing(stokes_ctx *ctx, int enable);
+int stokes_kernel_time(stokes_ctx *ctx, double *ms_total, long *launches, double *bytes_total);
+
+void stokes_destroy(stokes_ctx *ctx);
+const char *stokes_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STOKES_MI355X_H */

@@ -1162,8 +1162,12 @@ int orc_create(const orc_params *p, const double *rho, const double *mu,
   int nlev = 1;
   while ((nmin >> (nlev - 1)) > 2) nlev++;
   if ((nmin >> (nlev - 1)) != 2 || (2 << (nlev - 1)) != nmin) return ORC_EINVAL;
-  for (int a = 0; a < g.d; a++)
+  for (int a = 0; a < g.d; a++) {
     if (g.n[a] % (1 << (nlev - 1)) != 0) return ORC_EINVAL;
+    /* multicolour Gauss-Seidel needs an even count around a periodic axis on
+       every level (else two neighbours across the wrap share a colour) */
+    if (!g.ns[a] && ((g.n[a] >> (nlev - 1)) & 1)) return ORC_EINVAL;
+  }
 
   orc_ctx *X = (orc_ctx *)calloc(1, sizeof(orc_ctx));
   if (!X) return ORC_ENOMEM;

@@ -1,0 +1,949 @@
+// stokes_api.cpp -- host side of the MI355X MAC Stokes library: workspace
+// layout, coefficient hierarchy, multigrid V-cycles, block preconditioners,
+// restarted GMRES / flexible GMRES and the adjoint, behind the C ABI of
+// include/stokes.h.  All arithmetic runs in the HIP kernels of
+// stokes_kernels.hip; the host only sequences launches, runs the Givens
+// rotations of the (m+1) x m Hessenberg matrix and tests convergence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "stokes.h"
+#include "stokes_internal.h"
+
+using namespace stk;
+
+namespace {
+
+constexpr int kMaxLev = 24;
+constexpr int kMaxRestart = 32;
+constexpr size_t kAlign = 256;
+constexpr int kEventPool = 2048;
+
+struct Level {
+  Geo g;
+  void *alpha, *beta, *muc, *mue;             // precision T of the hierarchy
+  void *phi_u, *rhs_u, *res_u, *phi_p, *rhs_p, *res_p;
+};
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base((char *)b) {}
+  void *take(size_t bytes) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    void *p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+bool valid_params(const stokes_params *p, int *nlev_out) {
+  if (!p) return false;
+  if (p->dim != 2 && p->dim != 3) return false;
+  if (!(p->h > 0.0) || !std::isfinite(p->h)) return false;
+  if (!(p->theta >= 0.0) || !std::isfinite(p->theta)) return false;
+  if (p->precond < STOKES_P1 || p->precond > STOKES_P5) return false;
+  if (p->precision != STOKES_FP64 && p->precision != STOKES_MG_FP32) return false;
+  if (p->krylov != STOKES_GMRES_LEFT && p->krylov != STOKES_FGMRES) return false;
+  if (p->precision == STOKES_MG_FP32 && p->krylov != STOKES_FGMRES) return false;
+  if (p->restart < 1 || p->restart > kMaxRestart) return false;
+  if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_coarse < 1 || p->vcycles < 1) return false;
+  if (p->nu_pre > 64 || p->nu_post > 64 || p->nu_coarse > 4096 || p->vcycles > 1000) return false;
+  if (p->edge_avg < STOKES_EDGE_ARITH || p->edge_avg > STOKES_EDGE_GIVEN) return false;
+  int nmin = 1 << 30;
+  for (int a = 0; a < p->dim; a++) {
+    if (p->n[a] < 2 || p->n[a] > (1 << 20)) return false;
+    if (p->bc[a] != STOKES_PERIODIC && p->bc[a] != STOKES_NOSLIP) return false;
+    if (p->n[a] < nmin) nmin = p->n[a];
+  }
+  // coarsen by 2 until the smallest axis has two cells (Appendix C)
+  int nlev = 1;
+  while ((nmin >> (nlev - 1)) > 2) nlev++;
+  if ((2 << (nlev - 1)) != nmin) return false;
+  if (nlev > kMaxLev) return false;
+  for (int a = 0; a < p->dim; a++) {
+    if (p->n[a] % (1 << (nlev - 1)) != 0) return false;
+    // red-black colouring needs an even cell count around every periodic axis
+    // on every level, the coarsest included
+    if (p->bc[a] == STOKES_PERIODIC && ((p->n[a] >> (nlev - 1)) & 1)) return false;
+  }
+  long long cells = 1;
+  for (int a = 0; a < p->dim; a++) cells *= p->n[a];
+  if (cells > (1LL << 31)) return false;
+  if (nlev_out) *nlev_out = nlev;
+  return true;
+}
+
+}  // namespace
+
+struct stokes_ctx {
+  stokes_params p;
+  hipStream_t s = nullptr;
+  int d = 0, nlev = 0;
+  int mg32 = 0;
+  int vel_singular = 0;
+  double c = 1.0;
+  Level lev[kMaxLev];
+  i64 nvel = 0, ncell = 0, nedge = 0, n = 0;
+  // FP64 scaled fine-level coefficients for M (alias level 0 in FP64 mode)
+  double *m_alpha = nullptr, *m_muc = nullptr, *m_mue = nullptr;
+  // Krylov storage (FP64 [u | p] vectors; Z in the preconditioner precision)
+  double *V[kMaxRestart + 1];
+  void *Z[kMaxRestart];
+  double *r = nullptr, *w = nullptr, *t = nullptr, *x = nullptr, *b = nullptr;
+  // preconditioner temporaries (precision T, level-0 sizes)
+  void *pin = nullptr, *pout = nullptr;           // [u | p]
+  void *xs = nullptr, *tu = nullptr, *eu = nullptr;  // velocity
+  void *cv = nullptr, *q = nullptr;                 // cells
+  void *vs_r = nullptr, *vs_t = nullptr, *vs_de = nullptr;
+  void *ps_r = nullptr, *ps_t = nullptr, *ps_de = nullptr;
+  double *gedge = nullptr, *gcell = nullptr;        // gradient scratch (FP64)
+  // FP64 coefficient chain used to build an FP32 hierarchy (setup only)
+  double *c64a[kMaxLev], *c64b[kMaxLev], *c64m[kMaxLev], *c64e[kMaxLev];
+  // reductions
+  double *part = nullptr;   // partial sums
+  double *dsc = nullptr;    // device scalars
+  int *dflag = nullptr;
+  double *host = nullptr;   // pinned host mirror
+  // timing of the finest-level velocity colour passes
+  int timing = 0;
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  double t_ms = 0.0;
+  long launches = 0;
+  double bytes = 0.0;
+  double gs_bytes[3] = {0, 0, 0};
+  int err = 0;
+};
+
+namespace {
+
+constexpr int kDscSlots = 256;  // device scalar slots
+
+void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
+  const int d = p->dim;
+  const size_t tb = (p->precision == STOKES_MG_FP32) ? sizeof(float) : sizeof(double);
+  int ns[3], n[3];
+  for (int a = 0; a < 3; a++) {
+    n[a] = (a < d) ? p->n[a] : 1;
+    ns[a] = (a < d) ? p->bc[a] : 0;
+  }
+  Geo g0 = make_geo(d, n, ns, p->h);
+  const i64 nv = g0.nvel, nc = g0.ncell, ne = g0.nedge, nn = nv + nc;
+  for (int l = 0; l < nlev; l++) {
+    int nl[3];
+    for (int a = 0; a < 3; a++) nl[a] = (a < d) ? (n[a] >> l) : 1;
+    Geo g = make_geo(d, nl, ns, p->h * (double)(1 << l));
+    Level L;
+    L.g = g;
+    L.alpha = cv.take(g.nvel * tb);
+    L.beta = cv.take(g.nvel * tb);
+    L.muc = cv.take(g.ncell * tb);
+    L.mue = cv.take(g.nedge * tb);
+    L.phi_u = cv.take(g.nvel * tb);
+    L.rhs_u = cv.take(g.nvel * tb);
+    L.res_u = cv.take(g.nvel * tb);
+    L.phi_p = cv.take(g.ncell * tb);
+    L.rhs_p = cv.take(g.ncell * tb);
+    L.res_p = cv.take(g.ncell * tb);
+    if (X) X->lev[l] = L;
+  }
+  // FP64 fine coefficients of M (rescaled)
+  double *ma = (double *)cv.take(nv * 8);
+  double *mc = (double *)cv.take(nc * 8), *me = (double *)cv.take(ne * 8);
+  if (X) {
+    X->m_alpha = ma;
+    X->m_muc = mc;
+    X->m_mue = me;
+  }
+  const int m = p->restart;
+  for (int i = 0; i <= m; i++) {
+    void *v = cv.take(nn * 8);
+    if (X) X->V[i] = (double *)v;
+  }
+  if (p->krylov == STOKES_FGMRES) {
+    for (int i = 0; i < m; i++) {
+      void *z = cv.take(nn * tb);
+      if (X) X->Z[i] = z;
+    }
+  }
+  double *r = (double *)cv.take(nn * 8), *w = (double *)cv.take(nn * 8);
+  double *t = (double *)cv.take(nn * 8), *x = (double *)cv.take(nn * 8);
+  double *b = (double *)cv.take(nn * 8);
+  void *pin = cv.take(nn * tb), *pout = cv.take(nn * tb);
+  void *xs = cv.take(nv * tb), *tu = cv.take(nv * tb), *eu = cv.take(nv * tb);
+  void *cvv = cv.take(nc * tb), *q = cv.take(nc * tb);
+  void *vs_r = cv.take(nv * tb), *vs_t = cv.take(nv * tb), *vs_de = cv.take(nv * tb);
+  void *ps_r = cv.take(nc * tb), *ps_t = cv.take(nc * tb), *ps_de = cv.take(nc * tb);
+  double *ge = (double *)cv.take(ne * 8);
+  double *gc = (double *)cv.take(nc * 8);
+  double *part = (double *)cv.take((size_t)kRedBlocks * (kMaxRestart + 2) * 8);
+  double *dsc = (double *)cv.take(kDscSlots * 8);
+  int *dflag = (int *)cv.take(64);
+  // FP64 coefficient chain for building the FP32 hierarchy: level-0 beta and
+  // every coarser level (alpha, beta, mu_cell, mu_edge)
+  if (p->precision == STOKES_MG_FP32) {
+    double *b0 = (double *)cv.take(nv * 8);
+    if (X) {
+      X->c64a[0] = ma;
+      X->c64b[0] = b0;
+      X->c64m[0] = mc;
+      X->c64e[0] = me;
+    }
+    for (int l = 1; l < nlev; l++) {
+      int nl[3];
+      for (int a = 0; a < 3; a++) nl[a] = (a < d) ? (n[a] >> l) : 1;
+      Geo g = make_geo(d, nl, ns, p->h * (double)(1 << l));
+      double *a_ = (double *)cv.take(g.nvel * 8), *b_ = (double *)cv.take(g.nvel * 8);
+      double *m_ = (double *)cv.take(g.ncell * 8), *e_ = (double *)cv.take(g.nedge * 8);
+      if (X) {
+        X->c64a[l] = a_;
+        X->c64b[l] = b_;
+        X->c64m[l] = m_;
+        X->c64e[l] = e_;
+      }
+    }
+  }
+  if (X) {
+    X->r = r; X->w = w; X->t = t; X->x = x; X->b = b;
+    X->pin = pin; X->pout = pout; X->xs = xs; X->tu = tu; X->eu = eu;
+    X->cv = cvv; X->q = q;
+    X->vs_r = vs_r; X->vs_t = vs_t; X->vs_de = vs_de;
+    X->ps_r = ps_r; X->ps_t = ps_t; X->ps_de = ps_de;
+    X->gedge = ge; X->gcell = gc; X->part = part; X->dsc = dsc; X->dflag = dflag;
+  }
+}
+
+inline bool hip_ok(stokes_ctx *X, hipError_t e) {
+  if (e != hipSuccess) {
+    X->err = 1;
+    return false;
+  }
+  return true;
+}
+
+int finish(stokes_ctx *X, int rc) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || X->err) {
+    X->err = 0;
+    return STOKES_EDEVICE;
+  }
+  return rc;
+}
+
+// ---------------- timing ----------------
+void fold_events(stokes_ctx *X) {
+  if (X->ev_used == 0) return;
+  (void)hipStreamSynchronize(X->s);
+  for (int i = 0; i < X->ev_used; i++) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, X->ev[2 * i], X->ev[2 * i + 1]) == hipSuccess) X->t_ms += ms;
+  }
+  X->ev_used = 0;
+}
+
+// ---------------- device helpers (precision T) ----------------
+template <typename T>
+inline T *P(void *a) {
+  return (T *)a;
+}
+
+template <typename T>
+void remove_mean(stokes_ctx *X, T *a, i64 n, int slot) {
+  launch_sum<T>(a, n, X->part, X->dsc + slot, X->s);
+  launch_sub_mean<T>(a, n, X->dsc + slot, X->s);
+}
+
+template <typename T>
+void remove_vel_means(stokes_ctx *X, const Geo &g, T *u) {
+  // only used when every axis is periodic: every face is an unknown
+  for (int k = 0; k < g.d; k++) remove_mean<T>(X, u + g.foff[k], g.fcnt[k], 8 + k);
+}
+
+template <typename T>
+void sweep_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
+  const Level &L = X->lev[l];
+  for (int k = 0; k < L.g.d; k++)
+    for (int colour = 0; colour < 2; colour++) {
+      const bool tm = X->timing && l == 0;
+      if (tm) {
+        if (X->ev_used == kEventPool) fold_events(X);
+        (void)hipEventRecord(X->ev[2 * X->ev_used], X->s);
+      }
+      launch_vel_gs<T>(L.g, k, colour, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), rhs, phi, X->s);
+      if (tm) {
+        (void)hipEventRecord(X->ev[2 * X->ev_used + 1], X->s);
+        X->ev_used++;
+        X->launches++;
+        X->bytes += X->gs_bytes[k];
+      }
+    }
+}
+
+template <typename T>
+void sweep_p(stokes_ctx *X, int l, const T *rhs, T *phi) {
+  const Level &L = X->lev[l];
+  launch_p_gs<T>(L.g, 0, P<T>(L.beta), rhs, phi, X->s);
+  launch_p_gs<T>(L.g, 1, P<T>(L.beta), rhs, phi, X->s);
+}
+
+// velocity V-cycle on level l from zero (Appendix C)
+template <typename T>
+void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
+  Level &L = X->lev[l];
+  launch_fill<T>(phi, (T)0, L.g.nvel, X->s);
+  if (l == X->nlev - 1) {
+    T *r = P<T>(L.res_u);
+    launch_cast<T, T>(rhs, r, L.g.nvel, X->s);
+    if (X->vel_singular) remove_vel_means<T>(X, L.g, r);
+    for (int s = 0; s < X->p.nu_coarse; s++) sweep_vel<T>(X, l, r, phi);
+    if (X->vel_singular) remove_vel_means<T>(X, L.g, phi);
+    return;
+  }
+  Level &C = X->lev[l + 1];
+  for (int s = 0; s < X->p.nu_pre; s++) sweep_vel<T>(X, l, rhs, phi);
+  launch_vel_residual<T>(L.g, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), rhs, phi, nullptr,
+                         P<T>(L.res_u), X->s);
+  launch_face_restrict<T>(L.g, C.g, P<T>(L.res_u), P<T>(C.rhs_u), X->s);
+  vcycle_vel<T>(X, l + 1, P<T>(C.rhs_u), P<T>(C.phi_u));
+  launch_face_prolong_add<T>(C.g, L.g, P<T>(C.phi_u), phi, X->s);
+  for (int s = 0; s < X->p.nu_post; s++) sweep_vel<T>(X, l, rhs, phi);
+}
+
+// pressure V-cycle; singular operator: consistent coarsest problem by mean
+// removal
+template <typename T>
+void vcycle_p(stokes_ctx *X, int l, const T *rhs, T *phi) {
+  Level &L = X->lev[l];
+  launch_fill<T>(phi, (T)0, L.g.ncell, X->s);
+  if (l == X->nlev - 1) {
+    T *r = P<T>(L.res_p);
+    launch_cast<T, T>(rhs, r, L.g.ncell, X->s);
+    remove_mean<T>(X, r, L.g.ncell, 16);
+    for (int s = 0; s < X->p.nu_coarse; s++) sweep_p<T>(X, l, r, phi);
+    remove_mean<T>(X, phi, L.g.ncell, 17);
+    return;
+  }
+  Level &C = X->lev[l + 1];
+  for (int s = 0; s < X->p.nu_pre; s++) sweep_p<T>(X, l, rhs, phi);
+  launch_p_residual<T>(L.g, P<T>(L.beta), rhs, phi, P<T>(L.res_p), X->s);
+  launch_cell_restrict<T>(L.g, C.g, P<T>(L.res_p), P<T>(C.rhs_p), X->s);
+  vcycle_p<T>(X, l + 1, P<T>(C.rhs_p), P<T>(C.phi_p));
+  launch_cell_prolong_add<T>(C.g, L.g, P<T>(C.phi_p), phi, X->s);
+  for (int s = 0; s < X->p.nu_post; s++) sweep_p<T>(X, l, rhs, phi);
+}
+
+// A~^{-1} r: `vcycles` V-cycles, zero initial guess (Sec. 3.2)
+template <typename T>
+void vel_sub(stokes_ctx *X, const T *r, T *e) {
+  Level &L = X->lev[0];
+  const T *rr = r;
+  if (X->vel_singular) {
+    launch_cast<T, T>(r, P<T>(X->vs_r), L.g.nvel, X->s);
+    remove_vel_means<T>(X, L.g, P<T>(X->vs_r));
+    rr = P<T>(X->vs_r);
+  }
+  vcycle_vel<T>(X, 0, rr, e);
+  for (int v = 1; v < X->p.vcycles; v++) {
+    launch_vel_residual<T>(L.g, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), rr, e, nullptr,
+                           P<T>(X->vs_t), X->s);
+    vcycle_vel<T>(X, 0, P<T>(X->vs_t), P<T>(X->vs_de));
+    launch_axpy<T>((T)1, P<T>(X->vs_de), e, L.g.nvel, X->s);
+  }
+  if (X->vel_singular) remove_vel_means<T>(X, L.g, e);
+}
+
+// L~_rho^{-1} r
+template <typename T>
+void p_sub(stokes_ctx *X, const T *r, T *e) {
+  Level &L = X->lev[0];
+  launch_cast<T, T>(r, P<T>(X->ps_r), L.g.ncell, X->s);
+  remove_mean<T>(X, P<T>(X->ps_r), L.g.ncell, 18);
+  const T *rr = P<T>(X->ps_r);
+  vcycle_p<T>(X, 0, rr, e);
+  for (int v = 1; v < X->p.vcycles; v++) {
+    launch_p_residual<T>(L.g, P<T>(L.beta), rr, e, P<T>(X->ps_t), X->s);
+    vcycle_p<T>(X, 0, P<T>(X->ps_t), P<T>(X->ps_de));
+    launch_axpy<T>((T)1, P<T>(X->ps_de), e, L.g.ncell, X->s);
+  }
+  remove_mean<T>(X, e, L.g.ncell, 19);
+}
+
+// out = -S~^{-1} c = theta L~_rho^{-1} c - 2 mu c  (eq. Schur_app_varDen_varVis)
+template <typename T>
+void neg_schur(stokes_ctx *X, const T *c, T *out) {
+  Level &L = X->lev[0];
+  if (X->p.theta != 0.0) {
+    p_sub<T>(X, c, P<T>(X->q));
+    launch_schur_combine<T>(P<T>(X->q), c, P<T>(L.muc), (T)X->p.theta, (T)-2, out, L.g.ncell,
+                            X->s);
+  } else {
+    launch_schur_combine<T>(nullptr, c, P<T>(L.muc), (T)0, (T)-2, out, L.g.ncell, X->s);
+  }
+}
+
+// z = P^{-1} b on the rescaled system (Sec. 2 block factorisations)
+template <typename T>
+void precond(stokes_ctx *X, const T *bu, const T *bp, T *zu, T *zp) {
+  Level &L = X->lev[0];
+  const Geo &g = L.g;
+  T *xs = P<T>(X->xs), *tu = P<T>(X->tu), *eu = P<T>(X->eu), *cv = P<T>(X->cv), *q = P<T>(X->q);
+  switch (X->p.precond) {
+    case STOKES_P1:
+      // x* = A~^{-1} b_u; c = -(D x* + b_p); q = L~^{-1} c;
+      // x_u = x* + rho_f^{-1} G q; x_p = -theta q + 2 mu c
+      vel_sub<T>(X, bu, xs);
+      launch_div<T>(g, xs, bp, (T)-1, cv, X->s);
+      p_sub<T>(X, cv, q);
+      launch_proj_update<T>(g, xs, P<T>(L.beta), q, zu, X->s);
+      launch_schur_combine<T>(q, cv, P<T>(L.muc), (T)(-X->p.theta), (T)2, zp, g.ncell, X->s);
+      break;
+    case STOKES_P2:
+      // x_u = A~^{-1} b_u; x_p = -S~^{-1}(D x_u + b_p)
+      vel_sub<T>(X, bu, zu);
+      launch_div<T>(g, zu, bp, (T)1, cv, X->s);
+      neg_schur<T>(X, cv, zp);
+      break;
+    case STOKES_P3:
+      // x_p = -S~^{-1} b_p; x_u = A~^{-1}(b_u - G x_p)
+      neg_schur<T>(X, bp, zp);
+      launch_grad_sub<T>(g, bu, zp, tu, X->s);
+      vel_sub<T>(X, tu, zu);
+      break;
+    case STOKES_P4:
+      vel_sub<T>(X, bu, zu);
+      neg_schur<T>(X, bp, zp);
+      break;
+    case STOKES_P5:
+      // x* = A~^{-1} b_u; x_p = -S~^{-1}(D x* + b_p);
+      // x_u = x* + A~^{-1}(b_u - G x_p - A x*)
+      vel_sub<T>(X, bu, xs);
+      launch_div<T>(g, xs, bp, (T)1, cv, X->s);
+      neg_schur<T>(X, cv, zp);
+      launch_vel_residual<T>(g, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), bu, xs, zp, tu, X->s);
+      vel_sub<T>(X, tu, eu);
+      launch_cast<T, T>(xs, zu, g.nvel, X->s);
+      launch_axpy<T>((T)1, eu, zu, g.nvel, X->s);
+      break;
+  }
+  remove_mean<T>(X, zp, g.ncell, 20);
+  if (X->vel_singular) remove_vel_means<T>(X, g, zu);
+}
+
+// z (precision of the hierarchy, [u|p]) = P^{-1} v with v FP64 [u|p]
+void precond_from64(stokes_ctx *X, const double *v, void *z) {
+  const i64 nv = X->nvel;
+  if (X->mg32) {
+    float *pin = P<float>(X->pin);
+    launch_cast<float, double>(v, pin, X->n, X->s);
+    precond<float>(X, pin, pin + nv, P<float>(z), P<float>(z) + nv);
+  } else {
+    precond<double>(X, v, v + nv, P<double>(z), P<double>(z) + nv);
+  }
+}
+
+// y = M' x on the rescaled system (FP64)
+void apply_scaled(stokes_ctx *X, const double *x, double *y) {
+  const Geo &g = X->lev[0].g;
+  launch_apply_m<double>(g, X->m_alpha, X->m_muc, X->m_mue, x, x + X->nvel, nullptr, nullptr, y,
+                         y + X->nvel, X->s);
+}
+
+double fetch(stokes_ctx *X, const double *dev, int count, double *dst) {
+  hip_ok(X, hipMemcpyAsync(dst, dev, count * sizeof(double), hipMemcpyDeviceToHost, X->s));
+  hip_ok(X, hipStreamSynchronize(X->s));
+  return dst[0];
+}
+
+// Restarted GMRES(m), left-preconditioned or flexible, on the rescaled system
+// b' -> x' held in X->b, X->x.  The same algorithm as the CPU oracle:
+// classical Gram-Schmidt with one re-orthogonalisation when the norm falls
+// below 1/sqrt(2) of its previous value; Givens rotations on the host; the
+// solve ends on the true residual, each cycle on the Givens estimate reduced
+// by the factor the true residual still lacks.
+int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
+  const int m = X->p.restart;
+  const int flexible = (X->p.krylov == STOKES_FGMRES);
+  const i64 n = X->n, nv = X->nvel;
+  stokes_stats local;
+  if (!st) st = &local;
+  std::memset(st, 0, sizeof(*st));
+  double *hb = X->host;
+  launch_norm2(X->b, n, X->part, X->dsc + 0, X->s);
+  const double nb = std::sqrt(fetch(X, X->dsc, 1, hb));
+  if (X->err) return STOKES_EDEVICE;
+  if (nb == 0.0) {
+    launch_fill<double>(X->x, 0.0, n, X->s);
+    return STOKES_OK;
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hc2(m + 2);
+  const double eta = 0.70710678118654752440;
+  int it = 0, rc = STOKES_OK;
+  for (;;) {
+    // r = b - M x and its norm
+    launch_apply_m<double>(X->lev[0].g, X->m_alpha, X->m_muc, X->m_mue, X->x, X->x + nv, X->b,
+                           X->b + nv, X->r, X->r + nv, X->s);
+    launch_norm2(X->r, n, X->part, X->dsc + 0, X->s);
+    const double rho = std::sqrt(fetch(X, X->dsc, 1, hb));
+    if (X->err) return STOKES_EDEVICE;
+    st->rel_res_true = rho / nb;
+    if (!std::isfinite(rho)) { rc = STOKES_ENONFINITE; break; }
+    if (rho <= tol * nb) { rc = STOKES_OK; break; }
+    if (it >= max_iter) { rc = STOKES_ENOCONV; break; }
+    st->restarts++;
+    double beta;
+    if (flexible) {
+      beta = rho;
+      launch_scale(X->r, 1.0 / beta, X->V[0], n, X->s);
+    } else {
+      precond<double>(X, X->r, X->r + nv, X->V[0], X->V[0] + nv);
+      st->precond_applies++;
+      launch_norm2(X->V[0], n, X->part, X->dsc + 0, X->s);
+      beta = std::sqrt(fetch(X, X->dsc, 1, hb));
+      if (!std::isfinite(beta)) { rc = STOKES_ENONFINITE; break; }
+      if (beta == 0.0) { rc = STOKES_EBREAKDOWN; break; }
+      launch_scale(X->V[0], 1.0 / beta, X->V[0], n, X->s);
+    }
+    const double target = beta * tol * nb / rho;
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jj = 0;
+    for (int j = 0; j < m; j++) {
+      if (flexible) {
+        precond_from64(X, X->V[j], X->Z[j]);
+        if (X->mg32)
+          launch_apply_m<float>(X->lev[0].g, X->m_alpha, X->m_muc, X->m_mue, P<float>(X->Z[j]),
+                                P<float>(X->Z[j]) + nv, nullptr, nullptr, X->w, X->w + nv, X->s);
+        else
+          apply_scaled(X, P<double>(X->Z[j]), X->w);
+      } else {
+        apply_scaled(X, X->V[j], X->t);
+        precond<double>(X, X->t, X->t + nv, X->w, X->w + nv);
+      }
+      st->precond_applies++;
+      it++;
+      // classical Gram-Schmidt: dots with v_0..v_j and (w,w), then update
+      launch_multidot(X->w, X->V, j + 1, n, X->part, X->dsc + 32, X->s);
+      launch_multiaxpy_norm(X->w, X->V, X->dsc + 32, j + 1, n, X->part, X->dsc + 0, X->s);
+      hip_ok(X, hipMemcpyAsync(hb, X->dsc, sizeof(double), hipMemcpyDeviceToHost, X->s));
+      hip_ok(X, hipMemcpyAsync(hb + 32, X->dsc + 32, (j + 2) * sizeof(double),
+                               hipMemcpyDeviceToHost, X->s));
+      hip_ok(X, hipStreamSynchronize(X->s));
+      if (X->err) return STOKES_EDEVICE;
+      double *hcol = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i <= j; i++) hcol[i] = hb[32 + i];
+      const double nw0 = std::sqrt(hb[32 + j + 1]);
+      double hn = std::sqrt(hb[0]);
+      if (hn < eta * nw0) {
+        launch_multidot(X->w, X->V, j + 1, n, X->part, X->dsc + 80, X->s);
+        launch_multiaxpy_norm(X->w, X->V, X->dsc + 80, j + 1, n, X->part, X->dsc + 0, X->s);
+        hip_ok(X, hipMemcpyAsync(hb, X->dsc, sizeof(double), hipMemcpyDeviceToHost, X->s));
+        hip_ok(X, hipMemcpyAsync(hb + 80, X->dsc + 80, (j + 1) * sizeof(double),
+                                 hipMemcpyDeviceToHost, X->s));
+        hip_ok(X, hipStreamSynchronize(X->s));
+        if (X->err) return STOKES_EDEVICE;
+        for (int i = 0; i <= j; i++) hcol[i] += hb[80 + i];
+        hn = std::sqrt(hb[0]);
+      }
+      hcol[j + 1] = hn;
+      for (int i = 0; i < j; i++) {
+        const double a = hcol[i], bb = hcol[i + 1];
+        hcol[i] = cs[i] * a + sn[i] * bb;
+        hcol[i + 1] = -sn[i] * a + cs[i] * bb;
+      }
+      const double den = std::hypot(hcol[j], hcol[j + 1]);
+      if (den == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        cs[j] = hcol[j] / den;
+        sn[j] = hcol[j + 1] / den;
+      }
+      hcol[j] = den;
+      hcol[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      jj = j + 1;
+      const double est = std::fabs(g[j + 1]);
+      st->rel_res_est = est / beta * (rho / nb);
+      if (!std::isfinite(est)) break;
+      if (hn == 0.0 || est <= target || it >= max_iter) break;
+      launch_scale(X->w, 1.0 / hn, X->V[j + 1], n, X->s);
+    }
+    for (int i = jj - 1; i >= 0; i--) {
+      double s = g[i];
+      for (int k = i + 1; k < jj; k++) s -= H[i + (size_t)k * (m + 1)] * y[k];
+      const double dg = H[i + (size_t)i * (m + 1)];
+      y[i] = (dg != 0.0) ? s / dg : 0.0;
+    }
+    if (flexible) {
+      if (X->mg32)
+        launch_update_x<float>(X->x, (const float *const *)X->Z, y.data(), jj, n, X->s);
+      else
+        launch_update_x<double>(X->x, (const double *const *)X->Z, y.data(), jj, n, X->s);
+    } else {
+      launch_update_x<double>(X->x, (const double *const *)X->V, y.data(), jj, n, X->s);
+    }
+  }
+  st->iters = it;
+  const int vel_per = (X->p.precond == STOKES_P5) ? 2 : 1;
+  const int p_per = (X->p.precond == STOKES_P1) ? 1 : (X->p.theta != 0.0 ? 1 : 0);
+  st->scalar_vcycles = st->precond_applies * X->p.vcycles * (X->d * vel_per + p_per);
+  return rc;
+}
+
+// compatibility of b' with the null space (Sec. 3.2); b' in X->b
+int check_rhs(stokes_ctx *X) {
+  const Geo &g = X->lev[0].g;
+  double *hb = X->host;
+  launch_sum<double>(X->b + X->nvel, X->ncell, X->part, X->dsc + 1, X->s);
+  launch_norm2(X->b + X->nvel, X->ncell, X->part, X->dsc + 2, X->s);
+  launch_norm2(X->b, X->nvel, X->part, X->dsc + 3, X->s);
+  for (int k = 0; k < g.d; k++) launch_sum<double>(X->b + g.foff[k], g.fcnt[k], X->part,
+                                                   X->dsc + 4 + k, X->s);
+  fetch(X, X->dsc, 8, hb);
+  if (X->err) return STOKES_EDEVICE;
+  const double c = X->c;
+  const double nrm = std::sqrt(hb[2] + hb[3] / (c * c)) + 1e-300;
+  if (std::fabs(hb[1]) > 1e-10 * nrm * std::sqrt((double)X->ncell)) return STOKES_EINCOMPAT;
+  if (X->vel_singular) {
+    for (int k = 0; k < g.d; k++)
+      if (std::fabs(hb[4 + k] / c) > 1e-10 * nrm * std::sqrt((double)g.fcnt[k]))
+        return STOKES_EINCOMPAT;
+  }
+  return STOKES_OK;
+}
+
+// unscaled x -> user buffers: x_u = x'_u, x_p = x'_p / c; zero means
+void finish_solution(stokes_ctx *X, const double *xs, double su, double sp, double *xu,
+                     double *xp) {
+  const Geo &g = X->lev[0].g;
+  launch_pack_vel(g, xs, su, xu, X->s);
+  launch_scale(xs + X->nvel, sp, xp, X->ncell, X->s);
+  remove_mean<double>(X, xp, X->ncell, 24);
+  if (X->vel_singular) remove_vel_means<double>(X, g, xu);
+}
+
+int grad_impl(stokes_ctx *X, const double *u, const double *lam, double *dmu_cell,
+              double *dmu_edge, double *drho) {
+  const Geo &g = X->lev[0].g;
+  double *de = dmu_edge ? dmu_edge : X->gedge;
+  launch_grad_edges(g, u, lam, de, X->s);
+  if (dmu_cell || drho) {
+    // write into temporaries when a requested output is missing
+    double *dc = dmu_cell ? dmu_cell : X->gcell;
+    launch_grad_cells(g, u, lam, X->p.theta, dc, drho, X->s);
+    if (dmu_cell && X->p.edge_avg != STOKES_EDGE_GIVEN)
+      launch_grad_chain(g, de, X->m_mue, X->m_muc, X->p.edge_avg, dmu_cell, X->s);
+  }
+  return STOKES_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+int stokes_sizes(const stokes_params *p, size_t *nvel, size_t *ncell, size_t *nedge,
+                 int *nlevels) {
+  int nlev = 0;
+  if (!valid_params(p, &nlev)) return STOKES_EINVAL;
+  int n[3], ns[3];
+  for (int a = 0; a < 3; a++) {
+    n[a] = (a < p->dim) ? p->n[a] : 1;
+    ns[a] = (a < p->dim) ? p->bc[a] : 0;
+  }
+  Geo g = make_geo(p->dim, n, ns, p->h);
+  if (nvel) *nvel = (size_t)g.nvel;
+  if (ncell) *ncell = (size_t)g.ncell;
+  if (nedge) *nedge = (size_t)g.nedge;
+  if (nlevels) *nlevels = nlev;
+  return STOKES_OK;
+}
+
+size_t stokes_workspace_bytes(const stokes_params *p) {
+  int nlev = 0;
+  if (!valid_params(p, &nlev)) return 0;
+  Carver cv(nullptr);
+  carve_all(p, nlev, cv, nullptr);
+  return cv.off + kAlign;
+}
+
+int stokes_create(const stokes_params *p, const double *rho, const double *mu,
+                  const double *mu_edges, void *workspace, size_t ws_bytes, void *hip_stream,
+                  stokes_ctx **out) {
+  if (!out) return STOKES_EINVAL;
+  *out = nullptr;
+  int nlev = 0;
+  if (!valid_params(p, &nlev) || !rho || !mu || !workspace) return STOKES_EINVAL;
+  if (p->edge_avg == STOKES_EDGE_GIVEN && !mu_edges) return STOKES_EINVAL;
+  if (((uintptr_t)workspace) % kAlign != 0) return STOKES_EINVAL;
+  if (ws_bytes < stokes_workspace_bytes(p)) return STOKES_ENOMEM;
+  stokes_ctx *X = new (std::nothrow) stokes_ctx();
+  if (!X) return STOKES_ENOMEM;
+  X->p = *p;
+  X->s = (hipStream_t)hip_stream;
+  X->d = p->dim;
+  X->nlev = nlev;
+  X->mg32 = (p->precision == STOKES_MG_FP32);
+  Carver cv(workspace);
+  carve_all(p, nlev, cv, X);
+  const Geo &g0 = X->lev[0].g;
+  X->nvel = g0.nvel;
+  X->ncell = g0.ncell;
+  X->nedge = g0.nedge;
+  X->n = g0.nvel + g0.ncell;
+  X->vel_singular = (p->theta == 0.0);
+  for (int a = 0; a < p->dim; a++)
+    if (p->bc[a] == STOKES_NOSLIP) X->vel_singular = 0;
+  if (hipHostMalloc((void **)&X->host, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete X;
+    return STOKES_EDEVICE;
+  }
+  hipStream_t s = X->s;
+  // all internal buffers start at zero (wall faces stay 0 for good)
+  (void)hipMemsetAsync(workspace, 0, cv.off, s);
+  // coefficient check and rescaling factor
+  launch_fill<int>(X->dflag, 0, 1, s);
+  launch_check_coefs(rho, mu, g0.ncell, X->dflag, s);
+  launch_logsum(mu, g0.ncell, X->part, X->dsc, s);
+  int flag = 0;
+  (void)hipMemcpyAsync(&X->host[0], X->dsc, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(&X->host[8], X->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipHostFree(X->host);
+    delete X;
+    return STOKES_EDEVICE;
+  }
+  std::memcpy(&flag, &X->host[8], sizeof(int));
+  if (flag) {
+    (void)hipHostFree(X->host);
+    delete X;
+    return STOKES_EINVAL;
+  }
+  if (p->rescale_c > 0.0) {
+    X->c = p->rescale_c;
+  } else {
+    const double sl = X->host[0], cnt = X->host[1];
+    X->c = (cnt > 0.0) ? p->h / std::exp(sl / cnt) : 1.0;
+  }
+  // FP64 fine coefficients (scaled), then the hierarchy (Appendix C).  The
+  // FP32 form coarsens in FP64 and rounds each level once.
+  if (!X->mg32) {
+    Level &L0 = X->lev[0];
+    launch_setup_faces(g0, rho, p->theta, X->c, P<double>(L0.alpha), P<double>(L0.beta), s);
+    launch_setup_cells(g0, mu, X->c, P<double>(L0.muc), s);
+    launch_setup_edges(g0, mu, mu_edges, p->edge_avg, X->c, P<double>(L0.mue), s);
+    (void)hipMemcpyAsync(X->m_alpha, L0.alpha, g0.nvel * 8, hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(X->m_muc, L0.muc, g0.ncell * 8, hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(X->m_mue, L0.mue, g0.nedge * 8, hipMemcpyDeviceToDevice, s);
+    for (int l = 1; l < nlev; l++) {
+      Level &F = X->lev[l - 1], &C = X->lev[l];
+      launch_coarsen(F.g, C.g, P<double>(F.alpha), P<double>(F.beta), P<double>(F.muc),
+                     P<double>(F.mue), P<double>(C.alpha), P<double>(C.beta), P<double>(C.muc),
+                     P<double>(C.mue), s);
+    }
+  } else {
+    launch_setup_faces(g0, rho, p->theta, X->c, X->c64a[0], X->c64b[0], s);
+    launch_setup_cells(g0, mu, X->c, X->c64m[0], s);
+    launch_setup_edges(g0, mu, mu_edges, p->edge_avg, X->c, X->c64e[0], s);
+    for (int l = 1; l < nlev; l++)
+      launch_coarsen(X->lev[l - 1].g, X->lev[l].g, X->c64a[l - 1], X->c64b[l - 1], X->c64m[l - 1],
+                     X->c64e[l - 1], X->c64a[l], X->c64b[l], X->c64m[l], X->c64e[l], s);
+    for (int l = 0; l < nlev; l++) {
+      Level &L = X->lev[l];
+      launch_cast<float, double>(X->c64a[l], P<float>(L.alpha), L.g.nvel, s);
+      launch_cast<float, double>(X->c64b[l], P<float>(L.beta), L.g.nvel, s);
+      launch_cast<float, double>(X->c64m[l], P<float>(L.muc), L.g.ncell, s);
+      launch_cast<float, double>(X->c64e[l], P<float>(L.mue), L.g.nedge, s);
+    }
+  }
+  // algorithmic bytes of one finest-level velocity colour pass of component
+  // k: read all velocity components, rhs_k, alpha_k, mu_cell and the d-1 edge
+  // families around k; write u_k (each array counted once)
+  const double tb = X->mg32 ? 4.0 : 8.0;
+  for (int k = 0; k < g0.d; k++) {
+    double e = 0.0;
+    for (int m = 0; m < 3; m++)
+      if (m != k && g0.ecnt[m] > 0) e += (double)g0.ecnt[m];
+    if (g0.d == 2) e = (double)g0.ecnt[2];
+    X->gs_bytes[k] = tb * ((double)g0.nvel + 3.0 * (double)g0.fcnt[k] + (double)g0.ncell + e);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
+    (void)hipHostFree(X->host);
+    delete X;
+    return STOKES_EDEVICE;
+  }
+  *out = X;
+  return STOKES_OK;
+}
+
+void stokes_destroy(stokes_ctx *X) {
+  if (!X) return;
+  if (X->s) (void)hipStreamSynchronize(X->s);
+  for (auto e : X->ev) (void)hipEventDestroy(e);
+  if (X->host) (void)hipHostFree(X->host);
+  delete X;
+}
+
+double stokes_rescale(const stokes_ctx *X) { return X ? X->c : 0.0; }
+
+int stokes_apply(stokes_ctx *X, const double *xu, const double *xp, double *yu, double *yp) {
+  if (!X || !xu || !xp || !yu || !yp) return STOKES_EINVAL;
+  const Geo &g = X->lev[0].g;
+  // x' = (x_u, c x_p); y_u = (M' x')_u / c, y_p = (M' x')_p
+  launch_pack_vel(g, xu, 1.0, X->t, X->s);
+  launch_scale(xp, X->c, X->t + X->nvel, X->ncell, X->s);
+  apply_scaled(X, X->t, X->w);
+  launch_pack_vel(g, X->w, 1.0 / X->c, yu, X->s);
+  launch_scale(X->w + X->nvel, 1.0, yp, X->ncell, X->s);
+  return finish(X, STOKES_OK);
+}
+
+int stokes_precond(stokes_ctx *X, const double *bu, const double *bp, double *zu, double *zp) {
+  if (!X || !bu || !bp || !zu || !zp) return STOKES_EINVAL;
+  const Geo &g = X->lev[0].g;
+  launch_pack_vel(g, bu, X->c, X->t, X->s);
+  launch_scale(bp, 1.0, X->t + X->nvel, X->ncell, X->s);
+  if (X->mg32) {
+    precond_from64(X, X->t, X->pout);
+    launch_cast<double, float>(P<float>(X->pout), X->w, X->n, X->s);
+  } else {
+    precond<double>(X, X->t, X->t + X->nvel, X->w, X->w + X->nvel);
+  }
+  launch_pack_vel(g, X->w, 1.0, zu, X->s);
+  launch_scale(X->w + X->nvel, 1.0 / X->c, zp, X->ncell, X->s);
+  return finish(X, STOKES_OK);
+}
+
+int stokes_vel_subsolve(stokes_ctx *X, const double *r, double *e) {
+  if (!X || !r || !e) return STOKES_EINVAL;
+  const Geo &g = X->lev[0].g;
+  launch_pack_vel(g, r, X->c, X->t, X->s);
+  if (X->mg32) {
+    launch_cast<float, double>(X->t, P<float>(X->pin), X->nvel, X->s);
+    vel_sub<float>(X, P<float>(X->pin), P<float>(X->pout));
+    launch_cast<double, float>(P<float>(X->pout), X->w, X->nvel, X->s);
+  } else {
+    vel_sub<double>(X, X->t, X->w);
+  }
+  launch_pack_vel(g, X->w, 1.0, e, X->s);
+  return finish(X, STOKES_OK);
+}
+
+int stokes_p_subsolve(stokes_ctx *X, const double *r, double *e) {
+  if (!X || !r || !e) return STOKES_EINVAL;
+  if (X->mg32) {
+    launch_cast<float, double>(r, P<float>(X->pin), X->ncell, X->s);
+    p_sub<float>(X, P<float>(X->pin), P<float>(X->pout));
+    launch_cast<double, float>(P<float>(X->pout), X->w, X->ncell, X->s);
+  } else {
+    p_sub<double>(X, r, X->w);
+  }
+  launch_scale(X->w, 1.0 / X->c, e, X->ncell, X->s);
+  return finish(X, STOKES_OK);
+}
+
+int stokes_solve(stokes_ctx *X, const double *bu, const double *bp, double *xu, double *xp,
+                 double tol, int max_iter, int use_x0, stokes_stats *st) {
+  if (!X || !bu || !bp || !xu || !xp || !(tol > 0.0) || max_iter < 0) return STOKES_EINVAL;
+  const Geo &g = X->lev[0].g;
+  // rescaled system (eq. Stokes_rescaled): b' = (c b_u, b_p), x' = (x_u, c x_p)
+  launch_pack_vel(g, bu, X->c, X->b, X->s);
+  launch_scale(bp, 1.0, X->b + X->nvel, X->ncell, X->s);
+  int rc = check_rhs(X);
+  if (rc != STOKES_OK) return finish(X, rc);
+  if (use_x0) {
+    launch_pack_vel(g, xu, 1.0, X->x, X->s);
+    launch_scale(xp, X->c, X->x + X->nvel, X->ncell, X->s);
+  } else {
+    launch_fill<double>(X->x, 0.0, X->n, X->s);
+  }
+  rc = krylov(X, tol, max_iter, st);
+  finish_solution(X, X->x, 1.0, 1.0 / X->c, xu, xp);
+  hip_ok(X, hipStreamSynchronize(X->s));
+  return finish(X, rc);
+}
+
+int stokes_grad(stokes_ctx *X, const double *xu, const double *lu, double *dmu_cell,
+                double *dmu_edge, double *drho_cell) {
+  if (!X || !xu || !lu) return STOKES_EINVAL;
+  const Geo &g = X->lev[0].g;
+  launch_pack_vel(g, xu, 1.0, X->t, X->s);
+  launch_pack_vel(g, lu, 1.0, X->r, X->s);
+  grad_impl(X, X->t, X->r, dmu_cell, dmu_edge, drho_cell);
+  return finish(X, STOKES_OK);
+}
+
+int stokes_adjoint_solve(stokes_ctx *X, const double *xu, const double *xp, const double *gu,
+                         const double *gp, double *lu, double *lp, double *dmu_cell,
+                         double *dmu_edge, double *drho_cell, double tol, int max_iter,
+                         stokes_stats *st) {
+  (void)xp;
+  if (!X || !xu || !gu || !gp || !lu || !lp || !(tol > 0.0) || max_iter < 0)
+    return STOKES_EINVAL;
+  const Geo &g = X->lev[0].g;
+  // M' = diag(c,1) M diag(1,1/c) is symmetric: lambda = diag(c,1) M'^{-1} (g_u, g_p / c)
+  launch_pack_vel(g, gu, 1.0, X->b, X->s);
+  launch_scale(gp, 1.0 / X->c, X->b + X->nvel, X->ncell, X->s);
+  int rc = check_rhs(X);
+  if (rc != STOKES_OK) return finish(X, rc);
+  launch_fill<double>(X->x, 0.0, X->n, X->s);
+  rc = krylov(X, tol, max_iter, st);
+  finish_solution(X, X->x, X->c, 1.0, lu, lp);
+  launch_pack_vel(g, xu, 1.0, X->t, X->s);
+  grad_impl(X, X->t, lu, dmu_cell, dmu_edge, drho_cell);
+  hip_ok(X, hipStreamSynchronize(X->s));
+  return finish(X, rc);
+}
+
+int stokes_set_timing(stokes_ctx *X, int enable) {
+  if (!X) return STOKES_EINVAL;
+  if (enable && X->ev.empty()) {
+    X->ev.resize(2 * kEventPool);
+    for (auto &e : X->ev)
+      if (hipEventCreate(&e) != hipSuccess) return STOKES_EDEVICE;
+  }
+  fold_events(X);
+  X->timing = enable ? 1 : 0;
+  X->t_ms = 0.0;
+  X->launches = 0;
+  X->bytes = 0.0;
+  return STOKES_OK;
+}
+
+int stokes_kernel_time(stokes_ctx *X, double *ms_total, long *launches, double *bytes_total) {
+  if (!X) return STOKES_EINVAL;
+  fold_events(X);
+  if (ms_total) *ms_total = X->t_ms;
+  if (launches) *launches = X->launches;
+  if (bytes_total) *bytes_total = X->bytes;
+  return STOKES_OK;
+}
+
+const char *stokes_strerror(int code) {
+  switch (code) {
+    case STOKES_OK: return "ok";
+    case STOKES_EINVAL: return "invalid argument";
+    case STOKES_ENOMEM: return "workspace too small";
+    case STOKES_EDEVICE: return "HIP runtime error";
+    case STOKES_ENOCONV: return "not converged within max_iter";
+    case STOKES_EBREAKDOWN: return "Krylov breakdown";
+    case STOKES_ENONFINITE: return "non-finite residual";
+    case STOKES_EINCOMPAT: return "right-hand side incompatible with the null space";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// stokes_internal.h -- device geometry descriptor and kernel launch wrappers
+// shared by the HIP kernels (stokes_kernels.hip) and the host driver
+// (stokes_api.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace stk {
+
+typedef long long i64;
+
+// Geometry of one multigrid level on the staggered (MAC) grid.
+//   cells: n[0] x n[1] x n[2] (n[2] = 1 in 2D), x fastest;
+//   velocity component k: dims fd[k] = n + ns[k] e_k, offset foff[k] in the
+//     concatenated velocity buffer;
+//   edge family m (parallel to axis m): dims ed[m] = n + ns on the other axes,
+//     offset eoff[m] in the concatenated edge buffer.
+struct Geo {
+  int d;
+  int n[3];
+  int ns[3];
+  double h;
+  i64 ncell, nvel, nedge;
+  i64 foff[3];
+  int fd[3][3];
+  i64 fcnt[3];
+  i64 eoff[3];
+  int ed[3][3];
+  i64 ecnt[3];
+};
+
+Geo make_geo(int d, const int n[3], const int ns[3], double h);
+
+// ---- launch wrappers (all asynchronous on stream s) ----------------------
+
+// coefficient setup (scaled by c): faces alpha = c*theta*rho_f, beta =
+// (1/rho_f)/c; cells mu_c = c*mu; edges = c * mean/harmonic/given.
+void launch_setup_faces(const Geo &g, const double *rho, double theta, double c, double *alpha,
+                        double *beta, hipStream_t s);
+void launch_setup_cells(const Geo &g, const double *mu, double c, double *muc, hipStream_t s);
+void launch_setup_edges(const Geo &g, const double *mu, const double *given, int mode, double c,
+                        double *mue, hipStream_t s);
+void launch_coarsen(const Geo &gf, const Geo &gc, const double *af, const double *bf,
+                    const double *mcf, const double *mef, double *ac, double *bc, double *mcc,
+                    double *mec, hipStream_t s);
+void launch_check_coefs(const double *rho, const double *mu, i64 n, int *flag, hipStream_t s);
+
+// element-wise
+template <typename TO, typename TI>
+void launch_cast(const TI *in, TO *out, i64 n, hipStream_t s);
+template <typename T>
+void launch_fill(T *a, T v, i64 n, hipStream_t s);
+// out = scale * in on a velocity buffer with wall faces forced to 0
+void launch_pack_vel(const Geo &g, const double *in, double scale, double *out, hipStream_t s);
+void launch_scale(const double *in, double scale, double *out, i64 n, hipStream_t s);
+template <typename T>
+void launch_axpy(T a, const T *x, T *y, i64 n, hipStream_t s);  // y += a x
+
+// saddle operator on the fine level in FP64:
+//   y_u = alpha u - L_mu u + G p, y_p = -D u            (b == nullptr)
+//   y = b - M x                                         (b != nullptr)
+template <typename TI>
+void launch_apply_m(const Geo &g, const double *alpha, const double *muc, const double *mue,
+                    const TI *xu, const TI *xp, const double *bu, const double *bp, double *yu,
+                    double *yp, hipStream_t s);
+
+// multigrid level kernels, T = float or double
+template <typename T>
+void launch_vel_gs(const Geo &g, int k, int colour, const T *alpha, const T *muc, const T *mue,
+                   const T *rhs, T *phi, hipStream_t s);
+template <typename T>
+void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mue, const T *rhs,
+                         const T *phi, const T *p, T *res, hipStream_t s);  // res = rhs - A phi - G p
+template <typename T>
+void launch_face_restrict(const Geo &gf, const Geo &gc, const T *rf, T *rc, hipStream_t s);
+template <typename T>
+void launch_face_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *phif, hipStream_t s);
+template <typename T>
+void launch_p_gs(const Geo &g, int colour, const T *beta, const T *rhs, T *phi, hipStream_t s);
+template <typename T>
+void launch_p_residual(const Geo &g, const T *beta, const T *rhs, const T *phi, T *res,
+                       hipStream_t s);
+template <typename T>
+void launch_cell_restrict(const Geo &gf, const Geo &gc, const T *rf, T *rc, hipStream_t s);
+template <typename T>
+void launch_cell_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *pf, hipStream_t s);
+
+// preconditioner glue (level 0, precision T)
+template <typename T>  // out = sgn * (D u + bp)   (bp may be null)
+void launch_div(const Geo &g, const T *u, const T *bp, T sgn, T *out, hipStream_t s);
+template <typename T>  // zu = xs + beta * G q
+void launch_proj_update(const Geo &g, const T *xs, const T *beta, const T *q, T *zu, hipStream_t s);
+template <typename T>  // out = bu - G p
+void launch_grad_sub(const Geo &g, const T *bu, const T *p, T *out, hipStream_t s);
+template <typename T>  // out = a*q + b*mu*c  (q may be null)
+void launch_schur_combine(const T *q, const T *c, const T *mu, T a, T b, T *out, i64 n,
+                          hipStream_t s);
+
+// means (deterministic two-stage reductions; result stays on the device)
+template <typename T>
+void launch_sum(const T *a, i64 n, double *partials, double *out, hipStream_t s);
+template <typename T>
+void launch_sub_mean(T *a, i64 n, const double *sum, hipStream_t s);
+
+// Krylov (FP64)
+constexpr int kRedBlocks = 512;
+// dots[i] = (w, v_i) for i < nv; dots[nv] = (w, w)
+void launch_multidot(const double *w, const double *const *v, int nv, i64 n, double *partials,
+                     double *dots, hipStream_t s);
+// w -= sum_i h_i v_i (h on the device); nrm2 = (w, w)
+void launch_multiaxpy_norm(double *w, const double *const *v, const double *h, int nv, i64 n,
+                           double *partials, double *nrm2, hipStream_t s);
+// x += sum_i y_i z_i with z in precision TZ (y: host array, passed by value)
+template <typename TZ>
+void launch_update_x(double *x, const TZ *const *z, const double *y, int nz, i64 n,
+                     hipStream_t s);
+// out2 = {sum of log(mu) over mu > 0, count of mu > 0}
+void launch_logsum(const double *mu, i64 n, double *partials, double *out2, hipStream_t s);
+// nrm2 = (a, a)
+void launch_norm2(const double *a, i64 n, double *partials, double *nrm2, hipStream_t s);
+
+// gradient contraction (unscaled forward u and adjoint lambda)
+void launch_grad_cells(const Geo &g, const double *u, const double *lam, double theta,
+                       double *dmu_cell, double *drho, hipStream_t s);
+void launch_grad_edges(const Geo &g, const double *u, const double *lam, double *dmu_edge,
+                       hipStream_t s);
+void launch_grad_chain(const Geo &g, const double *dmu_edge, const double *mue_raw,
+                       const double *muc_raw, int mode, double *dmu_cell, hipStream_t s);
+
+}  // namespace stk

@@ -1,0 +1,1308 @@
+// stokes_kernels.hip -- gfx950 kernels of the variable-coefficient MAC Stokes
+// solver (arXiv:1308.4605).  Every kernel is bandwidth bound: low-order
+// stencils, transfers, pointwise glue and reductions.  No matrix cores: no
+// step is a dense contraction.
+//
+// Conventions: cell-indexed launches cover the cells of a level; a thread at
+// cell (i0,i1,i2) handles the face of component k whose index is the same
+// triple (the face on the low side of the cell along k).  That visits every
+// face with index < n[k] along k; the high wall faces (index n[k] on a
+// no-slip axis) are never written, and internal vectors keep 0 there.  Low
+// wall faces (index 0 on a no-slip axis) are skipped.  All internal velocity
+// vectors therefore hold 0 on every wall face, which lets the stencils read
+// wall values without branches.
+#include <hip/hip_runtime.h>
+
+#include "stokes_internal.h"
+
+namespace stk {
+
+constexpr int kBlock = 256;
+
+static inline unsigned blocks_for(i64 n) {
+  i64 b = (n + kBlock - 1) / kBlock;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+Geo make_geo(int d, const int n[3], const int ns[3], double h) {
+  Geo g;
+  g.d = d;
+  g.h = h;
+  for (int a = 0; a < 3; a++) {
+    g.n[a] = (a < d) ? n[a] : 1;
+    g.ns[a] = (a < d) ? ns[a] : 0;
+  }
+  g.ncell = (i64)g.n[0] * g.n[1] * g.n[2];
+  i64 off = 0;
+  for (int k = 0; k < 3; k++) {
+    for (int a = 0; a < 3; a++) g.fd[k][a] = g.n[a] + ((a == k && k < d) ? g.ns[a] : 0);
+    g.foff[k] = off;
+    g.fcnt[k] = (k < d) ? (i64)g.fd[k][0] * g.fd[k][1] * g.fd[k][2] : 0;
+    off += g.fcnt[k];
+  }
+  g.nvel = off;
+  off = 0;
+  for (int m = 0; m < 3; m++) {
+    for (int a = 0; a < 3; a++) g.ed[m][a] = g.n[a] + ((a != m && a < d) ? g.ns[a] : 0);
+    g.eoff[m] = 0;
+    g.ecnt[m] = 0;
+  }
+  for (int m = 2; m >= 0; m--) {  // storage order m = 2, 1, 0 (2D: m = 2)
+    if (d == 2 && m != 2) continue;
+    g.eoff[m] = off;
+    g.ecnt[m] = (i64)g.ed[m][0] * g.ed[m][1] * g.ed[m][2];
+    off += g.ecnt[m];
+  }
+  g.nedge = off;
+  return g;
+}
+
+// ------------------------------------------------------------------------
+// index helpers
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ i64 fidx(const Geo &g, int k, int i0, int i1, int i2) {
+  return g.foff[k] + ((i64)i2 * g.fd[k][1] + i1) * g.fd[k][0] + i0;
+}
+__device__ __forceinline__ i64 fidx3(const Geo &g, int k, const int i[3]) {
+  return fidx(g, k, i[0], i[1], i[2]);
+}
+__device__ __forceinline__ i64 cidx3(const Geo &g, const int i[3]) {
+  return ((i64)i[2] * g.n[1] + i[1]) * g.n[0] + i[0];
+}
+__device__ __forceinline__ i64 eidx3(const Geo &g, int m, const int i[3]) {
+  return g.eoff[m] + ((i64)i[2] * g.ed[m][1] + i[1]) * g.ed[m][0] + i[0];
+}
+__device__ __forceinline__ void cell_of(const Geo &g, i64 t, int i[3]) {
+  i64 q = t / g.n[0];
+  i[0] = (int)(t - q * g.n[0]);
+  i[2] = (int)(q / g.n[1]);
+  i[1] = (int)(q - (i64)i[2] * g.n[1]);
+}
+// +1 / -1 neighbour along a periodic axis (index stays in range otherwise)
+__device__ __forceinline__ int up1(const Geo &g, int a, int i) {
+  int j = i + 1;
+  return (!g.ns[a] && j == g.n[a]) ? 0 : j;
+}
+__device__ __forceinline__ int dn1(const Geo &g, int a, int i) {
+  int j = i - 1;
+  return (j < 0) ? j + g.n[a] : j;
+}
+
+// ------------------------------------------------------------------------
+// A = alpha - L_mu at one face (paper Sec. 3.1, eq. div_stress).  Returns
+// (A u)_f and the diagonal of A at f.  Tangential no-slip walls use the ghost
+// value -u_f, which equals the one-sided wall difference (u_f - 0)/(h/2).
+// ------------------------------------------------------------------------
+template <typename T, int DIM>
+__device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const T *__restrict__ u,
+                                      const T *__restrict__ alpha, const T *__restrict__ muc,
+                                      const T *__restrict__ mue, T &Au, T &diag) {
+  const T h = (T)g.h;
+  const T h2 = h * h;
+  const i64 fq = fidx3(g, k, i);
+  const T uf = u[fq];
+  int t[3] = {i[0], i[1], i[2]};
+  // normal stresses at the cells right (index i) and left (index i - e_k)
+  const int kp = up1(g, k, i[k]);
+  const int km = dn1(g, k, i[k]);
+  t[k] = kp;
+  const T ukp = u[fidx3(g, k, t)];
+  t[k] = km;
+  const T ukm = u[fidx3(g, k, t)];
+  const T mr = muc[cidx3(g, i)];
+  const T ml = muc[cidx3(g, t)];
+  t[k] = i[k];
+  const T tr = (T)2 * mr * ((ukp - uf) / h);
+  const T tl = (T)2 * ml * ((uf - ukm) / h);
+  T s = (tr - tl) / h;
+  T dg = alpha[fq] + (T)2 * (mr + ml) / h2;
+#pragma unroll
+  for (int l = 0; l < DIM; l++) {
+    if (l == k) continue;
+    const int m = 3 - k - l;
+    const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
+    const bool bot = g.ns[l] && (i[l] == 0);
+    const int lp = up1(g, l, i[l]);
+    const int lm = dn1(g, l, i[l]);
+    t[l] = top ? i[l] : lp;  // component k has no face at index n[l] along l
+    const T ua = top ? -uf : u[fidx3(g, k, t)];
+    t[l] = lp;
+    const T mhi = mue[eidx3(g, m, t)];
+    // u_l on the two faces beside the upper edge (cells i[k] and i[k]-1 along k)
+    const T ulh_r = u[fidx3(g, l, t)];
+    t[k] = km;
+    const T ulh_l = u[fidx3(g, l, t)];
+    t[k] = i[k];
+    t[l] = lm;
+    const T ub = bot ? -uf : u[fidx3(g, k, t)];
+    t[l] = i[l];
+    const T mlo = mue[eidx3(g, m, t)];
+    const T ull_r = u[fidx3(g, l, t)];
+    t[k] = km;
+    const T ull_l = u[fidx3(g, l, t)];
+    t[k] = i[k];
+    const T ghi = (ua - uf) / h + (ulh_r - ulh_l) / h;
+    const T glo = (uf - ub) / h + (ull_r - ull_l) / h;
+    s += (mhi * ghi - mlo * glo) / h;
+    dg += ((top ? (T)2 : (T)1) * mhi + (bot ? (T)2 : (T)1) * mlo) / h2;
+  }
+  Au = alpha[fq] * uf - s;
+  diag = dg;
+}
+
+__device__ __forceinline__ bool low_wall(const Geo &g, int k, const int i[3]) {
+  return g.ns[k] && i[k] == 0;
+}
+
+// ------------------------------------------------------------------------
+// coefficient setup (Sec. 3.1 averages, Sec. 3.3 rescaling)
+// ------------------------------------------------------------------------
+
+__global__ void k_setup_faces(Geo g, const double *__restrict__ rho, double theta, double c,
+                              double *__restrict__ alpha, double *__restrict__ beta) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ncell) return;
+  int i[3];
+  cell_of(g, t, i);
+  for (int k = 0; k < g.d; k++) {
+    const i64 q = fidx3(g, k, i);
+    if (low_wall(g, k, i)) {
+      alpha[q] = 0.0;
+      beta[q] = 0.0;
+      continue;
+    }
+    int l[3] = {i[0], i[1], i[2]};
+    l[k] = dn1(g, k, i[k]);
+    const double rf = 0.5 * (rho[cidx3(g, i)] + rho[cidx3(g, l)]);
+    alpha[q] = c * (theta * rf);
+    beta[q] = (1.0 / rf) / c;
+  }
+}
+
+__global__ void k_scale_copy(const double *__restrict__ in, double c, double *__restrict__ out,
+                             i64 n) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = c * in[t];
+}
+
+// edge family m: mean (arithmetic, harmonic) of the existing neighbouring
+// cells; 4 inside, 2 on a wall, 1 in a corner
+__global__ void k_setup_edges(Geo g, int m, const double *__restrict__ mu,
+                              const double *__restrict__ given, int mode, double c,
+                              double *__restrict__ mue) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ecnt[m]) return;
+  int e[3];
+  {
+    i64 q = t / g.ed[m][0];
+    e[0] = (int)(t - q * g.ed[m][0]);
+    e[2] = (int)(q / g.ed[m][1]);
+    e[1] = (int)(q - (i64)e[2] * g.ed[m][1]);
+  }
+  const i64 out = g.eoff[m] + t;
+  if (mode == 2) {
+    mue[out] = c * given[out];
+    return;
+  }
+  const int k = (m == 0) ? 1 : 0;
+  const int l = (m == 2) ? 1 : 2;
+  double s = 0.0, sinv = 0.0;
+  int cnt = 0;
+  for (int a = 0; a < 2; a++)
+    for (int b = 0; b < 2; b++) {
+      int cc[3] = {e[0], e[1], e[2]};
+      cc[k] -= a;
+      cc[l] -= b;
+      if (g.ns[k] && (cc[k] < 0 || cc[k] >= g.n[k])) continue;
+      if (g.ns[l] && (cc[l] < 0 || cc[l] >= g.n[l])) continue;
+      if (cc[k] < 0) cc[k] += g.n[k];
+      if (cc[k] >= g.n[k]) cc[k] -= g.n[k];
+      if (cc[l] < 0) cc[l] += g.n[l];
+      if (cc[l] >= g.n[l]) cc[l] -= g.n[l];
+      const double v = mu[cidx3(g, cc)];
+      s += v;
+      sinv += 1.0 / v;
+      cnt++;
+    }
+  const double val = (mode == 1) ? (double)cnt / sinv : s / (double)cnt;
+  mue[out] = c * val;
+}
+
+// coarse coefficients (Appendix C): faces = mean of overlaid fine faces,
+// cells = mean of 2^d fine cells, edges = mean of the two overlaid fine edges
+// (3D) or injection (2D nodes)
+__global__ void k_coarsen_faces_cells(Geo gf, Geo gc, const double *__restrict__ af,
+                                      const double *__restrict__ bf,
+                                      const double *__restrict__ mcf, double *__restrict__ ac,
+                                      double *__restrict__ bc, double *__restrict__ mcc) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gc.ncell) return;
+  int I[3];
+  cell_of(gc, t, I);
+  const int d = gc.d;
+  for (int k = 0; k < d; k++) {
+    const i64 q = fidx3(gc, k, I);
+    if (low_wall(gc, k, I)) {
+      ac[q] = 0.0;
+      bc[q] = 0.0;
+      continue;
+    }
+    int tax[2] = {0, 0}, nt = 0;
+    for (int b = 0; b < d; b++)
+      if (b != k) tax[nt++] = b;
+    double sa = 0.0, sb = 0.0;
+    int cnt = 0;
+    for (int o1 = 0; o1 < 2; o1++)
+      for (int o0 = 0; o0 < (nt == 2 ? 2 : 1); o0++) {
+        int f[3] = {2 * I[0], 2 * I[1], d == 3 ? 2 * I[2] : 0};
+        f[tax[0]] += o1;
+        if (nt == 2) f[tax[1]] += o0;
+        const i64 fq = fidx3(gf, k, f);
+        sa += af[fq];
+        sb += bf[fq];
+        cnt++;
+      }
+    ac[q] = sa / cnt;
+    bc[q] = sb / cnt;
+  }
+  double s = 0.0;
+  for (int o2 = 0; o2 < (d == 3 ? 2 : 1); o2++)
+    for (int o1 = 0; o1 < 2; o1++)
+      for (int o0 = 0; o0 < 2; o0++) {
+        int f[3] = {2 * I[0] + o0, 2 * I[1] + o1, d == 3 ? 2 * I[2] + o2 : 0};
+        s += mcf[cidx3(gf, f)];
+      }
+  mcc[t] = s / (double)(1 << d);
+}
+
+__global__ void k_coarsen_edges(Geo gf, Geo gc, int m, const double *__restrict__ mef,
+                                double *__restrict__ mec) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gc.ecnt[m]) return;
+  int E[3];
+  {
+    i64 q = t / gc.ed[m][0];
+    E[0] = (int)(t - q * gc.ed[m][0]);
+    E[2] = (int)(q / gc.ed[m][1]);
+    E[1] = (int)(q - (i64)E[2] * gc.ed[m][1]);
+  }
+  int e[3] = {2 * E[0], 2 * E[1], gc.d == 3 ? 2 * E[2] : 0};
+  double v;
+  if (m < gc.d) {
+    int e2[3] = {e[0], e[1], e[2]};
+    e2[m] += 1;
+    v = 0.5 * (mef[eidx3(gf, m, e)] + mef[eidx3(gf, m, e2)]);
+  } else {
+    v = mef[eidx3(gf, m, e)];
+  }
+  mec[gc.eoff[m] + t] = v;
+}
+
+__global__ void k_check_coefs(const double *__restrict__ rho, const double *__restrict__ mu,
+                              i64 n, int *flag) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double r = rho[t], m = mu[t];
+  const bool ok = (r > 0.0) && (m >= 0.0) && isfinite(r) && isfinite(m);
+  if (!ok) atomicOr(flag, 1);
+}
+
+void launch_setup_faces(const Geo &g, const double *rho, double theta, double c, double *alpha,
+                        double *beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup_faces, dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, rho, theta,
+                     c, alpha, beta);
+}
+void launch_setup_cells(const Geo &g, const double *mu, double c, double *muc, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, mu, c, muc,
+                     g.ncell);
+}
+void launch_setup_edges(const Geo &g, const double *mu, const double *given, int mode, double c,
+                        double *mue, hipStream_t s) {
+  for (int m = 0; m < 3; m++) {
+    if (g.ecnt[m] == 0) continue;
+    hipLaunchKernelGGL(k_setup_edges, dim3(blocks_for(g.ecnt[m])), dim3(kBlock), 0, s, g, m, mu,
+                       given, mode, c, mue);
+  }
+}
+void launch_coarsen(const Geo &gf, const Geo &gc, const double *af, const double *bf,
+                    const double *mcf, const double *mef, double *ac, double *bc, double *mcc,
+                    double *mec, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarsen_faces_cells, dim3(blocks_for(gc.ncell)), dim3(kBlock), 0, s, gf,
+                     gc, af, bf, mcf, ac, bc, mcc);
+  for (int m = 0; m < 3; m++) {
+    if (gc.ecnt[m] == 0) continue;
+    hipLaunchKernelGGL(k_coarsen_edges, dim3(blocks_for(gc.ecnt[m])), dim3(kBlock), 0, s, gf, gc,
+                       m, mef, mec);
+  }
+}
+void launch_check_coefs(const double *rho, const double *mu, i64 n, int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_coefs, dim3(blocks_for(n)), dim3(kBlock), 0, s, rho, mu, n, flag);
+}
+
+// ------------------------------------------------------------------------
+// element-wise helpers
+// ------------------------------------------------------------------------
+
+template <typename TO, typename TI>
+__global__ void k_cast(const TI *__restrict__ in, TO *__restrict__ out, i64 n) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = (TO)in[t];
+}
+template <typename TO, typename TI>
+void launch_cast(const TI *in, TO *out, i64 n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast<TO, TI>), dim3(blocks_for(n)), dim3(kBlock), 0, s, in, out, n);
+}
+template void launch_cast<float, double>(const double *, float *, i64, hipStream_t);
+template void launch_cast<double, float>(const float *, double *, i64, hipStream_t);
+template void launch_cast<double, double>(const double *, double *, i64, hipStream_t);
+template void launch_cast<float, float>(const float *, float *, i64, hipStream_t);
+
+template <typename T>
+__global__ void k_fill(T *__restrict__ a, T v, i64 n) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) a[t] = v;
+}
+template <typename T>
+void launch_fill(T *a, T v, i64 n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, v, n);
+}
+template void launch_fill<float>(float *, float, i64, hipStream_t);
+template void launch_fill<double>(double *, double, i64, hipStream_t);
+template void launch_fill<int>(int *, int, i64, hipStream_t);
+
+__global__ void k_pack_vel(Geo g, const double *__restrict__ in, double scale,
+                           double *__restrict__ out) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.nvel) return;
+  int k = 0;
+  while (k + 1 < g.d && t >= g.foff[k + 1]) k++;
+  const i64 r = t - g.foff[k];
+  // index along axis k
+  i64 stride = 1;
+  for (int a = 0; a < k; a++) stride *= g.fd[k][a];
+  const int ik = (int)((r / stride) % g.fd[k][k]);
+  const bool wall = g.ns[k] && (ik == 0 || ik == g.n[k]);
+  out[t] = wall ? 0.0 : scale * in[t];
+}
+void launch_pack_vel(const Geo &g, const double *in, double scale, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_vel, dim3(blocks_for(g.nvel)), dim3(kBlock), 0, s, g, in, scale, out);
+}
+void launch_scale(const double *in, double scale, double *out, i64 n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(blocks_for(n)), dim3(kBlock), 0, s, in, scale, out, n);
+}
+
+template <typename T>
+__global__ void k_axpy(T a, const T *__restrict__ x, T *__restrict__ y, i64 n) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] += a * x[t];
+}
+template <typename T>
+void launch_axpy(T a, const T *x, T *y, i64 n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, x, y, n);
+}
+template void launch_axpy<float>(float, const float *, float *, i64, hipStream_t);
+template void launch_axpy<double>(double, const double *, double *, i64, hipStream_t);
+
+// ------------------------------------------------------------------------
+// saddle operator (FP64 arithmetic, input in TI)
+// ------------------------------------------------------------------------
+
+template <typename TI, int DIM>
+__device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
+                                            const TI *__restrict__ u,
+                                            const double *__restrict__ alpha,
+                                            const double *__restrict__ muc,
+                                            const double *__restrict__ mue, double &Au) {
+  const double h = g.h;
+  const i64 fq = fidx3(g, k, i);
+  const double uf = (double)u[fq];
+  int t[3] = {i[0], i[1], i[2]};
+  const int kp = up1(g, k, i[k]);
+  const int km = dn1(g, k, i[k]);
+  t[k] = kp;
+  const double ukp = (double)u[fidx3(g, k, t)];
+  t[k] = km;
+  const double ukm = (double)u[fidx3(g, k, t)];
+  const double mr = muc[cidx3(g, i)];
+  const double ml = muc[cidx3(g, t)];
+  t[k] = i[k];
+  const double tr = 2.0 * mr * ((ukp - uf) / h);
+  const double tl = 2.0 * ml * ((uf - ukm) / h);
+  double s = (tr - tl) / h;
+#pragma unroll
+  for (int l = 0; l < DIM; l++) {
+    if (l == k) continue;
+    const int m = 3 - k - l;
+    const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
+    const bool bot = g.ns[l] && (i[l] == 0);
+    const int lp = up1(g, l, i[l]);
+    const int lm = dn1(g, l, i[l]);
+    t[l] = top ? i[l] : lp;  // component k has no face at index n[l] along l
+    const double ua = top ? -uf : (double)u[fidx3(g, k, t)];
+    t[l] = lp;
+    const double mhi = mue[eidx3(g, m, t)];
+    const double ulh_r = (double)u[fidx3(g, l, t)];
+    t[k] = km;
+    const double ulh_l = (double)u[fidx3(g, l, t)];
+    t[k] = i[k];
+    t[l] = lm;
+    const double ub = bot ? -uf : (double)u[fidx3(g, k, t)];
+    t[l] = i[l];
+    const double mlo = mue[eidx3(g, m, t)];
+    const double ull_r = (double)u[fidx3(g, l, t)];
+    t[k] = km;
+    const double ull_l = (double)u[fidx3(g, l, t)];
+    t[k] = i[k];
+    const double ghi = (ua - uf) / h + (ulh_r - ulh_l) / h;
+    const double glo = (uf - ub) / h + (ull_r - ull_l) / h;
+    s += (mhi * ghi - mlo * glo) / h;
+  }
+  Au = alpha[fq] * uf - s;
+}
+
+template <typename TI, int DIM>
+__global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double *__restrict__ muc,
+                          const double *__restrict__ mue, const TI *__restrict__ xu,
+                          const TI *__restrict__ xp, const double *__restrict__ bu,
+                          const double *__restrict__ bp, double *__restrict__ yu,
+                          double *__restrict__ yp) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ncell) return;
+  int i[3];
+  cell_of(g, t, i);
+  const double h = g.h;
+  const double pc = (double)xp[t];
+  double div = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    int r[3] = {i[0], i[1], i[2]};
+    r[k] = i[k] + 1;
+    if (!g.ns[k] && r[k] == g.n[k]) r[k] = 0;
+    div += ((double)xu[fidx3(g, k, r)] - (double)xu[fidx3(g, k, i)]) / h;
+    const i64 q = fidx3(g, k, i);
+    if (low_wall(g, k, i)) {
+      continue;
+    }
+    double Au;
+    a_row_mixed<TI, DIM>(g, k, i, xu, alpha, muc, mue, Au);
+    int l[3] = {i[0], i[1], i[2]};
+    l[k] = dn1(g, k, i[k]);
+    const double gp = (pc - (double)xp[cidx3(g, l)]) / h;
+    const double y = Au + gp;
+    yu[q] = bu ? bu[q] - y : y;
+  }
+  yp[t] = bp ? bp[t] + div : -div;
+}
+
+template <typename TI>
+void launch_apply_m(const Geo &g, const double *alpha, const double *muc, const double *mue,
+                    const TI *xu, const TI *xp, const double *bu, const double *bp, double *yu,
+                    double *yp, hipStream_t s) {
+  if (g.d == 3)
+    hipLaunchKernelGGL((k_apply_m<TI, 3>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g,
+                       alpha, muc, mue, xu, xp, bu, bp, yu, yp);
+  else
+    hipLaunchKernelGGL((k_apply_m<TI, 2>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g,
+                       alpha, muc, mue, xu, xp, bu, bp, yu, yp);
+}
+template void launch_apply_m<double>(const Geo &, const double *, const double *, const double *,
+                                     const double *, const double *, const double *,
+                                     const double *, double *, double *, hipStream_t);
+template void launch_apply_m<float>(const Geo &, const double *, const double *, const double *,
+                                    const float *, const float *, const double *, const double *,
+                                    double *, double *, hipStream_t);
+
+// ------------------------------------------------------------------------
+// velocity multigrid (Appendix C)
+// ------------------------------------------------------------------------
+
+// one colour of multicolour Gauss-Seidel for component K: faces with
+// (i0 + i1 + i2) % 2 == colour.  Thread t covers one face of that colour:
+// i0 = 2 * (t mod n0/2) + parity.  Same-colour faces do not couple, so the
+// in-place update is race-free.
+// colour mapping shared by the Gauss-Seidel kernels: thread t -> (tx, row)
+// with tx < ceil(n0/2); i0 = 2 tx + parity (odd n0 occurs only on no-slip x
+// axes at the coarsest level; periodic axes are even on every level)
+__device__ __forceinline__ bool colour_cell(const Geo &g, i64 t, int colour, int i[3]) {
+  const int hx = (g.n[0] + 1) >> 1;
+  const i64 rows = (i64)g.n[1] * g.n[2];
+  if (t >= (i64)hx * rows) return false;
+  i64 q = t / hx;
+  const int tx = (int)(t - q * hx);
+  i[2] = (int)(q / g.n[1]);
+  i[1] = (int)(q - (i64)i[2] * g.n[1]);
+  i[0] = 2 * tx + ((i[1] + i[2] + colour) & 1);
+  return i[0] < g.n[0];
+}
+__host__ __forceinline__ i64 colour_threads(const Geo &g) {
+  return (i64)((g.n[0] + 1) >> 1) * g.n[1] * g.n[2];
+}
+
+template <typename T, int DIM, int K>
+__global__ void k_vel_gs(Geo g, int colour, const T *__restrict__ alpha,
+                         const T *__restrict__ muc, const T *__restrict__ mue,
+                         const T *__restrict__ rhs, T *__restrict__ phi) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  int i[3];
+  if (!colour_cell(g, t, colour, i)) return;
+  if (low_wall(g, K, i)) return;
+  T Au, dg;
+  a_row<T, DIM>(g, K, i, phi, alpha, muc, mue, Au, dg);
+  const i64 fq = fidx3(g, K, i);
+  phi[fq] += (rhs[fq] - Au) / dg;
+}
+
+template <typename T>
+void launch_vel_gs(const Geo &g, int k, int colour, const T *alpha, const T *muc, const T *mue,
+                   const T *rhs, T *phi, hipStream_t s) {
+  const unsigned nb = blocks_for(colour_threads(g));
+#define GS_CASE(D, KK)                                                                       \
+  hipLaunchKernelGGL((k_vel_gs<T, D, KK>), dim3(nb), dim3(kBlock), 0, s, g, colour, alpha, muc, \
+                     mue, rhs, phi)
+  if (g.d == 3) {
+    if (k == 0) GS_CASE(3, 0);
+    else if (k == 1) GS_CASE(3, 1);
+    else GS_CASE(3, 2);
+  } else {
+    if (k == 0) GS_CASE(2, 0);
+    else GS_CASE(2, 1);
+  }
+#undef GS_CASE
+}
+
+// res = rhs - A phi - G p (p may be null); cell-indexed over all components
+template <typename T, int DIM>
+__global__ void k_vel_residual(Geo g, const T *__restrict__ alpha, const T *__restrict__ muc,
+                               const T *__restrict__ mue, const T *__restrict__ rhs,
+                               const T *__restrict__ phi, const T *__restrict__ p,
+                               T *__restrict__ res) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ncell) return;
+  int i[3];
+  cell_of(g, t, i);
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    if (low_wall(g, k, i)) continue;
+    T Au, dg;
+    a_row<T, DIM>(g, k, i, phi, alpha, muc, mue, Au, dg);
+    const i64 fq = fidx3(g, k, i);
+    T r = rhs[fq] - Au;
+    if (p) {
+      int l[3] = {i[0], i[1], i[2]};
+      l[k] = dn1(g, k, i[k]);
+      r -= (p[t] - p[cidx3(g, l)]) / (T)g.h;
+    }
+    res[fq] = r;
+  }
+}
+
+template <typename T>
+void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mue, const T *rhs,
+                         const T *phi, const T *p, T *res, hipStream_t s) {
+  if (g.d == 3)
+    hipLaunchKernelGGL((k_vel_residual<T, 3>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g,
+                       alpha, muc, mue, rhs, phi, p, res);
+  else
+    hipLaunchKernelGGL((k_vel_residual<T, 2>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g,
+                       alpha, muc, mue, rhs, phi, p, res);
+}
+
+// face restriction (Appendix C): normal weights 1/4, 1/2, 1/4 at fine faces
+// 2I-1, 2I, 2I+1 times the mean over the 2^(d-1) fine faces along the
+// tangential axes (2D: the printed 6-point stencil; 3D: 12 points)
+template <typename T, int DIM>
+__global__ void k_face_restrict(Geo gf, Geo gc, const T *__restrict__ rf, T *__restrict__ rc) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gc.ncell) return;
+  int I[3];
+  cell_of(gc, t, I);
+  const T wn[3] = {(T)0.25, (T)0.5, (T)0.25};
+  const T wt = (DIM == 3) ? (T)0.25 : (T)0.5;
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    if (low_wall(gc, k, I)) continue;
+    int tax[2] = {0, 0}, nt = 0;
+    for (int b = 0; b < DIM; b++)
+      if (b != k) tax[nt++] = b;
+    T s = 0;
+    for (int a = -1; a <= 1; a++) {
+      T acc = 0;
+      for (int o2 = 0; o2 < (DIM == 3 ? 2 : 1); o2++)
+        for (int o1 = 0; o1 < 2; o1++) {
+          int f[3] = {2 * I[0], 2 * I[1], DIM == 3 ? 2 * I[2] : 0};
+          int fk = 2 * I[k] + a;
+          if (!gf.ns[k]) {
+            if (fk < 0) fk += gf.n[k];
+            if (fk >= gf.n[k]) fk -= gf.n[k];
+          }
+          f[k] = fk;
+          f[tax[0]] += o1;
+          if (DIM == 3) f[tax[1]] += o2;
+          acc += rf[fidx3(gf, k, f)];
+        }
+      s += wn[a + 1] * wt * acc;
+    }
+    rc[fidx3(gc, k, I)] = s;
+  }
+}
+
+template <typename T>
+void launch_face_restrict(const Geo &gf, const Geo &gc, const T *rf, T *rc, hipStream_t s) {
+  if (gc.d == 3)
+    hipLaunchKernelGGL((k_face_restrict<T, 3>), dim3(blocks_for(gc.ncell)), dim3(kBlock), 0, s, gf,
+                       gc, rf, rc);
+  else
+    hipLaunchKernelGGL((k_face_restrict<T, 2>), dim3(blocks_for(gc.ncell)), dim3(kBlock), 0, s, gf,
+                       gc, rf, rc);
+}
+
+// tangential prolongation weights (Appendix C): 3/4 on the parent coarse
+// face, 1/4 on the next one away from the parent's centre; at a no-slip wall
+// the missing neighbour is the odd reflection -phi(J)
+__device__ __forceinline__ void tang_w(const Geo &gc, int a, int j, int idx[2], double w[2]) {
+  const int J = j >> 1;
+  const int Jn = (j & 1) ? J + 1 : J - 1;
+  idx[0] = J;
+  w[0] = 0.75;
+  if (gc.ns[a] && (Jn < 0 || Jn >= gc.n[a])) {
+    idx[1] = J;
+    w[1] = -0.25;
+  } else {
+    int jj = Jn;
+    if (!gc.ns[a]) {
+      if (jj < 0) jj += gc.n[a];
+      if (jj >= gc.n[a]) jj -= gc.n[a];
+    }
+    idx[1] = jj;
+    w[1] = 0.25;
+  }
+}
+
+template <typename T, int DIM>
+__global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
+                                   T *__restrict__ phif) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gf.ncell) return;
+  int f[3];
+  cell_of(gf, t, f);
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    if (low_wall(gf, k, f)) continue;
+    int nidx[2];
+    T nw[2];
+    int nn;
+    if ((f[k] & 1) == 0) {
+      nidx[0] = f[k] >> 1;
+      nw[0] = (T)1;
+      nn = 1;
+    } else {
+      nidx[0] = (f[k] - 1) >> 1;
+      int up = (f[k] + 1) >> 1;
+      if (!gc.ns[k] && up == gc.n[k]) up = 0;
+      nidx[1] = up;
+      nw[0] = nw[1] = (T)0.5;
+      nn = 2;
+    }
+    int tax[2] = {0, 0}, nt = 0;
+    for (int b = 0; b < DIM; b++)
+      if (b != k) tax[nt++] = b;
+    int t0i[2], t1i[2] = {0, 0};
+    double t0w[2], t1w[2] = {1.0, 0.0};
+    tang_w(gc, tax[0], f[tax[0]], t0i, t0w);
+    int n1 = 1;
+    if (DIM == 3) {
+      tang_w(gc, tax[1], f[tax[1]], t1i, t1w);
+      n1 = 2;
+    }
+    T s = 0;
+    for (int a = 0; a < nn; a++)
+      for (int b0 = 0; b0 < 2; b0++)
+        for (int b1 = 0; b1 < n1; b1++) {
+          int cf[3] = {0, 0, 0};
+          cf[k] = nidx[a];
+          cf[tax[0]] = t0i[b0];
+          if (DIM == 3) cf[tax[1]] = t1i[b1];
+          s += nw[a] * (T)t0w[b0] * (T)t1w[b1] * ec[fidx3(gc, k, cf)];
+        }
+    phif[fidx3(gf, k, f)] += s;
+  }
+}
+
+template <typename T>
+void launch_face_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *phif, hipStream_t s) {
+  if (gf.d == 3)
+    hipLaunchKernelGGL((k_face_prolong_add<T, 3>), dim3(blocks_for(gf.ncell)), dim3(kBlock), 0, s,
+                       gc, gf, ec, phif);
+  else
+    hipLaunchKernelGGL((k_face_prolong_add<T, 2>), dim3(blocks_for(gf.ncell)), dim3(kBlock), 0, s,
+                       gc, gf, ec, phif);
+}
+
+// ------------------------------------------------------------------------
+// pressure multigrid: L_rho = D beta G with zero flux through walls
+// ------------------------------------------------------------------------
+
+template <typename T, int DIM>
+__device__ __forceinline__ void p_row(const Geo &g, const int i[3], const T *__restrict__ beta,
+                                      const T *__restrict__ p, T &Lp, T &diag) {
+  const T h = (T)g.h;
+  const T pc = p[cidx3(g, i)];
+  T s = 0, dg = 0;
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    int r[3] = {i[0], i[1], i[2]};
+    // flux through the high face (index i+1) and the low face (index i)
+    T fr = 0, fl = 0;
+    const bool wr = g.ns[k] && (i[k] + 1 == g.n[k]);
+    const bool wl = g.ns[k] && (i[k] == 0);
+    if (!wr) {
+      r[k] = up1(g, k, i[k]);
+      const T b = beta[fidx3(g, k, r)];
+      fr = b * ((p[cidx3(g, r)] - pc) / h);
+      dg -= b;
+    }
+    if (!wl) {
+      r[k] = dn1(g, k, i[k]);
+      const T b = beta[fidx3(g, k, i)];
+      fl = b * ((pc - p[cidx3(g, r)]) / h);
+      dg -= b;
+    }
+    s += (fr - fl) / h;
+  }
+  Lp = s;
+  diag = dg / (h * h);
+}
+
+template <typename T, int DIM>
+__global__ void k_p_gs(Geo g, int colour, const T *__restrict__ beta, const T *__restrict__ rhs,
+                       T *__restrict__ phi) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  int i[3];
+  if (!colour_cell(g, t, colour, i)) return;
+  T Lp, dg;
+  p_row<T, DIM>(g, i, beta, phi, Lp, dg);
+  const i64 c = cidx3(g, i);
+  phi[c] += (rhs[c] - Lp) / dg;
+}
+
+template <typename T>
+void launch_p_gs(const Geo &g, int colour, const T *beta, const T *rhs, T *phi, hipStream_t s) {
+  const unsigned nb = blocks_for(colour_threads(g));
+  if (g.d == 3)
+    hipLaunchKernelGGL((k_p_gs<T, 3>), dim3(nb), dim3(kBlock), 0, s, g, colour, beta, rhs, phi);
+  else
+    hipLaunchKernelGGL((k_p_gs<T, 2>), dim3(nb), dim3(kBlock), 0, s, g, colour, beta, rhs, phi);
+}
+
+template <typename T, int DIM>
+__global__ void k_p_residual(Geo g, const T *__restrict__ beta, const T *__restrict__ rhs,
+                             const T *__restrict__ phi, T *__restrict__ res) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ncell) return;
+  int i[3];
+  cell_of(g, t, i);
+  T Lp, dg;
+  p_row<T, DIM>(g, i, beta, phi, Lp, dg);
+  res[t] = rhs[t] - Lp;
+}
+
+template <typename T>
+void launch_p_residual(const Geo &g, const T *beta, const T *rhs, const T *phi, T *res,
+                       hipStream_t s) {
+  if (g.d == 3)
+    hipLaunchKernelGGL((k_p_residual<T, 3>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, beta,
+                       rhs, phi, res);
+  else
+    hipLaunchKernelGGL((k_p_residual<T, 2>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, beta,
+                       rhs, phi, res);
+}
+
+template <typename T>
+__global__ void k_cell_restrict(Geo gf, Geo gc, const T *__restrict__ rf, T *__restrict__ rc) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gc.ncell) return;
+  int I[3];
+  cell_of(gc, t, I);
+  const int d = gc.d;
+  T s = 0;
+  for (int o2 = 0; o2 < (d == 3 ? 2 : 1); o2++)
+    for (int o1 = 0; o1 < 2; o1++)
+      for (int o0 = 0; o0 < 2; o0++) {
+        int f[3] = {2 * I[0] + o0, 2 * I[1] + o1, d == 3 ? 2 * I[2] + o2 : 0};
+        s += rf[cidx3(gf, f)];
+      }
+  rc[t] = s / (T)(1 << d);
+}
+
+template <typename T>
+void launch_cell_restrict(const Geo &gf, const Geo &gc, const T *rf, T *rc, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_restrict<T>, dim3(blocks_for(gc.ncell)), dim3(kBlock), 0, s, gf, gc,
+                     rf, rc);
+}
+
+template <typename T>
+__global__ void k_cell_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec, T *__restrict__ pf) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gf.ncell) return;
+  int f[3];
+  cell_of(gf, t, f);
+  int I[3] = {f[0] >> 1, f[1] >> 1, gf.d == 3 ? f[2] >> 1 : 0};
+  pf[t] += ec[cidx3(gc, I)];
+}
+
+template <typename T>
+void launch_cell_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *pf, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_prolong_add<T>, dim3(blocks_for(gf.ncell)), dim3(kBlock), 0, s, gc, gf,
+                     ec, pf);
+}
+
+// ------------------------------------------------------------------------
+// preconditioner glue (Sec. 2: P1..P5 compositions)
+// ------------------------------------------------------------------------
+
+template <typename T, int DIM>
+__global__ void k_div(Geo g, const T *__restrict__ u, const T *__restrict__ bp, T sgn,
+                      T *__restrict__ out) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ncell) return;
+  int i[3];
+  cell_of(g, t, i);
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    int r[3] = {i[0], i[1], i[2]};
+    r[k] = up1(g, k, i[k]);
+    s += (u[fidx3(g, k, r)] - u[fidx3(g, k, i)]) / (T)g.h;
+  }
+  if (bp) s += bp[t];
+  out[t] = sgn * s;
+}
+
+template <typename T>
+void launch_div(const Geo &g, const T *u, const T *bp, T sgn, T *out, hipStream_t s) {
+  if (g.d == 3)
+    hipLaunchKernelGGL((k_div<T, 3>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, u, bp, sgn,
+                       out);
+  else
+    hipLaunchKernelGGL((k_div<T, 2>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, u, bp, sgn,
+                       out);
+}
+
+// mode 0: zu = xs + beta * G q ; mode 1: out = bu - G q
+template <typename T, int DIM>
+__global__ void k_grad_combine(Geo g, int mode, const T *__restrict__ base,
+                               const T *__restrict__ beta, const T *__restrict__ q,
+                               T *__restrict__ out) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ncell) return;
+  int i[3];
+  cell_of(g, t, i);
+  const T qc = q[t];
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    if (low_wall(g, k, i)) continue;
+    int l[3] = {i[0], i[1], i[2]};
+    l[k] = dn1(g, k, i[k]);
+    const i64 fq = fidx3(g, k, i);
+    const T gq = (qc - q[cidx3(g, l)]) / (T)g.h;
+    out[fq] = (mode == 0) ? base[fq] + beta[fq] * gq : base[fq] - gq;
+  }
+}
+
+template <typename T>
+void launch_proj_update(const Geo &g, const T *xs, const T *beta, const T *q, T *zu,
+                        hipStream_t s) {
+  if (g.d == 3)
+    hipLaunchKernelGGL((k_grad_combine<T, 3>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, 0,
+                       xs, beta, q, zu);
+  else
+    hipLaunchKernelGGL((k_grad_combine<T, 2>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, 0,
+                       xs, beta, q, zu);
+}
+template <typename T>
+void launch_grad_sub(const Geo &g, const T *bu, const T *p, T *out, hipStream_t s) {
+  if (g.d == 3)
+    hipLaunchKernelGGL((k_grad_combine<T, 3>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, 1,
+                       bu, (const T *)nullptr, p, out);
+  else
+    hipLaunchKernelGGL((k_grad_combine<T, 2>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, 1,
+                       bu, (const T *)nullptr, p, out);
+}
+
+template <typename T>
+__global__ void k_schur_combine(const T *__restrict__ q, const T *__restrict__ c,
+                                const T *__restrict__ mu, T a, T b, T *__restrict__ out, i64 n) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const T v = b * mu[t] * c[t];
+  out[t] = q ? a * q[t] + v : v;
+}
+template <typename T>
+void launch_schur_combine(const T *q, const T *c, const T *mu, T a, T b, T *out, i64 n,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_schur_combine<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, q, c, mu, a, b,
+                     out, n);
+}
+
+// ------------------------------------------------------------------------
+// reductions: fixed grid, fixed tree -> bitwise reproducible
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ double warp_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// block-wide sum; result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  v = warp_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int w = 0; w < nw; w++) r += sh[w];
+  }
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ void k_sum_partial(const T *__restrict__ a, i64 n, double *__restrict__ partials) {
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0;
+  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x)
+    acc += (double)a[t];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// out[j] = sum_b partials[b * stride + j] for j < nout, fixed order
+__global__ void k_finish(const double *__restrict__ partials, int nblocks, int stride, int nout,
+                         double *__restrict__ out) {
+  __shared__ double sh[kBlock / 64];
+  for (int j = 0; j < nout; j++) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += partials[(i64)b * stride + j];
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[j] = r;
+  }
+}
+
+static int red_blocks(i64 n) {
+  i64 b = (n + kBlock - 1) / kBlock;
+  if (b > kRedBlocks) b = kRedBlocks;
+  return (int)(b < 1 ? 1 : b);
+}
+
+template <typename T>
+void launch_sum(const T *a, i64 n, double *partials, double *out, hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_sum_partial<T>, dim3(nb), dim3(kBlock), 0, s, a, n, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, out);
+}
+
+template <typename T>
+__global__ void k_sub_mean(T *__restrict__ a, i64 n, const double *__restrict__ sum) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) a[t] -= (T)(sum[0] / (double)n);
+}
+template <typename T>
+void launch_sub_mean(T *a, i64 n, const double *sum, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_mean<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n, sum);
+}
+
+struct PtrPack {
+  const void *p[34];
+};
+
+// dots[i] = (w, v_i), dots[nv] = (w, w); vectors processed in chunks of 8
+template <int NC>
+__global__ void k_multidot(const double *__restrict__ w, PtrPack v, int base, int nv, i64 n,
+                           int stride, double *__restrict__ partials, int want_ww) {
+  __shared__ double sh[kBlock / 64];
+  double acc[NC + 1];
+#pragma unroll
+  for (int j = 0; j <= NC; j++) acc[j] = 0.0;
+  const int cnt = (nv - base < NC) ? nv - base : NC;
+  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+    const double wv = w[t];
+#pragma unroll
+    for (int j = 0; j < NC; j++)
+      if (j < cnt) acc[j] += wv * ((const double *)v.p[base + j])[t];
+    if (want_ww) acc[NC] += wv * wv;
+  }
+#pragma unroll
+  for (int j = 0; j < NC; j++) {
+    if (j < cnt) {
+      const double r = block_sum(acc[j], sh);
+      if (threadIdx.x == 0) partials[(i64)blockIdx.x * stride + base + j] = r;
+    }
+  }
+  if (want_ww) {
+    const double r = block_sum(acc[NC], sh);
+    if (threadIdx.x == 0) partials[(i64)blockIdx.x * stride + nv] = r;
+  }
+}
+
+void launch_multidot(const double *w, const double *const *v, int nv, i64 n, double *partials,
+                     double *dots, hipStream_t s) {
+  PtrPack pk;
+  for (int j = 0; j < nv; j++) pk.p[j] = v[j];
+  const int nb = red_blocks(n);
+  const int stride = nv + 1;
+  for (int base = 0; base < nv || base == 0; base += 8) {
+    const int last = (base + 8 >= nv);
+    hipLaunchKernelGGL(k_multidot<8>, dim3(nb), dim3(kBlock), 0, s, w, pk, base, nv, n, stride,
+                       partials, last ? 1 : 0);
+    if (last) break;
+  }
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, stride, stride, dots);
+}
+
+// w -= sum h_i v_i ; (w, w) partials
+__global__ void k_multiaxpy_norm(double *__restrict__ w, PtrPack v, const double *__restrict__ h,
+                                 int nv, i64 n, double *__restrict__ partials) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ double hs[34];
+  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  double acc = 0.0;
+  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+    double x = w[t];
+    for (int j = 0; j < nv; j++) x -= hs[j] * ((const double *)v.p[j])[t];
+    w[t] = x;
+    acc += x * x;
+  }
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+void launch_multiaxpy_norm(double *w, const double *const *v, const double *h, int nv, i64 n,
+                           double *partials, double *nrm2, hipStream_t s) {
+  PtrPack pk;
+  for (int j = 0; j < nv; j++) pk.p[j] = v[j];
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_multiaxpy_norm, dim3(nb), dim3(kBlock), 0, s, w, pk, h, nv, n, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, nrm2);
+}
+
+struct CoefPack {
+  double c[34];
+};
+
+template <typename TZ>
+__global__ void k_update_x(double *__restrict__ x, PtrPack z, CoefPack y, int nz, i64 n) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double acc = x[t];
+  for (int j = 0; j < nz; j++) acc += y.c[j] * (double)((const TZ *)z.p[j])[t];
+  x[t] = acc;
+}
+
+template <typename TZ>
+void launch_update_x(double *x, const TZ *const *z, const double *y, int nz, i64 n,
+                     hipStream_t s) {
+  PtrPack pk;
+  CoefPack cy;
+  for (int j = 0; j < nz; j++) {
+    pk.p[j] = z[j];
+    cy.c[j] = y[j];
+  }
+  hipLaunchKernelGGL(k_update_x<TZ>, dim3(blocks_for(n)), dim3(kBlock), 0, s, x, pk, cy, nz, n);
+}
+template void launch_update_x<double>(double *, const double *const *, const double *, int, i64,
+                                      hipStream_t);
+template void launch_update_x<float>(double *, const float *const *, const double *, int, i64,
+                                     hipStream_t);
+
+__global__ void k_norm2_partial(const double *__restrict__ a, i64 n, double *__restrict__ partials) {
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0;
+  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x)
+    acc += a[t] * a[t];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+void launch_norm2(const double *a, i64 n, double *partials, double *nrm2, hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kBlock), 0, s, a, n, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, nrm2);
+}
+
+
+// sum of log(mu) over mu > 0 and the count of such cells (rescaling, Sec. 3.3)
+__global__ void k_logsum_partial(const double *__restrict__ mu, i64 n, double *__restrict__ partials) {
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0, cnt = 0.0;
+  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+    const double v = mu[t];
+    if (v > 0.0) {
+      acc += log(v);
+      cnt += 1.0;
+    }
+  }
+  const double r0 = block_sum(acc, sh);
+  const double r1 = block_sum(cnt, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = r0;
+    partials[2 * blockIdx.x + 1] = r1;
+  }
+}
+void launch_logsum(const double *mu, i64 n, double *partials, double *out2, hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_logsum_partial, dim3(nb), dim3(kBlock), 0, s, mu, n, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 2, 2, out2);
+}
+
+// ------------------------------------------------------------------------
+// gradient contraction (adjoint): strain rates of u and lambda
+// ------------------------------------------------------------------------
+
+// derivative of component k along axis l at an edge point e (node along k, l)
+// with the one-sided no-slip wall rule
+__device__ __forceinline__ double dkl(const Geo &g, const double *__restrict__ u, int k, int l,
+                                      const int e[3]) {
+  int f[3] = {e[0], e[1], e[2]};
+  const double h = g.h;
+  if (g.ns[l] && e[l] == 0) return 2.0 * u[fidx3(g, k, f)] / h;
+  if (g.ns[l] && e[l] == g.n[l]) {
+    f[l] = g.n[l] - 1;
+    return -2.0 * u[fidx3(g, k, f)] / h;
+  }
+  int fb[3] = {e[0], e[1], e[2]};
+  fb[l] = dn1(g, l, e[l]);
+  return (u[fidx3(g, k, f)] - u[fidx3(g, k, fb)]) / h;
+}
+
+__global__ void k_grad_cells(Geo g, const double *__restrict__ u, const double *__restrict__ lam,
+                             double theta, double *__restrict__ dmu, double *__restrict__ drho) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ncell) return;
+  int i[3];
+  cell_of(g, t, i);
+  double s = 0.0, r = 0.0;
+  for (int k = 0; k < g.d; k++) {
+    int hi[3] = {i[0], i[1], i[2]};
+    hi[k] = up1(g, k, i[k]);
+    const i64 ql = fidx3(g, k, i), qh = fidx3(g, k, hi);
+    const double du = (u[qh] - u[ql]) / g.h;
+    const double dl = (lam[qh] - lam[ql]) / g.h;
+    s += dl * du;
+    // density: both faces of the cell along k (wall faces hold 0)
+    r += lam[ql] * u[ql] + lam[qh] * u[qh];
+  }
+  if (dmu) dmu[t] = -2.0 * s;
+  if (drho) drho[t] = -theta * 0.5 * r;
+}
+
+__global__ void k_grad_edges(Geo g, int m, const double *__restrict__ u,
+                             const double *__restrict__ lam, double *__restrict__ dme) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ecnt[m]) return;
+  int e[3];
+  {
+    i64 q = t / g.ed[m][0];
+    e[0] = (int)(t - q * g.ed[m][0]);
+    e[2] = (int)(q / g.ed[m][1]);
+    e[1] = (int)(q - (i64)e[2] * g.ed[m][1]);
+  }
+  const int k = (m == 0) ? 1 : 0;
+  const int l = (m == 2) ? 1 : 2;
+  const bool wall = (g.ns[k] && (e[k] == 0 || e[k] == g.n[k])) ||
+                    (g.ns[l] && (e[l] == 0 || e[l] == g.n[l]));
+  const double gu = dkl(g, u, k, l, e) + dkl(g, u, l, k, e);
+  const double gl = dkl(g, lam, k, l, e) + dkl(g, lam, l, k, e);
+  dme[g.eoff[m] + t] = -(wall ? 0.5 : 1.0) * gl * gu;
+}
+
+// dmu_cell += sum over the cell's edges of dmu_edge * d mu_edge / d mu_cell
+__global__ void k_grad_chain(Geo g, const double *__restrict__ dme, const double *__restrict__ mue,
+                             const double *__restrict__ muc, int mode, double *__restrict__ dmu) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ncell) return;
+  int i[3];
+  cell_of(g, t, i);
+  double acc = 0.0;
+  for (int m = 0; m < 3; m++) {
+    if (g.ecnt[m] == 0) continue;
+    const int k = (m == 0) ? 1 : 0;
+    const int l = (m == 2) ? 1 : 2;
+    for (int a = 0; a < 2; a++)
+      for (int b = 0; b < 2; b++) {
+        int e[3] = {i[0], i[1], i[2]};
+        e[k] += a;
+        e[l] += b;
+        if (!g.ns[k] && e[k] == g.n[k]) e[k] = 0;
+        if (!g.ns[l] && e[l] == g.n[l]) e[l] = 0;
+        // number of cells adjacent to this edge
+        int ck = (g.ns[k] && (e[k] == 0 || e[k] == g.n[k])) ? 1 : 2;
+        int cl = (g.ns[l] && (e[l] == 0 || e[l] == g.n[l])) ? 1 : 2;
+        const int cnt = ck * cl;
+        const i64 q = eidx3(g, m, e);
+        double w;
+        if (mode == 1) {
+          const double me = mue[q], mc = muc[t];
+          w = me * me / ((double)cnt * mc * mc);
+        } else {
+          w = 1.0 / (double)cnt;
+        }
+        acc += dme[q] * w;
+      }
+  }
+  dmu[t] += acc;
+}
+
+void launch_grad_cells(const Geo &g, const double *u, const double *lam, double theta,
+                       double *dmu_cell, double *drho, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_cells, dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, u, lam, theta,
+                     dmu_cell, drho);
+}
+void launch_grad_edges(const Geo &g, const double *u, const double *lam, double *dmu_edge,
+                       hipStream_t s) {
+  for (int m = 0; m < 3; m++) {
+    if (g.ecnt[m] == 0) continue;
+    hipLaunchKernelGGL(k_grad_edges, dim3(blocks_for(g.ecnt[m])), dim3(kBlock), 0, s, g, m, u, lam,
+                       dmu_edge);
+  }
+}
+void launch_grad_chain(const Geo &g, const double *dmu_edge, const double *mue_raw,
+                       const double *muc_raw, int mode, double *dmu_cell, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_chain, dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, dmu_edge,
+                     mue_raw, muc_raw, mode, dmu_cell);
+}
+
+// ------------------------------------------------------------------------
+// explicit instantiations
+// ------------------------------------------------------------------------
+#define INST(T)                                                                                  \
+  template void launch_vel_gs<T>(const Geo &, int, int, const T *, const T *, const T *,         \
+                                 const T *, T *, hipStream_t);                                   \
+  template void launch_vel_residual<T>(const Geo &, const T *, const T *, const T *, const T *,  \
+                                       const T *, const T *, T *, hipStream_t);                  \
+  template void launch_face_restrict<T>(const Geo &, const Geo &, const T *, T *, hipStream_t);  \
+  template void launch_face_prolong_add<T>(const Geo &, const Geo &, const T *, T *,             \
+                                           hipStream_t);                                         \
+  template void launch_p_gs<T>(const Geo &, int, const T *, const T *, T *, hipStream_t);        \
+  template void launch_p_residual<T>(const Geo &, const T *, const T *, const T *, T *,          \
+                                     hipStream_t);                                               \
+  template void launch_cell_restrict<T>(const Geo &, const Geo &, const T *, T *, hipStream_t);  \
+  template void launch_cell_prolong_add<T>(const Geo &, const Geo &, const T *, T *,             \
+                                           hipStream_t);                                         \
+  template void launch_div<T>(const Geo &, const T *, const T *, T, T *, hipStream_t);           \
+  template void launch_proj_update<T>(const Geo &, const T *, const T *, const T *, T *,         \
+                                      hipStream_t);                                              \
+  template void launch_grad_sub<T>(const Geo &, const T *, const T *, T *, hipStream_t);         \
+  template void launch_schur_combine<T>(const T *, const T *, const T *, T, T, T *, i64,         \
+                                        hipStream_t);                                            \
+  template void launch_sum<T>(const T *, i64, double *, double *, hipStream_t);                  \
+  template void launch_sub_mean<T>(T *, i64, const double *, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace stk

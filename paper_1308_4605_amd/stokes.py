@@ -1,0 +1,262 @@
+"""Thin ctypes binding of libstokes_mi355x.so (include/stokes.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  PyTorch supplies device memory (the workspace and the caller's
+arrays) and the HIP stream.  There is no CPU fallback: if the library is
+missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstokes_mi355x.so")
+
+STOKES_OK = 0
+STOKES_EINVAL = -1
+STOKES_ENOMEM = -2
+STOKES_EDEVICE = -3
+STOKES_ENOCONV = -4
+STOKES_EBREAKDOWN = -5
+STOKES_ENONFINITE = -6
+STOKES_EINCOMPAT = -7
+
+# names declared in include/stokes.h
+ABI_FUNCTIONS = (
+    "stokes_sizes", "stokes_workspace_bytes", "stokes_create", "stokes_apply", "stokes_precond",
+    "stokes_vel_subsolve", "stokes_p_subsolve", "stokes_solve", "stokes_adjoint_solve",
+    "stokes_grad", "stokes_rescale", "stokes_set_timing", "stokes_kernel_time", "stokes_destroy",
+    "stokes_strerror",
+)
+
+
+class StokesParams(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
+                ("bc", ctypes.c_int * 3), ("theta", ctypes.c_double), ("precond", ctypes.c_int),
+                ("precision", ctypes.c_int), ("krylov", ctypes.c_int), ("restart", ctypes.c_int),
+                ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("nu_coarse", ctypes.c_int),
+                ("vcycles", ctypes.c_int), ("rescale_c", ctypes.c_double),
+                ("edge_avg", ctypes.c_int)]
+
+
+class StokesStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("precond_applies", ctypes.c_int), ("scalar_vcycles", ctypes.c_int),
+                ("rel_res_true", ctypes.c_double), ("rel_res_est", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class StokesError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with paper_1308_4605_amd.build.build() "
+                "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.c_void_p
+        PP = ctypes.POINTER(StokesParams)
+        L.stokes_sizes.argtypes = [PP, ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int)]
+        L.stokes_workspace_bytes.argtypes = [PP]
+        L.stokes_workspace_bytes.restype = ctypes.c_size_t
+        L.stokes_create.argtypes = [PP, dp, dp, dp, dp, ctypes.c_size_t, vp,
+                                    ctypes.POINTER(ctypes.c_void_p)]
+        L.stokes_apply.argtypes = [vp, dp, dp, dp, dp]
+        L.stokes_precond.argtypes = [vp, dp, dp, dp, dp]
+        L.stokes_vel_subsolve.argtypes = [vp, dp, dp]
+        L.stokes_p_subsolve.argtypes = [vp, dp, dp]
+        L.stokes_solve.argtypes = [vp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(StokesStats)]
+        L.stokes_adjoint_solve.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                           ctypes.c_double, ctypes.c_int,
+                                           ctypes.POINTER(StokesStats)]
+        L.stokes_grad.argtypes = [vp, dp, dp, dp, dp, dp]
+        L.stokes_rescale.argtypes = [vp]
+        L.stokes_rescale.restype = ctypes.c_double
+        L.stokes_set_timing.argtypes = [vp, ctypes.c_int]
+        L.stokes_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_long),
+                                         ctypes.POINTER(ctypes.c_double)]
+        L.stokes_destroy.argtypes = [vp]
+        L.stokes_strerror.argtypes = [ctypes.c_int]
+        L.stokes_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().stokes_strerror(int(code)).decode()
+
+
+def make_params(dim, n, bc, h, theta, precond=1, precision=0, krylov=0, restart=10, nu_pre=2,
+                nu_post=2, nu_coarse=8, vcycles=1, rescale_c=0.0, edge_avg=0, **_ignored):
+    p = StokesParams()
+    p.dim = int(dim)
+    n = tuple(n) + (1,) * (3 - len(n))
+    bc = tuple(bc) + (0,) * (3 - len(bc))
+    for a in range(3):
+        p.n[a] = int(n[a])
+        p.bc[a] = int(bc[a])
+    p.h, p.theta = float(h), float(theta)
+    p.precond, p.precision, p.krylov, p.restart = int(precond), int(precision), int(krylov), int(restart)
+    p.nu_pre, p.nu_post, p.nu_coarse, p.vcycles = int(nu_pre), int(nu_post), int(nu_coarse), int(vcycles)
+    p.rescale_c, p.edge_avg = float(rescale_c), int(edge_avg)
+    return p
+
+
+def stokes_sizes(params: StokesParams):
+    nv, nc, ne = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    nl = ctypes.c_int()
+    rc = lib().stokes_sizes(ctypes.byref(params), ctypes.byref(nv), ctypes.byref(nc),
+                            ctypes.byref(ne), ctypes.byref(nl))
+    if rc:
+        raise StokesError(rc, "stokes_sizes")
+    return nv.value, nc.value, ne.value, nl.value
+
+
+def stokes_workspace_bytes(params: StokesParams) -> int:
+    return int(lib().stokes_workspace_bytes(ctypes.byref(params)))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), (t.device, t.dtype)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Stokes:
+    """One solver context: coefficients, multigrid hierarchy and Krylov
+    workspace on the current HIP device, all in one caller-owned workspace
+    tensor.  Methods take and return torch float64 CUDA tensors in the ABI
+    layout (flat arrays)."""
+
+    def __init__(self, params: dict, rho, mu, mu_edges=None, stream=None):
+        import torch
+
+        self.params = dict(params)
+        self.p = make_params(**params)
+        self.nvel, self.ncell, self.nedge, self.nlevels = stokes_sizes(self.p)
+        self.ws_bytes = stokes_workspace_bytes(self.p)
+        dev = rho.device
+        self.device = dev
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        rc = lib().stokes_create(ctypes.byref(self.p), _ptr(rho), _ptr(mu), _ptr(mu_edges),
+                                 ctypes.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc:
+            raise StokesError(rc, "stokes_create")
+        self._h = h
+        self.c = lib().stokes_rescale(h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().stokes_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self, n):
+        import torch
+
+        return torch.empty(n, dtype=torch.float64, device=self.device)
+
+    def apply(self, xu, xp):
+        yu, yp = self._new(self.nvel), self._new(self.ncell)
+        rc = lib().stokes_apply(self._h, _ptr(xu), _ptr(xp), _ptr(yu), _ptr(yp))
+        if rc:
+            raise StokesError(rc, "stokes_apply")
+        return yu, yp
+
+    def precond(self, bu, bp):
+        zu, zp = self._new(self.nvel), self._new(self.ncell)
+        rc = lib().stokes_precond(self._h, _ptr(bu), _ptr(bp), _ptr(zu), _ptr(zp))
+        if rc:
+            raise StokesError(rc, "stokes_precond")
+        return zu, zp
+
+    def vel_subsolve(self, r):
+        e = self._new(self.nvel)
+        rc = lib().stokes_vel_subsolve(self._h, _ptr(r), _ptr(e))
+        if rc:
+            raise StokesError(rc, "stokes_vel_subsolve")
+        return e
+
+    def p_subsolve(self, r):
+        e = self._new(self.ncell)
+        rc = lib().stokes_p_subsolve(self._h, _ptr(r), _ptr(e))
+        if rc:
+            raise StokesError(rc, "stokes_p_subsolve")
+        return e
+
+    def solve(self, bu, bp, tol=1e-8, max_iter=1000, x0=None, check=True, out=None):
+        if out is not None:
+            xu, xp = out
+        else:
+            xu, xp = self._new(self.nvel), self._new(self.ncell)
+        if x0 is not None:
+            xu.copy_(x0[0])
+            xp.copy_(x0[1])
+        st = StokesStats()
+        rc = lib().stokes_solve(self._h, _ptr(bu), _ptr(bp), _ptr(xu), _ptr(xp), float(tol),
+                                int(max_iter), 1 if x0 is not None else 0, ctypes.byref(st))
+        if check and rc:
+            raise StokesError(rc, "stokes_solve")
+        return xu, xp, st.as_dict(), rc
+
+    def adjoint(self, xu, xp, gu, gp, tol=1e-8, max_iter=1000, check=True):
+        lu, lp = self._new(self.nvel), self._new(self.ncell)
+        dmc, dme, drho = self._new(self.ncell), self._new(self.nedge), self._new(self.ncell)
+        st = StokesStats()
+        rc = lib().stokes_adjoint_solve(self._h, _ptr(xu), _ptr(xp), _ptr(gu), _ptr(gp), _ptr(lu),
+                                        _ptr(lp), _ptr(dmc), _ptr(dme), _ptr(drho), float(tol),
+                                        int(max_iter), ctypes.byref(st))
+        if check and rc:
+            raise StokesError(rc, "stokes_adjoint_solve")
+        return dict(lu=lu, lp=lp, dmu_cell=dmc, dmu_edge=dme, drho_cell=drho,
+                    stats=st.as_dict(), rc=rc)
+
+    def grad(self, xu, lu):
+        dmc, dme, drho = self._new(self.ncell), self._new(self.nedge), self._new(self.ncell)
+        rc = lib().stokes_grad(self._h, _ptr(xu), _ptr(lu), _ptr(dmc), _ptr(dme), _ptr(drho))
+        if rc:
+            raise StokesError(rc, "stokes_grad")
+        return dict(dmu_cell=dmc, dmu_edge=dme, drho_cell=drho)
+
+    def set_timing(self, enable: bool):
+        rc = lib().stokes_set_timing(self._h, 1 if enable else 0)
+        if rc:
+            raise StokesError(rc, "stokes_set_timing")
+
+    def kernel_time(self):
+        ms, n, b = ctypes.c_double(), ctypes.c_long(), ctypes.c_double()
+        rc = lib().stokes_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b))
+        if rc:
+            raise StokesError(rc, "stokes_kernel_time")
+        return ms.value, n.value, b.value

@@ -288,7 +288,7 @@ def periodic_smooth_2d(seed=1000, n=32, dt=1e-2):
                     EDGE_ARITH, rho, mu, bu, np.zeros(lay.ncell))
 
 
-def discs_2d(seed=2000, n=1024, ndisc=64):
+def discs_2d(seed=2000, n=1024, ndisc=64, mu_in=1e3):
     """2D no-slip unit square, steady (theta = 0), rho = 1, mu = 1e3 inside 64
     random discs (radius U[0.02, 0.05], centres U[0,1]^2) and 1 outside,
     harmonic edge averaging, i.i.d. N(0,1) forcing on interior faces."""
@@ -304,7 +304,7 @@ def discs_2d(seed=2000, n=1024, ndisc=64):
     inside = np.zeros(lay.cell_shape, dtype=bool)
     for a, b, r in zip(cx, cy, rad):
         inside |= (X - a) ** 2 + (Y - b) ** 2 <= r * r
-    mu = np.where(inside, 1e3, 1.0).ravel()
+    mu = np.where(inside, mu_in, 1.0).ravel()
     rho = np.ones(lay.ncell)
     rf = np.random.default_rng(seed + 2)
     bu = rf.standard_normal(lay.nvel)

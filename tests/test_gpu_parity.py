@@ -1,0 +1,202 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+identical seeded inputs.  Sizes span several workgroups with ragged tails
+(non-power-of-two axes), both boundary conditions, 2D and 3D, and the
+degenerate 2-cell grid.
+
+Bars (norm-wise over the stored arrays, whose wall entries are 0 on both
+sides):
+  - FP64 operator applies and gradient contractions: 1e-12 relative;
+  - FP64 V-cycles and preconditioners (composites of ~10^2 stencil passes whose
+    FP64 rounding differs only in operation order and fused multiply-adds):
+    1e-11 relative;
+  - FP32 preconditioner against the FP64 oracle: 1e-4 relative (FP32 unit
+    roundoff 6e-8 amplified by the V-cycle's condition);
+  - solves: iteration counts within +-1 of the oracle, true residual of the
+    rescaled system <= tol checked with the oracle's own M;
+  - adjoint gradients: 1e-6 relative of the oracle's FP64 adjoint.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import N, T, pair, params, rel, scaled_residual
+from paper_1308_4605_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+OPS = [
+    (2, (32, 32), (0, 0)), (2, (48, 32), (1, 1)), (2, (192, 64), (0, 1)), (2, (2, 2), (1, 1)),
+    (3, (16, 16, 16), (1, 1, 1)), (3, (16, 16, 16), (0, 0, 0)), (3, (48, 40, 8), (1, 0, 1)),
+    (3, (32, 48, 16), (0, 1, 0)), (3, (24, 16, 16), (1, 1, 1)), (3, (2, 2, 2), (0, 0, 0)),
+]
+
+
+def _coefs(lay, seed=1):
+    return W.random_coefficients(seed, lay, mu_range=(0.2, 5.0), rho_range=(0.5, 2.0))
+
+
+@pytest.mark.parametrize("dim,n,bc", OPS)
+@pytest.mark.parametrize("edge_avg", [W.EDGE_ARITH, W.EDGE_HARMONIC, W.EDGE_GIVEN])
+def test_apply_parity(dim, n, bc, edge_avg):
+    print(f"apply {dim} {n} {bc} edge={edge_avg}", flush=True)
+    p, lay = params(dim, n, bc, 30.0, edge_avg=edge_avg)
+    rho, mu = _coefs(lay)
+    edges = np.random.default_rng(3).uniform(0.3, 3.0, lay.nedge) if edge_avg == W.EDGE_GIVEN else None
+    g, o = pair(p, rho, mu, edges)
+    xu = W.random_velocity(5, lay)
+    xp = W.random_cells(6, lay)
+    # wall entries of the input are ignored (read as 0)
+    xu_dirty = xu.copy()
+    xu_dirty[lay.wall_mask()] = 7.0
+    yu, yp = g.apply(T(xu_dirty), T(xp))
+    ou, op = o.apply(xu, xp)
+    assert rel(N(yu), ou) <= 1e-12
+    assert rel(N(yp), op) <= 1e-12
+    assert np.all(N(yu)[lay.wall_mask()] == 0.0)
+
+
+@pytest.mark.parametrize("dim,n,bc", OPS)
+@pytest.mark.parametrize("theta", [0.0, 40.0])
+def test_subsolver_parity(dim, n, bc, theta):
+    print(f"subsolve {dim} {n} {bc} theta={theta}", flush=True)
+    p, lay = params(dim, n, bc, theta)
+    rho, mu = _coefs(lay, 2)
+    g, o = pair(p, rho, mu)
+    singular = theta == 0.0 and all(b == 0 for b in lay.bc[:dim])
+    r = W.random_velocity(7, lay, remove_mean=singular)
+    e = N(g.vel_subsolve(T(r)))
+    assert rel(e, o.vel_subsolve(r)) <= 1e-11
+    q = W.random_cells(8, lay, remove_mean=True)
+    assert rel(N(g.p_subsolve(T(q))), o.p_subsolve(q)) <= 1e-11
+
+
+@pytest.mark.parametrize("dim,n,bc,theta", [(2, (48, 32), (1, 1), 25.0), (3, (16, 16, 16), (0, 0, 0), 0.0),
+                                            (3, (48, 40, 8), (1, 0, 1), 100.0), (2, (32, 32), (0, 0), 0.0)])
+@pytest.mark.parametrize("precond", [W.P1, W.P2, W.P3, W.P4, W.P5])
+def test_precond_parity(dim, n, bc, theta, precond):
+    print(f"precond P{precond} {dim} {n} {bc} theta={theta}", flush=True)
+    p, lay = params(dim, n, bc, theta, precond=precond)
+    rho, mu = _coefs(lay, 3)
+    g, o = pair(p, rho, mu)
+    singular = theta == 0.0 and all(b == 0 for b in lay.bc[:dim])
+    bu = W.random_velocity(9, lay, remove_mean=singular)
+    bp = W.random_cells(10, lay, remove_mean=True)
+    zu, zp = g.precond(T(bu), T(bp))
+    ou, op = o.precond(bu, bp)
+    assert rel(N(zu), ou) <= 1e-11
+    assert rel(N(zp), op) <= 1e-11
+
+
+SOLVES = [
+    # (name, workload builder at reduced size, overrides)
+    ("periodic-smooth-32", lambda: W.periodic_smooth_2d(n=32), {}),
+    ("discs-128-c100", lambda: W.discs_2d(n=128, mu_in=1e2), {}),
+    ("layers-32", lambda: W.layers_3d(n=32, precision=W.FP64), dict(krylov=W.GMRES_LEFT)),
+    ("contrast-32", lambda: W.contrast_periodic_3d(n=32, contrast=1e3, precision=W.FP64), {}),
+    ("adjoint-cfg-32", lambda: W.adjoint_3d(n=32), {}),
+]
+
+
+@pytest.mark.parametrize("name,mk,over", SOLVES, ids=[s[0] for s in SOLVES])
+@pytest.mark.parametrize("krylov", [W.GMRES_LEFT, W.FGMRES])
+def test_solve_parity_fp64(name, mk, over, krylov):
+    print(f"solve {name} krylov={krylov}", flush=True)
+    w = mk()
+    p = w.params(**over)
+    p.update(krylov=krylov, precision=W.FP64)
+    g, o = pair(p, w.rho, w.mu)
+    xu, xp, st, rc = g.solve(T(w.bu), T(w.bp), tol=1e-8, max_iter=500)
+    ou, op, ost, orc = o.solve(w.bu, w.bp, tol=1e-8, max_iter=500)
+    print(f"  gpu iters {st['iters']} oracle iters {ost['iters']}", flush=True)
+    assert abs(st["iters"] - ost["iters"]) <= 1
+    assert scaled_residual(o, o.c, w.bu, w.bp, N(xu), N(xp)) <= 1e-8 * (1 + 1e-6)
+    assert rel(N(xu), ou) <= 1e-5
+    assert rel(N(xp), op) <= 1e-5
+
+
+@pytest.mark.parametrize("name,mk,over", SOLVES[:4], ids=[s[0] for s in SOLVES[:4]])
+def test_mixed_precision_solve(name, mk, over):
+    """FP32 multigrid inside FP64 FGMRES reaches the FP64 tolerance; error
+    against the FP64 oracle and the iteration penalty are printed."""
+    print(f"mixed {name}", flush=True)
+    w = mk()
+    p = w.params(**over)
+    p.update(krylov=W.FGMRES, precision=W.MG_FP32)
+    g, o = pair(p, w.rho, w.mu)
+    # preconditioner itself: FP32 against the FP64 oracle
+    bu = W.random_velocity(11, w.layout, remove_mean=(w.theta == 0 and all(b == 0 for b in w.bc[:w.dim])))
+    bp = W.random_cells(12, w.layout, remove_mean=True)
+    zu, zp = g.precond(T(bu), T(bp))
+    ou, op = o.precond(bu, bp)
+    assert rel(N(zu), ou) <= 1e-4 and rel(N(zp), op) <= 1e-4
+    xu, xp, st, rc = g.solve(T(w.bu), T(w.bp), tol=1e-8, max_iter=500)
+    po = dict(p, precision=W.FP64)
+    o64 = oracle.Oracle(rho=w.rho, mu=w.mu, **po)
+    ou, op, ost, orc = o64.solve(w.bu, w.bp, tol=1e-8, max_iter=500)
+    err_u, err_p = rel(N(xu), ou), rel(N(xp), op)
+    print(f"  fp32-mg iters {st['iters']} fp64 oracle iters {ost['iters']} err_u {err_u:.2e} "
+          f"err_p {err_p:.2e}", flush=True)
+    assert scaled_residual(o64, o64.c, w.bu, w.bp, N(xu), N(xp)) <= 1e-8 * (1 + 1e-6)
+    assert st["iters"] <= ost["iters"] + 3
+    assert err_u <= 1e-5 and err_p <= 1e-5
+
+
+@pytest.mark.parametrize("dim,n,bc,theta", [(2, (32, 32), (1, 1), 100.0), (3, (16, 16, 16), (1, 1, 1), 100.0),
+                                            (2, (32, 32), (0, 0), 0.0), (3, (16, 16, 16), (0, 1, 0), 10.0)])
+@pytest.mark.parametrize("edge_avg", [W.EDGE_ARITH, W.EDGE_HARMONIC])
+def test_grad_contraction_parity(dim, n, bc, theta, edge_avg):
+    print(f"grad {dim} {n} {bc}", flush=True)
+    p, lay = params(dim, n, bc, theta, edge_avg=edge_avg)
+    rho, mu = _coefs(lay, 4)
+    g, o = pair(p, rho, mu)
+    u = W.random_velocity(13, lay)
+    lam = W.random_velocity(14, lay)
+    gg = g.grad(T(u), T(lam))
+    og = o.grad(u, lam)
+    for k in ("dmu_cell", "dmu_edge", "drho_cell"):
+        assert rel(N(gg[k]), og[k]) <= 1e-12, k
+
+
+@pytest.mark.parametrize("precision,krylov", [(W.FP64, W.GMRES_LEFT), (W.MG_FP32, W.FGMRES)])
+def test_adjoint_parity(precision, krylov):
+    """Adjoint solve + strain contraction: within 1e-6 of the oracle's FP64
+    adjoint (both solved to 1e-12)."""
+    w = W.adjoint_3d(n=16)
+    p = w.params(precision=precision, krylov=krylov)
+    g, o = pair(p, w.rho, w.mu)
+    xu, xp, st, rc = g.solve(T(w.bu), T(w.bp), tol=1e-12, max_iter=1000)
+    ou, op, ost, orc = oracle.Oracle(rho=w.rho, mu=w.mu, **dict(p, precision=W.FP64)).solve(
+        w.bu, w.bp, tol=1e-12, max_iter=1000)
+    target = 0.5 * ou
+    gu = ou - target
+    gp = np.zeros(w.layout.ncell)
+    ga = g.adjoint(xu, xp, T(N(xu) - target), T(gp), tol=1e-12, max_iter=1000)
+    oa = oracle.Oracle(rho=w.rho, mu=w.mu, **dict(p, precision=W.FP64, krylov=W.GMRES_LEFT)).adjoint(
+        ou, op, gu, gp, tol=1e-12, max_iter=1000)
+    for k in ("lu", "dmu_cell", "dmu_edge", "drho_cell"):
+        r = rel(N(ga[k]), oa[k])
+        print(f"  {k} rel {r:.2e}", flush=True)
+        assert r <= 1e-6, k
+
+
+def test_error_paths():
+    from paper_1308_4605_amd.stokes import Stokes, StokesError, STOKES_EINCOMPAT, STOKES_ENOCONV, STOKES_EINVAL
+
+    p, lay = params(2, (32, 32), (1, 1), 0.0)
+    rho, mu = _coefs(lay, 5)
+    g, o = pair(p, rho, mu)
+    bp = np.ones(lay.ncell)
+    with pytest.raises(StokesError) as e:
+        g.solve(T(np.zeros(lay.nvel)), T(bp))
+    assert e.value.code == STOKES_EINCOMPAT
+    xu, xp, st, rc = g.solve(T(W.random_velocity(1, lay)), T(np.zeros(lay.ncell)), tol=1e-14,
+                             max_iter=3, check=False)
+    assert rc == STOKES_ENOCONV and st["iters"] == 3
+    bad = rho.copy()
+    bad[5] = -1.0
+    with pytest.raises(StokesError) as e:
+        Stokes(p, T(bad), T(mu))
+    assert e.value.code == STOKES_EINVAL
+    # zero right-hand side: zero solution, no iterations
+    xu, xp, st, rc = g.solve(T(np.zeros(lay.nvel)), T(np.zeros(lay.ncell)))
+    assert rc == 0 and st["iters"] == 0 and np.all(N(xu) == 0)
