@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark: Stokes solves/s to a 1e-8 true relative residual on one MI355X.
+
+One step = one full solve (block-preconditioned flexible GMRES(10) with one
+FP32 multigrid V-cycle per subsolver, FP64 Krylov/M/residuals) of the 3D
+periodic steady workload with a 1e6 viscosity contrast on 256^3 cells, inputs
+resident in HBM.  The plain FP64 solver (same preconditioner, FP64 multigrid)
+is timed beside it, and the FP32-MG solution is compared with the FP64 one.
+
+The JSON line also carries
+  - roofline: the finest-level velocity Gauss-Seidel colour pass (the
+    dominant kernel), algorithmic bytes per launch / average launch time,
+    timed with HIP events on the solver's stream during the timed solves;
+  - cpu_baseline: the FP64 CPU oracle on a bounded sample of the same
+    workload (one Arnoldi step), scaled to solves/s with the iteration count
+    of the FP64 solve.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="cells per axis (default: the 256^3 workload)")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solver")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU path is a design note, not an implementation.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1308_4605_amd import workloads as W
+    from paper_1308_4605_amd.stokes import Stokes
+
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device visible", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+
+    t0 = time.time()
+    w = W.contrast_periodic_3d(n=args.n, precision=W.MG_FP32)
+    _log(f"workload {w.name} n={args.n} generated in {time.time() - t0:.1f}s")
+    lay = w.layout
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    rho, mu, bu, bp = T(w.rho), T(w.mu), T(w.bu), T(w.bp)
+
+    def timed_solves(params, steps, warmup, timing):
+        S = Stokes(params, rho, mu)
+        xu = torch.empty(S.nvel, dtype=torch.float64, device=dev)
+        xp = torch.empty(S.ncell, dtype=torch.float64, device=dev)
+        st = None
+        for i in range(warmup):
+            _, _, st, rc = S.solve(bu, bp, tol=args.tol, max_iter=3000, out=(xu, xp))
+            _log(f"warmup {i}: iters {st['iters']} rel_res {st['rel_res_true']:.2e}")
+        if timing:
+            S.set_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its = []
+        for i in range(steps):
+            _, _, st, rc = S.solve(bu, bp, tol=args.tol, max_iter=3000, out=(xu, xp))
+            its.append(st["iters"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        kt = S.kernel_time() if timing else None
+        if timing:
+            S.set_timing(False)
+        S.close()
+        return el, st, its, kt, xu, xp
+
+    p32 = w.params(precision=W.MG_FP32, krylov=W.FGMRES)
+    el, st, its, kt, xu32, xp32 = timed_solves(p32, args.steps, args.warmup, True)
+    ms_per_step = 1e3 * el / args.steps
+    value = args.steps / el
+    _log(f"FP32-MG FGMRES: {ms_per_step:.1f} ms/solve, iters {its}, rel_res {st['rel_res_true']:.2e}")
+
+    ms_k, launches, bytes_k = kt
+    avg_ms = ms_k / max(launches, 1)
+    achieved = (bytes_k / max(launches, 1)) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+
+    fp64 = None
+    if not args.no_fp64:
+        p64 = w.params(precision=W.FP64, krylov=W.FGMRES)
+        el64, st64, its64, _, xu64, xp64 = timed_solves(p64, max(1, args.steps - 1), 1, False)
+        n64 = max(1, args.steps - 1)
+        err_u = float(torch.linalg.norm(xu32 - xu64) / torch.linalg.norm(xu64))
+        err_p = float(torch.linalg.norm(xp32 - xp64) / torch.linalg.norm(xp64))
+        fp64 = {"solves_per_s": n64 / el64, "ms_per_solve": 1e3 * el64 / n64, "iters": its64[-1],
+                "rel_res_true": st64["rel_res_true"],
+                "fp32mg_vs_fp64_rel_err_u": err_u, "fp32mg_vs_fp64_rel_err_p": err_p}
+        _log(f"FP64 FGMRES: {fp64['ms_per_solve']:.1f} ms/solve, iters {its64}, "
+             f"err u {err_u:.2e} p {err_p:.2e}")
+        del xu64, xp64
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        o = oracle.Oracle.from_workload(w, precision=W.FP64, krylov=W.FGMRES)
+        k_it = 1
+        t = time.perf_counter()
+        o.solve(w.bu, w.bp, tol=args.tol, max_iter=k_it, check=False)
+        t_cpu = time.perf_counter() - t
+        iters_ref = fp64["iters"] if fp64 else st["iters"]
+        cpu = {"value": 1.0 / (t_cpu / k_it * iters_ref), "unit": "solves/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"FP64 oracle FGMRES(10)+P2 on the same {args.n}^3 workload, {k_it} Arnoldi "
+                         f"step(s) plus the two true-residual evaluations ({t_cpu:.1f} s), scaled by "
+                         f"the {iters_ref} iterations of the FP64 solve"}
+        _log(f"CPU oracle: {t_cpu:.1f}s for {k_it} iteration(s) on {cpu['cores']} threads")
+        del o
+
+    sv = st["scalar_vcycles"]
+    line = {
+        "metric": "Stokes solves/s to 1e-8 rel resid (FP32-MG in FP64 FGMRES)",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 multigrid / f64 krylov",
+        "data": "synthetic",
+        "config": {"workload": f"3d-periodic-contrast-{args.n}", "grid": f"{args.n}^3",
+                   "bc": "periodic", "theta": 0.0, "viscosity_contrast": 1e6, "precond": "P2",
+                   "krylov": "FGMRES(10)", "vcycles_per_subsolve": 1, "tol": args.tol},
+        "iters": st["iters"],
+        "scalar_vcycles_per_solve": sv,
+        "scalar_vcycles_per_s": sv * value,
+        "rel_res_true": st["rel_res_true"],
+        "fp64": fp64,
+        "speedup_fp32mg_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
+        "roofline": {"kernel": "velocity Gauss-Seidel colour pass, finest level (k_vel_gs)",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": 1e3 * avg_ms, "launches": launches,
+                     "bytes_per_launch": bytes_k / max(launches, 1)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -182,7 +182,10 @@ int stokes_solve(stokes_ctx *ctx, const double *bu, const double *bp, double *xu
      dL/dmu_edge  = -w_e gamma_e(lambda) gamma_e(u),  w_e = 1/2 on no-slip
                     wall edges, 1 elsewhere (partial derivative),
      dL/drho_cell = -theta sum over the cell's faces of 1/2 lambda_f u_f.
-   Gradient outputs may be NULL.  Synchronous. */
+   g is first projected onto the mean-free space of the solution (the adjoint
+   of the zero-mean normalisation of p, and of u when the velocity operator is
+   singular), so any g is accepted.  Gradient outputs may be NULL.
+   Synchronous. */
 int stokes_adjoint_solve(stokes_ctx *ctx, const double *xu, const double *xp, const double *gu,
                          const double *gp, double *lu, double *lp, double *dmu_cell,
                          double *dmu_edge, double *drho_cell, double tol, int max_iter,

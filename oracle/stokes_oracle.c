@@ -1462,14 +1462,16 @@ int orc_adjoint(orc_ctx *X, const double *xu, const double *xp, const double *gu
                 double *dmu_edge, double *drho, double tol, int max_iter, orc_stats *st) {
   (void)xp;
   if (!X || !xu || !gu || !gp || !lu || !lp || !(tol > 0.0)) return ORC_EINVAL;
-  if (!rhs_compatible(X, gu, gp)) return ORC_EINCOMPAT;
   const size_t nv = X->raw.nvel, nc = X->raw.ncell, n = nv + nc;
   double *b = (double *)malloc(n * sizeof(double));
   double *x = (double *)calloc(n, sizeof(double));
-  /* M = C_c^{-1}... : with M' = diag(c,1) M diag(1,1/c) symmetric,
-     lambda = diag(c,1) M'^{-1} (g_u, g_p / c) */
+  /* with M' = diag(c,1) M diag(1,1/c) symmetric,
+     lambda = diag(c,1) M'^{-1} (g_u, g_p / c); g is first projected onto the
+     mean-free space of the solution (adjoint of the zero-mean normalisation) */
   memcpy(b, gu, nv * sizeof(double));
   for (size_t i = 0; i < nc; i++) b[nv + i] = gp[i] / X->c;
+  remove_mean(b + nv, nc);
+  if (X->vel_singular) remove_vel_means(&X->raw, b);
   int rc = krylov_solve(X, b, x, tol, max_iter, st);
   for (size_t i = 0; i < nv; i++) lu[i] = X->c * x[i];
   memcpy(lp, x + nv, nc * sizeof(double));

@@ -1,0 +1,49 @@
+"""torch.autograd wrapper of the Stokes solve with the hand-written adjoint.
+
+forward:  (mu_cell, rho_cell, f_u) -> (u, p), the solution of M x = (f_u, 0)
+backward: one adjoint solve M lambda = (dL/du, dL/dp) with the same
+          preconditioner and a fresh Krylov space (M = M^T), then the
+          strain-contraction kernel; the Krylov basis of the forward solve is
+          not kept.  dL/df = lambda_u, dL/dmu_cell and dL/drho_cell come from the
+          library (the chain rule through the derived edge viscosity included).
+
+All arithmetic runs in libstokes_mi355x.so; this file only marshals tensors.
+Parametrisations such as mu = exp(s) are ordinary torch ops in the caller's
+graph.
+"""
+from __future__ import annotations
+
+import torch
+
+from .stokes import Stokes
+
+
+class StokesSolveFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, mu_cell, rho_cell, f_u, params, tol=1e-10, max_iter=2000):
+        S = Stokes(params, rho_cell.detach().contiguous(), mu_cell.detach().contiguous())
+        bp = torch.zeros(S.ncell, dtype=torch.float64, device=f_u.device)
+        xu, xp, st, rc = S.solve(f_u.detach().contiguous(), bp, tol=tol, max_iter=max_iter)
+        ctx.S = S
+        ctx.tol, ctx.max_iter = tol, max_iter
+        ctx.stats = st
+        ctx.save_for_backward(xu, xp)
+        return xu, xp
+
+    @staticmethod
+    def backward(ctx, gu, gp):
+        xu, xp = ctx.saved_tensors
+        S = ctx.S
+        if gu is None:
+            gu = torch.zeros_like(xu)
+        if gp is None:
+            gp = torch.zeros_like(xp)
+        res = S.adjoint(xu, xp, gu.contiguous(), gp.contiguous(), tol=ctx.tol,
+                        max_iter=ctx.max_iter)
+        ctx.adjoint_stats = res["stats"]
+        return res["dmu_cell"], res["drho_cell"], res["lu"], None, None, None
+
+
+def stokes_solve(mu_cell, rho_cell, f_u, params, tol=1e-10, max_iter=2000):
+    """Differentiable solve: returns (u, p)."""
+    return StokesSolveFn.apply(mu_cell, rho_cell, f_u, params, tol, max_iter)

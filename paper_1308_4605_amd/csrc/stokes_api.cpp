@@ -897,8 +897,12 @@ int stokes_adjoint_solve(stokes_ctx *X, const double *xu, const double *xp, cons
   // M' = diag(c,1) M diag(1,1/c) is symmetric: lambda = diag(c,1) M'^{-1} (g_u, g_p / c)
   launch_pack_vel(g, gu, 1.0, X->b, X->s);
   launch_scale(gp, 1.0 / X->c, X->b + X->nvel, X->ncell, X->s);
-  int rc = check_rhs(X);
-  if (rc != STOKES_OK) return finish(X, rc);
+  // the forward solution is normalised to zero-mean pressure (and zero-mean
+  // velocity components when singular); the adjoint of that normalisation
+  // projects g onto the same mean-free space
+  remove_mean<double>(X, X->b + X->nvel, X->ncell, 25);
+  if (X->vel_singular) remove_vel_means<double>(X, g, X->b);
+  int rc = STOKES_OK;
   launch_fill<double>(X->x, 0.0, X->n, X->s);
   rc = krylov(X, tol, max_iter, st);
   finish_solution(X, X->x, X->c, 1.0, lu, lp);
