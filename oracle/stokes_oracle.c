@@ -808,7 +808,9 @@ static void precond_scaled(orc_ctx *X, const double *b, double *z) {
   /* keep the pressure mean (and the velocity means when the velocity
      operator is singular) at zero (Sec. 3.2) */
   remove_mean(zp, nc);
-  if (X->vel_singular) remove_vel_means(L, zu);
+  /* the velocity subsolver output is already mean-free; only P1 adds
+     rho_f^{-1} G q, which need not be */
+  if (X->vel_singular && X->p.precond == ORC_P1) remove_vel_means(L, zu);
   free(cvec); free(tu); free(xs);
 }
 
@@ -829,32 +831,48 @@ static int p_cycles_per_apply(const orc_ctx *X) {
 /* GMRES(m) / FGMRES(m)                                                      */
 /* ------------------------------------------------------------------------ */
 
-/* Arnoldi orthogonalisation of w against v_0..v_j by classical Gram-Schmidt,
-   repeated once when the norm drops below 1/sqrt(2) of its previous value
-   (Daniel-Gragg-Kaufman-Stewart criterion).  Fills hcol[0..j] and returns the
-   norm of the orthogonalised w. */
-static double arnoldi_orth(double **V, int j, double *w, size_t n, double *hcol) {
-  const double eta = 0.70710678118654752440;
-  double nw0 = sqrt(dotv(w, w, n));
+/* Arnoldi orthogonalisation of w against v_0..v_j by classical Gram-Schmidt
+   applied twice (CGS2): h1 = V^T w, w' = w - V h1, h2 = V^T w'.  With V
+   orthonormal, w'' = w' - V h2 has ||w''||^2 = ||w'||^2 - ||h2||^2; that value
+   is used unless the second pass removed half or more of ||w'||^2, in which
+   case w'' is formed and its norm computed directly (*formed = 1).  Fills
+   hcol = h1 + h2 and h2; returns ||w''||. */
+static double arnoldi_orth(double **V, int j, double *w, size_t n, double *hcol, double *h2,
+                           int *formed) {
   for (int i = 0; i <= j; i++) hcol[i] = dotv(w, V[i], n);
   for (int i = 0; i <= j; i++) {
     const double hi = hcol[i];
     const double *vi = V[i];
     for (size_t t = 0; t < n; t++) w[t] -= hi * vi[t];
   }
-  double nw = sqrt(dotv(w, w, n));
-  if (nw < eta * nw0) {
-    double h2[64];
-    for (int i = 0; i <= j; i++) h2[i] = dotv(w, V[i], n);
-    for (int i = 0; i <= j; i++) {
-      const double hi = h2[i];
-      const double *vi = V[i];
-      for (size_t t = 0; t < n; t++) w[t] -= hi * vi[t];
-      hcol[i] += hi;
-    }
-    nw = sqrt(dotv(w, w, n));
+  for (int i = 0; i <= j; i++) h2[i] = dotv(w, V[i], n);
+  const double s2 = dotv(w, w, n);
+  double q = 0.0;
+  for (int i = 0; i <= j; i++) {
+    q += h2[i] * h2[i];
+    hcol[i] += h2[i];
   }
-  return nw;
+  const double nu2 = s2 - q;
+  *formed = 0;
+  if (nu2 > 0.5 * s2) return sqrt(nu2);
+  for (int i = 0; i <= j; i++) {
+    const double hi = h2[i];
+    const double *vi = V[i];
+    for (size_t t = 0; t < n; t++) w[t] -= hi * vi[t];
+  }
+  *formed = 1;
+  return sqrt(dotv(w, w, n));
+}
+
+/* next basis vector v_{j+1} = w'' / nu (w'' formed here unless already) */
+static void arnoldi_next(double **V, int j, const double *w, size_t n, const double *h2,
+                         int formed, double nu, double *out) {
+  for (size_t t = 0; t < n; t++) {
+    double x = w[t];
+    if (!formed)
+      for (int i = 0; i <= j; i++) x -= h2[i] * V[i][t];
+    out[t] = x / nu;
+  }
 }
 
 /* Solve the scaled system M' x = b by restarted GMRES: left-preconditioned
@@ -928,7 +946,9 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
       st->precond_applies++;
       it++;
       double *hc = H + (size_t)j * (m + 1);
-      double hn = arnoldi_orth(V, j, w, n, hc);
+      double h2[64];
+      int formed = 0;
+      double hn = arnoldi_orth(V, j, w, n, hc, h2, &formed);
       hc[j + 1] = hn;
       /* previous rotations, then a new one that zeroes H[j+1][j] */
       for (int i = 0; i < j; i++) {
@@ -948,7 +968,7 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
       st->rel_res_est = est / beta * (rho / nb);
       if (!isfinite(est)) break;
       if (hn == 0.0 || est <= target || it >= max_iter) break;
-      for (size_t i = 0; i < n; i++) V[j + 1][i] = w[i] / hn;
+      arnoldi_next(V, j, w, n, h2, formed, hn, V[j + 1]);
     }
     /* back substitution H y = g and update x */
     for (int i = jj - 1; i >= 0; i--) {

@@ -264,7 +264,7 @@ void remove_mean(stokes_ctx *X, T *a, i64 n, int slot) {
 template <typename T>
 void remove_vel_means(stokes_ctx *X, const Geo &g, T *u) {
   // only used when every axis is periodic: every face is an unknown
-  for (int k = 0; k < g.d; k++) remove_mean<T>(X, u + g.foff[k], g.fcnt[k], 8 + k);
+  launch_vel_remove_means<T>(g, u, u, X->part, X->dsc + 8, X->s);
 }
 
 template <typename T>
@@ -301,8 +301,10 @@ void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
   launch_fill<T>(phi, (T)0, L.g.nvel, X->s);
   if (l == X->nlev - 1) {
     T *r = P<T>(L.res_u);
-    launch_cast<T, T>(rhs, r, L.g.nvel, X->s);
-    if (X->vel_singular) remove_vel_means<T>(X, L.g, r);
+    if (X->vel_singular)
+      launch_vel_remove_means<T>(L.g, rhs, r, X->part, X->dsc + 8, X->s);
+    else
+      launch_cast<T, T>(rhs, r, L.g.nvel, X->s);
     for (int s = 0; s < X->p.nu_coarse; s++) sweep_vel<T>(X, l, r, phi);
     if (X->vel_singular) remove_vel_means<T>(X, L.g, phi);
     return;
@@ -346,8 +348,7 @@ void vel_sub(stokes_ctx *X, const T *r, T *e) {
   Level &L = X->lev[0];
   const T *rr = r;
   if (X->vel_singular) {
-    launch_cast<T, T>(r, P<T>(X->vs_r), L.g.nvel, X->s);
-    remove_vel_means<T>(X, L.g, P<T>(X->vs_r));
+    launch_vel_remove_means<T>(L.g, r, P<T>(X->vs_r), X->part, X->dsc + 8, X->s);
     rr = P<T>(X->vs_r);
   }
   vcycle_vel<T>(X, 0, rr, e);
@@ -434,7 +435,8 @@ void precond(stokes_ctx *X, const T *bu, const T *bp, T *zu, T *zp) {
       break;
   }
   remove_mean<T>(X, zp, g.ncell, 20);
-  if (X->vel_singular) remove_vel_means<T>(X, g, zu);
+  // the subsolver output is already mean-free; only P1 adds rho_f^{-1} G q
+  if (X->vel_singular && X->p.precond == STOKES_P1) remove_vel_means<T>(X, g, zu);
 }
 
 // z (precision of the hierarchy, [u|p]) = P^{-1} v with v FP64 [u|p]
@@ -530,28 +532,33 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       }
       st->precond_applies++;
       it++;
-      // classical Gram-Schmidt: dots with v_0..v_j and (w,w), then update
-      launch_multidot(X->w, X->V, j + 1, n, X->part, X->dsc + 32, X->s);
-      launch_multiaxpy_norm(X->w, X->V, X->dsc + 32, j + 1, n, X->part, X->dsc + 0, X->s);
-      hip_ok(X, hipMemcpyAsync(hb, X->dsc, sizeof(double), hipMemcpyDeviceToHost, X->s));
-      hip_ok(X, hipMemcpyAsync(hb + 32, X->dsc + 32, (j + 2) * sizeof(double),
+      // CGS2: pass A (h1 = V^T w), pass B (w -= V h1; h2 = V^T w; s2 = (w,w))
+      launch_cgs_dots(X->w, X->V, j + 1, n, X->part, X->dsc + 32, X->s);
+      launch_cgs_update(X->w, X->V, X->dsc + 32, j + 1, n, X->part, X->dsc + 72, X->s);
+      hip_ok(X, hipMemcpyAsync(hb + 32, X->dsc + 32, (j + 1) * sizeof(double),
+                               hipMemcpyDeviceToHost, X->s));
+      hip_ok(X, hipMemcpyAsync(hb + 72, X->dsc + 72, (j + 2) * sizeof(double),
                                hipMemcpyDeviceToHost, X->s));
       hip_ok(X, hipStreamSynchronize(X->s));
       if (X->err) return STOKES_EDEVICE;
       double *hcol = &H[(size_t)j * (m + 1)];
-      for (int i = 0; i <= j; i++) hcol[i] = hb[32 + i];
-      const double nw0 = std::sqrt(hb[32 + j + 1]);
-      double hn = std::sqrt(hb[0]);
-      if (hn < eta * nw0) {
-        launch_multidot(X->w, X->V, j + 1, n, X->part, X->dsc + 80, X->s);
-        launch_multiaxpy_norm(X->w, X->V, X->dsc + 80, j + 1, n, X->part, X->dsc + 0, X->s);
-        hip_ok(X, hipMemcpyAsync(hb, X->dsc, sizeof(double), hipMemcpyDeviceToHost, X->s));
-        hip_ok(X, hipMemcpyAsync(hb + 80, X->dsc + 80, (j + 1) * sizeof(double),
-                                 hipMemcpyDeviceToHost, X->s));
-        hip_ok(X, hipStreamSynchronize(X->s));
-        if (X->err) return STOKES_EDEVICE;
-        for (int i = 0; i <= j; i++) hcol[i] += hb[80 + i];
-        hn = std::sqrt(hb[0]);
+      double q = 0.0;
+      for (int i = 0; i <= j; i++) {
+        q += hb[72 + i] * hb[72 + i];
+        hcol[i] = hb[32 + i] + hb[72 + i];
+      }
+      const double s2 = hb[72 + j + 1];
+      const double nu2 = s2 - q;
+      // ||w - V h2||^2 = s2 - ||h2||^2 while V is orthonormal; form it
+      // explicitly when the second pass removed half or more of s2
+      bool formed = false;
+      double hn;
+      if (nu2 > 0.5 * s2) {
+        hn = std::sqrt(nu2);
+      } else {
+        launch_cgs_next(X->w, X->V, X->dsc + 72, j + 1, 1.0, n, X->w, X->part, X->dsc + 0, X->s);
+        hn = std::sqrt(fetch(X, X->dsc, 1, hb));
+        formed = true;
       }
       hcol[j + 1] = hn;
       for (int i = 0; i < j; i++) {
@@ -576,7 +583,9 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       st->rel_res_est = est / beta * (rho / nb);
       if (!std::isfinite(est)) break;
       if (hn == 0.0 || est <= target || it >= max_iter) break;
-      launch_scale(X->w, 1.0 / hn, X->V[j + 1], n, X->s);
+      // pass C: v_{j+1} = (w - V h2) / nu
+      launch_cgs_next(X->w, X->V, X->dsc + 72, formed ? 0 : j + 1, 1.0 / hn, n, X->V[j + 1],
+                      X->part, nullptr, X->s);
     }
     for (int i = jj - 1; i >= 0; i--) {
       double s = g[i];

@@ -104,14 +104,26 @@ void launch_sum(const T *a, i64 n, double *partials, double *out, hipStream_t s)
 template <typename T>
 void launch_sub_mean(T *a, i64 n, const double *sum, hipStream_t s);
 
+// out = in minus each velocity component's mean (all axes periodic: every
+// face is an unknown); out may alias in
+template <typename T>
+void launch_vel_remove_means(const Geo &g, const T *in, T *out, double *partials, double *sums,
+                             hipStream_t s);
+
 // Krylov (FP64)
-constexpr int kRedBlocks = 512;
-// dots[i] = (w, v_i) for i < nv; dots[nv] = (w, w)
-void launch_multidot(const double *w, const double *const *v, int nv, i64 n, double *partials,
-                     double *dots, hipStream_t s);
-// w -= sum_i h_i v_i (h on the device); nrm2 = (w, w)
-void launch_multiaxpy_norm(double *w, const double *const *v, const double *h, int nv, i64 n,
-                           double *partials, double *nrm2, hipStream_t s);
+constexpr int kRedBlocks = 2048;
+// Arnoldi by classical Gram-Schmidt applied twice (CGS2), three passes:
+//   h[i] = (w, v_i), i < nv
+void launch_cgs_dots(const double *w, const double *const *v, int nv, i64 n, double *partials,
+                     double *h, hipStream_t s);
+//   w -= sum_i h_i v_i; h2s2[i] = (w, v_i) for i < nv, h2s2[nv] = (w, w)
+void launch_cgs_update(double *w, const double *const *v, const double *h, int nv, i64 n,
+                       double *partials, double *h2s2, hipStream_t s);
+//   out = (w - sum_i h2_i v_i) * inv_nu (nv = 0: plain scale); nrm2 = (out, out)
+//   when nrm2 != nullptr.  out may alias w.
+void launch_cgs_next(const double *w, const double *const *v, const double *h2, int nv,
+                     double inv_nu, i64 n, double *out, double *partials, double *nrm2,
+                     hipStream_t s);
 // x += sum_i y_i z_i with z in precision TZ (y: host array, passed by value)
 template <typename TZ>
 void launch_update_x(double *x, const TZ *const *z, const double *y, int nz, i64 n,

@@ -1016,80 +1016,252 @@ void launch_sub_mean(T *a, i64 n, const double *sum, hipStream_t s) {
   hipLaunchKernelGGL(k_sub_mean<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n, sum);
 }
 
+// per-component sums of a velocity vector in one pass (all faces; used only
+// when every axis is periodic)
+template <typename T>
+__global__ void k_vel_sums_partial(Geo g, const T *__restrict__ u, double *__restrict__ partials) {
+  __shared__ double sh[kBlock / 64][3];
+  double acc[3] = {0.0, 0.0, 0.0};
+  const i64 o1 = g.foff[1], o2 = (g.d == 3) ? g.foff[2] : g.nvel;
+  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < g.nvel;
+       t += (i64)gridDim.x * blockDim.x) {
+    const double v = (double)u[t];
+    if (t < o1) acc[0] += v;
+    else if (t < o2) acc[1] += v;
+    else acc[2] += v;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < 3; k++) {
+    double r = acc[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+    if (lane == 0) sh[wid][k] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double r = 0.0;
+    for (int w = 0; w < kBlock / 64; w++) r += sh[w][threadIdx.x];
+    partials[(i64)blockIdx.x * 3 + threadIdx.x] = r;
+  }
+}
+
+// out = in - (component mean); out may alias in
+template <typename T>
+__global__ void k_vel_sub_means(Geo g, const T *__restrict__ in, T *__restrict__ out,
+                                const double *__restrict__ sums) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.nvel) return;
+  const int k = (t >= g.foff[1]) + ((g.d == 3) && (t >= g.foff[2]));
+  out[t] = in[t] - (T)(sums[k] / (double)g.fcnt[k]);
+}
+
+template <typename T>
+void launch_vel_remove_means(const Geo &g, const T *in, T *out, double *partials, double *sums,
+                             hipStream_t s) {
+  const int nb = red_blocks(g.nvel);
+  hipLaunchKernelGGL(k_vel_sums_partial<T>, dim3(nb), dim3(kBlock), 0, s, g, in, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 3, 3, sums);
+  hipLaunchKernelGGL(k_vel_sub_means<T>, dim3(blocks_for(g.nvel)), dim3(kBlock), 0, s, g, in, out,
+                     sums);
+}
+template void launch_vel_remove_means<float>(const Geo &, const float *, float *, double *,
+                                             double *, hipStream_t);
+template void launch_vel_remove_means<double>(const Geo &, const double *, double *, double *,
+                                              double *, hipStream_t);
+
 struct PtrPack {
   const void *p[34];
 };
 
-// dots[i] = (w, v_i), dots[nv] = (w, w); vectors processed in chunks of 8
-template <int NC>
-__global__ void k_multidot(const double *__restrict__ w, PtrPack v, int base, int nv, i64 n,
-                           int stride, double *__restrict__ partials, int want_ww) {
-  __shared__ double sh[kBlock / 64];
-  double acc[NC + 1];
+// ---- Arnoldi by classical Gram-Schmidt applied twice (CGS2) -------------
+// Three streaming passes over [w, v_0..v_j] with double2 loads, a fixed grid
+// and per-block partial sums (bitwise reproducible):
+//   A: h1 = V^T w
+//   B: w <- w - V h1, and h2 = V^T w, s2 = (w, w) in the same pass
+//   C: v_next = (w - V h2) * inv_nu   (or a plain scale when w is final)
+
+constexpr int kArnBlock = 256;
+constexpr int kArnGrid = 2048;
+
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-  for (int j = 0; j <= NC; j++) acc[j] = 0.0;
-  const int cnt = (nv - base < NC) ? nv - base : NC;
-  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
-    const double wv = w[t];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// reduce over the block: acc[0..nv) go to partials[blockIdx.x*stride + i] and,
+// when with_extra, acc[MAXV] goes to slot nv (constant register indices only)
+template <int MAXV>
+__device__ __forceinline__ void block_store(double (&acc)[MAXV + 1], int nv, bool with_extra,
+                                            int stride, double *__restrict__ partials) {
+  __shared__ double sh[kArnBlock / 64][MAXV + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < NC; j++)
-      if (j < cnt) acc[j] += wv * ((const double *)v.p[base + j])[t];
-    if (want_ww) acc[NC] += wv * wv;
-  }
-#pragma unroll
-  for (int j = 0; j < NC; j++) {
-    if (j < cnt) {
-      const double r = block_sum(acc[j], sh);
-      if (threadIdx.x == 0) partials[(i64)blockIdx.x * stride + base + j] = r;
+  for (int i = 0; i <= MAXV; i++) {
+    if (i < nv || (i == MAXV && with_extra)) {
+      const double r = wave_sum(acc[i]);
+      if (lane == 0) sh[wid][i] = r;
     }
   }
-  if (want_ww) {
-    const double r = block_sum(acc[NC], sh);
-    if (threadIdx.x == 0) partials[(i64)blockIdx.x * stride + nv] = r;
-  }
-}
-
-void launch_multidot(const double *w, const double *const *v, int nv, i64 n, double *partials,
-                     double *dots, hipStream_t s) {
-  PtrPack pk;
-  for (int j = 0; j < nv; j++) pk.p[j] = v[j];
-  const int nb = red_blocks(n);
-  const int stride = nv + 1;
-  for (int base = 0; base < nv || base == 0; base += 8) {
-    const int last = (base + 8 >= nv);
-    hipLaunchKernelGGL(k_multidot<8>, dim3(nb), dim3(kBlock), 0, s, w, pk, base, nv, n, stride,
-                       partials, last ? 1 : 0);
-    if (last) break;
-  }
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, stride, stride, dots);
-}
-
-// w -= sum h_i v_i ; (w, w) partials
-__global__ void k_multiaxpy_norm(double *__restrict__ w, PtrPack v, const double *__restrict__ h,
-                                 int nv, i64 n, double *__restrict__ partials) {
-  __shared__ double sh[kBlock / 64];
-  __shared__ double hs[34];
-  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
   __syncthreads();
-  double acc = 0.0;
-  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
-    double x = w[t];
-    for (int j = 0; j < nv; j++) x -= hs[j] * ((const double *)v.p[j])[t];
-    w[t] = x;
-    acc += x * x;
+  const int cnt = nv + (with_extra ? 1 : 0);
+  if (threadIdx.x < cnt) {
+    const int src = ((int)threadIdx.x < nv) ? (int)threadIdx.x : MAXV;
+    double r = 0.0;
+    for (int wv = 0; wv < kArnBlock / 64; wv++) r += sh[wv][src];
+    partials[(i64)blockIdx.x * stride + threadIdx.x] = r;
   }
-  const double r = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = r;
 }
 
-void launch_multiaxpy_norm(double *w, const double *const *v, const double *h, int nv, i64 n,
-                           double *partials, double *nrm2, hipStream_t s) {
+template <int MAXV>
+__global__ void __launch_bounds__(kArnBlock) k_cgs_dots(const double *__restrict__ w, PtrPack v,
+                                                        int nv, i64 n, int stride,
+                                                        double *__restrict__ partials) {
+  double acc[MAXV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXV; i++) acc[i] = 0.0;
+  const i64 n2 = n >> 1;
+  const double2 *__restrict__ w2 = (const double2 *)w;
+  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n2; t += (i64)gridDim.x * blockDim.x) {
+    const double2 a = w2[t];
+#pragma unroll
+    for (int i = 0; i < MAXV; i++) {
+      if (i < nv) {
+        const double2 b = ((const double2 *)v.p[i])[t];
+        acc[i] += a.x * b.x + a.y * b.y;
+      }
+    }
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double a = w[n - 1];
+    for (int i = 0; i < nv; i++) acc[i] += a * ((const double *)v.p[i])[n - 1];
+  }
+  block_store<MAXV>(acc, nv, false, stride, partials);
+}
+
+template <int MAXV>
+__global__ void __launch_bounds__(kArnBlock) k_cgs_update(double *__restrict__ w, PtrPack v,
+                                                          const double *__restrict__ h, int nv,
+                                                          i64 n, int stride,
+                                                          double *__restrict__ partials) {
+  double acc[MAXV + 1];
+  double hh[MAXV];
+#pragma unroll
+  for (int i = 0; i <= MAXV; i++) acc[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < MAXV; i++) hh[i] = (i < nv) ? h[i] : 0.0;
+  const i64 n2 = n >> 1;
+  double2 *__restrict__ w2 = (double2 *)w;
+  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n2; t += (i64)gridDim.x * blockDim.x) {
+    double2 a = w2[t];
+    double2 b[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; i++) {
+      if (i < nv) {
+        b[i] = ((const double2 *)v.p[i])[t];
+        a.x -= hh[i] * b[i].x;
+        a.y -= hh[i] * b[i].y;
+      }
+    }
+    w2[t] = a;
+#pragma unroll
+    for (int i = 0; i < MAXV; i++)
+      if (i < nv) acc[i] += a.x * b[i].x + a.y * b[i].y;
+    acc[MAXV] += a.x * a.x + a.y * a.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double a = w[n - 1];
+    for (int i = 0; i < nv; i++) a -= hh[i] * ((const double *)v.p[i])[n - 1];
+    w[n - 1] = a;
+    for (int i = 0; i < nv; i++) acc[i] += a * ((const double *)v.p[i])[n - 1];
+    acc[MAXV] += a * a;
+  }
+  // slot nv receives (w, w)
+  block_store<MAXV>(acc, nv, true, stride, partials);
+}
+
+template <int MAXV>
+__global__ void __launch_bounds__(kArnBlock) k_cgs_next(const double *__restrict__ w, PtrPack v,
+                                                        const double *__restrict__ h2, int nv,
+                                                        double inv_nu, i64 n,
+                                                        double *__restrict__ out,
+                                                        double *__restrict__ partials) {
+  double hh[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; i++) hh[i] = (i < nv) ? h2[i] : 0.0;
+  double acc[MAXV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXV; i++) acc[i] = 0.0;
+  const i64 n2 = n >> 1;
+  const double2 *__restrict__ w2 = (const double2 *)w;
+  double2 *__restrict__ o2 = (double2 *)out;
+  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n2; t += (i64)gridDim.x * blockDim.x) {
+    double2 a = w2[t];
+#pragma unroll
+    for (int i = 0; i < MAXV; i++) {
+      if (i < nv) {
+        const double2 b = ((const double2 *)v.p[i])[t];
+        a.x -= hh[i] * b.x;
+        a.y -= hh[i] * b.y;
+      }
+    }
+    a.x *= inv_nu;
+    a.y *= inv_nu;
+    o2[t] = a;
+    acc[MAXV] += a.x * a.x + a.y * a.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double a = w[n - 1];
+    for (int i = 0; i < nv; i++) a -= hh[i] * ((const double *)v.p[i])[n - 1];
+    a *= inv_nu;
+    out[n - 1] = a;
+    acc[MAXV] += a * a;
+  }
+  if (partials) block_store<MAXV>(acc, 0, true, 1, partials);
+}
+
+static int arn_blocks(i64 n) {
+  i64 b = ((n >> 1) + kArnBlock - 1) / kArnBlock;
+  if (b > kArnGrid) b = kArnGrid;
+  return (int)(b < 1 ? 1 : b);
+}
+
+#define ARN_DISPATCH(KERN, nv, ...)                                                          \
+  do {                                                                                       \
+    if ((nv) <= 12)                                                                          \
+      hipLaunchKernelGGL(KERN<12>, dim3(nb), dim3(kArnBlock), 0, s, __VA_ARGS__);            \
+    else                                                                                     \
+      hipLaunchKernelGGL(KERN<33>, dim3(nb), dim3(kArnBlock), 0, s, __VA_ARGS__);            \
+  } while (0)
+
+void launch_cgs_dots(const double *w, const double *const *v, int nv, i64 n, double *partials,
+                     double *h, hipStream_t s) {
   PtrPack pk;
   for (int j = 0; j < nv; j++) pk.p[j] = v[j];
-  const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_multiaxpy_norm, dim3(nb), dim3(kBlock), 0, s, w, pk, h, nv, n, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, nrm2);
+  const int nb = arn_blocks(n);
+  ARN_DISPATCH(k_cgs_dots, nv, w, pk, nv, n, nv, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, nv, nv, h);
 }
+
+void launch_cgs_update(double *w, const double *const *v, const double *h, int nv, i64 n,
+                       double *partials, double *h2s2, hipStream_t s) {
+  PtrPack pk;
+  for (int j = 0; j < nv; j++) pk.p[j] = v[j];
+  const int nb = arn_blocks(n);
+  ARN_DISPATCH(k_cgs_update, nv, w, pk, h, nv, n, nv + 1, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, nv + 1, nv + 1, h2s2);
+}
+
+void launch_cgs_next(const double *w, const double *const *v, const double *h2, int nv,
+                     double inv_nu, i64 n, double *out, double *partials, double *nrm2,
+                     hipStream_t s) {
+  PtrPack pk;
+  for (int j = 0; j < nv; j++) pk.p[j] = v[j];
+  const int nb = arn_blocks(n);
+  ARN_DISPATCH(k_cgs_next, nv, w, pk, h2, nv, inv_nu, n, out, nrm2 ? partials : nullptr);
+  if (nrm2) hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, nrm2);
+}
+#undef ARN_DISPATCH
 
 struct CoefPack {
   double c[34];
