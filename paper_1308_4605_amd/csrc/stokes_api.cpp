@@ -267,24 +267,28 @@ void remove_vel_means(stokes_ctx *X, const Geo &g, T *u) {
   launch_vel_remove_means<T>(g, u, u, X->part, X->dsc + 8, X->s);
 }
 
+// nsweeps multicolour Gauss-Seidel sweeps of the velocity (Appendix C: per
+// sweep x-red, x-black, y-red, y-black[, z-red, z-black]), one launch per
+// colour, in place.
 template <typename T>
-void sweep_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
-  const Level &L = X->lev[l];
-  for (int k = 0; k < L.g.d; k++)
-    for (int colour = 0; colour < 2; colour++) {
-      const bool tm = X->timing && l == 0;
-      if (tm) {
-        if (X->ev_used == kEventPool) fold_events(X);
-        (void)hipEventRecord(X->ev[2 * X->ev_used], X->s);
+void smooth_vel(stokes_ctx *X, int l, const T *rhs, T *phi, int nsweeps) {
+  Level &L = X->lev[l];
+  for (int s = 0; s < nsweeps; s++)
+    for (int k = 0; k < L.g.d; k++)
+      for (int colour = 0; colour < 2; colour++) {
+        const bool tm = X->timing && l == 0;
+        if (tm) {
+          if (X->ev_used == kEventPool) fold_events(X);
+          (void)hipEventRecord(X->ev[2 * X->ev_used], X->s);
+        }
+        launch_vel_gs<T>(L.g, k, colour, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), rhs, phi, X->s);
+        if (tm) {
+          (void)hipEventRecord(X->ev[2 * X->ev_used + 1], X->s);
+          X->ev_used++;
+          X->launches++;
+          X->bytes += X->gs_bytes[k];
+        }
       }
-      launch_vel_gs<T>(L.g, k, colour, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), rhs, phi, X->s);
-      if (tm) {
-        (void)hipEventRecord(X->ev[2 * X->ev_used + 1], X->s);
-        X->ev_used++;
-        X->launches++;
-        X->bytes += X->gs_bytes[k];
-      }
-    }
 }
 
 template <typename T>
@@ -305,18 +309,18 @@ void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
       launch_vel_remove_means<T>(L.g, rhs, r, X->part, X->dsc + 8, X->s);
     else
       launch_cast<T, T>(rhs, r, L.g.nvel, X->s);
-    for (int s = 0; s < X->p.nu_coarse; s++) sweep_vel<T>(X, l, r, phi);
+    smooth_vel<T>(X, l, r, phi, X->p.nu_coarse);
     if (X->vel_singular) remove_vel_means<T>(X, L.g, phi);
     return;
   }
   Level &C = X->lev[l + 1];
-  for (int s = 0; s < X->p.nu_pre; s++) sweep_vel<T>(X, l, rhs, phi);
+  smooth_vel<T>(X, l, rhs, phi, X->p.nu_pre);
   launch_vel_residual<T>(L.g, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), rhs, phi, nullptr,
                          P<T>(L.res_u), X->s);
   launch_face_restrict<T>(L.g, C.g, P<T>(L.res_u), P<T>(C.rhs_u), X->s);
   vcycle_vel<T>(X, l + 1, P<T>(C.rhs_u), P<T>(C.phi_u));
   launch_face_prolong_add<T>(C.g, L.g, P<T>(C.phi_u), phi, X->s);
-  for (int s = 0; s < X->p.nu_post; s++) sweep_vel<T>(X, l, rhs, phi);
+  smooth_vel<T>(X, l, rhs, phi, X->p.nu_post);
 }
 
 // pressure V-cycle; singular operator: consistent coarsest problem by mean

@@ -93,30 +93,30 @@ __device__ __forceinline__ int dn1(const Geo &g, int a, int i) {
 // A = alpha - L_mu at one face (paper Sec. 3.1, eq. div_stress).  Returns
 // (A u)_f and the diagonal of A at f.  Tangential no-slip walls use the ghost
 // value -u_f, which equals the one-sided wall difference (u_f - 0)/(h/2).
-// ------------------------------------------------------------------------
+// Core of the row: the caller supplies u_f, its two neighbours along the
+// normal axis k (ukp, ukm) and, for each tangential axis l, the u_k values
+// above/below (ua[l], ub[l]) with the wall ghost already applied; u_l values
+// and the coefficients are read from the component arrays comp[l].
 template <typename T, int DIM>
-__device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const T *__restrict__ u,
-                                      const T *__restrict__ alpha, const T *__restrict__ muc,
-                                      const T *__restrict__ mue, T &Au, T &diag) {
+__device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T uf, T ukp, T ukm,
+                                         const T (&ua)[3], const T (&ub)[3],
+                                         const T *const *comp, const T *__restrict__ alpha,
+                                         const T *__restrict__ muc, const T *__restrict__ mue,
+                                         T &Au, T &diag) {
   const T h = (T)g.h;
   const T h2 = h * h;
   const i64 fq = fidx3(g, k, i);
-  const T uf = u[fq];
   int t[3] = {i[0], i[1], i[2]};
-  // normal stresses at the cells right (index i) and left (index i - e_k)
-  const int kp = up1(g, k, i[k]);
   const int km = dn1(g, k, i[k]);
-  t[k] = kp;
-  const T ukp = u[fidx3(g, k, t)];
   t[k] = km;
-  const T ukm = u[fidx3(g, k, t)];
   const T mr = muc[cidx3(g, i)];
   const T ml = muc[cidx3(g, t)];
   t[k] = i[k];
   const T tr = (T)2 * mr * ((ukp - uf) / h);
   const T tl = (T)2 * ml * ((uf - ukm) / h);
   T s = (tr - tl) / h;
-  T dg = alpha[fq] + (T)2 * (mr + ml) / h2;
+  const T al = alpha[fq];
+  T dg = al + (T)2 * (mr + ml) / h2;
 #pragma unroll
   for (int l = 0; l < DIM; l++) {
     if (l == k) continue;
@@ -124,31 +124,60 @@ __device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const
     const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
     const bool bot = g.ns[l] && (i[l] == 0);
     const int lp = up1(g, l, i[l]);
-    const int lm = dn1(g, l, i[l]);
-    t[l] = top ? i[l] : lp;  // component k has no face at index n[l] along l
-    const T ua = top ? -uf : u[fidx3(g, k, t)];
+    const T *__restrict__ ul = comp[l];
+    const int f0 = g.fd[l][0], f1 = g.fd[l][1];
     t[l] = lp;
     const T mhi = mue[eidx3(g, m, t)];
     // u_l on the two faces beside the upper edge (cells i[k] and i[k]-1 along k)
-    const T ulh_r = u[fidx3(g, l, t)];
+    const T ulh_r = ul[((i64)t[2] * f1 + t[1]) * f0 + t[0]];
     t[k] = km;
-    const T ulh_l = u[fidx3(g, l, t)];
+    const T ulh_l = ul[((i64)t[2] * f1 + t[1]) * f0 + t[0]];
     t[k] = i[k];
-    t[l] = lm;
-    const T ub = bot ? -uf : u[fidx3(g, k, t)];
     t[l] = i[l];
     const T mlo = mue[eidx3(g, m, t)];
-    const T ull_r = u[fidx3(g, l, t)];
+    const T ull_r = ul[((i64)t[2] * f1 + t[1]) * f0 + t[0]];
     t[k] = km;
-    const T ull_l = u[fidx3(g, l, t)];
+    const T ull_l = ul[((i64)t[2] * f1 + t[1]) * f0 + t[0]];
     t[k] = i[k];
-    const T ghi = (ua - uf) / h + (ulh_r - ulh_l) / h;
-    const T glo = (uf - ub) / h + (ull_r - ull_l) / h;
+    const T ghi = (ua[l] - uf) / h + (ulh_r - ulh_l) / h;
+    const T glo = (uf - ub[l]) / h + (ull_r - ull_l) / h;
     s += (mhi * ghi - mlo * glo) / h;
     dg += ((top ? (T)2 : (T)1) * mhi + (bot ? (T)2 : (T)1) * mlo) / h2;
   }
-  Au = alpha[fq] * uf - s;
+  Au = al * uf - s;
   diag = dg;
+}
+
+// A = alpha - L_mu at one face (paper Sec. 3.1, eq. div_stress), all values
+// from the concatenated velocity buffer u.  Returns (A u)_f and the diagonal
+// of A at f.  Tangential no-slip walls use the ghost value -u_f, which equals
+// the one-sided wall difference (u_f - 0)/(h/2).
+template <typename T, int DIM>
+__device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const T *__restrict__ u,
+                                      const T *__restrict__ alpha, const T *__restrict__ muc,
+                                      const T *__restrict__ mue, T &Au, T &diag) {
+  const i64 fq = fidx3(g, k, i);
+  const T uf = u[fq];
+  int t[3] = {i[0], i[1], i[2]};
+  t[k] = up1(g, k, i[k]);
+  const T ukp = u[fidx3(g, k, t)];
+  t[k] = dn1(g, k, i[k]);
+  const T ukm = u[fidx3(g, k, t)];
+  t[k] = i[k];
+  T ua[3] = {0, 0, 0}, ub[3] = {0, 0, 0};
+#pragma unroll
+  for (int l = 0; l < DIM; l++) {
+    if (l == k) continue;
+    const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
+    const bool bot = g.ns[l] && (i[l] == 0);
+    t[l] = top ? i[l] : up1(g, l, i[l]);  // component k has no face at index n[l] along l
+    ua[l] = top ? -uf : u[fidx3(g, k, t)];
+    t[l] = dn1(g, l, i[l]);
+    ub[l] = bot ? -uf : u[fidx3(g, k, t)];
+    t[l] = i[l];
+  }
+  const T *comp[3] = {u + g.foff[0], u + g.foff[1], u + g.foff[2]};
+  a_row_nb<T, DIM>(g, k, i, uf, ukp, ukm, ua, ub, comp, alpha, muc, mue, Au, diag);
 }
 
 __device__ __forceinline__ bool low_wall(const Geo &g, int k, const int i[3]) {
