@@ -30,6 +30,29 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+KERNEL_SRC = os.path.join(ROOT, "paper_1308_4605_amd", "csrc", "stokes_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_vel_gs_3d-periodic-contrast-256.json")
+
+
+def _kernel_source_sha():
+    import hashlib
+
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _measured_traffic(n):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None when it was taken on other kernel
+    source or another size."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != _kernel_source_sha() or t.get("n") != n:
+        return None
+    return t.get("hbm_bytes_per_launch")
 
 
 def _log(msg):
@@ -45,6 +68,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solver")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -160,12 +185,18 @@ def main():
         "speedup_fp32mg_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
         "roofline": {"kernel": "velocity Gauss-Seidel colour pass, finest level (k_vel_gs)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _measured_traffic(args.n),
                      "avg_launch_us": 1e3 * avg_ms, "launches": launches,
                      "bytes_per_launch": bytes_k / max(launches, 1)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if args.calib_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        _log("calibration copy: 1 GiB read + 1 GiB write")
 
 
 if __name__ == "__main__":
