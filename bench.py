@@ -59,6 +59,41 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _adjoint_timing(torch, dev, W, Stokes, n=128, reps=2):
+    """Forward solve + adjoint solve with gradients on the 128^3 no-slip
+    unsteady workload (mu = exp(s)), loss 1/2 ||u - u_target||^2, in the FP64
+    and FP32-multigrid forms; the FP32-MG gradient is compared with FP64."""
+    w = W.adjoint_3d(n=n)
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    rho, mu, bu, bp = T(w.rho), T(w.mu), T(w.bu), T(w.bp)
+    out, grads = {}, {}
+    for name, prec, kry in (("fp64", W.FP64, W.GMRES_LEFT), ("fp32mg", W.MG_FP32, W.FGMRES)):
+        S = Stokes(w.params(precision=prec, krylov=kry), rho, mu)
+        S2 = Stokes(w.params(precision=prec, krylov=kry), rho, T(np.exp(w.extra["s2"])))
+        ut, _, _, _ = S2.solve(T(w.extra["bu2"]), bp, tol=1e-10)
+        S2.close()
+        res = None
+        for r in range(reps + 1):  # first repetition is a warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xu, xp, st, _ = S.solve(bu, bp, tol=1e-10)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            res = S.adjoint(xu, xp, xu - ut, torch.zeros_like(xp), tol=1e-10)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        out[name] = {"forward_ms": 1e3 * (t1 - t0), "adjoint_ms": 1e3 * (t2 - t1),
+                     "forward_iters": st["iters"], "adjoint_iters": res["stats"]["iters"]}
+        grads[name] = res["dmu_cell"] * mu  # dL/ds with mu = exp(s)
+        S.close()
+    out["workload"] = f"3d-noslip-adjoint-{n}"
+    out["tol"] = 1e-10
+    out["fp32mg_vs_fp64_grad_rel_diff"] = float(torch.linalg.norm(grads["fp32mg"] - grads["fp64"])
+                                                / torch.linalg.norm(grads["fp64"]))
+    _log(f"adjoint: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +103,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 solver")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -142,6 +178,10 @@ def main():
              f"err u {err_u:.2e} p {err_p:.2e}")
         del xu64, xp64
 
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = _adjoint_timing(torch, dev, W, Stokes)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -188,6 +228,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": _measured_traffic(args.n),
                      "avg_launch_us": 1e3 * avg_ms, "launches": launches,
                      "bytes_per_launch": bytes_k / max(launches, 1)},
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -407,12 +407,44 @@ def fd_directions(seed, lay: Layout, count):
     return ds, df
 
 
+def bubble(dim=3, n=32, r_mu=100.0, r_rho=100.0, theta=0.0, seed=6000):
+    """The paper's bubble test problem (Sec. 4, eq. varcoeff_def): a sphere
+    (disk in 2D) of radius L/4 at the centre of the unit cube (square) with
+    no-slip walls; mu = f(x; r_mu), rho = f(x; r_rho) with
+    f(x; r) = (r+1)/2 + (r-1)/2 tanh(d/eps) + 0.1 R, d the signed distance to
+    the interface (positive outside), eps = h, R ~ U(0,1) per cell.  So the
+    bubble holds ~1 and the surrounding fluid ~r.  Steady by default.
+    The right-hand side is left to the caller (the paper uses b = M x for a
+    random x); extra['x_u'], extra['x_p'] hold such a seeded random x."""
+    n3 = _n3(dim, n)
+    lay = make_layout(dim, n3, (NOSLIP,) * dim)
+    h = 1.0 / n3[0]
+    cc = lay.cell_centres(h)
+    d = np.sqrt(sum((c - 0.5) ** 2 for c in cc)) - 0.25
+    rng = np.random.default_rng(seed + 1)
+
+    def f(r):
+        return (0.5 * (r + 1) + 0.5 * (r - 1) * np.tanh(d / h) + 0.1 * rng.uniform(0, 1, d.shape)).ravel()
+
+    mu = f(r_mu)
+    rho = f(r_rho)
+    rx = np.random.default_rng(seed + 3)
+    xu = rx.standard_normal(lay.nvel)
+    xu[lay.wall_mask()] = 0.0
+    xp = rx.standard_normal(lay.ncell)
+    w = Workload(f"{dim}d-bubble-r{r_mu:g}", dim, lay.n, lay.bc, h, theta, P1, GMRES_LEFT, FP64,
+                 EDGE_ARITH, rho, mu, np.zeros(lay.nvel), np.zeros(lay.ncell))
+    w.extra.update(x_u=xu, x_p=xp)
+    return w
+
+
 WORKLOADS = {
     "2d-periodic-smooth": periodic_smooth_2d,
     "2d-noslip-discs": discs_2d,
     "3d-noslip-layers": layers_3d,
     "3d-periodic-contrast": contrast_periodic_3d,
     "3d-noslip-adjoint": adjoint_3d,
+    "bubble": bubble,
 }
 
 

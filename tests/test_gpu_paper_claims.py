@@ -1,0 +1,50 @@
+"""The GPU solver on the paper's bubble test problem: iteration counts equal
+the oracle's (+-1) for every preconditioner at 32^3, and respect the bounds
+the paper states (tests/golden/paper_claims.json) at 128^3, in both the FP64
+and the FP32-multigrid forms.  b = M x with the oracle's M (Sec. 4 protocol)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import N, T, pair
+from paper_1308_4605_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_claims.json")))
+
+
+def _rhs(o, w):
+    bu, bp = o.apply(w.extra["x_u"], w.extra["x_p"])
+    return bu, bp - bp.mean()
+
+
+@pytest.mark.parametrize("precond", [W.P1, W.P2, W.P3, W.P4, W.P5])
+def test_bubble_iterations_match_oracle(precond):
+    w = W.bubble(3, 32, 100.0, 100.0)
+    p = w.params(precond=precond)
+    g, o = pair(p, w.rho, w.mu)
+    bu, bp = _rhs(o, w)
+    _, _, st, rc = g.solve(T(bu), T(bp), tol=1e-10, max_iter=400)
+    _, _, ost, orc = o.solve(bu, bp, tol=1e-10, max_iter=400)
+    print(f"P{precond}: gpu {st['iters']} ({st['scalar_vcycles']} scalar V-cycles), oracle {ost['iters']}",
+          flush=True)
+    assert abs(st["iters"] - ost["iters"]) <= 1
+
+
+@pytest.mark.parametrize("precision,krylov", [(W.FP64, W.GMRES_LEFT), (W.MG_FP32, W.FGMRES)])
+def test_bubble_128_paper_bounds(precision, krylov):
+    g1, g2 = GOLD["bubble_p1_contrast_100"], GOLD["bubble_contrast_2"]
+    for r, bound in ((100.0, g1["max_gmres_iterations"]), (2.0, g2["max_gmres_iterations_exclusive"] - 1)):
+        w = W.bubble(3, 128, r, r)
+        p = w.params(precision=precision, krylov=krylov)
+        g, o = pair(p, w.rho, w.mu)
+        bu, bp = _rhs(o, w)
+        _, _, st, rc = g.solve(T(bu), T(bp), tol=1e-10, max_iter=400)
+        print(f"128^3 r={r} precision={precision}: {st['iters']} iterations, {st['scalar_vcycles']} "
+              f"scalar V-cycles, rel res {st['rel_res_true']:.1e}", flush=True)
+        assert rc == 0 and st["iters"] <= bound
+        if r == 100.0:
+            assert st["scalar_vcycles"] <= g1["max_scalar_vcycles"]

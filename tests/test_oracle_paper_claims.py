@@ -1,0 +1,42 @@
+"""The oracle against the iteration counts the paper states for its own
+bubble test problem (Sec. 4.2-4.3; values in tests/golden/paper_claims.json).
+These are soft pins (upper bounds and orderings read from the text; the
+figures themselves are not available)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1308_4605_amd import workloads as W
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_claims.json")))
+
+
+def _solve(w, **kw):
+    o = oracle.Oracle.from_workload(w, **kw)
+    bu, bp = o.apply(w.extra["x_u"], w.extra["x_p"])  # b = M x, x random (Sec. 4)
+    xu, xp, st, rc = o.solve(bu, bp - bp.mean(), tol=1e-10, max_iter=400)
+    return st
+
+
+@pytest.mark.parametrize("dim,n", [(2, 128), (3, 16), (3, 32)])
+def test_bubble_p1_iteration_bounds(dim, n):
+    g = GOLD["bubble_p1_contrast_100"]
+    st = _solve(W.bubble(dim, n, 100.0, 100.0))
+    assert st["iters"] <= g["max_gmres_iterations"], st
+    assert st["scalar_vcycles"] <= g["max_scalar_vcycles"], st
+    st2 = _solve(W.bubble(dim, n, 2.0, 2.0))
+    assert st2["iters"] < GOLD["bubble_contrast_2"]["max_gmres_iterations_exclusive"], st2
+
+
+def test_bubble_steady_preconditioner_ranking():
+    w = W.bubble(3, 32, 100.0, 100.0)
+    cost = {}
+    for P in (W.P1, W.P2, W.P3, W.P4, W.P5):
+        cost[P] = _solve(w, precond=P)["scalar_vcycles"]
+    assert cost[W.P2] < cost[W.P1] and cost[W.P3] < cost[W.P1]
+    assert cost[W.P4] == max(cost.values())
+    for P in (W.P1, W.P2, W.P3):
+        assert _solve(w, precond=P, restart=5)["iters"] >= _solve(w, precond=P)["iters"]
