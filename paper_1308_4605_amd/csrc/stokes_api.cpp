@@ -6,6 +6,7 @@
 // rotations of the (m+1) x m Hessenberg matrix and tests convergence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -89,6 +90,7 @@ struct stokes_ctx {
   int d = 0, nlev = 0;
   int mg32 = 0;
   int vel_singular = 0;
+  int tail_l = -1;  // first level of the single-workgroup coarse tail (-1: none)
   double c = 1.0;
   Level lev[kMaxLev];
   i64 nvel = 0, ncell = 0, nedge = 0, n = 0;
@@ -298,10 +300,47 @@ void sweep_p(stokes_ctx *X, int l, const T *rhs, T *phi) {
   launch_p_gs<T>(L.g, 1, P<T>(L.beta), rhs, phi, X->s);
 }
 
+// levels tail_l..nlev-1 of a V-cycle in one launch; level tail_l works on
+// the caller's rhs / phi, the deeper ones on the level buffers
+template <typename T>
+TailLevels<T> tail_levels(stokes_ctx *X, int l0, const T *rhs, T *phi, bool vel) {
+  TailLevels<T> t;
+  t.nl = X->nlev - l0;
+  t.singular = vel ? X->vel_singular : 1;
+  t.nu_pre = X->p.nu_pre;
+  t.nu_post = X->p.nu_post;
+  t.nu_coarse = X->p.nu_coarse;
+  for (int i = 0; i < kTailMax; i++) {
+    const int l = l0 + i;
+    if (i >= t.nl) {
+      t.g[i] = X->lev[l0].g;
+      t.a[i] = t.b[i] = t.mc[i] = t.me[i] = nullptr;
+      t.phi[i] = t.rhs[i] = t.res[i] = nullptr;
+      continue;
+    }
+    Level &L = X->lev[l];
+    t.g[i] = L.g;
+    t.a[i] = P<T>(L.alpha);
+    t.b[i] = P<T>(L.beta);
+    t.mc[i] = P<T>(L.muc);
+    t.me[i] = P<T>(L.mue);
+    t.phi[i] = P<T>(vel ? L.phi_u : L.phi_p);
+    t.rhs[i] = P<T>(vel ? L.rhs_u : L.rhs_p);
+    t.res[i] = P<T>(vel ? L.res_u : L.res_p);
+  }
+  t.rhs[0] = const_cast<T *>(rhs);
+  t.phi[0] = phi;
+  return t;
+}
+
 // velocity V-cycle on level l from zero (Appendix C)
 template <typename T>
 void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
   Level &L = X->lev[l];
+  if (l == X->tail_l) {
+    launch_tail_vel<T>(tail_levels<T>(X, l, rhs, phi, true), X->s);
+    return;
+  }
   launch_fill<T>(phi, (T)0, L.g.nvel, X->s);
   if (l == X->nlev - 1) {
     T *r = P<T>(L.res_u);
@@ -328,6 +367,10 @@ void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
 template <typename T>
 void vcycle_p(stokes_ctx *X, int l, const T *rhs, T *phi) {
   Level &L = X->lev[l];
+  if (l == X->tail_l) {
+    launch_tail_p<T>(tail_levels<T>(X, l, rhs, phi, false), X->s);
+    return;
+  }
   launch_fill<T>(phi, (T)0, L.g.ncell, X->s);
   if (l == X->nlev - 1) {
     T *r = P<T>(L.res_p);
@@ -490,7 +533,6 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     return STOKES_OK;
   }
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hc2(m + 2);
-  const double eta = 0.70710678118654752440;
   int it = 0, rc = STOKES_OK;
   for (;;) {
     // r = b - M x and its norm
@@ -720,6 +762,12 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
   X->vel_singular = (p->theta == 0.0);
   for (int a = 0; a < p->dim; a++)
     if (p->bc[a] == STOKES_NOSLIP) X->vel_singular = 0;
+  // coarse tail: the levels small enough for one workgroup (at most kTailMax)
+  for (int l = std::max(0, nlev - kTailMax); l < nlev; l++)
+    if (X->lev[l].g.ncell <= kTailCells) {
+      X->tail_l = l;
+      break;
+    }
   if (hipHostMalloc((void **)&X->host, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete X;
     return STOKES_EDEVICE;

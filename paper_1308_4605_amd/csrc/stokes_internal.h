@@ -87,6 +87,24 @@ void launch_cell_restrict(const Geo &gf, const Geo &gc, const T *rf, T *rc, hipS
 template <typename T>
 void launch_cell_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *pf, hipStream_t s);
 
+// coarse tail of a V-cycle (levels l0..nlev-1) in one workgroup
+constexpr int kTailMax = 8;
+constexpr int kTailBlock = 1024;
+constexpr i64 kTailCells = 4096;  // largest level run inside the tail
+template <typename T>
+struct TailLevels {
+  int nl;        // number of levels in the tail (the last is the coarsest)
+  int singular;  // velocity: remove component means at the coarsest level
+  int nu_pre, nu_post, nu_coarse;
+  Geo g[kTailMax];
+  const T *a[kTailMax], *b[kTailMax], *mc[kTailMax], *me[kTailMax];  // alpha, beta, mu_c, mu_e
+  T *phi[kTailMax], *rhs[kTailMax], *res[kTailMax];
+};
+template <typename T>
+void launch_tail_vel(const TailLevels<T> &L, hipStream_t s);
+template <typename T>
+void launch_tail_p(const TailLevels<T> &L, hipStream_t s);
+
 // preconditioner glue (level 0, precision T)
 template <typename T>  // out = sgn * (D u + bp)   (bp may be null)
 void launch_div(const Geo &g, const T *u, const T *bp, T sgn, T *out, hipStream_t s);

@@ -61,6 +61,12 @@ Geo make_geo(int d, const int n[3], const int ns[3], double h) {
 // index helpers
 // ------------------------------------------------------------------------
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ __forceinline__ i64 fidx(const Geo &g, int k, int i0, int i1, int i2) {
   return g.foff[k] + ((i64)i2 * g.fd[k][1] + i1) * g.fd[k][0] + i0;
 }
@@ -565,22 +571,31 @@ __device__ __forceinline__ bool colour_cell(const Geo &g, i64 t, int colour, int
   i[0] = 2 * tx + ((i[1] + i[2] + colour) & 1);
   return i[0] < g.n[0];
 }
-__host__ __forceinline__ i64 colour_threads(const Geo &g) {
+__host__ __device__ __forceinline__ i64 colour_threads(const Geo &g) {
   return (i64)((g.n[0] + 1) >> 1) * g.n[1] * g.n[2];
+}
+
+// one face of one colour of the velocity Gauss-Seidel sweep
+template <typename T, int DIM>
+__device__ __forceinline__ void vel_gs_elem(const Geo &g, int k, int colour, i64 t,
+                                            const T *__restrict__ alpha, const T *__restrict__ muc,
+                                            const T *__restrict__ mue, const T *__restrict__ rhs,
+                                            T *__restrict__ phi) {
+  int i[3];
+  if (!colour_cell(g, t, colour, i)) return;
+  if (low_wall(g, k, i)) return;
+  T Au, dg;
+  a_row<T, DIM>(g, k, i, phi, alpha, muc, mue, Au, dg);
+  const i64 fq = fidx3(g, k, i);
+  phi[fq] += (rhs[fq] - Au) / dg;
 }
 
 template <typename T, int DIM, int K>
 __global__ void k_vel_gs(Geo g, int colour, const T *__restrict__ alpha,
                          const T *__restrict__ muc, const T *__restrict__ mue,
                          const T *__restrict__ rhs, T *__restrict__ phi) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  int i[3];
-  if (!colour_cell(g, t, colour, i)) return;
-  if (low_wall(g, K, i)) return;
-  T Au, dg;
-  a_row<T, DIM>(g, K, i, phi, alpha, muc, mue, Au, dg);
-  const i64 fq = fidx3(g, K, i);
-  phi[fq] += (rhs[fq] - Au) / dg;
+  vel_gs_elem<T, DIM>(g, K, colour, (i64)blockIdx.x * blockDim.x + threadIdx.x, alpha, muc, mue,
+                      rhs, phi);
 }
 
 template <typename T>
@@ -603,11 +618,12 @@ void launch_vel_gs(const Geo &g, int k, int colour, const T *alpha, const T *muc
 
 // res = rhs - A phi - G p (p may be null); cell-indexed over all components
 template <typename T, int DIM>
-__global__ void k_vel_residual(Geo g, const T *__restrict__ alpha, const T *__restrict__ muc,
-                               const T *__restrict__ mue, const T *__restrict__ rhs,
-                               const T *__restrict__ phi, const T *__restrict__ p,
-                               T *__restrict__ res) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void vel_residual_elem(const Geo &g, i64 t, const T *__restrict__ alpha,
+                                                  const T *__restrict__ muc,
+                                                  const T *__restrict__ mue,
+                                                  const T *__restrict__ rhs,
+                                                  const T *__restrict__ phi,
+                                                  const T *__restrict__ p, T *__restrict__ res) {
   if (t >= g.ncell) return;
   int i[3];
   cell_of(g, t, i);
@@ -627,6 +643,15 @@ __global__ void k_vel_residual(Geo g, const T *__restrict__ alpha, const T *__re
   }
 }
 
+template <typename T, int DIM>
+__global__ void k_vel_residual(Geo g, const T *__restrict__ alpha, const T *__restrict__ muc,
+                               const T *__restrict__ mue, const T *__restrict__ rhs,
+                               const T *__restrict__ phi, const T *__restrict__ p,
+                               T *__restrict__ res) {
+  vel_residual_elem<T, DIM>(g, (i64)blockIdx.x * blockDim.x + threadIdx.x, alpha, muc, mue, rhs,
+                            phi, p, res);
+}
+
 template <typename T>
 void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mue, const T *rhs,
                          const T *phi, const T *p, T *res, hipStream_t s) {
@@ -642,8 +667,8 @@ void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mu
 // 2I-1, 2I, 2I+1 times the mean over the 2^(d-1) fine faces along the
 // tangential axes (2D: the printed 6-point stencil; 3D: 12 points)
 template <typename T, int DIM>
-__global__ void k_face_restrict(Geo gf, Geo gc, const T *__restrict__ rf, T *__restrict__ rc) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void face_restrict_elem(const Geo &gf, const Geo &gc, i64 t,
+                                                   const T *__restrict__ rf, T *__restrict__ rc) {
   if (t >= gc.ncell) return;
   int I[3];
   cell_of(gc, t, I);
@@ -675,6 +700,11 @@ __global__ void k_face_restrict(Geo gf, Geo gc, const T *__restrict__ rf, T *__r
     }
     rc[fidx3(gc, k, I)] = s;
   }
+}
+
+template <typename T, int DIM>
+__global__ void k_face_restrict(Geo gf, Geo gc, const T *__restrict__ rf, T *__restrict__ rc) {
+  face_restrict_elem<T, DIM>(gf, gc, (i64)blockIdx.x * blockDim.x + threadIdx.x, rf, rc);
 }
 
 template <typename T>
@@ -710,9 +740,8 @@ __device__ __forceinline__ void tang_w(const Geo &gc, int a, int j, int idx[2], 
 }
 
 template <typename T, int DIM>
-__global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
-                                   T *__restrict__ phif) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void face_prolong_elem(const Geo &gc, const Geo &gf, i64 t,
+                                                  const T *__restrict__ ec, T *__restrict__ phif) {
   if (t >= gf.ncell) return;
   int f[3];
   cell_of(gf, t, f);
@@ -757,6 +786,12 @@ __global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
         }
     phif[fidx3(gf, k, f)] += s;
   }
+}
+
+template <typename T, int DIM>
+__global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
+                                   T *__restrict__ phif) {
+  face_prolong_elem<T, DIM>(gc, gf, (i64)blockIdx.x * blockDim.x + threadIdx.x, ec, phif);
 }
 
 template <typename T>
@@ -805,15 +840,21 @@ __device__ __forceinline__ void p_row(const Geo &g, const int i[3], const T *__r
 }
 
 template <typename T, int DIM>
-__global__ void k_p_gs(Geo g, int colour, const T *__restrict__ beta, const T *__restrict__ rhs,
-                       T *__restrict__ phi) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void p_gs_elem(const Geo &g, int colour, i64 t,
+                                          const T *__restrict__ beta, const T *__restrict__ rhs,
+                                          T *__restrict__ phi) {
   int i[3];
   if (!colour_cell(g, t, colour, i)) return;
   T Lp, dg;
   p_row<T, DIM>(g, i, beta, phi, Lp, dg);
   const i64 c = cidx3(g, i);
   phi[c] += (rhs[c] - Lp) / dg;
+}
+
+template <typename T, int DIM>
+__global__ void k_p_gs(Geo g, int colour, const T *__restrict__ beta, const T *__restrict__ rhs,
+                       T *__restrict__ phi) {
+  p_gs_elem<T, DIM>(g, colour, (i64)blockIdx.x * blockDim.x + threadIdx.x, beta, rhs, phi);
 }
 
 template <typename T>
@@ -826,15 +867,21 @@ void launch_p_gs(const Geo &g, int colour, const T *beta, const T *rhs, T *phi, 
 }
 
 template <typename T, int DIM>
-__global__ void k_p_residual(Geo g, const T *__restrict__ beta, const T *__restrict__ rhs,
-                             const T *__restrict__ phi, T *__restrict__ res) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void p_residual_elem(const Geo &g, i64 t, const T *__restrict__ beta,
+                                                const T *__restrict__ rhs,
+                                                const T *__restrict__ phi, T *__restrict__ res) {
   if (t >= g.ncell) return;
   int i[3];
   cell_of(g, t, i);
   T Lp, dg;
   p_row<T, DIM>(g, i, beta, phi, Lp, dg);
   res[t] = rhs[t] - Lp;
+}
+
+template <typename T, int DIM>
+__global__ void k_p_residual(Geo g, const T *__restrict__ beta, const T *__restrict__ rhs,
+                             const T *__restrict__ phi, T *__restrict__ res) {
+  p_residual_elem<T, DIM>(g, (i64)blockIdx.x * blockDim.x + threadIdx.x, beta, rhs, phi, res);
 }
 
 template <typename T>
@@ -849,8 +896,8 @@ void launch_p_residual(const Geo &g, const T *beta, const T *rhs, const T *phi, 
 }
 
 template <typename T>
-__global__ void k_cell_restrict(Geo gf, Geo gc, const T *__restrict__ rf, T *__restrict__ rc) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void cell_restrict_elem(const Geo &gf, const Geo &gc, i64 t,
+                                                   const T *__restrict__ rf, T *__restrict__ rc) {
   if (t >= gc.ncell) return;
   int I[3];
   cell_of(gc, t, I);
@@ -866,14 +913,19 @@ __global__ void k_cell_restrict(Geo gf, Geo gc, const T *__restrict__ rf, T *__r
 }
 
 template <typename T>
+__global__ void k_cell_restrict(Geo gf, Geo gc, const T *__restrict__ rf, T *__restrict__ rc) {
+  cell_restrict_elem<T>(gf, gc, (i64)blockIdx.x * blockDim.x + threadIdx.x, rf, rc);
+}
+
+template <typename T>
 void launch_cell_restrict(const Geo &gf, const Geo &gc, const T *rf, T *rc, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_restrict<T>, dim3(blocks_for(gc.ncell)), dim3(kBlock), 0, s, gf, gc,
                      rf, rc);
 }
 
 template <typename T>
-__global__ void k_cell_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec, T *__restrict__ pf) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void cell_prolong_elem(const Geo &gc, const Geo &gf, i64 t,
+                                                  const T *__restrict__ ec, T *__restrict__ pf) {
   if (t >= gf.ncell) return;
   int f[3];
   cell_of(gf, t, f);
@@ -882,10 +934,177 @@ __global__ void k_cell_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec, T *
 }
 
 template <typename T>
+__global__ void k_cell_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec, T *__restrict__ pf) {
+  cell_prolong_elem<T>(gc, gf, (i64)blockIdx.x * blockDim.x + threadIdx.x, ec, pf);
+}
+
+template <typename T>
 void launch_cell_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *pf, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_prolong_add<T>, dim3(blocks_for(gf.ncell)), dim3(kBlock), 0, s, gc, gf,
                      ec, pf);
 }
+
+// ------------------------------------------------------------------------
+// Coarse tail of a V-cycle in one workgroup.  On the coarse levels every
+// kernel above is launch-latency bound (a few thousand unknowns each); one
+// 1024-thread workgroup runs all of them back to back, separated by block
+// barriers, with the same element functions (same arithmetic) and the same
+// order of operations as the host-sequenced cycle.  Mean removals use a
+// block reduction instead of the two-stage grid reduction.
+// ------------------------------------------------------------------------
+
+__device__ double tail_block_sum(double v) {
+  __shared__ double sh[kTailBlock / 64];
+  __shared__ double total;
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) r += sh[w];
+    total = r;
+  }
+  __syncthreads();
+  const double r = total;
+  __syncthreads();
+  return r;
+}
+
+// dst = src minus its mean over [0, n) (dst may alias src)
+template <typename T>
+__device__ void tail_sub_mean(const T *src, T *dst, i64 n) {
+  double acc = 0.0;
+  for (i64 t = threadIdx.x; t < n; t += blockDim.x) acc += (double)src[t];
+  const T mean = (T)(tail_block_sum(acc) / (double)n);
+  for (i64 t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t] - mean;
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void tail_copy(const T *src, T *dst, i64 n) {
+  for (i64 t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void tail_zero(T *dst, i64 n) {
+  for (i64 t = threadIdx.x; t < n; t += blockDim.x) dst[t] = (T)0;
+  __syncthreads();
+}
+
+template <typename T, int DIM>
+__device__ void tail_vel_smooth(const Geo &g, const T *alpha, const T *muc, const T *mue,
+                                const T *rhs, T *phi, int sweeps) {
+  const i64 nt = colour_threads(g);
+  for (int s = 0; s < sweeps; s++)
+    for (int k = 0; k < DIM; k++)
+      for (int colour = 0; colour < 2; colour++) {
+        for (i64 t = threadIdx.x; t < nt; t += blockDim.x)
+          vel_gs_elem<T, DIM>(g, k, colour, t, alpha, muc, mue, rhs, phi);
+        __syncthreads();
+      }
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kTailBlock) k_tail_vel(TailLevels<T> L) {
+  const int nl = L.nl;
+  for (int l = 0; l < nl - 1; l++) {
+    const Geo &g = L.g[l];
+    tail_zero<T>(L.phi[l], g.nvel);
+    tail_vel_smooth<T, DIM>(g, L.a[l], L.mc[l], L.me[l], L.rhs[l], L.phi[l], L.nu_pre);
+    for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x)
+      vel_residual_elem<T, DIM>(g, t, L.a[l], L.mc[l], L.me[l], L.rhs[l], L.phi[l],
+                                (const T *)nullptr, L.res[l]);
+    __syncthreads();
+    for (i64 t = threadIdx.x; t < L.g[l + 1].ncell; t += blockDim.x)
+      face_restrict_elem<T, DIM>(g, L.g[l + 1], t, L.res[l], L.rhs[l + 1]);
+    __syncthreads();
+  }
+  {
+    const int l = nl - 1;
+    const Geo &g = L.g[l];
+    tail_zero<T>(L.phi[l], g.nvel);
+    if (L.singular) {
+      for (int k = 0; k < g.d; k++)
+        tail_sub_mean<T>(L.rhs[l] + g.foff[k], L.res[l] + g.foff[k], g.fcnt[k]);
+    } else {
+      tail_copy<T>(L.rhs[l], L.res[l], g.nvel);
+    }
+    tail_vel_smooth<T, DIM>(g, L.a[l], L.mc[l], L.me[l], L.res[l], L.phi[l], L.nu_coarse);
+    if (L.singular)
+      for (int k = 0; k < g.d; k++)
+        tail_sub_mean<T>(L.phi[l] + g.foff[k], L.phi[l] + g.foff[k], g.fcnt[k]);
+  }
+  for (int l = nl - 2; l >= 0; l--) {
+    const Geo &g = L.g[l];
+    for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x)
+      face_prolong_elem<T, DIM>(L.g[l + 1], g, t, L.phi[l + 1], L.phi[l]);
+    __syncthreads();
+    tail_vel_smooth<T, DIM>(g, L.a[l], L.mc[l], L.me[l], L.rhs[l], L.phi[l], L.nu_post);
+  }
+}
+
+template <typename T, int DIM>
+__device__ void tail_p_smooth(const Geo &g, const T *beta, const T *rhs, T *phi, int sweeps) {
+  const i64 nt = colour_threads(g);
+  for (int s = 0; s < sweeps; s++)
+    for (int colour = 0; colour < 2; colour++) {
+      for (i64 t = threadIdx.x; t < nt; t += blockDim.x)
+        p_gs_elem<T, DIM>(g, colour, t, beta, rhs, phi);
+      __syncthreads();
+    }
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kTailBlock) k_tail_p(TailLevels<T> L) {
+  const int nl = L.nl;
+  for (int l = 0; l < nl - 1; l++) {
+    const Geo &g = L.g[l];
+    tail_zero<T>(L.phi[l], g.ncell);
+    tail_p_smooth<T, DIM>(g, L.b[l], L.rhs[l], L.phi[l], L.nu_pre);
+    for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x)
+      p_residual_elem<T, DIM>(g, t, L.b[l], L.rhs[l], L.phi[l], L.res[l]);
+    __syncthreads();
+    for (i64 t = threadIdx.x; t < L.g[l + 1].ncell; t += blockDim.x)
+      cell_restrict_elem<T>(g, L.g[l + 1], t, L.res[l], L.rhs[l + 1]);
+    __syncthreads();
+  }
+  {
+    const int l = nl - 1;
+    const Geo &g = L.g[l];
+    tail_zero<T>(L.phi[l], g.ncell);
+    tail_sub_mean<T>(L.rhs[l], L.res[l], g.ncell);
+    tail_p_smooth<T, DIM>(g, L.b[l], L.res[l], L.phi[l], L.nu_coarse);
+    tail_sub_mean<T>(L.phi[l], L.phi[l], g.ncell);
+  }
+  for (int l = nl - 2; l >= 0; l--) {
+    const Geo &g = L.g[l];
+    for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x)
+      cell_prolong_elem<T>(L.g[l + 1], g, t, L.phi[l + 1], L.phi[l]);
+    __syncthreads();
+    tail_p_smooth<T, DIM>(g, L.b[l], L.rhs[l], L.phi[l], L.nu_post);
+  }
+}
+
+template <typename T>
+void launch_tail_vel(const TailLevels<T> &L, hipStream_t s) {
+  if (L.g[0].d == 3)
+    hipLaunchKernelGGL((k_tail_vel<T, 3>), dim3(1), dim3(kTailBlock), 0, s, L);
+  else
+    hipLaunchKernelGGL((k_tail_vel<T, 2>), dim3(1), dim3(kTailBlock), 0, s, L);
+}
+template <typename T>
+void launch_tail_p(const TailLevels<T> &L, hipStream_t s) {
+  if (L.g[0].d == 3)
+    hipLaunchKernelGGL((k_tail_p<T, 3>), dim3(1), dim3(kTailBlock), 0, s, L);
+  else
+    hipLaunchKernelGGL((k_tail_p<T, 2>), dim3(1), dim3(kTailBlock), 0, s, L);
+}
+template void launch_tail_vel<float>(const TailLevels<float> &, hipStream_t);
+template void launch_tail_vel<double>(const TailLevels<double> &, hipStream_t);
+template void launch_tail_p<float>(const TailLevels<float> &, hipStream_t);
+template void launch_tail_p<double>(const TailLevels<double> &, hipStream_t);
 
 // ------------------------------------------------------------------------
 // preconditioner glue (Sec. 2: P1..P5 compositions)
@@ -1112,11 +1331,6 @@ struct PtrPack {
 constexpr int kArnBlock = 256;
 constexpr int kArnGrid = 2048;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // reduce over the block: acc[0..nv) go to partials[blockIdx.x*stride + i] and,
 // when with_extra, acc[MAXV] goes to slot nv (constant register indices only)
