@@ -125,7 +125,10 @@ typedef struct stokes_ctx stokes_ctx;
    exactly until its smallest axis has two cells (Appendix C: coarsening by 2
    down to two cells): the smallest n is a power of two >= 2, every n is
    divisible by min(n)/2, and a periodic axis keeps an even cell count on the
-   coarsest level (n divisible by min(n)), which the red-black colouring needs. */
+   coarsest level (n divisible by min(n)), which the red-black colouring needs.
+   The kernels index face, cell and edge storage with 32-bit integers, so
+   3 * prod(n + 1) must stay below 2^31 (about 890^3 cells; a grid that size
+   would not fit one GPU's memory with a Krylov basis anyway). */
 int stokes_sizes(const stokes_params *p, size_t *nvel, size_t *ncell, size_t *nedge,
                  int *nlevels);
 

@@ -75,9 +75,10 @@ bool valid_params(const stokes_params *p, int *nlev_out) {
     // on every level, the coarsest included
     if (p->bc[a] == STOKES_PERIODIC && ((p->n[a] >> (nlev - 1)) & 1)) return false;
   }
-  long long cells = 1;
-  for (int a = 0; a < p->dim; a++) cells *= p->n[a];
-  if (cells > (1LL << 31)) return false;
+  // the kernels index face, cell and edge storage with 32-bit integers
+  long long nodes = 1;
+  for (int a = 0; a < p->dim; a++) nodes *= (long long)p->n[a] + 1;
+  if (3 * nodes > 0x7fffffffLL) return false;
   if (nlev_out) *nlev_out = nlev;
   return true;
 }

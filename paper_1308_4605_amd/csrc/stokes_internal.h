@@ -21,7 +21,7 @@ struct Geo {
   int d;
   int n[3];
   int ns[3];
-  double h;
+  double h, ih;  // spacing and its reciprocal
   i64 ncell, nvel, nedge;
   i64 foff[3];
   int fd[3][3];
@@ -29,6 +29,7 @@ struct Geo {
   i64 eoff[3];
   int ed[3][3];
   i64 ecnt[3];
+  int xcd;  // stencil kernels: one band of rows per XCD
 };
 
 Geo make_geo(int d, const int n[3], const int ns[3], double h);

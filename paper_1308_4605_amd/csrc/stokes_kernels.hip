@@ -23,16 +23,23 @@ static inline unsigned blocks_for(i64 n) {
   i64 b = (n + kBlock - 1) / kBlock;
   return (unsigned)(b < 1 ? 1 : b);
 }
+static inline dim3 box_blocks(const Geo &g, int W) {
+  if (g.xcd && (g.n[1] & 7) == 0)
+    return dim3(8u * blocks_for((i64)(g.n[1] >> 3) * W), (unsigned)g.n[2]);
+  return dim3(blocks_for((i64)g.n[1] * W), (unsigned)g.n[2]);
+}
 
 Geo make_geo(int d, const int n[3], const int ns[3], double h) {
   Geo g;
   g.d = d;
   g.h = h;
+  g.ih = 1.0 / h;
   for (int a = 0; a < 3; a++) {
     g.n[a] = (a < d) ? n[a] : 1;
     g.ns[a] = (a < d) ? ns[a] : 0;
   }
   g.ncell = (i64)g.n[0] * g.n[1] * g.n[2];
+  g.xcd = 1;
   i64 off = 0;
   for (int k = 0; k < 3; k++) {
     for (int a = 0; a < 3; a++) g.fd[k][a] = g.n[a] + ((a == k && k < d) ? g.ns[a] : 0);
@@ -67,23 +74,26 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ i64 fidx(const Geo &g, int k, int i0, int i1, int i2) {
-  return g.foff[k] + ((i64)i2 * g.fd[k][1] + i1) * g.fd[k][0] + i0;
+// Index arithmetic is 32-bit: stokes_create rejects grids whose face, cell
+// or edge storage exceeds 2^31 - 1 entries.
+__device__ __forceinline__ int fidx(const Geo &g, int k, int i0, int i1, int i2) {
+  return (int)g.foff[k] + (i2 * g.fd[k][1] + i1) * g.fd[k][0] + i0;
 }
-__device__ __forceinline__ i64 fidx3(const Geo &g, int k, const int i[3]) {
+__device__ __forceinline__ int fidx3(const Geo &g, int k, const int i[3]) {
   return fidx(g, k, i[0], i[1], i[2]);
 }
-__device__ __forceinline__ i64 cidx3(const Geo &g, const int i[3]) {
-  return ((i64)i[2] * g.n[1] + i[1]) * g.n[0] + i[0];
+__device__ __forceinline__ int cidx3(const Geo &g, const int i[3]) {
+  return (i[2] * g.n[1] + i[1]) * g.n[0] + i[0];
 }
-__device__ __forceinline__ i64 eidx3(const Geo &g, int m, const int i[3]) {
-  return g.eoff[m] + ((i64)i[2] * g.ed[m][1] + i[1]) * g.ed[m][0] + i[0];
+__device__ __forceinline__ int eidx3(const Geo &g, int m, const int i[3]) {
+  return (int)g.eoff[m] + (i[2] * g.ed[m][1] + i[1]) * g.ed[m][0] + i[0];
 }
 __device__ __forceinline__ void cell_of(const Geo &g, i64 t, int i[3]) {
-  i64 q = t / g.n[0];
-  i[0] = (int)(t - q * g.n[0]);
-  i[2] = (int)(q / g.n[1]);
-  i[1] = (int)(q - (i64)i[2] * g.n[1]);
+  const unsigned u = (unsigned)t;
+  const unsigned q = u / (unsigned)g.n[0];
+  i[0] = (int)(u - q * (unsigned)g.n[0]);
+  i[2] = (int)(q / (unsigned)g.n[1]);
+  i[1] = (int)(q - (unsigned)i[2] * (unsigned)g.n[1]);
 }
 // +1 / -1 neighbour along a periodic axis (index stays in range otherwise)
 __device__ __forceinline__ int up1(const Geo &g, int a, int i) {
@@ -93,6 +103,31 @@ __device__ __forceinline__ int up1(const Geo &g, int a, int i) {
 __device__ __forceinline__ int dn1(const Geo &g, int a, int i) {
   int j = i - 1;
   return (j < 0) ? j + g.n[a] : j;
+}
+
+// Thread -> (w, y, z) over an index box of n2 planes x n1 rows x W, on a
+// grid of box_blocks() = (gx, n2) workgroups with z = blockIdx.y.  With
+// g.xcd set and n1 % 8 == 0, workgroup x-index b takes band b % 8 of n1/8
+// rows of its plane.  The hardware deals workgroups to the 8 XCDs in turn
+// (gx is a multiple of 8), so each XCD streams its own band plane by plane
+// and the y and z neighbours a stencil reads were fetched into that XCD's
+// L2 shortly before.
+__device__ __forceinline__ bool box_thread(const Geo &g, int W, int &w, int &y, int &z) {
+  z = (int)blockIdx.y;
+  unsigned u, y0 = 0;
+  if (g.xcd && (g.n[1] & 7) == 0) {
+    const unsigned band = (unsigned)g.n[1] >> 3;
+    u = (blockIdx.x >> 3) * blockDim.x + threadIdx.x;
+    if (u >= band * (unsigned)W) return false;
+    y0 = (blockIdx.x & 7u) * band;
+  } else {
+    u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= (unsigned)g.n[1] * (unsigned)W) return false;
+  }
+  const unsigned r = u / (unsigned)W;
+  y = (int)(y0 + r);
+  w = (int)(u - r * (unsigned)W);
+  return true;
 }
 
 // ------------------------------------------------------------------------
@@ -109,8 +144,8 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
                                          const T *const *comp, const T *__restrict__ alpha,
                                          const T *__restrict__ muc, const T *__restrict__ mue,
                                          T &Au, T &diag) {
-  const T h = (T)g.h;
-  const T h2 = h * h;
+  const T ih = (T)g.ih;
+  const T ih2 = ih * ih;
   const i64 fq = fidx3(g, k, i);
   int t[3] = {i[0], i[1], i[2]};
   const int km = dn1(g, k, i[k]);
@@ -118,11 +153,11 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
   const T mr = muc[cidx3(g, i)];
   const T ml = muc[cidx3(g, t)];
   t[k] = i[k];
-  const T tr = (T)2 * mr * ((ukp - uf) / h);
-  const T tl = (T)2 * ml * ((uf - ukm) / h);
-  T s = (tr - tl) / h;
+  const T tr = (T)2 * mr * ((ukp - uf) * ih);
+  const T tl = (T)2 * ml * ((uf - ukm) * ih);
+  T s = (tr - tl) * ih;
   const T al = alpha[fq];
-  T dg = al + (T)2 * (mr + ml) / h2;
+  T dg = al + (T)2 * (mr + ml) * ih2;
 #pragma unroll
   for (int l = 0; l < DIM; l++) {
     if (l == k) continue;
@@ -135,20 +170,20 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
     t[l] = lp;
     const T mhi = mue[eidx3(g, m, t)];
     // u_l on the two faces beside the upper edge (cells i[k] and i[k]-1 along k)
-    const T ulh_r = ul[((i64)t[2] * f1 + t[1]) * f0 + t[0]];
+    const T ulh_r = ul[(t[2] * f1 + t[1]) * f0 + t[0]];
     t[k] = km;
-    const T ulh_l = ul[((i64)t[2] * f1 + t[1]) * f0 + t[0]];
+    const T ulh_l = ul[(t[2] * f1 + t[1]) * f0 + t[0]];
     t[k] = i[k];
     t[l] = i[l];
     const T mlo = mue[eidx3(g, m, t)];
-    const T ull_r = ul[((i64)t[2] * f1 + t[1]) * f0 + t[0]];
+    const T ull_r = ul[(t[2] * f1 + t[1]) * f0 + t[0]];
     t[k] = km;
-    const T ull_l = ul[((i64)t[2] * f1 + t[1]) * f0 + t[0]];
+    const T ull_l = ul[(t[2] * f1 + t[1]) * f0 + t[0]];
     t[k] = i[k];
-    const T ghi = (ua[l] - uf) / h + (ulh_r - ulh_l) / h;
-    const T glo = (uf - ub[l]) / h + (ull_r - ull_l) / h;
-    s += (mhi * ghi - mlo * glo) / h;
-    dg += ((top ? (T)2 : (T)1) * mhi + (bot ? (T)2 : (T)1) * mlo) / h2;
+    const T ghi = (ua[l] - uf) * ih + (ulh_r - ulh_l) * ih;
+    const T glo = (uf - ub[l]) * ih + (ull_r - ull_l) * ih;
+    s += (mhi * ghi - mlo * glo) * ih;
+    dg += ((top ? (T)2 : (T)1) * mhi + (bot ? (T)2 : (T)1) * mlo) * ih2;
   }
   Au = al * uf - s;
   diag = dg;
@@ -450,7 +485,7 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
                                             const double *__restrict__ alpha,
                                             const double *__restrict__ muc,
                                             const double *__restrict__ mue, double &Au) {
-  const double h = g.h;
+  const double ih = g.ih;
   const i64 fq = fidx3(g, k, i);
   const double uf = (double)u[fq];
   int t[3] = {i[0], i[1], i[2]};
@@ -463,9 +498,9 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
   const double mr = muc[cidx3(g, i)];
   const double ml = muc[cidx3(g, t)];
   t[k] = i[k];
-  const double tr = 2.0 * mr * ((ukp - uf) / h);
-  const double tl = 2.0 * ml * ((uf - ukm) / h);
-  double s = (tr - tl) / h;
+  const double tr = 2.0 * mr * ((ukp - uf) * ih);
+  const double tl = 2.0 * ml * ((uf - ukm) * ih);
+  double s = (tr - tl) * ih;
 #pragma unroll
   for (int l = 0; l < DIM; l++) {
     if (l == k) continue;
@@ -490,9 +525,9 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
     t[k] = km;
     const double ull_l = (double)u[fidx3(g, l, t)];
     t[k] = i[k];
-    const double ghi = (ua - uf) / h + (ulh_r - ulh_l) / h;
-    const double glo = (uf - ub) / h + (ull_r - ull_l) / h;
-    s += (mhi * ghi - mlo * glo) / h;
+    const double ghi = (ua - uf) * ih + (ulh_r - ulh_l) * ih;
+    const double glo = (uf - ub) * ih + (ull_r - ull_l) * ih;
+    s += (mhi * ghi - mlo * glo) * ih;
   }
   Au = alpha[fq] * uf - s;
 }
@@ -503,11 +538,10 @@ __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double 
                           const TI *__restrict__ xp, const double *__restrict__ bu,
                           const double *__restrict__ bp, double *__restrict__ yu,
                           double *__restrict__ yp) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.ncell) return;
   int i[3];
-  cell_of(g, t, i);
-  const double h = g.h;
+  if (!box_thread(g, g.n[0], i[0], i[1], i[2])) return;
+  const i64 t = cidx3(g, i);
+  const double ih = g.ih;
   const double pc = (double)xp[t];
   double div = 0.0;
 #pragma unroll
@@ -515,7 +549,7 @@ __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double 
     int r[3] = {i[0], i[1], i[2]};
     r[k] = i[k] + 1;
     if (!g.ns[k] && r[k] == g.n[k]) r[k] = 0;
-    div += ((double)xu[fidx3(g, k, r)] - (double)xu[fidx3(g, k, i)]) / h;
+    div += ((double)xu[fidx3(g, k, r)] - (double)xu[fidx3(g, k, i)]) * ih;
     const i64 q = fidx3(g, k, i);
     if (low_wall(g, k, i)) {
       continue;
@@ -524,7 +558,7 @@ __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double 
     a_row_mixed<TI, DIM>(g, k, i, xu, alpha, muc, mue, Au);
     int l[3] = {i[0], i[1], i[2]};
     l[k] = dn1(g, k, i[k]);
-    const double gp = (pc - (double)xp[cidx3(g, l)]) / h;
+    const double gp = (pc - (double)xp[cidx3(g, l)]) * ih;
     const double y = Au + gp;
     yu[q] = bu ? bu[q] - y : y;
   }
@@ -536,10 +570,10 @@ void launch_apply_m(const Geo &g, const double *alpha, const double *muc, const 
                     const TI *xu, const TI *xp, const double *bu, const double *bp, double *yu,
                     double *yp, hipStream_t s) {
   if (g.d == 3)
-    hipLaunchKernelGGL((k_apply_m<TI, 3>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g,
+    hipLaunchKernelGGL((k_apply_m<TI, 3>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
                        alpha, muc, mue, xu, xp, bu, bp, yu, yp);
   else
-    hipLaunchKernelGGL((k_apply_m<TI, 2>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g,
+    hipLaunchKernelGGL((k_apply_m<TI, 2>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
                        alpha, muc, mue, xu, xp, bu, bp, yu, yp);
 }
 template void launch_apply_m<double>(const Geo &, const double *, const double *, const double *,
@@ -561,18 +595,32 @@ template void launch_apply_m<float>(const Geo &, const double *, const double *,
 // with tx < ceil(n0/2); i0 = 2 tx + parity (odd n0 occurs only on no-slip x
 // axes at the coarsest level; periodic axes are even on every level)
 __device__ __forceinline__ bool colour_cell(const Geo &g, i64 t, int colour, int i[3]) {
-  const int hx = (g.n[0] + 1) >> 1;
+  const unsigned hx = (unsigned)(g.n[0] + 1) >> 1;
   const i64 rows = (i64)g.n[1] * g.n[2];
   if (t >= (i64)hx * rows) return false;
-  i64 q = t / hx;
-  const int tx = (int)(t - q * hx);
-  i[2] = (int)(q / g.n[1]);
-  i[1] = (int)(q - (i64)i[2] * g.n[1]);
+  const unsigned u = (unsigned)t;
+  const unsigned q = u / hx;
+  const int tx = (int)(u - q * hx);
+  i[2] = (int)(q / (unsigned)g.n[1]);
+  i[1] = (int)(q - (unsigned)i[2] * (unsigned)g.n[1]);
   i[0] = 2 * tx + ((i[1] + i[2] + colour) & 1);
   return i[0] < g.n[0];
 }
 __host__ __device__ __forceinline__ i64 colour_threads(const Geo &g) {
   return (i64)((g.n[0] + 1) >> 1) * g.n[1] * g.n[2];
+}
+
+// Gauss-Seidel update of one velocity face (component k, cell index i)
+template <typename T, int DIM>
+__device__ __forceinline__ void gs_point(const Geo &g, int k, const int i[3],
+                                         const T *__restrict__ alpha, const T *__restrict__ muc,
+                                         const T *__restrict__ mue, const T *__restrict__ rhs,
+                                         T *__restrict__ phi) {
+  if (low_wall(g, k, i)) return;
+  T Au, dg;
+  a_row<T, DIM>(g, k, i, phi, alpha, muc, mue, Au, dg);
+  const i64 fq = fidx3(g, k, i);
+  phi[fq] += (rhs[fq] - Au) / dg;
 }
 
 // one face of one colour of the velocity Gauss-Seidel sweep
@@ -583,27 +631,25 @@ __device__ __forceinline__ void vel_gs_elem(const Geo &g, int k, int colour, i64
                                             T *__restrict__ phi) {
   int i[3];
   if (!colour_cell(g, t, colour, i)) return;
-  if (low_wall(g, k, i)) return;
-  T Au, dg;
-  a_row<T, DIM>(g, k, i, phi, alpha, muc, mue, Au, dg);
-  const i64 fq = fidx3(g, k, i);
-  phi[fq] += (rhs[fq] - Au) / dg;
+  gs_point<T, DIM>(g, k, i, alpha, muc, mue, rhs, phi);
 }
 
 template <typename T, int DIM, int K>
 __global__ void k_vel_gs(Geo g, int colour, const T *__restrict__ alpha,
                          const T *__restrict__ muc, const T *__restrict__ mue,
                          const T *__restrict__ rhs, T *__restrict__ phi) {
-  vel_gs_elem<T, DIM>(g, K, colour, (i64)blockIdx.x * blockDim.x + threadIdx.x, alpha, muc, mue,
-                      rhs, phi);
+  int tx, i[3];
+  if (!box_thread(g, (g.n[0] + 1) >> 1, tx, i[1], i[2])) return;
+  i[0] = 2 * tx + ((i[1] + i[2] + colour) & 1);
+  if (i[0] < g.n[0]) gs_point<T, DIM>(g, K, i, alpha, muc, mue, rhs, phi);
 }
 
 template <typename T>
 void launch_vel_gs(const Geo &g, int k, int colour, const T *alpha, const T *muc, const T *mue,
                    const T *rhs, T *phi, hipStream_t s) {
-  const unsigned nb = blocks_for(colour_threads(g));
+  const dim3 nb = box_blocks(g, (g.n[0] + 1) >> 1);
 #define GS_CASE(D, KK)                                                                       \
-  hipLaunchKernelGGL((k_vel_gs<T, D, KK>), dim3(nb), dim3(kBlock), 0, s, g, colour, alpha, muc, \
+  hipLaunchKernelGGL((k_vel_gs<T, D, KK>), nb, dim3(kBlock), 0, s, g, colour, alpha, muc, \
                      mue, rhs, phi)
   if (g.d == 3) {
     if (k == 0) GS_CASE(3, 0);
@@ -618,15 +664,13 @@ void launch_vel_gs(const Geo &g, int k, int colour, const T *alpha, const T *muc
 
 // res = rhs - A phi - G p (p may be null); cell-indexed over all components
 template <typename T, int DIM>
-__device__ __forceinline__ void vel_residual_elem(const Geo &g, i64 t, const T *__restrict__ alpha,
-                                                  const T *__restrict__ muc,
-                                                  const T *__restrict__ mue,
-                                                  const T *__restrict__ rhs,
-                                                  const T *__restrict__ phi,
-                                                  const T *__restrict__ p, T *__restrict__ res) {
-  if (t >= g.ncell) return;
-  int i[3];
-  cell_of(g, t, i);
+__device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i64 t,
+                                                const T *__restrict__ alpha,
+                                                const T *__restrict__ muc,
+                                                const T *__restrict__ mue,
+                                                const T *__restrict__ rhs,
+                                                const T *__restrict__ phi,
+                                                const T *__restrict__ p, T *__restrict__ res) {
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
     if (low_wall(g, k, i)) continue;
@@ -637,10 +681,23 @@ __device__ __forceinline__ void vel_residual_elem(const Geo &g, i64 t, const T *
     if (p) {
       int l[3] = {i[0], i[1], i[2]};
       l[k] = dn1(g, k, i[k]);
-      r -= (p[t] - p[cidx3(g, l)]) / (T)g.h;
+      r -= (p[t] - p[cidx3(g, l)]) * (T)g.ih;
     }
     res[fq] = r;
   }
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void vel_residual_elem(const Geo &g, i64 t, const T *__restrict__ alpha,
+                                                  const T *__restrict__ muc,
+                                                  const T *__restrict__ mue,
+                                                  const T *__restrict__ rhs,
+                                                  const T *__restrict__ phi,
+                                                  const T *__restrict__ p, T *__restrict__ res) {
+  if (t >= g.ncell) return;
+  int i[3];
+  cell_of(g, t, i);
+  vel_residual_at<T, DIM>(g, i, t, alpha, muc, mue, rhs, phi, p, res);
 }
 
 template <typename T, int DIM>
@@ -648,18 +705,19 @@ __global__ void k_vel_residual(Geo g, const T *__restrict__ alpha, const T *__re
                                const T *__restrict__ mue, const T *__restrict__ rhs,
                                const T *__restrict__ phi, const T *__restrict__ p,
                                T *__restrict__ res) {
-  vel_residual_elem<T, DIM>(g, (i64)blockIdx.x * blockDim.x + threadIdx.x, alpha, muc, mue, rhs,
-                            phi, p, res);
+  int i[3];
+  if (!box_thread(g, g.n[0], i[0], i[1], i[2])) return;
+  vel_residual_at<T, DIM>(g, i, cidx3(g, i), alpha, muc, mue, rhs, phi, p, res);
 }
 
 template <typename T>
 void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mue, const T *rhs,
                          const T *phi, const T *p, T *res, hipStream_t s) {
   if (g.d == 3)
-    hipLaunchKernelGGL((k_vel_residual<T, 3>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g,
+    hipLaunchKernelGGL((k_vel_residual<T, 3>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
                        alpha, muc, mue, rhs, phi, p, res);
   else
-    hipLaunchKernelGGL((k_vel_residual<T, 2>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g,
+    hipLaunchKernelGGL((k_vel_residual<T, 2>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
                        alpha, muc, mue, rhs, phi, p, res);
 }
 
@@ -811,7 +869,7 @@ void launch_face_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *phif,
 template <typename T, int DIM>
 __device__ __forceinline__ void p_row(const Geo &g, const int i[3], const T *__restrict__ beta,
                                       const T *__restrict__ p, T &Lp, T &diag) {
-  const T h = (T)g.h;
+  const T ih = (T)g.ih;
   const T pc = p[cidx3(g, i)];
   T s = 0, dg = 0;
 #pragma unroll
@@ -824,19 +882,19 @@ __device__ __forceinline__ void p_row(const Geo &g, const int i[3], const T *__r
     if (!wr) {
       r[k] = up1(g, k, i[k]);
       const T b = beta[fidx3(g, k, r)];
-      fr = b * ((p[cidx3(g, r)] - pc) / h);
+      fr = b * ((p[cidx3(g, r)] - pc) * ih);
       dg -= b;
     }
     if (!wl) {
       r[k] = dn1(g, k, i[k]);
       const T b = beta[fidx3(g, k, i)];
-      fl = b * ((pc - p[cidx3(g, r)]) / h);
+      fl = b * ((pc - p[cidx3(g, r)]) * ih);
       dg -= b;
     }
-    s += (fr - fl) / h;
+    s += (fr - fl) * ih;
   }
   Lp = s;
-  diag = dg / (h * h);
+  diag = dg * (ih * ih);
 }
 
 template <typename T, int DIM>

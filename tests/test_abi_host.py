@@ -55,7 +55,7 @@ def test_sizes_match_layout(S, dim, n, bc):
     dict(dim=4), dict(n=(12, 12)), dict(n=(32, 24)), dict(h=0.0), dict(theta=-1.0),
     dict(precond=6), dict(precision=1, krylov=0), dict(restart=0), dict(restart=33),
     dict(nu_coarse=0), dict(vcycles=0), dict(edge_avg=3), dict(bc=(2, 0)),
-    dict(n=(96, 64))])
+    dict(n=(96, 64)), dict(dim=3, n=(1024, 1024, 1024), bc=(0, 0, 0))])
 def test_invalid_parameters_rejected_on_host(S, bad):
     base = dict(dim=2, n=(32, 32), bc=(0, 0), h=1 / 32, theta=1.0)
     base.update(bad)
