@@ -488,11 +488,12 @@ void precond(stokes_ctx *X, const T *bu, const T *bp, T *zu, T *zp) {
 }
 
 // z (precision of the hierarchy, [u|p]) = P^{-1} v with v FP64 [u|p]
-void precond_from64(stokes_ctx *X, const double *v, void *z) {
+// have32: the FP32 copy of v is already in X->pin (written by the Arnoldi pass)
+void precond_from64(stokes_ctx *X, const double *v, void *z, bool have32 = false) {
   const i64 nv = X->nvel;
   if (X->mg32) {
     float *pin = P<float>(X->pin);
-    launch_cast<float, double>(v, pin, X->n, X->s);
+    if (!have32) launch_cast<float, double>(v, pin, X->n, X->s);
     precond<float>(X, pin, pin + nv, P<float>(z), P<float>(z) + nv);
   } else {
     precond<double>(X, v, v + nv, P<double>(z), P<double>(z) + nv);
@@ -567,7 +568,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     int jj = 0;
     for (int j = 0; j < m; j++) {
       if (flexible) {
-        precond_from64(X, X->V[j], X->Z[j]);
+        precond_from64(X, X->V[j], X->Z[j], j > 0);
         if (X->mg32)
           launch_apply_m<float>(X->lev[0].g, X->m_alpha, X->m_muc, X->m_mue, P<float>(X->Z[j]),
                                 P<float>(X->Z[j]) + nv, nullptr, nullptr, X->w, X->w + nv, X->s);
@@ -579,9 +580,9 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       }
       st->precond_applies++;
       it++;
-      // CGS2: pass A (h1 = V^T w), pass B (w -= V h1; h2 = V^T w; s2 = (w,w))
+      // CGS2: pass A (h1 = V^T w), pass B (w' = w - V h1; h2 = V^T w'; s2 = (w',w'))
       launch_cgs_dots(X->w, X->V, j + 1, n, X->part, X->dsc + 32, X->s);
-      launch_cgs_update(X->w, X->V, X->dsc + 32, j + 1, n, X->part, X->dsc + 72, X->s);
+      launch_cgs_proj(X->w, X->V, X->dsc + 32, j + 1, n, X->part, X->dsc + 72, X->s);
       hip_ok(X, hipMemcpyAsync(hb + 32, X->dsc + 32, (j + 1) * sizeof(double),
                                hipMemcpyDeviceToHost, X->s));
       hip_ok(X, hipMemcpyAsync(hb + 72, X->dsc + 72, (j + 2) * sizeof(double),
@@ -603,7 +604,8 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       if (nu2 > 0.5 * s2) {
         hn = std::sqrt(nu2);
       } else {
-        launch_cgs_next(X->w, X->V, X->dsc + 72, j + 1, 1.0, n, X->w, X->part, X->dsc + 0, X->s);
+        launch_cgs_next(X->w, X->V, X->dsc + 32, X->dsc + 72, j + 1, 1.0, n, X->w, nullptr,
+                        X->part, X->dsc + 0, X->s);
         hn = std::sqrt(fetch(X, X->dsc, 1, hb));
         formed = true;
       }
@@ -630,9 +632,11 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       st->rel_res_est = est / beta * (rho / nb);
       if (!std::isfinite(est)) break;
       if (hn == 0.0 || est <= target || it >= max_iter) break;
-      // pass C: v_{j+1} = (w - V h2) / nu
-      launch_cgs_next(X->w, X->V, X->dsc + 72, formed ? 0 : j + 1, 1.0 / hn, n, X->V[j + 1],
-                      X->part, nullptr, X->s);
+      // pass C: v_{j+1} = (w - V (h1 + h2)) / nu, plus the FP32 copy the next
+      // flexible preconditioner application starts from
+      launch_cgs_next(X->w, X->V, X->dsc + 32, X->dsc + 72, formed ? 0 : j + 1, 1.0 / hn, n,
+                      X->V[j + 1], (flexible && X->mg32) ? P<float>(X->pin) : nullptr, X->part,
+                      nullptr, X->s);
     }
     for (int i = jj - 1; i >= 0; i--) {
       double s = g[i];

@@ -135,14 +135,16 @@ constexpr int kRedBlocks = 2048;
 //   h[i] = (w, v_i), i < nv
 void launch_cgs_dots(const double *w, const double *const *v, int nv, i64 n, double *partials,
                      double *h, hipStream_t s);
-//   w -= sum_i h_i v_i; h2s2[i] = (w, v_i) for i < nv, h2s2[nv] = (w, w)
-void launch_cgs_update(double *w, const double *const *v, const double *h, int nv, i64 n,
-                       double *partials, double *h2s2, hipStream_t s);
-//   out = (w - sum_i h2_i v_i) * inv_nu (nv = 0: plain scale); nrm2 = (out, out)
-//   when nrm2 != nullptr.  out may alias w.
-void launch_cgs_next(const double *w, const double *const *v, const double *h2, int nv,
-                     double inv_nu, i64 n, double *out, double *partials, double *nrm2,
-                     hipStream_t s);
+//   w' = w - sum_i h_i v_i (not stored); h2s2[i] = (w', v_i) for i < nv,
+//   h2s2[nv] = (w', w')
+void launch_cgs_proj(const double *w, const double *const *v, const double *h, int nv, i64 n,
+                     double *partials, double *h2s2, hipStream_t s);
+//   out = (w - sum_i (h1_i + h2_i) v_i) * inv_nu (nv = 0: plain scale), also
+//   cast to out32 when out32 != nullptr; nrm2 = (out, out) when nrm2 !=
+//   nullptr.  out may alias w.
+void launch_cgs_next(const double *w, const double *const *v, const double *h1, const double *h2,
+                     int nv, double inv_nu, i64 n, double *out, float *out32, double *partials,
+                     double *nrm2, hipStream_t s);
 // x += sum_i y_i z_i with z in precision TZ (y: host array, passed by value)
 template <typename TZ>
 void launch_update_x(double *x, const TZ *const *z, const double *y, int nz, i64 n,

@@ -1180,7 +1180,7 @@ __global__ void k_div(Geo g, const T *__restrict__ u, const T *__restrict__ bp, 
   for (int k = 0; k < DIM; k++) {
     int r[3] = {i[0], i[1], i[2]};
     r[k] = up1(g, k, i[k]);
-    s += (u[fidx3(g, k, r)] - u[fidx3(g, k, i)]) / (T)g.h;
+    s += (u[fidx3(g, k, r)] - u[fidx3(g, k, i)]) * (T)g.ih;
   }
   if (bp) s += bp[t];
   out[t] = sgn * s;
@@ -1212,7 +1212,7 @@ __global__ void k_grad_combine(Geo g, int mode, const T *__restrict__ base,
     int l[3] = {i[0], i[1], i[2]};
     l[k] = dn1(g, k, i[k]);
     const i64 fq = fidx3(g, k, i);
-    const T gq = (qc - q[cidx3(g, l)]) / (T)g.h;
+    const T gq = (qc - q[cidx3(g, l)]) * (T)g.ih;
     out[fq] = (mode == 0) ? base[fq] + beta[fq] * gq : base[fq] - gq;
   }
 }
@@ -1383,8 +1383,9 @@ struct PtrPack {
 // Three streaming passes over [w, v_0..v_j] with double2 loads, a fixed grid
 // and per-block partial sums (bitwise reproducible):
 //   A: h1 = V^T w
-//   B: w <- w - V h1, and h2 = V^T w, s2 = (w, w) in the same pass
-//   C: v_next = (w - V h2) * inv_nu   (or a plain scale when w is final)
+//   B: w' = w - V h1 formed on the fly (not stored): h2 = V^T w', s2 = (w', w')
+//   C: v_next = (w - V (h1 + h2)) * inv_nu, optionally also as FP32 (the
+//      next flexible preconditioner input), or a plain scale when w is final
 
 constexpr int kArnBlock = 256;
 constexpr int kArnGrid = 2048;
@@ -1441,10 +1442,10 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_dots(const double *__restrict
 }
 
 template <int MAXV>
-__global__ void __launch_bounds__(kArnBlock) k_cgs_update(double *__restrict__ w, PtrPack v,
-                                                          const double *__restrict__ h, int nv,
-                                                          i64 n, int stride,
-                                                          double *__restrict__ partials) {
+__global__ void __launch_bounds__(kArnBlock) k_cgs_proj(const double *__restrict__ w, PtrPack v,
+                                                        const double *__restrict__ h, int nv,
+                                                        i64 n, int stride,
+                                                        double *__restrict__ partials) {
   double acc[MAXV + 1];
   double hh[MAXV];
 #pragma unroll
@@ -1452,7 +1453,7 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_update(double *__restrict__ w
 #pragma unroll
   for (int i = 0; i < MAXV; i++) hh[i] = (i < nv) ? h[i] : 0.0;
   const i64 n2 = n >> 1;
-  double2 *__restrict__ w2 = (double2 *)w;
+  const double2 *__restrict__ w2 = (const double2 *)w;
   for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n2; t += (i64)gridDim.x * blockDim.x) {
     double2 a = w2[t];
     double2 b[MAXV];
@@ -1464,7 +1465,6 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_update(double *__restrict__ w
         a.y -= hh[i] * b[i].y;
       }
     }
-    w2[t] = a;
 #pragma unroll
     for (int i = 0; i < MAXV; i++)
       if (i < nv) acc[i] += a.x * b[i].x + a.y * b[i].y;
@@ -1473,29 +1473,31 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_update(double *__restrict__ w
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
     double a = w[n - 1];
     for (int i = 0; i < nv; i++) a -= hh[i] * ((const double *)v.p[i])[n - 1];
-    w[n - 1] = a;
     for (int i = 0; i < nv; i++) acc[i] += a * ((const double *)v.p[i])[n - 1];
     acc[MAXV] += a * a;
   }
-  // slot nv receives (w, w)
+  // slot nv receives (w', w')
   block_store<MAXV>(acc, nv, true, stride, partials);
 }
 
 template <int MAXV>
 __global__ void __launch_bounds__(kArnBlock) k_cgs_next(const double *__restrict__ w, PtrPack v,
+                                                        const double *__restrict__ h1,
                                                         const double *__restrict__ h2, int nv,
                                                         double inv_nu, i64 n,
                                                         double *__restrict__ out,
+                                                        float *__restrict__ out32,
                                                         double *__restrict__ partials) {
   double hh[MAXV];
 #pragma unroll
-  for (int i = 0; i < MAXV; i++) hh[i] = (i < nv) ? h2[i] : 0.0;
+  for (int i = 0; i < MAXV; i++) hh[i] = (i < nv) ? h1[i] + h2[i] : 0.0;
   double acc[MAXV + 1];
 #pragma unroll
   for (int i = 0; i <= MAXV; i++) acc[i] = 0.0;
   const i64 n2 = n >> 1;
   const double2 *__restrict__ w2 = (const double2 *)w;
   double2 *__restrict__ o2 = (double2 *)out;
+  float2 *__restrict__ f2 = (float2 *)out32;
   for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n2; t += (i64)gridDim.x * blockDim.x) {
     double2 a = w2[t];
 #pragma unroll
@@ -1509,6 +1511,7 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_next(const double *__restrict
     a.x *= inv_nu;
     a.y *= inv_nu;
     o2[t] = a;
+    if (out32) f2[t] = make_float2((float)a.x, (float)a.y);
     acc[MAXV] += a.x * a.x + a.y * a.y;
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1516,6 +1519,7 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_next(const double *__restrict
     for (int i = 0; i < nv; i++) a -= hh[i] * ((const double *)v.p[i])[n - 1];
     a *= inv_nu;
     out[n - 1] = a;
+    if (out32) out32[n - 1] = (float)a;
     acc[MAXV] += a * a;
   }
   if (partials) block_store<MAXV>(acc, 0, true, 1, partials);
@@ -1544,22 +1548,23 @@ void launch_cgs_dots(const double *w, const double *const *v, int nv, i64 n, dou
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, nv, nv, h);
 }
 
-void launch_cgs_update(double *w, const double *const *v, const double *h, int nv, i64 n,
-                       double *partials, double *h2s2, hipStream_t s) {
+void launch_cgs_proj(const double *w, const double *const *v, const double *h, int nv, i64 n,
+                     double *partials, double *h2s2, hipStream_t s) {
   PtrPack pk;
   for (int j = 0; j < nv; j++) pk.p[j] = v[j];
   const int nb = arn_blocks(n);
-  ARN_DISPATCH(k_cgs_update, nv, w, pk, h, nv, n, nv + 1, partials);
+  ARN_DISPATCH(k_cgs_proj, nv, w, pk, h, nv, n, nv + 1, partials);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, nv + 1, nv + 1, h2s2);
 }
 
-void launch_cgs_next(const double *w, const double *const *v, const double *h2, int nv,
-                     double inv_nu, i64 n, double *out, double *partials, double *nrm2,
-                     hipStream_t s) {
+void launch_cgs_next(const double *w, const double *const *v, const double *h1, const double *h2,
+                     int nv, double inv_nu, i64 n, double *out, float *out32, double *partials,
+                     double *nrm2, hipStream_t s) {
   PtrPack pk;
   for (int j = 0; j < nv; j++) pk.p[j] = v[j];
   const int nb = arn_blocks(n);
-  ARN_DISPATCH(k_cgs_next, nv, w, pk, h2, nv, inv_nu, n, out, nrm2 ? partials : nullptr);
+  ARN_DISPATCH(k_cgs_next, nv, w, pk, h1, h2, nv, inv_nu, n, out, out32,
+               nrm2 ? partials : nullptr);
   if (nrm2) hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, nrm2);
 }
 #undef ARN_DISPATCH
