@@ -331,6 +331,7 @@ TailLevels<T> tail_levels(stokes_ctx *X, int l0, const T *rhs, T *phi, bool vel)
   }
   t.rhs[0] = const_cast<T *>(rhs);
   t.phi[0] = phi;
+  tail_plan_lds<T>(t, vel);
   return t;
 }
 

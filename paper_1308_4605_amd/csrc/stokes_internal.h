@@ -100,7 +100,16 @@ struct TailLevels {
   Geo g[kTailMax];
   const T *a[kTailMax], *b[kTailMax], *mc[kTailMax], *me[kTailMax];  // alpha, beta, mu_c, mu_e
   T *phi[kTailMax], *rhs[kTailMax], *res[kTailMax];
+  // levels lds0..nl-1 live in dynamic LDS: byte offsets of
+  // {alpha or beta, mu_c, mu_e, phi, rhs, res}; lds_bytes in total
+  int lds0;
+  unsigned lds_bytes;
+  unsigned off[kTailMax][6];
 };
+constexpr unsigned kTailLds = 60 * 1024;  // dynamic LDS budget of a tail launch
+// fills lds0 / off / lds_bytes for the velocity (vel) or pressure tail
+template <typename T>
+void tail_plan_lds(TailLevels<T> &L, bool vel);
 template <typename T>
 void launch_tail_vel(const TailLevels<T> &L, hipStream_t s);
 template <typename T>

@@ -1064,42 +1064,85 @@ __device__ void tail_vel_smooth(const Geo &g, const T *alpha, const T *muc, cons
       }
 }
 
+// Per-level pointers of a tail launch.  Levels lds0.. (the smallest ones)
+// are staged in LDS: their coefficients are copied there at the start and
+// their iterates, right-hand sides and residuals live there, so their
+// phases wait on LDS instead of L2 latency.  The element functions address
+// both through generic pointers.
+template <typename T>
+struct TailPtrs {
+  const T *a[kTailMax], *b[kTailMax], *mc[kTailMax], *me[kTailMax];
+  T *phi[kTailMax], *rhs[kTailMax], *res[kTailMax];
+};
+
+template <typename T>
+__device__ void tail_stage(const TailLevels<T> &L, unsigned char *lds, TailPtrs<T> &P, bool vel) {
+  if (threadIdx.x == 0) {
+    for (int l = 0; l < L.nl; l++) {
+      const bool in = l >= L.lds0;
+      P.a[l] = in ? (const T *)(lds + L.off[l][0]) : L.a[l];
+      P.b[l] = in ? (const T *)(lds + L.off[l][0]) : L.b[l];
+      P.mc[l] = in ? (const T *)(lds + L.off[l][1]) : L.mc[l];
+      P.me[l] = in ? (const T *)(lds + L.off[l][2]) : L.me[l];
+      P.phi[l] = in ? (T *)(lds + L.off[l][3]) : L.phi[l];
+      P.rhs[l] = in ? (T *)(lds + L.off[l][4]) : L.rhs[l];
+      P.res[l] = in ? (T *)(lds + L.off[l][5]) : L.res[l];
+    }
+  }
+  for (int l = L.lds0; l < L.nl; l++) {
+    const Geo &g = L.g[l];
+    if (vel) {
+      T *a = (T *)(lds + L.off[l][0]), *mc = (T *)(lds + L.off[l][1]), *me = (T *)(lds + L.off[l][2]);
+      for (i64 t = threadIdx.x; t < g.nvel; t += blockDim.x) a[t] = L.a[l][t];
+      for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x) mc[t] = L.mc[l][t];
+      for (i64 t = threadIdx.x; t < g.nedge; t += blockDim.x) me[t] = L.me[l][t];
+    } else {
+      T *b = (T *)(lds + L.off[l][0]);
+      for (i64 t = threadIdx.x; t < g.nvel; t += blockDim.x) b[t] = L.b[l][t];
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kTailBlock) k_tail_vel(TailLevels<T> L) {
+  extern __shared__ __align__(16) unsigned char tail_lds[];
+  __shared__ TailPtrs<T> P;
+  tail_stage<T>(L, tail_lds, P, true);
   const int nl = L.nl;
   for (int l = 0; l < nl - 1; l++) {
     const Geo &g = L.g[l];
-    tail_zero<T>(L.phi[l], g.nvel);
-    tail_vel_smooth<T, DIM>(g, L.a[l], L.mc[l], L.me[l], L.rhs[l], L.phi[l], L.nu_pre);
+    tail_zero<T>(P.phi[l], g.nvel);
+    tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.rhs[l], P.phi[l], L.nu_pre);
     for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x)
-      vel_residual_elem<T, DIM>(g, t, L.a[l], L.mc[l], L.me[l], L.rhs[l], L.phi[l],
-                                (const T *)nullptr, L.res[l]);
+      vel_residual_elem<T, DIM>(g, t, P.a[l], P.mc[l], P.me[l], P.rhs[l], P.phi[l],
+                                (const T *)nullptr, P.res[l]);
     __syncthreads();
     for (i64 t = threadIdx.x; t < L.g[l + 1].ncell; t += blockDim.x)
-      face_restrict_elem<T, DIM>(g, L.g[l + 1], t, L.res[l], L.rhs[l + 1]);
+      face_restrict_elem<T, DIM>(g, L.g[l + 1], t, P.res[l], P.rhs[l + 1]);
     __syncthreads();
   }
   {
     const int l = nl - 1;
     const Geo &g = L.g[l];
-    tail_zero<T>(L.phi[l], g.nvel);
+    tail_zero<T>(P.phi[l], g.nvel);
     if (L.singular) {
       for (int k = 0; k < g.d; k++)
-        tail_sub_mean<T>(L.rhs[l] + g.foff[k], L.res[l] + g.foff[k], g.fcnt[k]);
+        tail_sub_mean<T>(P.rhs[l] + g.foff[k], P.res[l] + g.foff[k], g.fcnt[k]);
     } else {
-      tail_copy<T>(L.rhs[l], L.res[l], g.nvel);
+      tail_copy<T>(P.rhs[l], P.res[l], g.nvel);
     }
-    tail_vel_smooth<T, DIM>(g, L.a[l], L.mc[l], L.me[l], L.res[l], L.phi[l], L.nu_coarse);
+    tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.res[l], P.phi[l], L.nu_coarse);
     if (L.singular)
       for (int k = 0; k < g.d; k++)
-        tail_sub_mean<T>(L.phi[l] + g.foff[k], L.phi[l] + g.foff[k], g.fcnt[k]);
+        tail_sub_mean<T>(P.phi[l] + g.foff[k], P.phi[l] + g.foff[k], g.fcnt[k]);
   }
   for (int l = nl - 2; l >= 0; l--) {
     const Geo &g = L.g[l];
     for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x)
-      face_prolong_elem<T, DIM>(L.g[l + 1], g, t, L.phi[l + 1], L.phi[l]);
+      face_prolong_elem<T, DIM>(L.g[l + 1], g, t, P.phi[l + 1], P.phi[l]);
     __syncthreads();
-    tail_vel_smooth<T, DIM>(g, L.a[l], L.mc[l], L.me[l], L.rhs[l], L.phi[l], L.nu_post);
+    tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.rhs[l], P.phi[l], L.nu_post);
   }
 }
 
@@ -1116,48 +1159,83 @@ __device__ void tail_p_smooth(const Geo &g, const T *beta, const T *rhs, T *phi,
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kTailBlock) k_tail_p(TailLevels<T> L) {
+  extern __shared__ __align__(16) unsigned char tail_lds[];
+  __shared__ TailPtrs<T> P;
+  tail_stage<T>(L, tail_lds, P, false);
   const int nl = L.nl;
   for (int l = 0; l < nl - 1; l++) {
     const Geo &g = L.g[l];
-    tail_zero<T>(L.phi[l], g.ncell);
-    tail_p_smooth<T, DIM>(g, L.b[l], L.rhs[l], L.phi[l], L.nu_pre);
+    tail_zero<T>(P.phi[l], g.ncell);
+    tail_p_smooth<T, DIM>(g, P.b[l], P.rhs[l], P.phi[l], L.nu_pre);
     for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x)
-      p_residual_elem<T, DIM>(g, t, L.b[l], L.rhs[l], L.phi[l], L.res[l]);
+      p_residual_elem<T, DIM>(g, t, P.b[l], P.rhs[l], P.phi[l], P.res[l]);
     __syncthreads();
     for (i64 t = threadIdx.x; t < L.g[l + 1].ncell; t += blockDim.x)
-      cell_restrict_elem<T>(g, L.g[l + 1], t, L.res[l], L.rhs[l + 1]);
+      cell_restrict_elem<T>(g, L.g[l + 1], t, P.res[l], P.rhs[l + 1]);
     __syncthreads();
   }
   {
     const int l = nl - 1;
     const Geo &g = L.g[l];
-    tail_zero<T>(L.phi[l], g.ncell);
-    tail_sub_mean<T>(L.rhs[l], L.res[l], g.ncell);
-    tail_p_smooth<T, DIM>(g, L.b[l], L.res[l], L.phi[l], L.nu_coarse);
-    tail_sub_mean<T>(L.phi[l], L.phi[l], g.ncell);
+    tail_zero<T>(P.phi[l], g.ncell);
+    tail_sub_mean<T>(P.rhs[l], P.res[l], g.ncell);
+    tail_p_smooth<T, DIM>(g, P.b[l], P.res[l], P.phi[l], L.nu_coarse);
+    tail_sub_mean<T>(P.phi[l], P.phi[l], g.ncell);
   }
   for (int l = nl - 2; l >= 0; l--) {
     const Geo &g = L.g[l];
     for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x)
-      cell_prolong_elem<T>(L.g[l + 1], g, t, L.phi[l + 1], L.phi[l]);
+      cell_prolong_elem<T>(L.g[l + 1], g, t, P.phi[l + 1], P.phi[l]);
     __syncthreads();
-    tail_p_smooth<T, DIM>(g, L.b[l], L.rhs[l], L.phi[l], L.nu_post);
+    tail_p_smooth<T, DIM>(g, P.b[l], P.rhs[l], P.phi[l], L.nu_post);
   }
 }
 
 template <typename T>
+void tail_plan_lds(TailLevels<T> &L, bool vel) {
+  auto up = [](unsigned x) { return (x + 15u) & ~15u; };
+  L.lds0 = L.nl;
+  L.lds_bytes = 0;
+  for (int l = 0; l < kTailMax; l++)
+    for (int q = 0; q < 6; q++) L.off[l][q] = 0;
+  unsigned total = 0;
+  // from the coarsest level up; the first tail level keeps the caller's
+  // buffers in global memory
+  for (int l = L.nl - 1; l >= 1; l--) {
+    const Geo &g = L.g[l];
+    const unsigned nv = (unsigned)g.nvel * sizeof(T), nc = (unsigned)g.ncell * sizeof(T);
+    const unsigned ne = (unsigned)g.nedge * sizeof(T);
+    const unsigned sz[6] = {up(nv), vel ? up(nc) : 0u, vel ? up(ne) : 0u,
+                            up(vel ? nv : nc), up(vel ? nv : nc), up(vel ? nv : nc)};
+    unsigned need = 0;
+    for (int q = 0; q < 6; q++) need += sz[q];
+    if (total + need > kTailLds) break;
+    unsigned o = total;
+    for (int q = 0; q < 6; q++) {
+      L.off[l][q] = o;
+      o += sz[q];
+    }
+    total += need;
+    L.lds0 = l;
+  }
+  L.lds_bytes = total;
+}
+template void tail_plan_lds<float>(TailLevels<float> &, bool);
+template void tail_plan_lds<double>(TailLevels<double> &, bool);
+
+template <typename T>
 void launch_tail_vel(const TailLevels<T> &L, hipStream_t s) {
   if (L.g[0].d == 3)
-    hipLaunchKernelGGL((k_tail_vel<T, 3>), dim3(1), dim3(kTailBlock), 0, s, L);
+    hipLaunchKernelGGL((k_tail_vel<T, 3>), dim3(1), dim3(kTailBlock), L.lds_bytes, s, L);
   else
-    hipLaunchKernelGGL((k_tail_vel<T, 2>), dim3(1), dim3(kTailBlock), 0, s, L);
+    hipLaunchKernelGGL((k_tail_vel<T, 2>), dim3(1), dim3(kTailBlock), L.lds_bytes, s, L);
 }
 template <typename T>
 void launch_tail_p(const TailLevels<T> &L, hipStream_t s) {
   if (L.g[0].d == 3)
-    hipLaunchKernelGGL((k_tail_p<T, 3>), dim3(1), dim3(kTailBlock), 0, s, L);
+    hipLaunchKernelGGL((k_tail_p<T, 3>), dim3(1), dim3(kTailBlock), L.lds_bytes, s, L);
   else
-    hipLaunchKernelGGL((k_tail_p<T, 2>), dim3(1), dim3(kTailBlock), 0, s, L);
+    hipLaunchKernelGGL((k_tail_p<T, 2>), dim3(1), dim3(kTailBlock), L.lds_bytes, s, L);
 }
 template void launch_tail_vel<float>(const TailLevels<float> &, hipStream_t);
 template void launch_tail_vel<double>(const TailLevels<double> &, hipStream_t);
