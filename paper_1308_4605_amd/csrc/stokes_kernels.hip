@@ -211,11 +211,15 @@ __device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const
     if (l == k) continue;
     const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
     const bool bot = g.ns[l] && (i[l] == 0);
+    // loads are unconditional (from an in-range index) so that all of them
+    // issue before the first wait; the wall ghost -u_f is selected afterwards
     t[l] = top ? i[l] : up1(g, l, i[l]);  // component k has no face at index n[l] along l
-    ua[l] = top ? -uf : u[fidx3(g, k, t)];
+    const T va = u[fidx3(g, k, t)];
     t[l] = dn1(g, l, i[l]);
-    ub[l] = bot ? -uf : u[fidx3(g, k, t)];
+    const T vb = u[fidx3(g, k, t)];
     t[l] = i[l];
+    ua[l] = top ? -uf : va;
+    ub[l] = bot ? -uf : vb;
   }
   const T *comp[3] = {u + g.foff[0], u + g.foff[1], u + g.foff[2]};
   a_row_nb<T, DIM>(g, k, i, uf, ukp, ukm, ua, ub, comp, alpha, muc, mue, Au, diag);
@@ -510,7 +514,8 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
     const int lp = up1(g, l, i[l]);
     const int lm = dn1(g, l, i[l]);
     t[l] = top ? i[l] : lp;  // component k has no face at index n[l] along l
-    const double ua = top ? -uf : (double)u[fidx3(g, k, t)];
+    const double va = (double)u[fidx3(g, k, t)];  // unconditional; ghost selected below
+    const double ua = top ? -uf : va;
     t[l] = lp;
     const double mhi = mue[eidx3(g, m, t)];
     const double ulh_r = (double)u[fidx3(g, l, t)];
@@ -518,7 +523,8 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
     const double ulh_l = (double)u[fidx3(g, l, t)];
     t[k] = i[k];
     t[l] = lm;
-    const double ub = bot ? -uf : (double)u[fidx3(g, k, t)];
+    const double vb = (double)u[fidx3(g, k, t)];
+    const double ub = bot ? -uf : vb;
     t[l] = i[l];
     const double mlo = mue[eidx3(g, m, t)];
     const double ull_r = (double)u[fidx3(g, l, t)];
@@ -797,49 +803,38 @@ __device__ __forceinline__ void tang_w(const Geo &gc, int a, int j, int idx[2], 
   }
 }
 
+// Fixed taps, unconditional loads: two along the normal (weights 1 and 0 on
+// an even fine index, 1/2 and 1/2 on an odd one) times two per tangential
+// axis (3/4 and +-1/4, the odd wall reflection giving -1/4 on J itself).
 template <typename T, int DIM>
-__device__ __forceinline__ void face_prolong_elem(const Geo &gc, const Geo &gf, i64 t,
-                                                  const T *__restrict__ ec, T *__restrict__ phif) {
-  if (t >= gf.ncell) return;
-  int f[3];
-  cell_of(gf, t, f);
+__device__ __forceinline__ void face_prolong_at(const Geo &gc, const Geo &gf, const int f[3],
+                                                const T *__restrict__ ec, T *__restrict__ phif) {
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
     if (low_wall(gf, k, f)) continue;
+    const int fk = f[k];
     int nidx[2];
-    T nw[2];
-    int nn;
-    if ((f[k] & 1) == 0) {
-      nidx[0] = f[k] >> 1;
-      nw[0] = (T)1;
-      nn = 1;
-    } else {
-      nidx[0] = (f[k] - 1) >> 1;
-      int up = (f[k] + 1) >> 1;
-      if (!gc.ns[k] && up == gc.n[k]) up = 0;
-      nidx[1] = up;
-      nw[0] = nw[1] = (T)0.5;
-      nn = 2;
-    }
-    int tax[2] = {0, 0}, nt = 0;
-    for (int b = 0; b < DIM; b++)
-      if (b != k) tax[nt++] = b;
+    nidx[0] = fk >> 1;
+    nidx[1] = (fk + 1) >> 1;
+    if (!gc.ns[k] && nidx[1] == gc.n[k]) nidx[1] = 0;
+    const T nw[2] = {(fk & 1) ? (T)0.5 : (T)1, (fk & 1) ? (T)0.5 : (T)0};
+    const int ta = (k == 0) ? 1 : 0;
+    const int tb = (k == 2) ? 1 : 2;
     int t0i[2], t1i[2] = {0, 0};
     double t0w[2], t1w[2] = {1.0, 0.0};
-    tang_w(gc, tax[0], f[tax[0]], t0i, t0w);
-    int n1 = 1;
-    if (DIM == 3) {
-      tang_w(gc, tax[1], f[tax[1]], t1i, t1w);
-      n1 = 2;
-    }
+    tang_w(gc, ta, f[ta], t0i, t0w);
+    if (DIM == 3) tang_w(gc, tb, f[tb], t1i, t1w);
     T s = 0;
-    for (int a = 0; a < nn; a++)
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
       for (int b0 = 0; b0 < 2; b0++)
-        for (int b1 = 0; b1 < n1; b1++) {
+#pragma unroll
+        for (int b1 = 0; b1 < (DIM == 3 ? 2 : 1); b1++) {
           int cf[3] = {0, 0, 0};
           cf[k] = nidx[a];
-          cf[tax[0]] = t0i[b0];
-          if (DIM == 3) cf[tax[1]] = t1i[b1];
+          cf[ta] = t0i[b0];
+          if (DIM == 3) cf[tb] = t1i[b1];
           s += nw[a] * (T)t0w[b0] * (T)t1w[b1] * ec[fidx3(gc, k, cf)];
         }
     phif[fidx3(gf, k, f)] += s;
@@ -847,18 +842,29 @@ __device__ __forceinline__ void face_prolong_elem(const Geo &gc, const Geo &gf, 
 }
 
 template <typename T, int DIM>
+__device__ __forceinline__ void face_prolong_elem(const Geo &gc, const Geo &gf, i64 t,
+                                                  const T *__restrict__ ec, T *__restrict__ phif) {
+  if (t >= gf.ncell) return;
+  int f[3];
+  cell_of(gf, t, f);
+  face_prolong_at<T, DIM>(gc, gf, f, ec, phif);
+}
+
+template <typename T, int DIM>
 __global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
                                    T *__restrict__ phif) {
-  face_prolong_elem<T, DIM>(gc, gf, (i64)blockIdx.x * blockDim.x + threadIdx.x, ec, phif);
+  int f[3];
+  if (!box_thread(gf, gf.n[0], f[0], f[1], f[2])) return;
+  face_prolong_at<T, DIM>(gc, gf, f, ec, phif);
 }
 
 template <typename T>
 void launch_face_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *phif, hipStream_t s) {
   if (gf.d == 3)
-    hipLaunchKernelGGL((k_face_prolong_add<T, 3>), dim3(blocks_for(gf.ncell)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_face_prolong_add<T, 3>), box_blocks(gf, gf.n[0]), dim3(kBlock), 0, s,
                        gc, gf, ec, phif);
   else
-    hipLaunchKernelGGL((k_face_prolong_add<T, 2>), dim3(blocks_for(gf.ncell)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_face_prolong_add<T, 2>), box_blocks(gf, gf.n[0]), dim3(kBlock), 0, s,
                        gc, gf, ec, phif);
 }
 
@@ -874,23 +880,22 @@ __device__ __forceinline__ void p_row(const Geo &g, const int i[3], const T *__r
   T s = 0, dg = 0;
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
-    int r[3] = {i[0], i[1], i[2]};
-    // flux through the high face (index i+1) and the low face (index i)
-    T fr = 0, fl = 0;
+    // flux through the high face (index i+1) and the low face (index i); a
+    // wall face carries none.  Loads use in-range indices unconditionally and
+    // the wall cases are selected afterwards.
     const bool wr = g.ns[k] && (i[k] + 1 == g.n[k]);
     const bool wl = g.ns[k] && (i[k] == 0);
-    if (!wr) {
-      r[k] = up1(g, k, i[k]);
-      const T b = beta[fidx3(g, k, r)];
-      fr = b * ((p[cidx3(g, r)] - pc) * ih);
-      dg -= b;
-    }
-    if (!wl) {
-      r[k] = dn1(g, k, i[k]);
-      const T b = beta[fidx3(g, k, i)];
-      fl = b * ((pc - p[cidx3(g, r)]) * ih);
-      dg -= b;
-    }
+    int f[3] = {i[0], i[1], i[2]}, c[3] = {i[0], i[1], i[2]};
+    f[k] = wr ? i[k] : up1(g, k, i[k]);
+    c[k] = f[k];
+    const T br = beta[fidx3(g, k, f)];
+    const T pr = p[cidx3(g, c)];
+    c[k] = dn1(g, k, i[k]);
+    const T bl = beta[fidx3(g, k, i)];
+    const T pl = p[cidx3(g, c)];
+    const T fr = wr ? (T)0 : br * ((pr - pc) * ih);
+    const T fl = wl ? (T)0 : bl * ((pc - pl) * ih);
+    dg -= (wr ? (T)0 : br) + (wl ? (T)0 : bl);
     s += (fr - fl) * ih;
   }
   Lp = s;
@@ -1400,53 +1405,64 @@ void launch_sub_mean(T *a, i64 n, const double *sum, hipStream_t s) {
   hipLaunchKernelGGL(k_sub_mean<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n, sum);
 }
 
-// per-component sums of a velocity vector in one pass (all faces; used only
-// when every axis is periodic)
+// Per-component sums of a velocity vector (used only when every axis is
+// periodic): blockIdx.y is the component, each block reduces a contiguous
+// stretch of it with four independent accumulators per thread.
 template <typename T>
 __global__ void k_vel_sums_partial(Geo g, const T *__restrict__ u, double *__restrict__ partials) {
-  __shared__ double sh[kBlock / 64][3];
-  double acc[3] = {0.0, 0.0, 0.0};
-  const i64 o1 = g.foff[1], o2 = (g.d == 3) ? g.foff[2] : g.nvel;
-  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < g.nvel;
-       t += (i64)gridDim.x * blockDim.x) {
-    const double v = (double)u[t];
-    if (t < o1) acc[0] += v;
-    else if (t < o2) acc[1] += v;
-    else acc[2] += v;
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int k = 0; k < 3; k++) {
-    double r = acc[k];
+  __shared__ double sh[kBlock / 64];
+  const int k = blockIdx.y;
+  const T *__restrict__ c = u + g.foff[k];
+  const i64 n = g.fcnt[k];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const i64 stride = (i64)gridDim.x * blockDim.x * 4;
+  for (i64 t0 = (i64)blockIdx.x * blockDim.x * 4 + threadIdx.x; t0 < n; t0 += stride) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
-    if (lane == 0) sh[wid][k] = r;
+    for (int j = 0; j < 4; j++) {
+      const i64 t = t0 + (i64)j * blockDim.x;
+      if (t < n) acc[j] += (double)c[t];
+    }
   }
+  double r = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  r = wave_sum(r);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = r;
   __syncthreads();
-  if (threadIdx.x < 3) {
-    double r = 0.0;
-    for (int w = 0; w < kBlock / 64; w++) r += sh[w][threadIdx.x];
-    partials[(i64)blockIdx.x * 3 + threadIdx.x] = r;
+  if (threadIdx.x == 0) {
+    double q = 0.0;
+    for (int w = 0; w < kBlock / 64; w++) q += sh[w];
+    partials[(i64)blockIdx.x * 3 + k] = q;
   }
 }
 
-// out = in - (component mean); out may alias in
+// out = in - (component mean); out may alias in; blockIdx.y is the component
 template <typename T>
 __global__ void k_vel_sub_means(Geo g, const T *__restrict__ in, T *__restrict__ out,
                                 const double *__restrict__ sums) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.nvel) return;
-  const int k = (t >= g.foff[1]) + ((g.d == 3) && (t >= g.foff[2]));
-  out[t] = in[t] - (T)(sums[k] / (double)g.fcnt[k]);
+  const int k = blockIdx.y;
+  const i64 n = g.fcnt[k];
+  const T mean = (T)(sums[k] / (double)n);
+  const T *__restrict__ a = in + g.foff[k];
+  T *__restrict__ o = out + g.foff[k];
+  const i64 t0 = (i64)blockIdx.x * blockDim.x * 4 + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const i64 t = t0 + (i64)j * blockDim.x;
+    if (t < n) o[t] = a[t] - mean;
+  }
 }
 
 template <typename T>
 void launch_vel_remove_means(const Geo &g, const T *in, T *out, double *partials, double *sums,
                              hipStream_t s) {
-  const int nb = red_blocks(g.nvel);
-  hipLaunchKernelGGL(k_vel_sums_partial<T>, dim3(nb), dim3(kBlock), 0, s, g, in, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 3, 3, sums);
-  hipLaunchKernelGGL(k_vel_sub_means<T>, dim3(blocks_for(g.nvel)), dim3(kBlock), 0, s, g, in, out,
-                     sums);
+  i64 nmax = 0;
+  for (int k = 0; k < g.d; k++) nmax = g.fcnt[k] > nmax ? g.fcnt[k] : nmax;
+  i64 nbx = (nmax + 4 * kBlock - 1) / (4 * kBlock);
+  const int nr = (int)(nbx < kRedBlocks ? (nbx < 1 ? 1 : nbx) : kRedBlocks);
+  hipLaunchKernelGGL(k_vel_sums_partial<T>, dim3(nr, g.d), dim3(kBlock), 0, s, g, in, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nr, 3, g.d, sums);
+  hipLaunchKernelGGL(k_vel_sub_means<T>, dim3((unsigned)(nbx < 1 ? 1 : nbx), g.d), dim3(kBlock),
+                     0, s, g, in, out, sums);
 }
 template void launch_vel_remove_means<float>(const Geo &, const float *, float *, double *,
                                              double *, hipStream_t);
