@@ -258,6 +258,17 @@ inline T *P(void *a) {
   return (T *)a;
 }
 
+// The mass coefficient alpha = theta rho_f is identically zero for steady
+// problems; the kernels then get no alpha array and skip the term (0 * u
+// adds nothing, so the result is the same bit for bit).
+template <typename T>
+inline const T *alpha_of(const stokes_ctx *X, const Level &L) {
+  return X->p.theta == 0.0 ? nullptr : (const T *)L.alpha;
+}
+inline const double *m_alpha_of(const stokes_ctx *X) {
+  return X->p.theta == 0.0 ? nullptr : X->m_alpha;
+}
+
 template <typename T>
 void remove_mean(stokes_ctx *X, T *a, i64 n, int slot) {
   launch_sum<T>(a, n, X->part, X->dsc + slot, X->s);
@@ -284,7 +295,8 @@ void smooth_vel(stokes_ctx *X, int l, const T *rhs, T *phi, int nsweeps) {
           if (X->ev_used == kEventPool) fold_events(X);
           (void)hipEventRecord(X->ev[2 * X->ev_used], X->s);
         }
-        launch_vel_gs<T>(L.g, k, colour, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), rhs, phi, X->s);
+        launch_vel_gs<T>(L.g, k, colour, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), rhs, phi,
+                         X->s);
         if (tm) {
           (void)hipEventRecord(X->ev[2 * X->ev_used + 1], X->s);
           X->ev_used++;
@@ -321,7 +333,7 @@ TailLevels<T> tail_levels(stokes_ctx *X, int l0, const T *rhs, T *phi, bool vel)
     }
     Level &L = X->lev[l];
     t.g[i] = L.g;
-    t.a[i] = P<T>(L.alpha);
+    t.a[i] = alpha_of<T>(X, L);
     t.b[i] = P<T>(L.beta);
     t.mc[i] = P<T>(L.muc);
     t.me[i] = P<T>(L.mue);
@@ -356,7 +368,7 @@ void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
   }
   Level &C = X->lev[l + 1];
   smooth_vel<T>(X, l, rhs, phi, X->p.nu_pre);
-  launch_vel_residual<T>(L.g, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), rhs, phi, nullptr,
+  launch_vel_residual<T>(L.g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), rhs, phi, nullptr,
                          P<T>(L.res_u), X->s);
   launch_face_restrict<T>(L.g, C.g, P<T>(L.res_u), P<T>(C.rhs_u), X->s);
   vcycle_vel<T>(X, l + 1, P<T>(C.rhs_u), P<T>(C.phi_u));
@@ -402,7 +414,7 @@ void vel_sub(stokes_ctx *X, const T *r, T *e) {
   }
   vcycle_vel<T>(X, 0, rr, e);
   for (int v = 1; v < X->p.vcycles; v++) {
-    launch_vel_residual<T>(L.g, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), rr, e, nullptr,
+    launch_vel_residual<T>(L.g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), rr, e, nullptr,
                            P<T>(X->vs_t), X->s);
     vcycle_vel<T>(X, 0, P<T>(X->vs_t), P<T>(X->vs_de));
     launch_axpy<T>((T)1, P<T>(X->vs_de), e, L.g.nvel, X->s);
@@ -477,7 +489,7 @@ void precond(stokes_ctx *X, const T *bu, const T *bp, T *zu, T *zp) {
       vel_sub<T>(X, bu, xs);
       launch_div<T>(g, xs, bp, (T)1, cv, X->s);
       neg_schur<T>(X, cv, zp);
-      launch_vel_residual<T>(g, P<T>(L.alpha), P<T>(L.muc), P<T>(L.mue), bu, xs, zp, tu, X->s);
+      launch_vel_residual<T>(g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), bu, xs, zp, tu, X->s);
       vel_sub<T>(X, tu, eu);
       launch_cast<T, T>(xs, zu, g.nvel, X->s);
       launch_axpy<T>((T)1, eu, zu, g.nvel, X->s);
@@ -504,7 +516,7 @@ void precond_from64(stokes_ctx *X, const double *v, void *z, bool have32 = false
 // y = M' x on the rescaled system (FP64)
 void apply_scaled(stokes_ctx *X, const double *x, double *y) {
   const Geo &g = X->lev[0].g;
-  launch_apply_m<double>(g, X->m_alpha, X->m_muc, X->m_mue, x, x + X->nvel, nullptr, nullptr, y,
+  launch_apply_m<double>(g, m_alpha_of(X), X->m_muc, X->m_mue, x, x + X->nvel, nullptr, nullptr, y,
                          y + X->nvel, X->s);
 }
 
@@ -539,7 +551,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
   int it = 0, rc = STOKES_OK;
   for (;;) {
     // r = b - M x and its norm
-    launch_apply_m<double>(X->lev[0].g, X->m_alpha, X->m_muc, X->m_mue, X->x, X->x + nv, X->b,
+    launch_apply_m<double>(X->lev[0].g, m_alpha_of(X), X->m_muc, X->m_mue, X->x, X->x + nv, X->b,
                            X->b + nv, X->r, X->r + nv, X->s);
     launch_norm2(X->r, n, X->part, X->dsc + 0, X->s);
     const double rho = std::sqrt(fetch(X, X->dsc, 1, hb));
@@ -571,7 +583,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       if (flexible) {
         precond_from64(X, X->V[j], X->Z[j], j > 0);
         if (X->mg32)
-          launch_apply_m<float>(X->lev[0].g, X->m_alpha, X->m_muc, X->m_mue, P<float>(X->Z[j]),
+          launch_apply_m<float>(X->lev[0].g, m_alpha_of(X), X->m_muc, X->m_mue, P<float>(X->Z[j]),
                                 P<float>(X->Z[j]) + nv, nullptr, nullptr, X->w, X->w + nv, X->s);
         else
           apply_scaled(X, P<double>(X->Z[j]), X->w);
@@ -845,7 +857,10 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
     for (int m = 0; m < 3; m++)
       if (m != k && g0.ecnt[m] > 0) e += (double)g0.ecnt[m];
     if (g0.d == 2) e = (double)g0.ecnt[2];
-    X->gs_bytes[k] = tb * ((double)g0.nvel + 3.0 * (double)g0.fcnt[k] + (double)g0.ncell + e);
+    // reads: every velocity component, rhs_k, alpha_k (not when theta = 0),
+    // mu_cell, the edge families touching k; writes: component k
+    const double own = (p->theta == 0.0) ? 2.0 : 3.0;
+    X->gs_bytes[k] = tb * ((double)g0.nvel + own * (double)g0.fcnt[k] + (double)g0.ncell + e);
   }
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
     (void)hipHostFree(X->host);

@@ -156,7 +156,7 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
   const T tr = (T)2 * mr * ((ukp - uf) * ih);
   const T tl = (T)2 * ml * ((uf - ukm) * ih);
   T s = (tr - tl) * ih;
-  const T al = alpha[fq];
+  const T al = alpha ? alpha[fq] : (T)0;  // no alpha array: theta = 0
   T dg = al + (T)2 * (mr + ml) * ih2;
 #pragma unroll
   for (int l = 0; l < DIM; l++) {
@@ -535,7 +535,7 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
     const double glo = (uf - ub) * ih + (ull_r - ull_l) * ih;
     s += (mhi * ghi - mlo * glo) * ih;
   }
-  Au = alpha[fq] * uf - s;
+  Au = (alpha ? alpha[fq] * uf : 0.0) - s;  // no alpha array: theta = 0
 }
 
 template <typename TI, int DIM>
@@ -1085,7 +1085,7 @@ __device__ void tail_stage(const TailLevels<T> &L, unsigned char *lds, TailPtrs<
   if (threadIdx.x == 0) {
     for (int l = 0; l < L.nl; l++) {
       const bool in = l >= L.lds0;
-      P.a[l] = in ? (const T *)(lds + L.off[l][0]) : L.a[l];
+      P.a[l] = (in && L.a[l]) ? (const T *)(lds + L.off[l][0]) : L.a[l];
       P.b[l] = in ? (const T *)(lds + L.off[l][0]) : L.b[l];
       P.mc[l] = in ? (const T *)(lds + L.off[l][1]) : L.mc[l];
       P.me[l] = in ? (const T *)(lds + L.off[l][2]) : L.me[l];
@@ -1098,7 +1098,8 @@ __device__ void tail_stage(const TailLevels<T> &L, unsigned char *lds, TailPtrs<
     const Geo &g = L.g[l];
     if (vel) {
       T *a = (T *)(lds + L.off[l][0]), *mc = (T *)(lds + L.off[l][1]), *me = (T *)(lds + L.off[l][2]);
-      for (i64 t = threadIdx.x; t < g.nvel; t += blockDim.x) a[t] = L.a[l][t];
+      if (L.a[l])
+        for (i64 t = threadIdx.x; t < g.nvel; t += blockDim.x) a[t] = L.a[l][t];
       for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x) mc[t] = L.mc[l][t];
       for (i64 t = threadIdx.x; t < g.nedge; t += blockDim.x) me[t] = L.me[l][t];
     } else {
