@@ -200,6 +200,20 @@ def main():
         _log(f"CPU oracle: {t_cpu:.1f}s for {k_it} iteration(s) on {cpu['cores']} threads")
         del o
 
+    # device copy ceiling: a plain 1 GiB read + 1 GiB write on the same GPU
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    _log(f"device copy: {copy_gbs:.0f} GB/s")
+
     sv = st["scalar_vcycles"]
     line = {
         "metric": "Stokes solves/s to 1e-8 rel resid (FP32-MG in FP64 FGMRES)",
@@ -226,6 +240,7 @@ def main():
         "roofline": {"kernel": "velocity Gauss-Seidel colour pass, finest level (k_vel_gs)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": _measured_traffic(args.n),
+                     "copy_ceiling": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "avg_launch_us": 1e3 * avg_ms, "launches": launches,
                      "bytes_per_launch": bytes_k / max(launches, 1)},
         "adjoint": adjoint,
