@@ -38,9 +38,9 @@
  *
  * Streams: every call enqueues its kernels on the HIP stream given at
  * creation.  stokes_apply, stokes_precond, stokes_vel_subsolve,
- * stokes_p_subsolve and stokes_grad are asynchronous; stokes_solve and
- * stokes_adjoint_solve read Arnoldi scalars back every iteration and return
- * after the stream has drained.  A context is not thread-safe; two calls on
+ * stokes_p_subsolve and stokes_grad are asynchronous; stokes_solve,
+ * stokes_adjoint_solve and the two *_mg_solve calls read scalars back every
+ * iteration and return after the stream has drained.  A context is not thread-safe; two calls on
  * one context must not overlap.
  *
  * Errors: every function returns a status code; validation happens on the
@@ -164,6 +164,25 @@ int stokes_precond(stokes_ctx *ctx, const double *bu, const double *bp, double *
    L_rho = D rho_f^{-1} G; r must have zero mean; e has zero mean). */
 int stokes_vel_subsolve(stokes_ctx *ctx, const double *r, double *e);
 int stokes_p_subsolve(stokes_ctx *ctx, const double *r, double *e);
+
+/* The same two multigrid solvers run to convergence on their own, the cost
+   reference of a split (projection-like) method in the study of V-cycles per
+   subsolve (Sec. 4.3.1): starting from e = 0, each cycle adds one V-cycle
+   applied to the current residual, e <- e + V(r - A e), until
+   ||r - A e|| <= tol ||r|| or max_cycles cycles.  A is the velocity operator
+   theta rho - L_mu (vel) or L_rho (p), unscaled as for the subsolvers; r is
+   first projected onto the operator's range (component means for the
+   periodic steady velocity, the mean for the pressure), and so is e.
+   Residuals, the iterate and the norms are FP64; with STOKES_MG_FP32 the
+   V-cycles run in FP32, i.e. as iterative refinement.
+   *cycles: V-cycles done; *rel_res: final ||r - A e|| / ||r|| (host
+   pointers).  Returns STOKES_OK, STOKES_ENOCONV when max_cycles ran out (e
+   holds the last iterate), STOKES_EINVAL for null pointers, tol <= 0 or
+   max_cycles < 0.  Synchronous: returns after the stream has drained. */
+int stokes_vel_mg_solve(stokes_ctx *ctx, const double *r, double *e, double tol, int max_cycles,
+                        int *cycles, double *rel_res);
+int stokes_p_mg_solve(stokes_ctx *ctx, const double *r, double *e, double tol, int max_cycles,
+                      int *cycles, double *rel_res);
 
 /* Solve M x = b until the true relative residual of the rescaled system
    ||b' - M' x'|| <= tol ||b'|| (Sec. 3.2 "true residual"), at most max_iter

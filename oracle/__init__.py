@@ -71,6 +71,9 @@ def lib():
         L.orc_precond.argtypes = [ctypes.c_void_p, P, P, P, P]
         L.orc_vel_subsolve.argtypes = [ctypes.c_void_p, P, P]
         L.orc_p_subsolve.argtypes = [ctypes.c_void_p, P, P]
+        for f in ("orc_vel_mg_solve", "orc_p_mg_solve"):
+            getattr(L, f).argtypes = [ctypes.c_void_p, P, P, ctypes.c_double, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.orc_vel_sweep.argtypes = [ctypes.c_void_p, P, P]
         L.orc_p_sweep.argtypes = [ctypes.c_void_p, P, P]
         L.orc_level_coef.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, P, ctypes.c_size_t]
@@ -177,6 +180,25 @@ class Oracle:
         if rc:
             raise OracleError(rc, "p_subsolve")
         return e
+
+    def _mg_solve(self, fn, r, n, tol, max_cycles):
+        r = _f64(r)
+        e = np.empty(n)
+        cyc, rel = ctypes.c_int(), ctypes.c_double()
+        rc = getattr(lib(), fn)(self._h, _p(r), _p(e), float(tol), int(max_cycles),
+                                ctypes.byref(cyc), ctypes.byref(rel))
+        if rc not in (ORC_OK, ORC_ENOCONV):
+            raise OracleError(rc, fn)
+        return e, cyc.value, rel.value, rc
+
+    def vel_mg_solve(self, r, tol=1e-10, max_cycles=200):
+        """Stand-alone velocity multigrid: V-cycles to ||r - A e|| <= tol ||r||.
+        Returns (e, cycles, rel_res, rc)."""
+        return self._mg_solve("orc_vel_mg_solve", r, self.nvel, tol, max_cycles)
+
+    def p_mg_solve(self, r, tol=1e-10, max_cycles=200):
+        """Stand-alone pressure multigrid, as vel_mg_solve for L_rho e = r."""
+        return self._mg_solve("orc_p_mg_solve", r, self.ncell, tol, max_cycles)
 
     def vel_sweep(self, rhs, phi):
         rhs, phi = _f64(rhs), _f64(phi).copy()

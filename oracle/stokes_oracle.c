@@ -702,6 +702,57 @@ static void p_sub(orc_ctx *X, const double *r_in, double *e) {
   free(r); free(t); free(de);
 }
 
+/* Stand-alone multigrid on one subproblem of the scaled system (Sec. 4.3.1:
+   the velocity and pressure multigrid solvers run to convergence are the
+   reference cost of a split, projection-like method).  Starting from e = 0,
+   each cycle applies one V-cycle to the current residual and adds the
+   correction, e <- e + V(r - A e), until ||r - A e|| <= tol ||r|| or
+   max_cycles cycles.  The right-hand side is first projected onto the range
+   of a singular operator (component means for the periodic steady velocity,
+   the mean for the pressure), and so is the result. */
+static int mg_solve(orc_ctx *X, int vel, const double *r_in, double *e, double tol,
+                    int max_cycles, int *cycles, double *rel) {
+  level_t *L = &X->lev[0];
+  const size_t n = vel ? L->nvel : L->ncell;
+  double *r = (double *)malloc(n * sizeof(double));
+  double *res = (double *)malloc(n * sizeof(double));
+  double *de = (double *)malloc(n * sizeof(double));
+  if (!r || !res || !de) {
+    free(r); free(res); free(de);
+    return ORC_ENOMEM;
+  }
+  copyv(r, r_in, n);
+  if (vel) {
+    if (X->vel_singular) remove_vel_means(L, r);
+  } else {
+    remove_mean(r, n);
+  }
+  const double nr = sqrt(dotv(r, r, n));
+  zerov(e, n);
+  copyv(res, r, n);
+  double q = (nr > 0.0) ? 1.0 : 0.0;
+  int c = 0;
+  while (q > tol && c < max_cycles) {
+    if (vel) vcycle_vel(X, 0, res, de);
+    else vcycle_p(X, 0, res, de);
+    for (size_t i = 0; i < n; i++) e[i] += de[i];
+    c++;
+    if (vel) vel_residual(L, r, e, res);
+    else p_residual(L, r, e, res);
+    q = sqrt(dotv(res, res, n)) / nr;
+  }
+  if (vel) {
+    if (X->vel_singular) remove_vel_means(L, e);
+  } else {
+    remove_mean(e, n);
+  }
+  free(r); free(res); free(de);
+  *cycles = c;
+  *rel = q;
+  if (!isfinite(q)) return ORC_ENONFINITE;
+  return (q <= tol) ? ORC_OK : ORC_ENOCONV;
+}
+
 /* ------------------------------------------------------------------------ */
 /* preconditioners (Sec. 2)                                                  */
 /* ------------------------------------------------------------------------ */
@@ -1290,6 +1341,26 @@ int orc_p_subsolve(orc_ctx *X, const double *r, double *e) {
   p_sub(X, r, e);
   for (size_t i = 0; i < X->raw.ncell; i++) e[i] /= X->c;
   return ORC_OK;
+}
+
+int orc_vel_mg_solve(orc_ctx *X, const double *r, double *e, double tol, int max_cycles,
+                     int *cycles, double *rel_res) {
+  if (!X || !r || !e || !cycles || !rel_res || !(tol > 0.0) || max_cycles < 0) return ORC_EINVAL;
+  const size_t nv = X->raw.nvel;
+  double *t = (double *)malloc(nv * sizeof(double));
+  if (!t) return ORC_ENOMEM;
+  for (size_t i = 0; i < nv; i++) t[i] = X->c * r[i];
+  const int rc = mg_solve(X, 1, t, e, tol, max_cycles, cycles, rel_res);
+  free(t);
+  return rc;
+}
+
+int orc_p_mg_solve(orc_ctx *X, const double *r, double *e, double tol, int max_cycles,
+                   int *cycles, double *rel_res) {
+  if (!X || !r || !e || !cycles || !rel_res || !(tol > 0.0) || max_cycles < 0) return ORC_EINVAL;
+  const int rc = mg_solve(X, 0, r, e, tol, max_cycles, cycles, rel_res);
+  for (size_t i = 0; i < X->raw.ncell; i++) e[i] /= X->c;
+  return rc;
 }
 
 int orc_vel_sweep(orc_ctx *X, const double *rhs, double *phi) {

@@ -74,6 +74,14 @@ int orc_precond(orc_ctx *c, const double *bu, const double *bp, double *zu, doub
 /* velocity subsolver e = A~^{-1} r and pressure subsolver e = L~_rho^{-1} r (unscaled). */
 int orc_vel_subsolve(orc_ctx *c, const double *r, double *e);
 int orc_p_subsolve(orc_ctx *c, const double *r, double *e);
+/* Stand-alone multigrid solves of the same subproblems (unscaled): V-cycles
+   e <- e + V(r - A e) from e = 0 until ||r - A e|| <= tol ||r|| or
+   max_cycles; *cycles and *rel_res report what was done.  ORC_ENOCONV when
+   max_cycles ran out (e holds the last iterate). */
+int orc_vel_mg_solve(orc_ctx *c, const double *r, double *e, double tol, int max_cycles,
+                     int *cycles, double *rel_res);
+int orc_p_mg_solve(orc_ctx *c, const double *r, double *e, double tol, int max_cycles,
+                   int *cycles, double *rel_res);
 /* one multicolour Gauss-Seidel sweep on level 0 (unscaled operator), in place. */
 int orc_vel_sweep(orc_ctx *c, const double *rhs, double *phi);
 int orc_p_sweep(orc_ctx *c, const double *rhs, double *phi);

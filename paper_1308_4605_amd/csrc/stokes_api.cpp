@@ -720,6 +720,64 @@ int grad_impl(stokes_ctx *X, const double *u, const double *lam, double *dmu_cel
   return STOKES_OK;
 }
 
+// Stand-alone multigrid on one subproblem of the scaled system: V-cycles
+// e <- e + V(r - A e) from e = 0 until ||r - A e|| <= tol ||r||.  Residuals,
+// the iterate and the norms are FP64; the V-cycles run in the hierarchy's
+// precision (an FP32 hierarchy then acts as iterative refinement and still
+// reaches FP64 tolerances).  r and e are FP64 device vectors of the scaled
+// system (velocity: c times the user's r; pressure: the user's r).
+int mg_solve(stokes_ctx *X, bool vel, double tol, int max_cycles, int *cycles, double *rel) {
+  const Geo &g = X->lev[0].g;
+  const i64 n = vel ? X->nvel : X->ncell;
+  double *r = X->t, *e = X->x, *res = X->w, *de = X->r;
+  double *hb = X->host;
+  if (vel) {
+    if (X->vel_singular) remove_vel_means<double>(X, g, r);
+  } else {
+    remove_mean<double>(X, r, n, 21);
+  }
+  launch_norm2(r, n, X->part, X->dsc, X->s);
+  const double nr = std::sqrt(fetch(X, X->dsc, 1, hb));
+  if (X->err) return STOKES_EDEVICE;
+  launch_fill<double>(e, 0.0, n, X->s);
+  launch_scale(r, 1.0, res, n, X->s);
+  const double *beta64 = X->mg32 ? X->c64b[0] : P<double>(X->lev[0].beta);
+  double q = (nr > 0.0) ? 1.0 : 0.0;
+  int c = 0;
+  while (q > tol && c < max_cycles) {
+    if (X->mg32) {
+      float *pin = P<float>(X->pin), *pout = P<float>(X->pout);
+      launch_cast<float, double>(res, pin, n, X->s);
+      if (vel) vcycle_vel<float>(X, 0, pin, pout);
+      else vcycle_p<float>(X, 0, pin, pout);
+      const float *zs[1] = {pout};
+      const double one = 1.0;
+      launch_update_x<float>(e, zs, &one, 1, n, X->s);
+    } else {
+      if (vel) vcycle_vel<double>(X, 0, res, de);
+      else vcycle_p<double>(X, 0, res, de);
+      launch_axpy<double>(1.0, de, e, n, X->s);
+    }
+    c++;
+    if (vel)
+      launch_vel_residual<double>(g, m_alpha_of(X), X->m_muc, X->m_mue, r, e, nullptr, res, X->s);
+    else
+      launch_p_residual<double>(g, beta64, r, e, res, X->s);
+    launch_norm2(res, n, X->part, X->dsc, X->s);
+    q = std::sqrt(fetch(X, X->dsc, 1, hb)) / nr;
+    if (X->err) return STOKES_EDEVICE;
+  }
+  if (vel) {
+    if (X->vel_singular) remove_vel_means<double>(X, g, e);
+  } else {
+    remove_mean<double>(X, e, n, 22);
+  }
+  *cycles = c;
+  *rel = q;
+  if (!std::isfinite(q)) return STOKES_ENONFINITE;
+  return (q <= tol) ? STOKES_OK : STOKES_ENOCONV;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -935,6 +993,31 @@ int stokes_p_subsolve(stokes_ctx *X, const double *r, double *e) {
   }
   launch_scale(X->w, 1.0 / X->c, e, X->ncell, X->s);
   return finish(X, STOKES_OK);
+}
+
+int stokes_vel_mg_solve(stokes_ctx *X, const double *r, double *e, double tol, int max_cycles,
+                        int *cycles, double *rel_res) {
+  if (!X || !r || !e || !cycles || !rel_res || !(tol > 0.0) || max_cycles < 0)
+    return STOKES_EINVAL;
+  const Geo &g = X->lev[0].g;
+  launch_pack_vel(g, r, X->c, X->t, X->s);
+  const int rc = mg_solve(X, true, tol, max_cycles, cycles, rel_res);
+  if (rc == STOKES_EDEVICE) return finish(X, rc);
+  launch_pack_vel(g, X->x, 1.0, e, X->s);
+  hip_ok(X, hipStreamSynchronize(X->s));
+  return finish(X, rc);
+}
+
+int stokes_p_mg_solve(stokes_ctx *X, const double *r, double *e, double tol, int max_cycles,
+                      int *cycles, double *rel_res) {
+  if (!X || !r || !e || !cycles || !rel_res || !(tol > 0.0) || max_cycles < 0)
+    return STOKES_EINVAL;
+  launch_scale(r, 1.0, X->t, X->ncell, X->s);
+  const int rc = mg_solve(X, false, tol, max_cycles, cycles, rel_res);
+  if (rc == STOKES_EDEVICE) return finish(X, rc);
+  launch_scale(X->x, 1.0 / X->c, e, X->ncell, X->s);
+  hip_ok(X, hipStreamSynchronize(X->s));
+  return finish(X, rc);
 }
 
 int stokes_solve(stokes_ctx *X, const double *bu, const double *bp, double *xu, double *xp,

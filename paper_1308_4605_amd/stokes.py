@@ -28,7 +28,8 @@ STOKES_EINCOMPAT = -7
 # names declared in include/stokes.h
 ABI_FUNCTIONS = (
     "stokes_sizes", "stokes_workspace_bytes", "stokes_create", "stokes_apply", "stokes_precond",
-    "stokes_vel_subsolve", "stokes_p_subsolve", "stokes_solve", "stokes_adjoint_solve",
+    "stokes_vel_subsolve", "stokes_p_subsolve", "stokes_vel_mg_solve", "stokes_p_mg_solve",
+    "stokes_solve", "stokes_adjoint_solve",
     "stokes_grad", "stokes_rescale", "stokes_set_timing", "stokes_kernel_time", "stokes_destroy",
     "stokes_strerror",
 )
@@ -83,6 +84,9 @@ def lib():
         L.stokes_precond.argtypes = [vp, dp, dp, dp, dp]
         L.stokes_vel_subsolve.argtypes = [vp, dp, dp]
         L.stokes_p_subsolve.argtypes = [vp, dp, dp]
+        for f in ("stokes_vel_mg_solve", "stokes_p_mg_solve"):
+            getattr(L, f).argtypes = [vp, dp, dp, ctypes.c_double, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.stokes_solve.argtypes = [vp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(StokesStats)]
         L.stokes_adjoint_solve.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
@@ -214,6 +218,23 @@ class Stokes:
         if rc:
             raise StokesError(rc, "stokes_p_subsolve")
         return e
+
+    def _mg_solve(self, fn, r, n, tol, max_cycles):
+        e = self._new(n)
+        cyc, rel = ctypes.c_int(), ctypes.c_double()
+        rc = getattr(lib(), fn)(self._h, _ptr(r), _ptr(e), float(tol), int(max_cycles),
+                                ctypes.byref(cyc), ctypes.byref(rel))
+        if rc not in (STOKES_OK, STOKES_ENOCONV):
+            raise StokesError(rc, fn)
+        return e, cyc.value, rel.value, rc
+
+    def vel_mg_solve(self, r, tol=1e-10, max_cycles=200):
+        """Velocity multigrid run to ||r - A e|| <= tol ||r||: (e, cycles, rel_res, rc)."""
+        return self._mg_solve("stokes_vel_mg_solve", r, self.nvel, tol, max_cycles)
+
+    def p_mg_solve(self, r, tol=1e-10, max_cycles=200):
+        """Pressure multigrid run to ||r - L e|| <= tol ||r||: (e, cycles, rel_res, rc)."""
+        return self._mg_solve("stokes_p_mg_solve", r, self.ncell, tol, max_cycles)
 
     def solve(self, bu, bp, tol=1e-8, max_iter=1000, x0=None, check=True, out=None):
         if out is not None:
