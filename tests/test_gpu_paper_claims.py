@@ -48,3 +48,23 @@ def test_bubble_128_paper_bounds(precision, krylov):
         assert rc == 0 and st["iters"] <= bound
         if r == 100.0:
             assert st["scalar_vcycles"] <= g1["max_scalar_vcycles"]
+
+
+@pytest.mark.parametrize("precision,krylov", [(W.FP64, W.GMRES_LEFT), (W.MG_FP32, W.FGMRES)])
+def test_bubble_viscous_cfl_sweep_128(precision, krylov):
+    """Sec. 4.4.1 at the paper's 3D size: the steady limit is slowest,
+    convergence slows with beta, P2 beats P1 at theta = 0, P1 is at least as
+    good as P2 for intermediate beta (tests/golden/paper_claims.json)."""
+    from test_oracle_paper_claims import _cfl_sweep, check_cfl_claims
+
+    def solve(w, P):
+        p = w.params(precond=P, precision=precision, krylov=krylov)
+        g, o = pair(p, w.rho, w.mu)
+        bu, bp = _rhs(o, w)
+        _, _, st, rc = g.solve(T(bu), T(bp), tol=1e-10, max_iter=400)
+        assert rc == 0
+        return st["iters"], st["scalar_vcycles"]
+
+    res = {P: _cfl_sweep(3, 128, P, solve) for P in (W.P1, W.P2)}
+    print(f"128^3 precision={precision}: {res}", flush=True)
+    check_cfl_claims(res)

@@ -40,3 +40,39 @@ def test_bubble_steady_preconditioner_ranking():
     assert cost[W.P4] == max(cost.values())
     for P in (W.P1, W.P2, W.P3):
         assert _solve(w, precond=P, restart=5)["iters"] >= _solve(w, precond=P)["iters"]
+
+
+def _cfl_sweep(dim, n, P, solve):
+    """Iterations and scalar V-cycles over the viscous CFL numbers of the
+    golden entry (surrounding fluid mu0 = rho0 = r, so theta = 1/(beta h^2))."""
+    h = 1.0 / n
+    out = []
+    for beta in GOLD["viscous_cfl"]["betas"]:
+        w = W.bubble(dim, n, 100.0, 100.0)
+        theta = 0.0 if beta == "steady" else 1.0 / (h * h * beta)
+        w.theta = theta
+        out.append(solve(w, P))
+    return out
+
+
+def check_cfl_claims(res):
+    """res[P] = [(iters, scalar_vcycles) per beta, last = steady]."""
+    for P, row in res.items():
+        its = [r[0] for r in row]
+        assert its[-1] == max(its), (P, its)
+        assert all(b >= a - 1 for a, b in zip(its, its[1:])), (P, its)
+        assert its[-1] > its[0], (P, its)
+    assert res[W.P2][-1][1] < res[W.P1][-1][1]
+    for k in range(1, len(res[W.P1]) - 1):
+        assert res[W.P1][k][0] <= res[W.P2][k][0] + 1
+
+
+@pytest.mark.parametrize("dim,n", [(2, 128), (3, 32)])
+def test_bubble_viscous_cfl_sweep(dim, n):
+    def solve(w, P):
+        st = _solve(w, precond=P, theta=w.theta)
+        return st["iters"], st["scalar_vcycles"]
+
+    res = {P: _cfl_sweep(dim, n, P, solve) for P in (W.P1, W.P2)}
+    print(dim, n, res)
+    check_cfl_claims(res)
