@@ -20,13 +20,14 @@
  *     entries (n[2] = 1 in 2D).
  *   velocity: the d components stored back to back in one buffer.  Component
  *     k lives on faces normal to axis k and has n[a] entries along a != k and
- *     n[k] + bc[k] entries along k (bc = 1 for no-slip walls).  Wall faces
- *     (index 0 and n[k] on a no-slip axis) are not unknowns: inputs may hold
- *     anything there (they are read as 0); outputs hold 0 there.
+ *     n[k] + w[k] entries along k, w[k] = 1 when axis k has walls (no-slip or
+ *     free-slip) and 0 when it is periodic.  Wall faces (index 0 and n[k] on
+ *     a wall axis) are not unknowns: inputs may hold anything there (they are
+ *     read as 0); outputs hold 0 there.
  *   edge viscosity: families m = 2, 1, 0 (3D) or m = 2 (2D, the grid nodes)
  *     stored back to back.  Family m is parallel to axis m and carries the
  *     viscosity of the shear stress between the two other axes; it has
- *     n[a] + bc[a] entries along each a != m and n[m] along m.
+ *     n[a] + w[a] entries along each a != m and n[m] along m.
  * Every pointer passed to the functions below is a DEVICE pointer except the
  * parameter/stat structs and `hip_stream`, unless stated otherwise.  Inputs
  * are never modified.  All vectors are FP64.
@@ -69,7 +70,10 @@ enum {
 };
 
 /* boundary condition per axis (both ends) */
-enum { STOKES_PERIODIC = 0, STOKES_NOSLIP = 1 };
+/* Boundary conditions per axis (Sec. 3.1).  No-slip: u = 0 on the wall, the
+   shear next to it one-sided.  Free-slip: zero normal velocity and no
+   tangential momentum flux through the wall. */
+enum { STOKES_PERIODIC = 0, STOKES_NOSLIP = 1, STOKES_FREESLIP = 2 };
 
 /* block preconditioners of Sec. 2: projection (eq. P1_practical), lower
    triangular (eq. CC_Pre_lower), upper triangular (eq. CC_Pre_upper),
@@ -93,7 +97,7 @@ typedef struct {
   int dim;          /* 2 or 3 */
   int n[3];         /* cells per axis (n[2] ignored in 2D) */
   double h;         /* grid spacing (> 0) */
-  int bc[3];        /* STOKES_PERIODIC or STOKES_NOSLIP per axis */
+  int bc[3];        /* STOKES_PERIODIC, STOKES_NOSLIP or STOKES_FREESLIP per axis */
   double theta;     /* >= 0 */
   int precond;      /* STOKES_P1..STOKES_P5 */
   int precision;    /* STOKES_FP64 or STOKES_MG_FP32 */
@@ -155,8 +159,9 @@ int stokes_apply(stokes_ctx *ctx, const double *xu, const double *xp, double *yu
 
 /* z = P^{-1} b for the configured preconditioner and precision (Sec. 2), the
    same operator the Krylov solver applies.  Output pressure has zero mean;
-   with a singular velocity operator (all axes periodic, theta = 0) the output
-   velocity components have zero mean (Sec. 3.2 null-space care). */
+   the output velocity components that are singular have zero mean (Sec. 3.2
+   null-space care).  Component k of the velocity operator is singular when
+   theta = 0, axis k is periodic and no axis has no-slip walls. */
 int stokes_precond(stokes_ctx *ctx, const double *bu, const double *bp, double *zu, double *zp);
 
 /* The two multigrid subsolvers alone (Sec. 3.2, Appendix C): e = A~^{-1} r
@@ -189,9 +194,9 @@ int stokes_p_mg_solve(stokes_ctx *ctx, const double *r, double *e, double tol, i
    Arnoldi steps.  use_x0 != 0 starts from the given x (a restart, Sec. 4.2.2),
    else from 0.  x is the solution of the unscaled system with p of zero mean
    (and zero-mean velocity components when the velocity operator is singular).
-   b_p must have zero mean (STOKES_EINCOMPAT otherwise), as must each velocity
-   component of b_u when all axes are periodic and theta = 0.  stats may be
-   NULL.  Synchronous. */
+   b_p must have zero mean (STOKES_EINCOMPAT otherwise), as must each singular
+   velocity component of b_u (see stokes_precond).  stats may be NULL.
+   Synchronous. */
 int stokes_solve(stokes_ctx *ctx, const double *bu, const double *bp, double *xu, double *xp,
                  double tol, int max_iter, int use_x0, stokes_stats *stats);
 
@@ -202,7 +207,8 @@ int stokes_solve(stokes_ctx *ctx, const double *bu, const double *bp, double *xu
      dL/dmu_cell  = -2 sum_k (D^k lambda_k)(D^k u_k)  + chain through the
                     derived edge viscosity (EDGE_ARITH/HARMONIC),
      dL/dmu_edge  = -w_e gamma_e(lambda) gamma_e(u),  w_e = 1/2 on no-slip
-                    wall edges, 1 elsewhere (partial derivative),
+                    wall edges, 0 on free-slip wall edges, 1 elsewhere
+                    (partial derivative),
      dL/drho_cell = -theta sum over the cell's faces of 1/2 lambda_f u_f.
    g is first projected onto the mean-free space of the solution (the adjoint
    of the zero-mean normalisation of p, and of u when the velocity operator is

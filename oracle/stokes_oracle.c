@@ -46,7 +46,9 @@
 typedef struct {
   int d;      /* dimension */
   int n[3];   /* cells per axis (n[2] = 1 for d = 2) */
-  int ns[3];  /* 1: no-slip walls on this axis, 0: periodic */
+  int ns[3];  /* 1: walls on this axis (no-slip or free-slip), 0: periodic */
+  int fs[3];  /* 1: the walls on this axis are free-slip */
+  int sing;   /* bit k: velocity component k is singular (mean removed) */
   double h;   /* grid spacing */
 } grid_t;
 
@@ -216,8 +218,15 @@ static double dkl(const level_t *L, const double *u, int k, int l, const int e[3
   return (fget(L, u, k, f) - fget(L, u, k, fb)) / h;
 }
 
-/* shear rate gamma_kl = du_k/dx_l + du_l/dx_k at an edge */
+/* the edge lies on a free-slip wall of axis a */
+static int on_free_slip(const grid_t *g, int a, const int e[3]) {
+  return g->fs[a] && (e[a] == 0 || e[a] == g->n[a]);
+}
+
+/* shear rate gamma_kl = du_k/dx_l + du_l/dx_k at an edge; zero on a free-slip
+   wall, where the tangential momentum flux vanishes (Sec. 3.1) */
 static double shear_rate(const level_t *L, const double *u, int k, int l, const int e[3]) {
+  if (on_free_slip(&L->g, k, e) || on_free_slip(&L->g, l, e)) return 0.0;
   return dkl(L, u, k, l, e) + dkl(L, u, l, k, e);
 }
 
@@ -274,8 +283,11 @@ static double a_diag(const level_t *L, const double *alpha, const double *mu_c,
     int ehi[3] = {f[0], f[1], f[2]};
     ehi[l] += 1;
     if (!g->ns[l]) ehi[l] = wrapi(ehi[l], g->n[l]);
-    double wlo = (g->ns[l] && f[l] == 0) ? 2.0 : 1.0;
-    double whi = (g->ns[l] && f[l] + 1 == g->n[l]) ? 2.0 : 1.0;
+    /* a no-slip wall edge carries the one-sided difference (weight 2), a
+       free-slip wall edge no flux (weight 0) */
+    const double wwall = g->fs[l] ? 0.0 : 2.0;
+    double wlo = (g->ns[l] && f[l] == 0) ? wwall : 1.0;
+    double whi = (g->ns[l] && f[l] + 1 == g->n[l]) ? wwall : 1.0;
     dg += (whi * mu_e[eidx(L, m, ehi)] + wlo * mu_e[eidx(L, m, elo)]) / h2;
   }
   return dg;
@@ -386,6 +398,7 @@ static void zerov(double *a, size_t n) { memset(a, 0, n * sizeof(double)); }
 static void remove_vel_means(const level_t *L, double *u) {
   const grid_t *g = &L->g;
   for (int k = 0; k < g->d; k++) {
+    if (!((g->sing >> k) & 1)) continue;
     int dm[3];
     face_dims(g, k, dm);
     double s = 0.0;
@@ -530,7 +543,8 @@ static void restrict_faces(const level_t *F, const level_t *C, const double *rf,
    weight 3/4 and the next coarse neighbour away from j's parent centre with
    weight 1/4 (j even: J-1, j odd: J+1).  At a no-slip wall the missing
    neighbour is the odd reflection -phi(J), consistent with zero tangential
-   velocity on the wall (reading). */
+   velocity on the wall; at a free-slip wall the even reflection +phi(J),
+   consistent with zero normal derivative (reading). */
 static int tang_weights(const grid_t *gc, int a, int j, int idx[2], double w[2]) {
   int J = j / 2;
   int Jn = (j % 2 == 0) ? J - 1 : J + 1;
@@ -538,7 +552,7 @@ static int tang_weights(const grid_t *gc, int a, int j, int idx[2], double w[2])
   w[0] = 0.75;
   if (gc->ns[a] && (Jn < 0 || Jn >= gc->n[a])) {
     idx[1] = J;
-    w[1] = -0.25;
+    w[1] = gc->fs[a] ? 0.25 : -0.25;
   } else {
     idx[1] = gc->ns[a] ? Jn : wrapi(Jn, gc->n[a]);
     w[1] = 0.25;
@@ -1219,13 +1233,15 @@ int orc_create(const orc_params *p, const double *rho, const double *mu,
   int nmin = 1 << 30;
   for (int a = 0; a < 3; a++) {
     if (a < g.d) {
-      if (p->n[a] < 2 || (p->bc[a] != 0 && p->bc[a] != 1)) return ORC_EINVAL;
+      if (p->n[a] < 2 || p->bc[a] < ORC_PERIODIC || p->bc[a] > ORC_FREESLIP) return ORC_EINVAL;
       g.n[a] = p->n[a];
-      g.ns[a] = p->bc[a];
+      g.ns[a] = (p->bc[a] != ORC_PERIODIC);
+      g.fs[a] = (p->bc[a] == ORC_FREESLIP);
       if (g.n[a] < nmin) nmin = g.n[a];
     } else {
       g.n[a] = 1;
       g.ns[a] = 0;
+      g.fs[a] = 0;
     }
   }
   /* the smallest axis must be a power of two >= 2; every axis must halve
@@ -1264,9 +1280,18 @@ int orc_create(const orc_params *p, const double *rho, const double *mu,
       if (mu[i] > 0.0) { sl += log(mu[i]); cnt++; }
     X->c = cnt ? g.h / exp(sl / (double)cnt) : 1.0;
   }
-  X->vel_singular = (p->theta == 0.0);
-  for (int a = 0; a < g.d; a++)
-    if (g.ns[a]) X->vel_singular = 0;
+  /* velocity null space at theta = 0: component k is constant-invariant when
+     its own axis is periodic and no axis has no-slip walls (free-slip walls
+     only fix the normal component) */
+  X->vel_singular = 0;
+  if (p->theta == 0.0) {
+    int noslip = 0;
+    for (int a = 0; a < g.d; a++) noslip |= (g.ns[a] && !g.fs[a]);
+    for (int k = 0; k < g.d; k++)
+      if (!g.ns[k] && !noslip) X->vel_singular |= 1 << k;
+  }
+  g.sing = X->vel_singular;
+  X->raw.g.sing = g.sing;
 
   X->lev = (level_t *)calloc((size_t)nlev, sizeof(level_t));
   if (!X->lev) { orc_destroy(X); return ORC_ENOMEM; }
@@ -1409,6 +1434,7 @@ static int rhs_compatible(const orc_ctx *X, const double *bu, const double *bp) 
   if (fabs(s) > 1e-10 * scale * sqrt((double)L->ncell)) return 0;
   if (X->vel_singular) {
     for (int k = 0; k < L->g.d; k++) {
+      if (!((X->vel_singular >> k) & 1)) continue;
       double sk = 0.0;
       for (size_t i = 0; i < L->fcnt[k]; i++) sk += bu[L->foff[k] + i];
       if (fabs(sk) > 1e-10 * scale * sqrt((double)L->fcnt[k])) return 0;

@@ -31,7 +31,7 @@ extern "C" {
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ENOCONV = -4,
        ORC_EBREAKDOWN = -5, ORC_ENONFINITE = -6, ORC_EINCOMPAT = -7 };
-enum { ORC_PERIODIC = 0, ORC_NOSLIP = 1 };
+enum { ORC_PERIODIC = 0, ORC_NOSLIP = 1, ORC_FREESLIP = 2 };
 enum { ORC_P1 = 1, ORC_P2 = 2, ORC_P3 = 3, ORC_P4 = 4, ORC_P5 = 5 };
 enum { ORC_GMRES_LEFT = 0, ORC_FGMRES = 1 };
 enum { ORC_EDGE_ARITH = 0, ORC_EDGE_HARMONIC = 1, ORC_EDGE_GIVEN = 2 };

@@ -61,7 +61,8 @@ bool valid_params(const stokes_params *p, int *nlev_out) {
   int nmin = 1 << 30;
   for (int a = 0; a < p->dim; a++) {
     if (p->n[a] < 2 || p->n[a] > (1 << 20)) return false;
-    if (p->bc[a] != STOKES_PERIODIC && p->bc[a] != STOKES_NOSLIP) return false;
+    if (p->bc[a] != STOKES_PERIODIC && p->bc[a] != STOKES_NOSLIP && p->bc[a] != STOKES_FREESLIP)
+      return false;
     if (p->n[a] < nmin) nmin = p->n[a];
   }
   // coarsen by 2 until the smallest axis has two cells (Appendix C)
@@ -90,7 +91,7 @@ struct stokes_ctx {
   hipStream_t s = nullptr;
   int d = 0, nlev = 0;
   int mg32 = 0;
-  int vel_singular = 0;
+  int vel_singular = 0;  // bit k: velocity component k has a constant null space
   int tail_l = -1;  // first level of the single-workgroup coarse tail (-1: none)
   double c = 1.0;
   Level lev[kMaxLev];
@@ -687,11 +688,10 @@ int check_rhs(stokes_ctx *X) {
   const double c = X->c;
   const double nrm = std::sqrt(hb[2] + hb[3] / (c * c)) + 1e-300;
   if (std::fabs(hb[1]) > 1e-10 * nrm * std::sqrt((double)X->ncell)) return STOKES_EINCOMPAT;
-  if (X->vel_singular) {
-    for (int k = 0; k < g.d; k++)
-      if (std::fabs(hb[4 + k] / c) > 1e-10 * nrm * std::sqrt((double)g.fcnt[k]))
-        return STOKES_EINCOMPAT;
-  }
+  for (int k = 0; k < g.d; k++)
+    if (((X->vel_singular >> k) & 1) &&
+        std::fabs(hb[4 + k] / c) > 1e-10 * nrm * std::sqrt((double)g.fcnt[k]))
+      return STOKES_EINCOMPAT;
   return STOKES_OK;
 }
 
@@ -835,9 +835,17 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
   X->ncell = g0.ncell;
   X->nedge = g0.nedge;
   X->n = g0.nvel + g0.ncell;
-  X->vel_singular = (p->theta == 0.0);
-  for (int a = 0; a < p->dim; a++)
-    if (p->bc[a] == STOKES_NOSLIP) X->vel_singular = 0;
+  // velocity null space at theta = 0: component k is constant-invariant when
+  // its own axis is periodic and no axis has no-slip walls (free-slip walls
+  // only fix the normal component)
+  X->vel_singular = 0;
+  if (p->theta == 0.0) {
+    int noslip = 0;
+    for (int a = 0; a < p->dim; a++) noslip |= (p->bc[a] == STOKES_NOSLIP);
+    for (int k = 0; k < p->dim; k++)
+      if (p->bc[k] == STOKES_PERIODIC && !noslip) X->vel_singular |= 1 << k;
+  }
+  for (int l = 0; l < nlev; l++) X->lev[l].g.sing = X->vel_singular;
   // coarse tail: the levels small enough for one workgroup (at most kTailMax)
   for (int l = std::max(0, nlev - kTailMax); l < nlev; l++)
     if (X->lev[l].g.ncell <= kTailCells) {

@@ -20,7 +20,9 @@ typedef long long i64;
 struct Geo {
   int d;
   int n[3];
-  int ns[3];
+  int ns[3];  // walls on this axis (no-slip or free-slip)
+  int fs[3];  // the walls on this axis are free-slip
+  int sing;   // bit k: velocity component k has a constant null space
   double h, ih;  // spacing and its reciprocal
   i64 ncell, nvel, nedge;
   i64 foff[3];
@@ -32,7 +34,8 @@ struct Geo {
   int xcd;  // stencil kernels: one band of rows per XCD
 };
 
-Geo make_geo(int d, const int n[3], const int ns[3], double h);
+// bc[a]: STOKES_PERIODIC, STOKES_NOSLIP or STOKES_FREESLIP per axis
+Geo make_geo(int d, const int n[3], const int bc[3], double h);
 
 // ---- launch wrappers (all asynchronous on stream s) ----------------------
 
@@ -95,7 +98,7 @@ constexpr i64 kTailCells = 4096;  // largest level run inside the tail
 template <typename T>
 struct TailLevels {
   int nl;        // number of levels in the tail (the last is the coarsest)
-  int singular;  // velocity: remove component means at the coarsest level
+  int singular;  // velocity: bit k set = remove component k's mean at the coarsest level
   int nu_pre, nu_post, nu_coarse;
   Geo g[kTailMax];
   const T *a[kTailMax], *b[kTailMax], *mc[kTailMax], *me[kTailMax];  // alpha, beta, mu_c, mu_e

@@ -29,15 +29,17 @@ static inline dim3 box_blocks(const Geo &g, int W) {
   return dim3(blocks_for((i64)g.n[1] * W), (unsigned)g.n[2]);
 }
 
-Geo make_geo(int d, const int n[3], const int ns[3], double h) {
+Geo make_geo(int d, const int n[3], const int bc[3], double h) {
   Geo g;
   g.d = d;
   g.h = h;
   g.ih = 1.0 / h;
   for (int a = 0; a < 3; a++) {
     g.n[a] = (a < d) ? n[a] : 1;
-    g.ns[a] = (a < d) ? ns[a] : 0;
+    g.ns[a] = (a < d) ? (bc[a] != 0) : 0;
+    g.fs[a] = (a < d) ? (bc[a] == 2) : 0;
   }
+  g.sing = 0;
   g.ncell = (i64)g.n[0] * g.n[1] * g.n[2];
   g.xcd = 1;
   i64 off = 0;
@@ -183,7 +185,8 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
     const T ghi = (ua[l] - uf) * ih + (ulh_r - ulh_l) * ih;
     const T glo = (uf - ub[l]) * ih + (ull_r - ull_l) * ih;
     s += (mhi * ghi - mlo * glo) * ih;
-    dg += ((top ? (T)2 : (T)1) * mhi + (bot ? (T)2 : (T)1) * mlo) * ih2;
+    const T ww = g.fs[l] ? (T)0 : (T)2;  // wall edge: one-sided (no-slip) or no flux
+    dg += ((top ? ww : (T)1) * mhi + (bot ? ww : (T)1) * mlo) * ih2;
   }
   Au = al * uf - s;
   diag = dg;
@@ -218,8 +221,10 @@ __device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const
     t[l] = dn1(g, l, i[l]);
     const T vb = u[fidx3(g, k, t)];
     t[l] = i[l];
-    ua[l] = top ? -uf : va;
-    ub[l] = bot ? -uf : vb;
+    // no-slip: odd ghost (zero wall value); free-slip: even ghost (no shear)
+    const T gs = g.fs[l] ? uf : -uf;
+    ua[l] = top ? gs : va;
+    ub[l] = bot ? gs : vb;
   }
   const T *comp[3] = {u + g.foff[0], u + g.foff[1], u + g.foff[2]};
   a_row_nb<T, DIM>(g, k, i, uf, ukp, ukm, ua, ub, comp, alpha, muc, mue, Au, diag);
@@ -515,7 +520,8 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
     const int lm = dn1(g, l, i[l]);
     t[l] = top ? i[l] : lp;  // component k has no face at index n[l] along l
     const double va = (double)u[fidx3(g, k, t)];  // unconditional; ghost selected below
-    const double ua = top ? -uf : va;
+    const double gsv = g.fs[l] ? uf : -uf;  // wall ghost: even (free-slip) or odd
+    const double ua = top ? gsv : va;
     t[l] = lp;
     const double mhi = mue[eidx3(g, m, t)];
     const double ulh_r = (double)u[fidx3(g, l, t)];
@@ -524,7 +530,7 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
     t[k] = i[k];
     t[l] = lm;
     const double vb = (double)u[fidx3(g, k, t)];
-    const double ub = bot ? -uf : vb;
+    const double ub = bot ? gsv : vb;
     t[l] = i[l];
     const double mlo = mue[eidx3(g, m, t)];
     const double ull_r = (double)u[fidx3(g, l, t)];
@@ -791,7 +797,7 @@ __device__ __forceinline__ void tang_w(const Geo &gc, int a, int j, int idx[2], 
   w[0] = 0.75;
   if (gc.ns[a] && (Jn < 0 || Jn >= gc.n[a])) {
     idx[1] = J;
-    w[1] = -0.25;
+    w[1] = gc.fs[a] ? 0.25 : -0.25;  // even reflection at a free-slip wall
   } else {
     int jj = Jn;
     if (!gc.ns[a]) {
@@ -1132,15 +1138,15 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_vel(TailLevels<T> L) {
     const int l = nl - 1;
     const Geo &g = L.g[l];
     tail_zero<T>(P.phi[l], g.nvel);
-    if (L.singular) {
-      for (int k = 0; k < g.d; k++)
+    for (int k = 0; k < g.d; k++) {
+      if ((L.singular >> k) & 1)
         tail_sub_mean<T>(P.rhs[l] + g.foff[k], P.res[l] + g.foff[k], g.fcnt[k]);
-    } else {
-      tail_copy<T>(P.rhs[l], P.res[l], g.nvel);
+      else
+        tail_copy<T>(P.rhs[l] + g.foff[k], P.res[l] + g.foff[k], g.fcnt[k]);
     }
     tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.res[l], P.phi[l], L.nu_coarse);
-    if (L.singular)
-      for (int k = 0; k < g.d; k++)
+    for (int k = 0; k < g.d; k++)
+      if ((L.singular >> k) & 1)
         tail_sub_mean<T>(P.phi[l] + g.foff[k], P.phi[l] + g.foff[k], g.fcnt[k]);
   }
   for (int l = nl - 2; l >= 0; l--) {
@@ -1442,7 +1448,8 @@ __global__ void k_vel_sub_means(Geo g, const T *__restrict__ in, T *__restrict__
                                 const double *__restrict__ sums) {
   const int k = blockIdx.y;
   const i64 n = g.fcnt[k];
-  const T mean = (T)(sums[k] / (double)n);
+  // components without a constant null space are copied unchanged
+  const T mean = ((g.sing >> k) & 1) ? (T)(sums[k] / (double)n) : (T)0;
   const T *__restrict__ a = in + g.foff[k];
   T *__restrict__ o = out + g.foff[k];
   const i64 t0 = (i64)blockIdx.x * blockDim.x * 4 + threadIdx.x;
@@ -1788,9 +1795,12 @@ __global__ void k_grad_edges(Geo g, int m, const double *__restrict__ u,
   const int l = (m == 2) ? 1 : 2;
   const bool wall = (g.ns[k] && (e[k] == 0 || e[k] == g.n[k])) ||
                     (g.ns[l] && (e[l] == 0 || e[l] == g.n[l]));
+  // no shear stress (and no dependence on mu_edge) on a free-slip wall
+  const bool free = (g.fs[k] && (e[k] == 0 || e[k] == g.n[k])) ||
+                    (g.fs[l] && (e[l] == 0 || e[l] == g.n[l]));
   const double gu = dkl(g, u, k, l, e) + dkl(g, u, l, k, e);
   const double gl = dkl(g, lam, k, l, e) + dkl(g, lam, l, k, e);
-  dme[g.eoff[m] + t] = -(wall ? 0.5 : 1.0) * gl * gu;
+  dme[g.eoff[m] + t] = free ? 0.0 : -(wall ? 0.5 : 1.0) * gl * gu;
 }
 
 // dmu_cell += sum over the cell's edges of dmu_edge * d mu_edge / d mu_cell

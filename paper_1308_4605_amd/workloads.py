@@ -21,6 +21,7 @@ import numpy as np
 
 PERIODIC = 0
 NOSLIP = 1
+FREESLIP = 2
 
 P1, P2, P3, P4, P5 = 1, 2, 3, 4, 5
 GMRES_LEFT, FGMRES = 0, 1
@@ -37,7 +38,8 @@ class Layout:
     """Shapes of the flat ABI arrays (C order, x fastest).
 
     Velocity component k lives on the faces normal to axis k and has one more
-    entry along k when that axis has no-slip walls (the wall faces, held at 0).
+    entry along k when that axis has walls, no-slip or free-slip (the wall
+    faces, held at 0).
     Edge family m is parallel to axis m; it has one more entry along each of
     the other axes that has walls.  Families are stored in the order m = 2, 1, 0
     (3D) or m = 2 only (2D, where the edges are the grid nodes).
@@ -55,14 +57,18 @@ class Layout:
     def cell_shape(self):
         return self._np(self.n)
 
+    def wall(self, a):
+        """1 when axis a has walls (no-slip or free-slip), else 0."""
+        return 1 if (a < self.dim and self.bc[a] != PERIODIC) else 0
+
     def face_dims(self, k):
-        return tuple(self.n[a] + (self.bc[a] if (a == k and a < self.dim) else 0) for a in range(3))
+        return tuple(self.n[a] + (self.wall(a) if a == k else 0) for a in range(3))
 
     def face_shape(self, k):
         return self._np(self.face_dims(k))
 
     def edge_dims(self, m):
-        return tuple(self.n[a] + (self.bc[a] if (a != m and a < self.dim) else 0) for a in range(3))
+        return tuple(self.n[a] + (self.wall(a) if a != m else 0) for a in range(3))
 
     def edge_shape(self, m):
         return self._np(self.edge_dims(m))
@@ -103,11 +109,11 @@ class Layout:
         return out
 
     def wall_mask(self):
-        """Flat bool mask of stored velocity entries that are no-slip wall faces."""
+        """Flat bool mask of stored velocity entries that are wall faces."""
         parts = []
         for k in range(self.dim):
             m = np.zeros(self.face_shape(k), dtype=bool)
-            if self.bc[k] == NOSLIP:
+            if self.wall(k):
                 ax = self.dim - 1 - k  # numpy axis of grid axis k
                 idx = [slice(None)] * self.dim
                 idx[ax] = 0
@@ -128,6 +134,13 @@ class Layout:
                 axes.append((np.arange(dims) + 0.5) * h)
         grids = np.meshgrid(*axes[::-1], indexing="ij")
         return grids[::-1]
+
+    def singular_components(self, theta):
+        """Velocity components with a constant null space: theta = 0, the
+        component's own axis periodic and no axis with no-slip walls."""
+        if theta != 0.0 or any(self.bc[a] == NOSLIP for a in range(self.dim)):
+            return []
+        return [k for k in range(self.dim) if self.bc[k] == PERIODIC]
 
     def cell_centres(self, h):
         axes = [(np.arange(self.n[a]) + 0.5) * h for a in range(self.dim)]
@@ -214,15 +227,21 @@ def smooth_face_field(rng, lay: Layout, h, K, kmax, remove_mean=True):
         parts.append(v.ravel())
     u = np.concatenate(parts)
     u[lay.wall_mask()] = 0.0
-    if remove_mean:
+    if remove_mean is True:
         u = _remove_component_means(lay, u)
+    elif remove_mean:
+        u = _remove_component_means(lay, u, comps=tuple(remove_mean))
     return u
 
 
-def _remove_component_means(lay: Layout, u):
+def _remove_component_means(lay: Layout, u, comps=None):
+    """Subtract the interior mean of each velocity component (of `comps`
+    only, when given)."""
     u = u.copy()
     wm = lay.wall_mask()
-    for o, c in zip(lay.face_offsets, lay.face_counts):
+    for k, (o, c) in enumerate(zip(lay.face_offsets, lay.face_counts)):
+        if comps is not None and k not in comps:
+            continue
         seg = u[o:o + c]
         interior = ~wm[o:o + c]
         seg[interior] -= seg[interior].mean()

@@ -81,8 +81,9 @@ def kron_sum(mats):
 
 def textbook_vector_laplacian(lay: W.Layout, h):
     """Laplace-form vector Laplacian per component (no coupling), on the
-    interior unknowns of each component, with the no-slip rule (normal
-    direction: Dirichlet nodes; tangential: zero wall value half a cell out)."""
+    interior unknowns of each component, with the wall rules (normal
+    direction: Dirichlet nodes; tangential: zero wall value half a cell out
+    at no-slip walls, zero normal derivative at free-slip walls)."""
     blocks = []
     for k in range(lay.dim):
         mats = []
@@ -92,6 +93,8 @@ def textbook_vector_laplacian(lay: W.Layout, h):
                 mats.append(second_diff_1d(n, h, "periodic"))
             elif a == k:
                 mats.append(second_diff_1d(n, h, "dirichlet"))
+            elif lay.bc[a] == W.FREESLIP:
+                mats.append(second_diff_1d(n, h, "neumann_cc"))
             else:
                 mats.append(second_diff_1d(n, h, "wall_cc"))
         blocks.append(kron_sum(mats))

@@ -47,8 +47,7 @@ def test_full_precond(name, prec):
     p = w.params(precision=prec, krylov=_krylov(prec))
     g, _ = pair(p, w.rho, w.mu)
     o = oracle.Oracle(rho=w.rho, mu=w.mu, **dict(p, precision=W.FP64))
-    sing = w.theta == 0 and all(b == 0 for b in w.bc[:w.dim])
-    bu = W.random_velocity(3, w.layout, remove_mean=sing)
+    bu = W.random_velocity(3, w.layout, remove_mean=w.layout.singular_components(w.theta))
     bp = W.random_cells(4, w.layout, remove_mean=True)
     zu, zp = g.precond(T(bu), T(bp))
     ou, op = o.precond(bu, bp)

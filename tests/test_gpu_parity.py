@@ -28,6 +28,9 @@ OPS = [
     (2, (32, 32), (0, 0)), (2, (48, 32), (1, 1)), (2, (192, 64), (0, 1)), (2, (2, 2), (1, 1)),
     (3, (16, 16, 16), (1, 1, 1)), (3, (16, 16, 16), (0, 0, 0)), (3, (48, 40, 8), (1, 0, 1)),
     (3, (32, 48, 16), (0, 1, 0)), (3, (24, 16, 16), (1, 1, 1)), (3, (2, 2, 2), (0, 0, 0)),
+    # free-slip walls (2), alone and mixed
+    (2, (48, 32), (2, 2)), (2, (64, 32), (0, 2)), (3, (16, 16, 16), (2, 2, 2)),
+    (3, (48, 40, 8), (2, 0, 1)), (3, (32, 16, 16), (2, 1, 0)),
 ]
 
 
@@ -62,8 +65,7 @@ def test_subsolver_parity(dim, n, bc, theta):
     p, lay = params(dim, n, bc, theta)
     rho, mu = _coefs(lay, 2)
     g, o = pair(p, rho, mu)
-    singular = theta == 0.0 and all(b == 0 for b in lay.bc[:dim])
-    r = W.random_velocity(7, lay, remove_mean=singular)
+    r = W.random_velocity(7, lay, remove_mean=lay.singular_components(theta))
     e = N(g.vel_subsolve(T(r)))
     assert rel(e, o.vel_subsolve(r)) <= 1e-11
     q = W.random_cells(8, lay, remove_mean=True)
@@ -71,15 +73,16 @@ def test_subsolver_parity(dim, n, bc, theta):
 
 
 @pytest.mark.parametrize("dim,n,bc,theta", [(2, (48, 32), (1, 1), 25.0), (3, (16, 16, 16), (0, 0, 0), 0.0),
-                                            (3, (48, 40, 8), (1, 0, 1), 100.0), (2, (32, 32), (0, 0), 0.0)])
+                                            (3, (48, 40, 8), (1, 0, 1), 100.0), (2, (32, 32), (0, 0), 0.0),
+                                            (2, (48, 32), (2, 2), 0.0), (3, (32, 16, 16), (2, 0, 2), 0.0),
+                                            (3, (16, 16, 16), (2, 1, 2), 40.0)])
 @pytest.mark.parametrize("precond", [W.P1, W.P2, W.P3, W.P4, W.P5])
 def test_precond_parity(dim, n, bc, theta, precond):
     print(f"precond P{precond} {dim} {n} {bc} theta={theta}", flush=True)
     p, lay = params(dim, n, bc, theta, precond=precond)
     rho, mu = _coefs(lay, 3)
     g, o = pair(p, rho, mu)
-    singular = theta == 0.0 and all(b == 0 for b in lay.bc[:dim])
-    bu = W.random_velocity(9, lay, remove_mean=singular)
+    bu = W.random_velocity(9, lay, remove_mean=lay.singular_components(theta))
     bp = W.random_cells(10, lay, remove_mean=True)
     zu, zp = g.precond(T(bu), T(bp))
     ou, op = o.precond(bu, bp)
@@ -124,7 +127,7 @@ def test_mixed_precision_solve(name, mk, over):
     p.update(krylov=W.FGMRES, precision=W.MG_FP32)
     g, o = pair(p, w.rho, w.mu)
     # preconditioner itself: FP32 against the FP64 oracle
-    bu = W.random_velocity(11, w.layout, remove_mean=(w.theta == 0 and all(b == 0 for b in w.bc[:w.dim])))
+    bu = W.random_velocity(11, w.layout, remove_mean=w.layout.singular_components(w.theta))
     bp = W.random_cells(12, w.layout, remove_mean=True)
     zu, zp = g.precond(T(bu), T(bp))
     ou, op = o.precond(bu, bp)
@@ -142,7 +145,8 @@ def test_mixed_precision_solve(name, mk, over):
 
 
 @pytest.mark.parametrize("dim,n,bc,theta", [(2, (32, 32), (1, 1), 100.0), (3, (16, 16, 16), (1, 1, 1), 100.0),
-                                            (2, (32, 32), (0, 0), 0.0), (3, (16, 16, 16), (0, 1, 0), 10.0)])
+                                            (2, (32, 32), (0, 0), 0.0), (3, (16, 16, 16), (0, 1, 0), 10.0),
+                                            (2, (32, 32), (2, 2), 0.0), (3, (16, 16, 16), (2, 0, 1), 10.0)])
 @pytest.mark.parametrize("edge_avg", [W.EDGE_ARITH, W.EDGE_HARMONIC])
 def test_grad_contraction_parity(dim, n, bc, theta, edge_avg):
     print(f"grad {dim} {n} {bc}", flush=True)
@@ -200,3 +204,37 @@ def test_error_paths():
     # zero right-hand side: zero solution, no iterations
     xu, xp, st, rc = g.solve(T(np.zeros(lay.nvel)), T(np.zeros(lay.ncell)))
     assert rc == 0 and st["iters"] == 0 and np.all(N(xu) == 0)
+
+
+FREESLIP = [
+    # dim, n, bc, theta
+    (2, (64, 64), (2, 2), 0.0),
+    (3, (32, 32, 32), (2, 0, 2), 0.0),
+    (3, (32, 32, 32), (2, 2, 1), 10.0),
+]
+
+
+@pytest.mark.parametrize("dim,n,bc,theta", FREESLIP)
+@pytest.mark.parametrize("precond", [W.P1, W.P2])
+@pytest.mark.parametrize("precision,krylov", [(W.FP64, W.GMRES_LEFT), (W.FP64, W.FGMRES),
+                                              (W.MG_FP32, W.FGMRES)])
+def test_solve_parity_freeslip(dim, n, bc, theta, precond, precision, krylov):
+    """Free-slip walls (zero normal velocity, no tangential momentum flux),
+    variable coefficients, b = M x for a seeded x (Sec. 4 protocol)."""
+    print(f"free-slip solve {dim} {n} {bc} theta={theta} P{precond} prec={precision} kry={krylov}",
+          flush=True)
+    p, lay = params(dim, n, bc, theta, precond=precond, precision=precision, krylov=krylov)
+    rho, mu = W.random_coefficients(41, lay, mu_range=(0.2, 5.0), rho_range=(0.5, 2.0))
+    g, _ = pair(p, rho, mu)
+    o = oracle.Oracle(rho=rho, mu=mu, **dict(p, precision=W.FP64))
+    xu0 = W.random_velocity(42, lay, remove_mean=lay.singular_components(theta))
+    bu, bp = o.apply(xu0, W.random_cells(43, lay))
+    bp = bp - bp.mean()
+    xu, xp, st, rc = g.solve(T(bu), T(bp), tol=1e-9, max_iter=600)
+    ou, op, ost, orc = o.solve(bu, bp, tol=1e-9, max_iter=600)
+    print(f"  gpu iters {st['iters']} oracle iters {ost['iters']}", flush=True)
+    assert rc == 0 and orc == 0
+    if precision == W.FP64:
+        assert abs(st["iters"] - ost["iters"]) <= 1
+    assert scaled_residual(o, o.c, bu, bp, N(xu), N(xp)) <= 1e-9 * (1 + 1e-6)
+    assert rel(N(xu), ou) <= 1e-6

@@ -16,6 +16,12 @@ CASES = [
     (3, (4, 4, 4), (1, 1, 1)),
     (3, (4, 4, 4), (0, 0, 0)),
     (3, (4, 8, 4), (1, 0, 1)),
+    # free-slip walls (2) alone and mixed with no-slip / periodic axes
+    (2, (8, 8), (2, 2)),
+    (2, (8, 4), (0, 2)),
+    (2, (8, 8), (1, 2)),
+    (3, (4, 4, 4), (2, 2, 2)),
+    (3, (4, 8, 4), (2, 0, 1)),
 ]
 
 
@@ -174,13 +180,15 @@ def test_periodic_commuting_properties():
         assert rel(Lp @ D, D @ L) < 1e-13
 
 
-def test_energy_form_of_viscous_operator():
+@pytest.mark.parametrize("bc", [(1, 0, 1), (2, 0, 1), (2, 2, 2)])
+def test_energy_form_of_viscous_operator(bc):
     """-u^T L_mu u = sum_cells 2 mu_c sum_k (D^k u_k)^2 + sum_edges w_e mu_e
-    gamma_e^2, with w_e = 1/2 on no-slip wall edges (symmetric form used by the
-    adjoint).  The oracle's gradient contraction must equal the exact
-    derivative of lambda^T (-L_mu) u with respect to each coefficient, which is
-    a finite difference of the assembled operator (linear in mu)."""
-    dim, n, bc = 3, (4, 4, 4), (1, 0, 1)
+    gamma_e^2, with w_e = 1/2 on no-slip wall edges and no flux through
+    free-slip walls (symmetric form used by the adjoint).  The oracle's
+    gradient contraction must equal the exact derivative of
+    lambda^T (-L_mu) u with respect to each coefficient, which is a finite
+    difference of the assembled operator (linear in mu)."""
+    dim, n = 3, (4, 4, 4)
     lay = W.make_layout(dim, n, bc)
     h = 1.0 / lay.n[0]
     rho, mu = W.random_coefficients(5, lay)

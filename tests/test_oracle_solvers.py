@@ -84,7 +84,9 @@ def test_gmres_matches_fft_exact_solution(dim, n, theta, precond):
 
 @pytest.mark.parametrize("dim,n,bc,theta", [
     (2, (8, 8), (1, 1), 0.0), (2, (8, 8), (0, 0), 30.0), (2, (8, 8), (0, 1), 0.0),
-    (2, (8, 8), (0, 0), 0.0), (3, (4, 4, 4), (1, 1, 1), 10.0), (3, (4, 4, 4), (1, 0, 0), 0.0)])
+    (2, (8, 8), (0, 0), 0.0), (3, (4, 4, 4), (1, 1, 1), 10.0), (3, (4, 4, 4), (1, 0, 0), 0.0),
+    (2, (8, 8), (2, 2), 0.0), (2, (8, 8), (0, 2), 0.0), (3, (4, 4, 4), (2, 1, 2), 10.0),
+    (3, (4, 4, 4), (2, 2, 0), 0.0)])
 @pytest.mark.parametrize("precond,krylov", [(W.P1, W.GMRES_LEFT), (W.P2, W.GMRES_LEFT),
                                             (W.P3, W.GMRES_LEFT), (W.P5, W.GMRES_LEFT),
                                             (W.P1, W.FGMRES), (W.P4, W.FGMRES)])
@@ -92,7 +94,7 @@ def test_gmres_matches_dense_direct_solve(dim, n, bc, theta, precond, krylov):
     lay = W.make_layout(dim, n, bc)
     rho, mu = W.random_coefficients(17, lay, mu_range=(0.1, 10.0), rho_range=(0.5, 3.0))
     o, lay, h = _mk(dim, lay.n, lay.bc, theta, rho, mu, precond=precond, krylov=krylov)
-    singular_u = theta == 0.0 and all(b == 0 for b in lay.bc[:dim])
+    singular_u = lay.singular_components(theta)
     bu = W.random_velocity(5, lay, remove_mean=singular_u)
     bp = W.random_cells(6, lay, remove_mean=True)
     xu, xp, st, rc = o.solve(bu, bp, tol=1e-12, max_iter=2000)
@@ -106,7 +108,7 @@ def test_gmres_matches_dense_direct_solve(dim, n, bc, theta, precond, krylov):
     xu_d[vel] = x[:nv]
     xp_d = x[nv:]
     if singular_u:
-        xu_d = W._remove_component_means(lay, xu_d)
+        xu_d = W._remove_component_means(lay, xu_d, comps=singular_u)
     sv = np.linalg.svd(M, compute_uv=False)
     sv = sv[sv > 1e-12 * sv[0]]
     tol = max(10 * 1e-12 * sv[0] / sv[-1], 1e-10)
@@ -118,13 +120,26 @@ def test_gmres_matches_dense_direct_solve(dim, n, bc, theta, precond, krylov):
 # manufactured solutions: global second order (Sec. 3.1)
 # ---------------------------------------------------------------------------
 
-def _mms_fields(dim, periodic):
+def _mms_fields(dim, periodic, freeslip=False):
     """Exact velocity, pressure, viscosity, density as sympy expressions and
     the forcing f = theta rho u - div(mu (grad u + grad u^T)) + grad p."""
     import sympy as sp
 
     X = sp.symbols("x y z")[:dim]
     pi = sp.pi
+    if freeslip:
+        # divergence free; zero normal velocity and zero normal derivative of
+        # the tangential components on every wall (both shear terms vanish)
+        c = [sp.cos(pi * X[a]) for a in range(dim)]
+        sn = [sp.sin(pi * X[a]) for a in range(dim)]
+        if dim == 2:
+            u = [sn[0] * c[1], -c[0] * sn[1]]
+        else:
+            u = [sn[0] * c[1] * c[2], c[0] * sn[1] * c[2], -2 * c[0] * c[1] * sn[2]]
+        p = sp.cos(pi * X[0]) * sp.cos(2 * pi * X[1])
+        mu = 1 + sp.Rational(1, 2) * X[0] * X[1]
+        rho = 1 + X[1] ** 2
+        return X, u, p, mu, rho
     if periodic:
         if dim == 2:
             psi = sp.sin(2 * pi * X[0]) * sp.cos(2 * pi * X[1]) / (2 * pi)
@@ -154,10 +169,10 @@ def _mms_fields(dim, periodic):
     return X, u, p, mu, rho
 
 
-def _mms_case(dim, n, periodic, theta):
+def _mms_case(dim, n, periodic, theta, freeslip=False):
     import sympy as sp
 
-    X, u, p, mu, rho = _mms_fields(dim, periodic)
+    X, u, p, mu, rho = _mms_fields(dim, periodic, freeslip)
     f = []
     for k in range(dim):
         div_tau = sum(sp.diff(mu * (sp.diff(u[k], X[l]) + sp.diff(u[l], X[k])), X[l]) for l in range(dim))
@@ -165,7 +180,7 @@ def _mms_case(dim, n, periodic, theta):
     g = sum(sp.diff(u[k], X[k]) for k in range(dim))
     assert sp.simplify(g) == 0
     lam = lambda e: sp.lambdify(X, e, "numpy")
-    bc = (0 if periodic else 1,) * dim
+    bc = (0 if periodic else (2 if freeslip else 1),) * dim
     lay = W.make_layout(dim, (n,) * dim, bc)
     h = 1.0 / n
     cc = lay.cell_centres(h)
@@ -188,11 +203,13 @@ def _mms_case(dim, n, periodic, theta):
     return eu, ep
 
 
-@pytest.mark.parametrize("dim,ns,periodic,theta", [
-    (2, (16, 32, 64), True, 0.0), (2, (16, 32, 64), False, 0.0), (2, (16, 32, 64), False, 50.0),
-    (3, (8, 16), True, 10.0), (3, (8, 16), False, 0.0)])
-def test_manufactured_solution_second_order(dim, ns, periodic, theta):
-    errs = [_mms_case(dim, n, periodic, theta) for n in ns]
+@pytest.mark.parametrize("dim,ns,periodic,theta,freeslip", [
+    (2, (16, 32, 64), True, 0.0, False), (2, (16, 32, 64), False, 0.0, False),
+    (2, (16, 32, 64), False, 50.0, False), (3, (8, 16), True, 10.0, False),
+    (3, (8, 16), False, 0.0, False), (2, (16, 32, 64), False, 0.0, True),
+    (3, (8, 16), False, 10.0, True)])
+def test_manufactured_solution_second_order(dim, ns, periodic, theta, freeslip):
+    errs = [_mms_case(dim, n, periodic, theta, freeslip) for n in ns]
     for (eu0, ep0), (eu1, ep1) in zip(errs[:-1], errs[1:]):
         ou = np.log2(eu0 / eu1)
         op = np.log2(ep0 / ep1)
@@ -420,7 +437,8 @@ def _loss_and_grad(dim, n, bc, theta, s, f, target, tol):
 
 
 @pytest.mark.parametrize("dim,n,bc,theta", [(2, (16, 16), (1, 1), 100.0), (3, (8, 8, 8), (1, 1, 1), 100.0),
-                                            (2, (16, 16), (0, 1), 0.0)])
+                                            (2, (16, 16), (0, 1), 0.0), (2, (16, 16), (2, 2), 0.0),
+                                            (3, (8, 8, 8), (2, 1, 2), 100.0)])
 def test_adjoint_gradient_matches_central_differences(dim, n, bc, theta):
     """dL/ds (mu = exp(s)) and dL/df from the adjoint solve match central
     finite differences of L = 1/2 ||u - u_target||^2 with forward solves at
