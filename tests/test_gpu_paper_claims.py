@@ -68,3 +68,35 @@ def test_bubble_viscous_cfl_sweep_128(precision, krylov):
     res = {P: _cfl_sweep(3, 128, P, solve) for P in (W.P1, W.P2)}
     print(f"128^3 precision={precision}: {res}", flush=True)
     check_cfl_claims(res)
+
+
+@pytest.mark.parametrize("precision,krylov", [(W.MG_FP32, W.FGMRES), (W.FP64, W.GMRES_LEFT)])
+def test_bubble_512_paper_bound(precision, krylov):
+    """The paper's largest grid, 512^3 (134 M cells), contrast 100, P1: at
+    most 50 GMRES iterations and 200 scalar V-cycles to 1e-10 (Sec. 4.3.2).
+    b = M x is formed with the GPU's own M (parity-tested at smaller sizes)."""
+    import torch
+
+    from paper_1308_4605_amd.stokes import Stokes
+
+    g1 = GOLD["bubble_p1_contrast_100"]
+    w = W.bubble(3, 512, 100.0, 100.0)
+    p = w.params(precision=precision, krylov=krylov)
+    S = Stokes(p, T(w.rho), T(w.mu))
+    bu, bp = S.apply(T(w.extra["x_u"]), T(w.extra["x_p"]))
+    bp -= bp.mean()
+    import time
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xu, xp, st, rc = S.solve(bu, bp, tol=1e-10, max_iter=200)
+    torch.cuda.synchronize()
+    print(f"512^3 precision={precision}: {st['iters']} iterations, {st['scalar_vcycles']} scalar "
+          f"V-cycles, rel res {st['rel_res_true']:.2e}, {time.perf_counter() - t0:.2f} s",
+          flush=True)
+    S.close()
+    del S, bu, bp, xu, xp
+    torch.cuda.empty_cache()
+    assert rc == 0 and st["rel_res_true"] <= 1e-10
+    assert st["iters"] <= g1["max_gmres_iterations"]
+    assert st["scalar_vcycles"] <= g1["max_scalar_vcycles"]
