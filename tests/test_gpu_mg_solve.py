@@ -119,3 +119,27 @@ def test_coupled_costs_at_most_three_split_solves_64(precision):
     print(f"64^3 bubble precision {precision}: coupled {st['scalar_vcycles']} split {split} "
           f"ratio {ratio:.2f}", flush=True)
     assert gold["min_ratio_scalar_vcycles"] <= ratio <= gold["max_ratio_scalar_vcycles"]
+
+
+@pytest.mark.parametrize("dim,n", [(2, (512, 512)), (3, (128, 128, 128))])
+@pytest.mark.parametrize("precision", [W.FP64, W.MG_FP32])
+def test_vcycle_contraction_at_box_sizes(dim, n, precision):
+    """Constant-coefficient steady no-slip subproblems at 512^2 and 128^3: the
+    velocity V-cycle contracts the residual by at least 1/0.105 (2D) / 1/0.15
+    (3D) per cycle and the pressure V-cycle by at least tenfold (the same
+    bounds the oracle is pinned to at 128^2 / 32^3), so the stand-alone
+    multigrid reaches 1e-10 within ceil(log(1e-10) / log(rate)) + 1 cycles."""
+    import math
+
+    rate = {2: 0.105, 3: 0.15}[dim]
+    krylov = W.FGMRES if precision == W.MG_FP32 else W.GMRES_LEFT
+    p, lay = params(dim, n, (1,) * dim, 0.0, precision=precision, krylov=krylov)
+    g, _ = pair(p, np.ones(lay.ncell), np.ones(lay.ncell))
+    _, cv, qv, rcv = g.vel_mg_solve(T(W.random_velocity(35, lay)), tol=1e-10, max_cycles=100)
+    _, cp, qp, rcp = g.p_mg_solve(T(W.random_cells(36, lay, remove_mean=True)), tol=1e-10,
+                                  max_cycles=100)
+    print(f"{dim}D {n} precision={precision}: velocity {cv} cycles, pressure {cp} cycles",
+          flush=True)
+    assert rcv == rcp == 0
+    assert cv <= math.ceil(math.log(1e-10) / math.log(rate)) + 1
+    assert cp <= 11
