@@ -157,6 +157,21 @@ int stokes_create(const stokes_params *p, const double *rho_cell, const double *
    direct evaluation of the stencils at every interior face and cell, Sec. 3.2). */
 int stokes_apply(stokes_ctx *ctx, const double *xu, const double *xp, double *yu, double *yp);
 
+/* Prescribed (non-homogeneous) wall velocities (Sec. 3.2): with them the
+   operator is affine, M x + c, and the flow solves M x = b - c with the
+   homogeneous M used everywhere else.  This computes c = (cu, cp): M applied
+   to the field that is zero at the unknowns and carries
+     un: normal velocities on the wall faces (velocity layout; only the wall
+         entries are read), and
+     ut: tangential velocities on the wall edges (edge layout): an edge of
+         family m on a wall normal to axis l holds the wall value of velocity
+         component 3 - m - l (3D) or of the component parallel to the wall
+         (2D nodes); read on no-slip walls only (free-slip walls carry no
+         tangential flux).
+   cu is 0 on wall faces.  Asynchronous. */
+int stokes_boundary_rhs(stokes_ctx *ctx, const double *un, const double *ut, double *cu,
+                        double *cp);
+
 /* z = P^{-1} b for the configured preconditioner and precision (Sec. 2), the
    same operator the Krylov solver applies.  Output pressure has zero mean;
    the output velocity components that are singular have zero mean (Sec. 3.2

@@ -69,6 +69,7 @@ def lib():
         L.orc_rescale.restype = ctypes.c_double
         L.orc_apply.argtypes = [ctypes.c_void_p, P, P, P, P]
         L.orc_precond.argtypes = [ctypes.c_void_p, P, P, P, P]
+        L.orc_boundary_rhs.argtypes = [ctypes.c_void_p, P, P, P, P]
         L.orc_vel_subsolve.argtypes = [ctypes.c_void_p, P, P]
         L.orc_p_subsolve.argtypes = [ctypes.c_void_p, P, P]
         for f in ("orc_vel_mg_solve", "orc_p_mg_solve"):
@@ -180,6 +181,17 @@ class Oracle:
         if rc:
             raise OracleError(rc, "p_subsolve")
         return e
+
+    def boundary_rhs(self, un, ut):
+        """Boundary terms (cu, cp) of the affine operator for prescribed wall
+        velocities: normal values un on the wall faces (velocity layout) and
+        tangential values ut on the wall edges (edge layout)."""
+        un, ut = _f64(un), _f64(ut)
+        cu, cp = np.empty(self.nvel), np.empty(self.ncell)
+        rc = lib().orc_boundary_rhs(self._h, _p(un), _p(ut), _p(cu), _p(cp))
+        if rc:
+            raise OracleError(rc, "boundary_rhs")
+        return cu, cp
 
     def _mg_solve(self, fn, r, n, tol, max_cycles):
         r = _f64(r)

@@ -64,6 +64,10 @@ typedef struct {
   /* V-cycle work arrays */
   double *phi_u, *rhs_u, *res_u;
   double *phi_p, *rhs_p, *res_p;
+  /* prescribed wall velocities, set only while the boundary terms of the
+     affine operator are evaluated: normal values on wall faces (velocity
+     layout) and tangential values on wall edges (edge layout); NULL = 0 */
+  const double *bd_un, *bd_ut;
 } level_t;
 
 struct orc_ctx {
@@ -133,18 +137,18 @@ static int is_wall_face(const grid_t *g, int k, const int f[3]) {
   return g->ns[k] && (f[k] == 0 || f[k] == g->n[k]);
 }
 
-/* velocity component k at face index f; periodic indices wrap; no-slip wall
-   faces read as 0 (they are not unknowns). */
+/* velocity component k at face index f; periodic indices wrap; wall faces
+   are not unknowns and read as 0, or as the prescribed normal velocity while
+   boundary terms are evaluated. */
 static double fget(const level_t *L, const double *u, int k, const int f_in[3]) {
   const grid_t *g = &L->g;
   int f[3] = {f_in[0], f_in[1], f_in[2]};
+  int wall = 0;
   for (int a = 0; a < g->d; a++) {
     if (g->ns[a]) {
       if (a == k) {
-        if (f[a] <= 0 || f[a] >= g->n[a]) {
-          if (f[a] < 0 || f[a] > g->n[a]) fatal("face index outside wall range");
-          return 0.0;
-        }
+        if (f[a] < 0 || f[a] > g->n[a]) fatal("face index outside wall range");
+        if (f[a] == 0 || f[a] == g->n[a]) wall = 1;
       } else if (f[a] < 0 || f[a] >= g->n[a]) {
         fatal("tangential face index outside no-slip domain");
       }
@@ -154,7 +158,9 @@ static double fget(const level_t *L, const double *u, int k, const int f_in[3]) 
   }
   int dm[3];
   face_dims(g, k, dm);
-  return u[L->foff[k] + lin3(dm, f[0], f[1], f[2])];
+  const size_t q = L->foff[k] + lin3(dm, f[0], f[1], f[2]);
+  if (wall) return L->bd_un ? L->bd_un[q] : 0.0;
+  return u[q];
 }
 
 static size_t fidx(const level_t *L, int k, const int f[3]) {
@@ -206,12 +212,14 @@ static double dkl(const level_t *L, const double *u, int k, int l, const int e[3
   const grid_t *g = &L->g;
   const double h = g->h;
   int f[3] = {e[0], e[1], e[2]};
-  if (g->ns[l] && e[l] == 0) {
-    return 2.0 * fget(L, u, k, f) / h;
-  }
-  if (g->ns[l] && e[l] == g->n[l]) {
+  if (g->ns[l] && (e[l] == 0 || e[l] == g->n[l])) {
+    /* the wall value of u_k at this edge: 0, or the prescribed tangential
+       velocity while boundary terms are evaluated */
+    const int m = (g->d == 3) ? 3 - k - l : 2;
+    const double uw = L->bd_ut ? L->bd_ut[eidx(L, m, e)] : 0.0;
+    if (e[l] == 0) return 2.0 * (fget(L, u, k, f) - uw) / h;
     f[l] = g->n[l] - 1;
-    return -2.0 * fget(L, u, k, f) / h;
+    return -2.0 * (fget(L, u, k, f) - uw) / h;
   }
   int fb[3] = {e[0], e[1], e[2]};
   fb[l] -= 1;
@@ -1334,6 +1342,23 @@ double orc_rescale(const orc_ctx *X) { return X->c; }
 int orc_apply(orc_ctx *X, const double *xu, const double *xp, double *yu, double *yp) {
   if (!X || !xu || !xp || !yu || !yp) return ORC_EINVAL;
   apply_m(&X->raw, X->raw.alpha, X->raw.mu_c, X->raw.mu_e, xu, xp, yu, yp);
+  return ORC_OK;
+}
+
+int orc_boundary_rhs(orc_ctx *X, const double *un, const double *ut, double *cu, double *cp) {
+  if (!X || !un || !ut || !cu || !cp) return ORC_EINVAL;
+  level_t *L = &X->raw;
+  double *zu = (double *)calloc(L->nvel, sizeof(double));
+  double *zp = (double *)calloc(L->ncell, sizeof(double));
+  if (!zu || !zp) { free(zu); free(zp); return ORC_ENOMEM; }
+  /* M applied to the field that is zero inside and carries the prescribed
+     values on the walls: the boundary terms of the affine operator */
+  L->bd_un = un;
+  L->bd_ut = ut;
+  apply_m(L, L->alpha, L->mu_c, L->mu_e, zu, zp, cu, cp);
+  L->bd_un = NULL;
+  L->bd_ut = NULL;
+  free(zu); free(zp);
   return ORC_OK;
 }
 

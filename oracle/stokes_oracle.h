@@ -69,6 +69,13 @@ double orc_rescale(const orc_ctx *c);
 
 /* y = M x with the unscaled coefficients. */
 int orc_apply(orc_ctx *c, const double *xu, const double *xp, double *yu, double *yp);
+/* Boundary terms of the affine operator for prescribed wall velocities
+   (Sec. 3.2): (cu, cp) = M applied to the field that is zero at the unknowns
+   and holds un on the wall faces (normal velocity; interior entries of un
+   are ignored) and ut on the wall edges (tangential velocity of the
+   component parallel to the wall and normal to the edge; no-slip walls only).
+   The flow with those wall velocities solves M x = b - (cu, cp). */
+int orc_boundary_rhs(orc_ctx *c, const double *un, const double *ut, double *cu, double *cp);
 /* z = P^{-1} b (unscaled system). */
 int orc_precond(orc_ctx *c, const double *bu, const double *bp, double *zu, double *zp);
 /* velocity subsolver e = A~^{-1} r and pressure subsolver e = L~_rho^{-1} r (unscaled). */

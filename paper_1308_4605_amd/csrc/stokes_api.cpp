@@ -959,6 +959,22 @@ int stokes_apply(stokes_ctx *X, const double *xu, const double *xp, double *yu, 
   return finish(X, STOKES_OK);
 }
 
+int stokes_boundary_rhs(stokes_ctx *X, const double *un, const double *ut, double *cu,
+                        double *cp) {
+  if (!X || !un || !ut || !cu || !cp) return STOKES_EINVAL;
+  const Geo &g = X->lev[0].g;
+  // the wall-data field (prescribed normal velocities on the wall faces, zero
+  // at the unknowns) with p = 0, through the rescaled M with the prescribed
+  // tangential wall velocities in the no-slip ghosts
+  launch_pack_walls(g, un, 1.0, X->t, X->s);
+  launch_fill<double>(X->t + X->nvel, 0.0, X->ncell, X->s);
+  launch_apply_m_walls(g, m_alpha_of(X), X->m_muc, X->m_mue, X->t, X->t + X->nvel, ut, X->w,
+                       X->w + X->nvel, X->s);
+  launch_pack_vel(g, X->w, 1.0 / X->c, cu, X->s);
+  launch_scale(X->w + X->nvel, 1.0, cp, X->ncell, X->s);
+  return finish(X, STOKES_OK);
+}
+
 int stokes_precond(stokes_ctx *X, const double *bu, const double *bp, double *zu, double *zp) {
   if (!X || !bu || !bp || !zu || !zp) return STOKES_EINVAL;
   const Geo &g = X->lev[0].g;

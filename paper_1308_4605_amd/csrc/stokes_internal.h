@@ -69,6 +69,13 @@ template <typename TI>
 void launch_apply_m(const Geo &g, const double *alpha, const double *muc, const double *mue,
                     const TI *xu, const TI *xp, const double *bu, const double *bp, double *yu,
                     double *yp, hipStream_t s);
+// boundary terms of prescribed wall velocities: M applied to the wall-data
+// field xu (normal values on wall faces, zero inside) with tangential wall
+// values gw (edge layout) in the no-slip ghosts
+void launch_apply_m_walls(const Geo &g, const double *alpha, const double *muc,
+                          const double *mue, const double *xu, const double *xp,
+                          const double *gw, double *yu, double *yp, hipStream_t s);
+void launch_pack_walls(const Geo &g, const double *in, double scale, double *out, hipStream_t s);
 
 // multigrid level kernels, T = float or double
 template <typename T>

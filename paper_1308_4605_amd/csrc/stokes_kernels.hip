@@ -488,12 +488,15 @@ template void launch_axpy<double>(double, const double *, double *, i64, hipStre
 // saddle operator (FP64 arithmetic, input in TI)
 // ------------------------------------------------------------------------
 
-template <typename TI, int DIM>
+// GW: prescribed tangential wall velocities gw (edge layout) replace the
+// zero wall value of the no-slip ghost, 2 gw - u_f (boundary terms only).
+template <typename TI, int DIM, bool GW>
 __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
                                             const TI *__restrict__ u,
                                             const double *__restrict__ alpha,
                                             const double *__restrict__ muc,
-                                            const double *__restrict__ mue, double &Au) {
+                                            const double *__restrict__ mue,
+                                            const double *__restrict__ gw, double &Au) {
   const double ih = g.ih;
   const i64 fq = fidx3(g, k, i);
   const double uf = (double)u[fq];
@@ -521,35 +524,47 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
     t[l] = top ? i[l] : lp;  // component k has no face at index n[l] along l
     const double va = (double)u[fidx3(g, k, t)];  // unconditional; ghost selected below
     const double gsv = g.fs[l] ? uf : -uf;  // wall ghost: even (free-slip) or odd
-    const double ua = top ? gsv : va;
+    double ua = top ? gsv : va;
     t[l] = lp;
-    const double mhi = mue[eidx3(g, m, t)];
+    const int ehi = eidx3(g, m, t);
+    const double mhi = mue[ehi];
     const double ulh_r = (double)u[fidx3(g, l, t)];
     t[k] = km;
     const double ulh_l = (double)u[fidx3(g, l, t)];
     t[k] = i[k];
     t[l] = lm;
     const double vb = (double)u[fidx3(g, k, t)];
-    const double ub = bot ? gsv : vb;
+    double ub = bot ? gsv : vb;
     t[l] = i[l];
-    const double mlo = mue[eidx3(g, m, t)];
+    const int elo = eidx3(g, m, t);
+    const double mlo = mue[elo];
+    if (GW && !g.fs[l]) {
+      if (top) ua = 2.0 * gw[ehi] - uf;
+      if (bot) ub = 2.0 * gw[elo] - uf;
+    }
+    // with prescribed normal velocities on a free-slip wall the cross
+    // derivative along the wall need not vanish; the whole flux does
     const double ull_r = (double)u[fidx3(g, l, t)];
     t[k] = km;
     const double ull_l = (double)u[fidx3(g, l, t)];
     t[k] = i[k];
-    const double ghi = (ua - uf) * ih + (ulh_r - ulh_l) * ih;
-    const double glo = (uf - ub) * ih + (ull_r - ull_l) * ih;
+    double ghi = (ua - uf) * ih + (ulh_r - ulh_l) * ih;
+    double glo = (uf - ub) * ih + (ull_r - ull_l) * ih;
+    if (GW && g.fs[l]) {
+      if (top) ghi = 0.0;
+      if (bot) glo = 0.0;
+    }
     s += (mhi * ghi - mlo * glo) * ih;
   }
   Au = (alpha ? alpha[fq] * uf : 0.0) - s;  // no alpha array: theta = 0
 }
 
-template <typename TI, int DIM>
+template <typename TI, int DIM, bool GW>
 __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double *__restrict__ muc,
                           const double *__restrict__ mue, const TI *__restrict__ xu,
                           const TI *__restrict__ xp, const double *__restrict__ bu,
-                          const double *__restrict__ bp, double *__restrict__ yu,
-                          double *__restrict__ yp) {
+                          const double *__restrict__ bp, const double *__restrict__ gw,
+                          double *__restrict__ yu, double *__restrict__ yp) {
   int i[3];
   if (!box_thread(g, g.n[0], i[0], i[1], i[2])) return;
   const i64 t = cidx3(g, i);
@@ -567,7 +582,7 @@ __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double 
       continue;
     }
     double Au;
-    a_row_mixed<TI, DIM>(g, k, i, xu, alpha, muc, mue, Au);
+    a_row_mixed<TI, DIM, GW>(g, k, i, xu, alpha, muc, mue, gw, Au);
     int l[3] = {i[0], i[1], i[2]};
     l[k] = dn1(g, k, i[k]);
     const double gp = (pc - (double)xp[cidx3(g, l)]) * ih;
@@ -582,11 +597,11 @@ void launch_apply_m(const Geo &g, const double *alpha, const double *muc, const 
                     const TI *xu, const TI *xp, const double *bu, const double *bp, double *yu,
                     double *yp, hipStream_t s) {
   if (g.d == 3)
-    hipLaunchKernelGGL((k_apply_m<TI, 3>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
-                       alpha, muc, mue, xu, xp, bu, bp, yu, yp);
+    hipLaunchKernelGGL((k_apply_m<TI, 3, false>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
+                       alpha, muc, mue, xu, xp, bu, bp, nullptr, yu, yp);
   else
-    hipLaunchKernelGGL((k_apply_m<TI, 2>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
-                       alpha, muc, mue, xu, xp, bu, bp, yu, yp);
+    hipLaunchKernelGGL((k_apply_m<TI, 2, false>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
+                       alpha, muc, mue, xu, xp, bu, bp, nullptr, yu, yp);
 }
 template void launch_apply_m<double>(const Geo &, const double *, const double *, const double *,
                                      const double *, const double *, const double *,
@@ -594,6 +609,36 @@ template void launch_apply_m<double>(const Geo &, const double *, const double *
 template void launch_apply_m<float>(const Geo &, const double *, const double *, const double *,
                                     const float *, const float *, const double *, const double *,
                                     double *, double *, hipStream_t);
+
+void launch_apply_m_walls(const Geo &g, const double *alpha, const double *muc,
+                          const double *mue, const double *xu, const double *xp,
+                          const double *gw, double *yu, double *yp, hipStream_t s) {
+  if (g.d == 3)
+    hipLaunchKernelGGL((k_apply_m<double, 3, true>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s,
+                       g, alpha, muc, mue, xu, xp, nullptr, nullptr, gw, yu, yp);
+  else
+    hipLaunchKernelGGL((k_apply_m<double, 2, true>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s,
+                       g, alpha, muc, mue, xu, xp, nullptr, nullptr, gw, yu, yp);
+}
+
+// out = scale * in on the wall faces, 0 elsewhere (the wall-data field)
+__global__ void k_pack_walls(Geo g, const double *__restrict__ in, double scale,
+                             double *__restrict__ out) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.nvel) return;
+  int k = 0;
+  while (k + 1 < g.d && t >= g.foff[k + 1]) k++;
+  const i64 r = t - g.foff[k];
+  i64 stride = 1;
+  for (int a = 0; a < k; a++) stride *= g.fd[k][a];
+  const int ik = (int)((r / stride) % g.fd[k][k]);
+  const bool wall = g.ns[k] && (ik == 0 || ik == g.n[k]);
+  out[t] = wall ? scale * in[t] : 0.0;
+}
+void launch_pack_walls(const Geo &g, const double *in, double scale, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_walls, dim3(blocks_for(g.nvel)), dim3(kBlock), 0, s, g, in, scale,
+                     out);
+}
 
 // ------------------------------------------------------------------------
 // velocity multigrid (Appendix C)

@@ -27,7 +27,8 @@ STOKES_EINCOMPAT = -7
 
 # names declared in include/stokes.h
 ABI_FUNCTIONS = (
-    "stokes_sizes", "stokes_workspace_bytes", "stokes_create", "stokes_apply", "stokes_precond",
+    "stokes_sizes", "stokes_workspace_bytes", "stokes_create", "stokes_apply",
+    "stokes_boundary_rhs", "stokes_precond",
     "stokes_vel_subsolve", "stokes_p_subsolve", "stokes_vel_mg_solve", "stokes_p_mg_solve",
     "stokes_solve", "stokes_adjoint_solve",
     "stokes_grad", "stokes_rescale", "stokes_set_timing", "stokes_kernel_time", "stokes_destroy",
@@ -82,6 +83,7 @@ def lib():
                                     ctypes.POINTER(ctypes.c_void_p)]
         L.stokes_apply.argtypes = [vp, dp, dp, dp, dp]
         L.stokes_precond.argtypes = [vp, dp, dp, dp, dp]
+        L.stokes_boundary_rhs.argtypes = [vp, dp, dp, dp, dp]
         L.stokes_vel_subsolve.argtypes = [vp, dp, dp]
         L.stokes_p_subsolve.argtypes = [vp, dp, dp]
         for f in ("stokes_vel_mg_solve", "stokes_p_mg_solve"):
@@ -204,6 +206,15 @@ class Stokes:
         if rc:
             raise StokesError(rc, "stokes_precond")
         return zu, zp
+
+    def boundary_rhs(self, un, ut):
+        """Boundary terms (cu, cp) of prescribed wall velocities: normal values
+        un on the wall faces, tangential values ut on the wall edges."""
+        cu, cp = self._new(self.nvel), self._new(self.ncell)
+        rc = lib().stokes_boundary_rhs(self._h, _ptr(un), _ptr(ut), _ptr(cu), _ptr(cp))
+        if rc:
+            raise StokesError(rc, "stokes_boundary_rhs")
+        return cu, cp
 
     def vel_subsolve(self, r):
         e = self._new(self.nvel)

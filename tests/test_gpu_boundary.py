@@ -1,0 +1,83 @@
+"""Prescribed wall velocities on the GPU: the boundary terms against the
+oracle's (1e-12), Couette flow against its closed-form discrete solution, and
+a lid-driven cavity solved with the boundary terms on the right-hand side
+against the oracle (iterations +-1)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import N, T, pair, params, rel, scaled_residual
+from paper_1308_4605_amd import workloads as W
+from test_oracle_boundary import _couette_exact, _edge_views
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [
+    (2, (48, 32), (1, 1)), (2, (64, 32), (0, 1)), (2, (32, 32), (2, 1)),
+    (3, (16, 16, 16), (1, 1, 1)), (3, (32, 16, 16), (1, 2, 0)), (3, (16, 32, 16), (0, 0, 1)),
+]
+
+
+@pytest.mark.parametrize("dim,n,bc", GRIDS)
+@pytest.mark.parametrize("theta", [0.0, 20.0])
+def test_boundary_rhs_parity(dim, n, bc, theta):
+    print(f"boundary rhs {dim} {n} {bc} theta={theta}", flush=True)
+    p, lay = params(dim, n, bc, theta)
+    rho, mu = W.random_coefficients(61, lay, mu_range=(0.2, 5.0))
+    g, o = pair(p, rho, mu)
+    rng = np.random.default_rng(62)
+    un = rng.standard_normal(lay.nvel)
+    ut = rng.standard_normal(lay.nedge)
+    cu, cp = g.boundary_rhs(T(un), T(ut))
+    ocu, ocp = o.boundary_rhs(un, ut)
+    assert rel(N(cu), ocu) <= 1e-12
+    assert rel(N(cp), ocp) <= 1e-12
+    assert np.all(N(cu)[lay.wall_mask()] == 0.0)
+
+
+@pytest.mark.parametrize("precision,krylov", [(W.FP64, W.GMRES_LEFT), (W.MG_FP32, W.FGMRES)])
+def test_couette_flow_exact_gpu(precision, krylov):
+    n = (64, 256)
+    lay = W.make_layout(2, n, (W.PERIODIC, W.NOSLIP))
+    h = 1.0 / n[0]
+    rng = np.random.default_rng(63)
+    mu_nodes = rng.uniform(0.2, 5.0, n[1] + 1)
+    edges = np.repeat(mu_nodes[:, None], n[0], axis=1).ravel()
+    p, _ = params(2, n, (W.PERIODIC, W.NOSLIP), 0.0, precond=W.P2, precision=precision,
+                  krylov=krylov, edge_avg=W.EDGE_GIVEN)
+    g, _ = pair(p, np.ones(lay.ncell), np.ones(lay.ncell), edges)
+    ut = np.zeros(lay.nedge)
+    U = 2.5
+    _edge_views(lay, ut)[2][-1, :] = U
+    cu, cp = g.boundary_rhs(T(np.zeros(lay.nvel)), T(ut))
+    xu, xp, st, rc = g.solve(-cu, -cp, tol=1e-12, max_iter=1000)
+    assert rc == 0
+    ux, uy = lay.split_vel(N(xu))
+    uex, _ = _couette_exact(mu_nodes, h, U)
+    print(f"  precision {precision}: {st['iters']} iterations, max error "
+          f"{np.abs(ux - uex[:, None]).max():.2e}", flush=True)
+    assert np.abs(ux - uex[:, None]).max() <= 1e-9 * U
+    assert np.abs(uy).max() <= 1e-9 * U
+
+
+@pytest.mark.parametrize("precision,krylov", [(W.FP64, W.GMRES_LEFT), (W.MG_FP32, W.FGMRES)])
+def test_lid_driven_cavity_parity(precision, krylov):
+    """32^3 cavity with no-slip walls; the top z-wall moves along x at speed
+    1; variable viscosity; steady; P2."""
+    dim, n, bc = 3, (32, 32, 32), (1, 1, 1)
+    p, lay = params(dim, n, bc, 0.0, precond=W.P2, precision=precision, krylov=krylov)
+    rho, mu = W.random_coefficients(64, lay, mu_range=(0.5, 2.0))
+    g, _ = pair(p, rho, mu)
+    o = oracle.Oracle(rho=rho, mu=mu, **dict(p, precision=W.FP64))
+    ut = np.zeros(lay.nedge)
+    _edge_views(lay, ut)[1][-1, :, :] = 1.0
+    ocu, ocp = o.boundary_rhs(np.zeros(lay.nvel), ut)
+    cu, cp = g.boundary_rhs(T(np.zeros(lay.nvel)), T(ut))
+    xu, xp, st, rc = g.solve(-cu, -cp, tol=1e-9, max_iter=800)
+    ou, op, ost, orc = o.solve(-ocu, -ocp, tol=1e-9, max_iter=800)
+    print(f"  precision {precision}: gpu {st['iters']} oracle {ost['iters']} iterations", flush=True)
+    assert rc == orc == 0
+    if precision == W.FP64:
+        assert abs(st["iters"] - ost["iters"]) <= 1
+    assert scaled_residual(o, o.c, -ocu, -ocp, N(xu), N(xp)) <= 1e-9 * (1 + 1e-6)
+    assert rel(N(xu), ou) <= 1e-6
