@@ -12,7 +12,9 @@
  * cells sharing a face, L_mu the stress-form viscous operator
  * div(mu (grad u + grad u^T)) with cell viscosity on the normal stresses and
  * edge (3D) / node (2D) viscosity on the shear stresses.  theta = 0 is steady
- * Stokes flow, theta ~ 1/dt unsteady (Sec. 2).
+ * Stokes flow, theta ~ 1/dt unsteady (Sec. 2).  With bulk viscosity gamma
+ * (flows with div u = g != 0, Sec. 2) the stress gains
+ * (gamma - 2/3 mu)(div u) I, added to the normal stresses of each cell.
  *
  * ------------------------------------------------------------------------
  * Array layout (all arrays C-ordered, x fastest; axes 0,1,2 = x,y,z):
@@ -110,6 +112,8 @@ typedef struct {
   double rescale_c; /* rescaling c of eq. Stokes_rescaled; <= 0: c = h / mu_ref
                        with mu_ref the geometric mean of the positive mu_cell */
   int edge_avg;     /* STOKES_EDGE_* */
+  int bulk;         /* 0: incompressible stress form; 1: stress with bulk
+                       viscosity (stokes_create then takes gamma_cell) */
 } stokes_params;
 
 typedef struct {
@@ -145,13 +149,18 @@ size_t stokes_workspace_bytes(const stokes_params *p);
    coefficients (Appendix C), all on the device.
    rho_cell, mu_cell: cell fields (rho > 0, mu >= 0, finite);
    mu_edges: edge viscosity for STOKES_EDGE_GIVEN, else NULL;
+   gamma_cell: bulk viscosity per cell (>= 0, finite) when p->bulk = 1, else
+     NULL (STOKES_EINVAL otherwise).  With it the stress carries
+     (gamma - 2/3 mu)(div u) I (Sec. 2), coarse levels take the mean of the
+     fine cells' gamma - 2/3 mu, and the Schur approximation uses
+     gamma + 4/3 mu in place of 2 mu (eq. Schur_app_bulk);
    workspace: device buffer of ws_bytes >= stokes_workspace_bytes(p);
    hip_stream: a hipStream_t (NULL = the default stream).
    The coefficient fields are checked for sign and finiteness on the device
-   (one synchronisation); rho and mu are not retained. */
+   (one synchronisation); rho, mu and gamma are not retained. */
 int stokes_create(const stokes_params *p, const double *rho_cell, const double *mu_cell,
-                  const double *mu_edges, void *workspace, size_t ws_bytes, void *hip_stream,
-                  stokes_ctx **out);
+                  const double *mu_edges, const double *gamma_cell, void *workspace,
+                  size_t ws_bytes, void *hip_stream, stokes_ctx **out);
 
 /* y = M x with the caller's (unscaled) coefficients (Sec. 2, eq. Saddle_sys;
    direct evaluation of the stencils at every interior face and cell, Sec. 3.2). */
@@ -224,20 +233,24 @@ int stokes_solve(stokes_ctx *ctx, const double *bu, const double *bp, double *xu
      dL/dmu_edge  = -w_e gamma_e(lambda) gamma_e(u),  w_e = 1/2 on no-slip
                     wall edges, 0 on free-slip wall edges, 1 elsewhere
                     (partial derivative),
-     dL/drho_cell = -theta sum over the cell's faces of 1/2 lambda_f u_f.
+     dL/drho_cell = -theta sum over the cell's faces of 1/2 lambda_f u_f,
+   and with bulk viscosity (p->bulk = 1)
+     dL/dgamma_cell = -(D lambda)(D u), with -2/3 of it added to dL/dmu_cell
+                      (the coefficient gamma - 2/3 mu).
+   dgamma_cell must be NULL for contexts without bulk viscosity.
    g is first projected onto the mean-free space of the solution (the adjoint
    of the zero-mean normalisation of p, and of u when the velocity operator is
    singular), so any g is accepted.  Gradient outputs may be NULL.
    Synchronous. */
 int stokes_adjoint_solve(stokes_ctx *ctx, const double *xu, const double *xp, const double *gu,
                          const double *gp, double *lu, double *lp, double *dmu_cell,
-                         double *dmu_edge, double *drho_cell, double tol, int max_iter,
-                         stokes_stats *stats);
+                         double *dmu_edge, double *drho_cell, double *dgamma_cell, double tol,
+                         int max_iter, stokes_stats *stats);
 
 /* The strain-contraction gradient alone, given forward velocity u and adjoint
    velocity lambda (same formulas as above).  Asynchronous. */
 int stokes_grad(stokes_ctx *ctx, const double *xu, const double *lu, double *dmu_cell,
-                double *dmu_edge, double *drho_cell);
+                double *dmu_edge, double *drho_cell, double *dgamma_cell);
 
 /* Rescaling factor c in use (Sec. 3.3). */
 double stokes_rescale(const stokes_ctx *ctx);

@@ -59,7 +59,8 @@ def lib():
             build(force=True)
         L = ctypes.CDLL(_LIB)
         P = ctypes.POINTER(ctypes.c_double)
-        L.orc_create.argtypes = [ctypes.POINTER(_Params), P, P, P, ctypes.POINTER(ctypes.c_void_p)]
+        L.orc_create.argtypes = [ctypes.POINTER(_Params), P, P, P, P,
+                                 ctypes.POINTER(ctypes.c_void_p)]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         for f in ("orc_nvel", "orc_ncell", "orc_nedge"):
             getattr(L, f).argtypes = [ctypes.c_void_p]
@@ -81,9 +82,9 @@ def lib():
         L.orc_level_dims.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int * 3]
         L.orc_solve.argtypes = [ctypes.c_void_p, P, P, P, P, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_int, ctypes.POINTER(Stats)]
-        L.orc_adjoint.argtypes = [ctypes.c_void_p, P, P, P, P, P, P, P, P, P, ctypes.c_double,
-                                  ctypes.c_int, ctypes.POINTER(Stats)]
-        L.orc_grad.argtypes = [ctypes.c_void_p, P, P, P, P, P]
+        L.orc_adjoint.argtypes = [ctypes.c_void_p, P, P, P, P, P, P, P, P, P, P,
+                                  ctypes.c_double, ctypes.c_int, ctypes.POINTER(Stats)]
+        L.orc_grad.argtypes = [ctypes.c_void_p, P, P, P, P, P, P]
         L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -107,11 +108,13 @@ class OracleError(RuntimeError):
 
 
 class Oracle:
-    """One oracle context: coefficients, hierarchy and solver parameters."""
+    """One oracle context: coefficients, hierarchy and solver parameters.
+    gamma: bulk viscosity per cell (stress form with (gamma - 2/3 mu)(div u) I),
+    or None for the incompressible stress form."""
 
     def __init__(self, dim, n, bc, h, theta, rho, mu, edges=None, precond=1, krylov=0,
                  restart=10, nu_pre=2, nu_post=2, nu_coarse=8, vcycles=1, rescale_c=0.0,
-                 edge_avg=0, **_ignored):
+                 edge_avg=0, gamma=None, **_ignored):
         L = lib()
         p = _Params()
         p.dim = dim
@@ -126,9 +129,11 @@ class Oracle:
         p.rescale_c, p.edge_avg = float(rescale_c), edge_avg
         self._rho, self._mu = _f64(rho), _f64(mu)
         self._edges = None if edges is None else _f64(edges)
+        self._gamma = None if gamma is None else _f64(gamma)
+        self.bulk = gamma is not None
         h_ = ctypes.c_void_p()
         rc = L.orc_create(ctypes.byref(p), _p(self._rho), _p(self._mu), _p(self._edges),
-                          ctypes.byref(h_))
+                          _p(self._gamma), ctypes.byref(h_))
         if rc != ORC_OK:
             raise OracleError(rc, "create")
         self._h = h_
@@ -253,21 +258,30 @@ class Oracle:
         xu, xp, gu, gp = _f64(xu), _f64(xp), _f64(gu), _f64(gp)
         lu, lp = np.empty(self.nvel), np.empty(self.ncell)
         dmc, dme, drho = np.empty(self.ncell), np.empty(self.nedge), np.empty(self.ncell)
+        dg = np.empty(self.ncell) if self.bulk else None
         st = Stats()
         rc = lib().orc_adjoint(self._h, _p(xu), _p(xp), _p(gu), _p(gp), _p(lu), _p(lp),
-                               _p(dmc), _p(dme), _p(drho), tol, max_iter, ctypes.byref(st))
+                               _p(dmc), _p(dme), _p(drho), _p(dg), tol, max_iter,
+                               ctypes.byref(st))
         if check and rc:
             raise OracleError(rc, "adjoint")
-        return dict(lu=lu, lp=lp, dmu_cell=dmc, dmu_edge=dme, drho_cell=drho,
-                    stats=st.as_dict(), rc=rc)
+        out = dict(lu=lu, lp=lp, dmu_cell=dmc, dmu_edge=dme, drho_cell=drho,
+                   stats=st.as_dict(), rc=rc)
+        if self.bulk:
+            out["dgamma_cell"] = dg
+        return out
 
     def grad(self, xu, lu):
         xu, lu = _f64(xu), _f64(lu)
         dmc, dme, drho = np.empty(self.ncell), np.empty(self.nedge), np.empty(self.ncell)
-        rc = lib().orc_grad(self._h, _p(xu), _p(lu), _p(dmc), _p(dme), _p(drho))
+        dg = np.empty(self.ncell) if self.bulk else None
+        rc = lib().orc_grad(self._h, _p(xu), _p(lu), _p(dmc), _p(dme), _p(drho), _p(dg))
         if rc:
             raise OracleError(rc, "grad")
-        return dict(dmu_cell=dmc, dmu_edge=dme, drho_cell=drho)
+        out = dict(dmu_cell=dmc, dmu_edge=dme, drho_cell=drho)
+        if self.bulk:
+            out["dgamma_cell"] = dg
+        return out
 
 
 def threads() -> int:

@@ -61,6 +61,9 @@ typedef struct {
   double *beta;  /* 1/rho_f on faces (nvel) */
   double *mu_c;  /* cell viscosity (ncell) */
   double *mu_e;  /* edge viscosity (nedge) */
+  /* gamma - 2/3 mu per cell: the coefficient of (div u) I in the stress
+     when bulk viscosity is included (Sec. 2); NULL = incompressible form */
+  double *lam_c;
   /* V-cycle work arrays */
   double *phi_u, *rhs_u, *res_u;
   double *phi_p, *rhs_p, *res_p;
@@ -247,6 +250,8 @@ static double normal_rate(const level_t *L, const double *u, int k, const int c[
 
 static int third_axis(int k, int l) { return 3 - k - l; }
 
+static double div_cell(const level_t *L, const double *u, const int c[3]);
+
 /* (L_mu u)_k at interior face f: divergence of the stress tau = mu (grad u +
    grad u^T), eq. div_stress, with centred staggered differences. */
 static double lmu_row(const level_t *L, const double *mu_c, const double *mu_e,
@@ -259,6 +264,11 @@ static double lmu_row(const level_t *L, const double *mu_c, const double *mu_e,
   cl[k] -= 1;
   double tr = 2.0 * mu_c[cidx(g, cr)] * normal_rate(L, u, k, cr);
   double tl = 2.0 * mu_c[cidx(g, cl)] * normal_rate(L, u, k, cl);
+  /* bulk viscosity: tau_kk gains (gamma - 2/3 mu)(div u) */
+  if (L->lam_c) {
+    tr += L->lam_c[cidx(g, cr)] * div_cell(L, u, cr);
+    tl += L->lam_c[cidx(g, cl)] * div_cell(L, u, cl);
+  }
   double s = (tr - tl) / h;
   /* shear stresses tau_kl = mu_edge gamma_kl on the edges above/below f */
   for (int l = 0; l < g->d; l++) {
@@ -284,6 +294,7 @@ static double a_diag(const level_t *L, const double *alpha, const double *mu_c,
   int cl[3] = {f[0], f[1], f[2]};
   cl[k] -= 1;
   double dg = alpha[fidx(L, k, f)] + 2.0 * (mu_c[cidx(g, cr)] + mu_c[cidx(g, cl)]) / h2;
+  if (L->lam_c) dg += (L->lam_c[cidx(g, cr)] + L->lam_c[cidx(g, cl)]) / h2;
   for (int l = 0; l < g->d; l++) {
     if (l == k) continue;
     int m = third_axis(k, l);
@@ -800,17 +811,25 @@ static void grad_all(const level_t *L, const double *p, double *out) {
   }
 }
 
-/* x_p = -S~^{-1} c = theta L~_rho^{-1} c - 2 mu c  (eq. Schur_app_varDen_varVis) */
+/* viscous part of the Schur complement approximation at cell i: 2 mu
+   (eq. Schur_app_varDen_varVis), or gamma + 4/3 mu = 2 mu + (gamma - 2/3 mu)
+   with bulk viscosity (eq. Schur_app_bulk) */
+static double schur_visc(const level_t *L, size_t i) {
+  return 2.0 * L->mu_c[i] + (L->lam_c ? L->lam_c[i] : 0.0);
+}
+
+/* x_p = -S~^{-1} c = theta L~_rho^{-1} c - 2 mu c  (eq. Schur_app_varDen_varVis;
+   gamma + 4/3 mu in place of 2 mu with bulk viscosity, eq. Schur_app_bulk) */
 static void neg_schur(orc_ctx *X, const double *cvec, double *xp) {
   level_t *L = &X->lev[0];
   size_t nc = L->ncell;
   if (X->p.theta != 0.0) {
     double *q = (double *)malloc(nc * sizeof(double));
     p_sub(X, cvec, q);
-    for (size_t i = 0; i < nc; i++) xp[i] = X->p.theta * q[i] - 2.0 * L->mu_c[i] * cvec[i];
+    for (size_t i = 0; i < nc; i++) xp[i] = X->p.theta * q[i] - schur_visc(L, i) * cvec[i];
     free(q);
   } else {
-    for (size_t i = 0; i < nc; i++) xp[i] = -2.0 * L->mu_c[i] * cvec[i];
+    for (size_t i = 0; i < nc; i++) xp[i] = -schur_visc(L, i) * cvec[i];
   }
 }
 
@@ -834,7 +853,7 @@ static void precond_scaled(orc_ctx *X, const double *b, double *z) {
     p_sub(X, cvec, q);
     grad_all(L, q, tu);
     for (size_t i = 0; i < nv; i++) zu[i] = xs[i] + L->beta[i] * tu[i];
-    for (size_t i = 0; i < nc; i++) zp[i] = -X->p.theta * q[i] + 2.0 * L->mu_c[i] * cvec[i];
+    for (size_t i = 0; i < nc; i++) zp[i] = -X->p.theta * q[i] + schur_visc(L, i) * cvec[i];
     free(q);
     break;
   }
@@ -1072,8 +1091,12 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
 /* setup (Sec. 3.1 coefficients, Sec. 3.3 rescaling, Appendix C coarsening)  */
 /* ------------------------------------------------------------------------ */
 
-static int level_alloc(level_t *L, int work) {
+static int level_alloc(level_t *L, int work, int bulk) {
   level_layout(L);
+  if (bulk) {
+    L->lam_c = (double *)calloc(L->ncell, sizeof(double));
+    if (!L->lam_c) return ORC_ENOMEM;
+  }
   L->alpha = (double *)calloc(L->nvel, sizeof(double));
   L->beta = (double *)calloc(L->nvel, sizeof(double));
   L->mu_c = (double *)calloc(L->ncell, sizeof(double));
@@ -1093,7 +1116,7 @@ static int level_alloc(level_t *L, int work) {
 }
 
 static void level_free(level_t *L) {
-  free(L->alpha); free(L->beta); free(L->mu_c); free(L->mu_e);
+  free(L->alpha); free(L->beta); free(L->mu_c); free(L->mu_e); free(L->lam_c);
   free(L->phi_u); free(L->rhs_u); free(L->res_u);
   free(L->phi_p); free(L->rhs_p); free(L->res_p);
   memset(L, 0, sizeof(*L));
@@ -1193,6 +1216,18 @@ static void coarsen_coefficients(const level_t *F, level_t *C) {
               s += F->mu_c[lin3(F->g.n, 2 * i0 + o0, 2 * i1 + o1, d == 3 ? 2 * i2 + o2 : 0)];
         C->mu_c[lin3(g->n, i0, i1, i2)] = s / (double)(1 << d);
       }
+  /* bulk coefficient: mean of the 2^d fine cells, like the cell viscosity */
+  if (C->lam_c)
+    for (int i2 = 0; i2 < g->n[2]; i2++)
+      for (int i1 = 0; i1 < g->n[1]; i1++)
+        for (int i0 = 0; i0 < g->n[0]; i0++) {
+          double s = 0.0;
+          for (int o2 = 0; o2 < (d == 3 ? 2 : 1); o2++)
+            for (int o1 = 0; o1 < 2; o1++)
+              for (int o0 = 0; o0 < 2; o0++)
+                s += F->lam_c[lin3(F->g.n, 2 * i0 + o0, 2 * i1 + o1, d == 3 ? 2 * i2 + o2 : 0)];
+          C->lam_c[lin3(g->n, i0, i1, i2)] = s / (double)(1 << d);
+        }
   for (int m = 0; m < 3; m++) {
     if (C->ecnt[m] == 0) continue;
     int dm[3], fdm[3];
@@ -1225,7 +1260,7 @@ int orc_threads(void) {
 }
 
 int orc_create(const orc_params *p, const double *rho, const double *mu,
-               const double *edges_given, orc_ctx **out) {
+               const double *edges_given, const double *gamma, orc_ctx **out) {
   if (!p || !out || !rho || !mu) return ORC_EINVAL;
   *out = NULL;
   if (p->dim != 2 && p->dim != 3) return ORC_EINVAL;
@@ -1269,14 +1304,23 @@ int orc_create(const orc_params *p, const double *rho, const double *mu,
   X->p = *p;
   X->nlev = nlev;
   X->raw.g = g;
-  if (level_alloc(&X->raw, 0) != ORC_OK) { orc_destroy(X); return ORC_ENOMEM; }
+  const int bulk = gamma != NULL;
+  if (level_alloc(&X->raw, 0, bulk) != ORC_OK) { orc_destroy(X); return ORC_ENOMEM; }
   for (size_t i = 0; i < X->raw.ncell; i++) {
     if (!(rho[i] > 0.0) || !(mu[i] >= 0.0) || !isfinite(rho[i]) || !isfinite(mu[i])) {
       orc_destroy(X);
       return ORC_EINVAL;
     }
+    if (bulk && (!(gamma[i] >= 0.0) || !isfinite(gamma[i]))) {
+      orc_destroy(X);
+      return ORC_EINVAL;
+    }
   }
   fine_coefficients(X, &X->raw, rho, mu, edges_given);
+  /* stress with bulk viscosity (Sec. 2): the (div u) I coefficient is
+     gamma - 2/3 mu per cell */
+  if (bulk)
+    for (size_t i = 0; i < X->raw.ncell; i++) X->raw.lam_c[i] = gamma[i] - 2.0 / 3.0 * mu[i];
   /* rescale factor c = h / mu_ref, mu_ref = geometric mean of the positive
      cell viscosities (Sec. 3.3, reading of "typical magnitude") */
   if (p->rescale_c > 0.0) {
@@ -1308,7 +1352,7 @@ int orc_create(const orc_params *p, const double *rho, const double *mu,
     for (int a = 0; a < g.d; a++) gl.n[a] = g.n[a] >> l;
     gl.h = g.h * (double)(1 << l);
     X->lev[l].g = gl;
-    if (level_alloc(&X->lev[l], 1) != ORC_OK) { orc_destroy(X); return ORC_ENOMEM; }
+    if (level_alloc(&X->lev[l], 1, bulk) != ORC_OK) { orc_destroy(X); return ORC_ENOMEM; }
   }
   /* scaled fine level: alpha' = c alpha, mu' = c mu, beta' = beta / c */
   level_t *L0 = &X->lev[0];
@@ -1318,6 +1362,8 @@ int orc_create(const orc_params *p, const double *rho, const double *mu,
   }
   for (size_t i = 0; i < L0->ncell; i++) L0->mu_c[i] = X->c * X->raw.mu_c[i];
   for (size_t i = 0; i < L0->nedge; i++) L0->mu_e[i] = X->c * X->raw.mu_e[i];
+  if (bulk)
+    for (size_t i = 0; i < L0->ncell; i++) L0->lam_c[i] = X->c * X->raw.lam_c[i];
   for (int l = 1; l < nlev; l++) coarsen_coefficients(&X->lev[l - 1], &X->lev[l]);
   *out = X;
   return ORC_OK;
@@ -1441,6 +1487,7 @@ int orc_level_coef(orc_ctx *X, int level, int which, double *out, size_t cap) {
   case 1: src = L->beta; n = L->nvel; break;
   case 2: src = L->mu_c; n = L->ncell; break;
   case 3: src = L->mu_e; n = L->nedge; break;
+  case 4: src = L->lam_c; n = L->ncell; if (!src) return ORC_EINVAL; break;
   default: return ORC_EINVAL;
   }
   if (cap < n) return ORC_EINVAL;
@@ -1500,11 +1547,15 @@ int orc_solve(orc_ctx *X, const double *bu, const double *bp, double *xu, double
      dL/dmu_cell = -2 sum_k (D^k lambda_k)(D^k x_k),
      dL/dmu_edge = -w_e gamma_e(lambda) gamma_e(x),
      dL/drho_cell = -theta sum_{faces of the cell} 1/2 lambda_f x_f.
+   With bulk viscosity W also holds lam = gamma - 2/3 mu on the cell
+   divergences, so dL/dlam = -(D lambda)(D x) per cell; it is dL/dgamma, and
+   -2/3 of it is added to dL/dmu_cell.
    When the edges are derived from cells the chain through the averaging is
    added to dL/dmu_cell. */
 int orc_grad(orc_ctx *X, const double *xu, const double *lu, double *dmu_cell,
-             double *dmu_edge, double *drho) {
+             double *dmu_edge, double *drho, double *dgamma) {
   if (!X || !xu || !lu) return ORC_EINVAL;
+  if (dgamma && !X->raw.lam_c) return ORC_EINVAL;
   const level_t *L = &X->raw;
   const grid_t *g = &L->g;
   double *de = (double *)calloc(L->nedge, sizeof(double));
@@ -1516,6 +1567,11 @@ int orc_grad(orc_ctx *X, const double *xu, const double *lu, double *dmu_cell,
         double s = 0.0;
         for (int k = 0; k < g->d; k++) s += normal_rate(L, lu, k, c) * normal_rate(L, xu, k, c);
         dc[lin3(g->n, i0, i1, i2)] = -2.0 * s;
+        if (L->lam_c) {
+          const double dlam = -div_cell(L, lu, c) * div_cell(L, xu, c);
+          dc[lin3(g->n, i0, i1, i2)] -= 2.0 / 3.0 * dlam;
+          if (dgamma) dgamma[lin3(g->n, i0, i1, i2)] = dlam;
+        }
       }
   for (int m = 0; m < 3; m++) {
     if (L->ecnt[m] == 0) continue;
@@ -1601,9 +1657,11 @@ int orc_grad(orc_ctx *X, const double *xu, const double *lu, double *dmu_cell,
 
 int orc_adjoint(orc_ctx *X, const double *xu, const double *xp, const double *gu,
                 const double *gp, double *lu, double *lp, double *dmu_cell,
-                double *dmu_edge, double *drho, double tol, int max_iter, orc_stats *st) {
+                double *dmu_edge, double *drho, double *dgamma, double tol, int max_iter,
+                orc_stats *st) {
   (void)xp;
   if (!X || !xu || !gu || !gp || !lu || !lp || !(tol > 0.0)) return ORC_EINVAL;
+  if (dgamma && !X->raw.lam_c) return ORC_EINVAL;
   const size_t nv = X->raw.nvel, nc = X->raw.ncell, n = nv + nc;
   double *b = (double *)malloc(n * sizeof(double));
   double *x = (double *)calloc(n, sizeof(double));
@@ -1620,6 +1678,6 @@ int orc_adjoint(orc_ctx *X, const double *xu, const double *xp, const double *gu
   remove_mean(lp, nc);
   if (X->vel_singular) remove_vel_means(&X->raw, lu);
   free(b); free(x);
-  int rg = orc_grad(X, xu, lu, dmu_cell, dmu_edge, drho);
+  int rg = orc_grad(X, xu, lu, dmu_cell, dmu_edge, drho, dgamma);
   return rc != ORC_OK ? rc : rg;
 }

@@ -58,8 +58,12 @@ typedef struct {
 
 typedef struct orc_ctx orc_ctx;
 
+/* gamma_cell: bulk viscosity per cell (>= 0), or NULL.  Given, the stress
+   is mu (grad u + grad u^T) + (gamma - 2/3 mu)(div u) I (Sec. 2, the form
+   for div u = g != 0) and the Schur approximation uses gamma + 4/3 mu in place
+   of 2 mu (eq. Schur_app_bulk).  NULL: the incompressible stress form. */
 int    orc_create(const orc_params *p, const double *rho_cell, const double *mu_cell,
-                  const double *mu_edges_given, orc_ctx **out);
+                  const double *mu_edges_given, const double *gamma_cell, orc_ctx **out);
 void   orc_destroy(orc_ctx *c);
 size_t orc_nvel(const orc_ctx *c);    /* stored velocity entries (all components) */
 size_t orc_ncell(const orc_ctx *c);
@@ -104,10 +108,12 @@ int orc_solve(orc_ctx *c, const double *bu, const double *bp, double *xu, double
 int orc_adjoint(orc_ctx *c, const double *xu, const double *xp,
                 const double *gu, const double *gp, double *lu, double *lp,
                 double *dmu_cell, double *dmu_edge, double *drho_cell,
-                double tol, int max_iter, orc_stats *st);
-/* Gradient contraction only (no solve): given forward x and adjoint lambda. */
+                double *dgamma_cell, double tol, int max_iter, orc_stats *st);
+/* Gradient contraction only (no solve): given forward x and adjoint lambda.
+   dgamma_cell (bulk-viscosity contexts only, else NULL) receives
+   -(D lambda)(D x) per cell. */
 int orc_grad(orc_ctx *c, const double *xu, const double *lu,
-             double *dmu_cell, double *dmu_edge, double *drho_cell);
+             double *dmu_cell, double *dmu_edge, double *drho_cell, double *dgamma_cell);
 int orc_threads(void);
 
 #ifdef __cplusplus

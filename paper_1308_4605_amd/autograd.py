@@ -1,11 +1,14 @@
 """torch.autograd wrapper of the Stokes solve with the hand-written adjoint.
 
-forward:  (mu_cell, rho_cell, f_u) -> (u, p), the solution of M x = (f_u, 0)
+forward:  (mu_cell, rho_cell, f_u[, gamma_cell, b_p]) -> (u, p), the solution
+          of M x = (f_u, b_p) (b_p = -g, zero when not given); with gamma_cell
+          the stress carries the bulk-viscosity term (gamma - 2/3 mu)(div u) I
 backward: one adjoint solve M lambda = (dL/du, dL/dp) with the same
           preconditioner and a fresh Krylov space (M = M^T), then the
           strain-contraction kernel; the Krylov basis of the forward solve is
-          not kept.  dL/df = lambda_u, dL/dmu_cell and dL/drho_cell come from the
-          library (the chain rule through the derived edge viscosity included).
+          not kept.  dL/df = lambda_u, dL/db_p = lambda_p; dL/dmu_cell,
+          dL/drho_cell and dL/dgamma_cell come from the library (the chain rule
+          through the derived edge viscosity included).
 
 All arithmetic runs in libstokes_mi355x.so; this file only marshals tensors.
 Parametrisations such as mu = exp(s) are ordinary torch ops in the caller's
@@ -20,9 +23,14 @@ from .stokes import Stokes
 
 class StokesSolveFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, mu_cell, rho_cell, f_u, params, tol=1e-10, max_iter=2000):
-        S = Stokes(params, rho_cell.detach().contiguous(), mu_cell.detach().contiguous())
-        bp = torch.zeros(S.ncell, dtype=torch.float64, device=f_u.device)
+    def forward(ctx, mu_cell, rho_cell, f_u, gamma_cell, b_p, params, tol=1e-10, max_iter=2000):
+        gamma = None if gamma_cell is None else gamma_cell.detach().contiguous()
+        S = Stokes(params, rho_cell.detach().contiguous(), mu_cell.detach().contiguous(),
+                   gamma=gamma)
+        if b_p is None:
+            bp = torch.zeros(S.ncell, dtype=torch.float64, device=f_u.device)
+        else:
+            bp = b_p.detach().contiguous()
         xu, xp, st, rc = S.solve(f_u.detach().contiguous(), bp, tol=tol, max_iter=max_iter)
         ctx.S = S
         ctx.tol, ctx.max_iter = tol, max_iter
@@ -41,9 +49,13 @@ class StokesSolveFn(torch.autograd.Function):
         res = S.adjoint(xu, xp, gu.contiguous(), gp.contiguous(), tol=ctx.tol,
                         max_iter=ctx.max_iter)
         ctx.adjoint_stats = res["stats"]
-        return res["dmu_cell"], res["drho_cell"], res["lu"], None, None, None
+        dgamma = res.get("dgamma_cell") if ctx.needs_input_grad[3] else None
+        dbp = res["lp"] if ctx.needs_input_grad[4] else None
+        return res["dmu_cell"], res["drho_cell"], res["lu"], dgamma, dbp, None, None, None
 
 
-def stokes_solve(mu_cell, rho_cell, f_u, params, tol=1e-10, max_iter=2000):
-    """Differentiable solve: returns (u, p)."""
-    return StokesSolveFn.apply(mu_cell, rho_cell, f_u, params, tol, max_iter)
+def stokes_solve(mu_cell, rho_cell, f_u, params, tol=1e-10, max_iter=2000, gamma_cell=None,
+                 b_p=None):
+    """Differentiable solve: returns (u, p).  gamma_cell: bulk viscosity (or
+    None); b_p: pressure right-hand side -g for div u = g (or None = 0)."""
+    return StokesSolveFn.apply(mu_cell, rho_cell, f_u, gamma_cell, b_p, params, tol, max_iter)

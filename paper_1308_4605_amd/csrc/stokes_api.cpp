@@ -28,6 +28,7 @@ constexpr int kEventPool = 2048;
 struct Level {
   Geo g;
   void *alpha, *beta, *muc, *mue;             // precision T of the hierarchy
+  void *lam;                                  // bulk coefficient (null: none)
   void *phi_u, *rhs_u, *res_u, *phi_p, *rhs_p, *res_p;
 };
 
@@ -58,6 +59,7 @@ bool valid_params(const stokes_params *p, int *nlev_out) {
   if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_coarse < 1 || p->vcycles < 1) return false;
   if (p->nu_pre > 64 || p->nu_post > 64 || p->nu_coarse > 4096 || p->vcycles > 1000) return false;
   if (p->edge_avg < STOKES_EDGE_ARITH || p->edge_avg > STOKES_EDGE_GIVEN) return false;
+  if (p->bulk != 0 && p->bulk != 1) return false;
   int nmin = 1 << 30;
   for (int a = 0; a < p->dim; a++) {
     if (p->n[a] < 2 || p->n[a] > (1 << 20)) return false;
@@ -92,12 +94,18 @@ struct stokes_ctx {
   int d = 0, nlev = 0;
   int mg32 = 0;
   int vel_singular = 0;  // bit k: velocity component k has a constant null space
+  int bulk = 0;          // stress with bulk viscosity (lam arrays present)
   int tail_l = -1;  // first level of the single-workgroup coarse tail (-1: none)
   double c = 1.0;
   Level lev[kMaxLev];
   i64 nvel = 0, ncell = 0, nedge = 0, n = 0;
   // FP64 scaled fine-level coefficients for M (alias level 0 in FP64 mode)
-  double *m_alpha = nullptr, *m_muc = nullptr, *m_mue = nullptr;
+  double *m_alpha = nullptr, *m_muc = nullptr, *m_mue = nullptr, *m_lam = nullptr;
+  // level-0 coefficient s of the Schur approximation's viscous part 2 s:
+  // mu (eq. Schur_app_varDen_varVis) or (gamma + 4/3 mu) / 2 (eq.
+  // Schur_app_bulk); precision T; aliases level 0's mu_cell without bulk
+  void *sig = nullptr;
+  double *sig64 = nullptr;  // FP64 form while an FP32 hierarchy is built
   // Krylov storage (FP64 [u | p] vectors; Z in the preconditioner precision)
   double *V[kMaxRestart + 1];
   void *Z[kMaxRestart];
@@ -110,7 +118,7 @@ struct stokes_ctx {
   void *ps_r = nullptr, *ps_t = nullptr, *ps_de = nullptr;
   double *gedge = nullptr, *gcell = nullptr;        // gradient scratch (FP64)
   // FP64 coefficient chain used to build an FP32 hierarchy (setup only)
-  double *c64a[kMaxLev], *c64b[kMaxLev], *c64m[kMaxLev], *c64e[kMaxLev];
+  double *c64a[kMaxLev], *c64b[kMaxLev], *c64m[kMaxLev], *c64e[kMaxLev], *c64l[kMaxLev];
   // reductions
   double *part = nullptr;   // partial sums
   double *dsc = nullptr;    // device scalars
@@ -151,6 +159,7 @@ void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
     L.beta = cv.take(g.nvel * tb);
     L.muc = cv.take(g.ncell * tb);
     L.mue = cv.take(g.nedge * tb);
+    L.lam = p->bulk ? cv.take(g.ncell * tb) : nullptr;
     L.phi_u = cv.take(g.nvel * tb);
     L.rhs_u = cv.take(g.nvel * tb);
     L.res_u = cv.take(g.nvel * tb);
@@ -162,10 +171,16 @@ void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
   // FP64 fine coefficients of M (rescaled)
   double *ma = (double *)cv.take(nv * 8);
   double *mc = (double *)cv.take(nc * 8), *me = (double *)cv.take(ne * 8);
+  double *ml = p->bulk ? (double *)cv.take(nc * 8) : nullptr;
+  void *sig = p->bulk ? cv.take(nc * tb) : nullptr;
+  double *sig64 = (p->bulk && p->precision == STOKES_MG_FP32) ? (double *)cv.take(nc * 8) : nullptr;
   if (X) {
     X->m_alpha = ma;
     X->m_muc = mc;
     X->m_mue = me;
+    X->m_lam = ml;
+    X->sig = sig ? sig : X->lev[0].muc;
+    X->sig64 = sig64;
   }
   const int m = p->restart;
   for (int i = 0; i <= m; i++) {
@@ -200,6 +215,7 @@ void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
       X->c64b[0] = b0;
       X->c64m[0] = mc;
       X->c64e[0] = me;
+      X->c64l[0] = ml;
     }
     for (int l = 1; l < nlev; l++) {
       int nl[3];
@@ -207,11 +223,13 @@ void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
       Geo g = make_geo(d, nl, ns, p->h * (double)(1 << l));
       double *a_ = (double *)cv.take(g.nvel * 8), *b_ = (double *)cv.take(g.nvel * 8);
       double *m_ = (double *)cv.take(g.ncell * 8), *e_ = (double *)cv.take(g.nedge * 8);
+      double *l_ = p->bulk ? (double *)cv.take(g.ncell * 8) : nullptr;
       if (X) {
         X->c64a[l] = a_;
         X->c64b[l] = b_;
         X->c64m[l] = m_;
         X->c64e[l] = e_;
+        X->c64l[l] = l_;
       }
     }
   }
@@ -269,6 +287,10 @@ inline const T *alpha_of(const stokes_ctx *X, const Level &L) {
 inline const double *m_alpha_of(const stokes_ctx *X) {
   return X->p.theta == 0.0 ? nullptr : X->m_alpha;
 }
+template <typename T>
+inline const T *lam_of(const Level &L) {
+  return (const T *)L.lam;
+}
 
 template <typename T>
 void remove_mean(stokes_ctx *X, T *a, i64 n, int slot) {
@@ -296,8 +318,8 @@ void smooth_vel(stokes_ctx *X, int l, const T *rhs, T *phi, int nsweeps) {
           if (X->ev_used == kEventPool) fold_events(X);
           (void)hipEventRecord(X->ev[2 * X->ev_used], X->s);
         }
-        launch_vel_gs<T>(L.g, k, colour, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), rhs, phi,
-                         X->s);
+        launch_vel_gs<T>(L.g, k, colour, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue),
+                         lam_of<T>(L), rhs, phi, X->s);
         if (tm) {
           (void)hipEventRecord(X->ev[2 * X->ev_used + 1], X->s);
           X->ev_used++;
@@ -328,7 +350,7 @@ TailLevels<T> tail_levels(stokes_ctx *X, int l0, const T *rhs, T *phi, bool vel)
     const int l = l0 + i;
     if (i >= t.nl) {
       t.g[i] = X->lev[l0].g;
-      t.a[i] = t.b[i] = t.mc[i] = t.me[i] = nullptr;
+      t.a[i] = t.b[i] = t.mc[i] = t.me[i] = t.lam[i] = nullptr;
       t.phi[i] = t.rhs[i] = t.res[i] = nullptr;
       continue;
     }
@@ -338,6 +360,7 @@ TailLevels<T> tail_levels(stokes_ctx *X, int l0, const T *rhs, T *phi, bool vel)
     t.b[i] = P<T>(L.beta);
     t.mc[i] = P<T>(L.muc);
     t.me[i] = P<T>(L.mue);
+    t.lam[i] = vel ? lam_of<T>(L) : nullptr;
     t.phi[i] = P<T>(vel ? L.phi_u : L.phi_p);
     t.rhs[i] = P<T>(vel ? L.rhs_u : L.rhs_p);
     t.res[i] = P<T>(vel ? L.res_u : L.res_p);
@@ -369,8 +392,8 @@ void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
   }
   Level &C = X->lev[l + 1];
   smooth_vel<T>(X, l, rhs, phi, X->p.nu_pre);
-  launch_vel_residual<T>(L.g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), rhs, phi, nullptr,
-                         P<T>(L.res_u), X->s);
+  launch_vel_residual<T>(L.g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), lam_of<T>(L), rhs,
+                         phi, nullptr, P<T>(L.res_u), X->s);
   launch_face_restrict<T>(L.g, C.g, P<T>(L.res_u), P<T>(C.rhs_u), X->s);
   vcycle_vel<T>(X, l + 1, P<T>(C.rhs_u), P<T>(C.phi_u));
   launch_face_prolong_add<T>(C.g, L.g, P<T>(C.phi_u), phi, X->s);
@@ -415,8 +438,8 @@ void vel_sub(stokes_ctx *X, const T *r, T *e) {
   }
   vcycle_vel<T>(X, 0, rr, e);
   for (int v = 1; v < X->p.vcycles; v++) {
-    launch_vel_residual<T>(L.g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), rr, e, nullptr,
-                           P<T>(X->vs_t), X->s);
+    launch_vel_residual<T>(L.g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), lam_of<T>(L), rr,
+                           e, nullptr, P<T>(X->vs_t), X->s);
     vcycle_vel<T>(X, 0, P<T>(X->vs_t), P<T>(X->vs_de));
     launch_axpy<T>((T)1, P<T>(X->vs_de), e, L.g.nvel, X->s);
   }
@@ -439,16 +462,17 @@ void p_sub(stokes_ctx *X, const T *r, T *e) {
   remove_mean<T>(X, e, L.g.ncell, 19);
 }
 
-// out = -S~^{-1} c = theta L~_rho^{-1} c - 2 mu c  (eq. Schur_app_varDen_varVis)
+// out = -S~^{-1} c = theta L~_rho^{-1} c - 2 mu c  (eq. Schur_app_varDen_varVis;
+// with bulk viscosity gamma + 4/3 mu in place of 2 mu, eq. Schur_app_bulk)
 template <typename T>
 void neg_schur(stokes_ctx *X, const T *c, T *out) {
   Level &L = X->lev[0];
   if (X->p.theta != 0.0) {
     p_sub<T>(X, c, P<T>(X->q));
-    launch_schur_combine<T>(P<T>(X->q), c, P<T>(L.muc), (T)X->p.theta, (T)-2, out, L.g.ncell,
+    launch_schur_combine<T>(P<T>(X->q), c, P<T>(X->sig), (T)X->p.theta, (T)-2, out, L.g.ncell,
                             X->s);
   } else {
-    launch_schur_combine<T>(nullptr, c, P<T>(L.muc), (T)0, (T)-2, out, L.g.ncell, X->s);
+    launch_schur_combine<T>(nullptr, c, P<T>(X->sig), (T)0, (T)-2, out, L.g.ncell, X->s);
   }
 }
 
@@ -466,7 +490,7 @@ void precond(stokes_ctx *X, const T *bu, const T *bp, T *zu, T *zp) {
       launch_div<T>(g, xs, bp, (T)-1, cv, X->s);
       p_sub<T>(X, cv, q);
       launch_proj_update<T>(g, xs, P<T>(L.beta), q, zu, X->s);
-      launch_schur_combine<T>(q, cv, P<T>(L.muc), (T)(-X->p.theta), (T)2, zp, g.ncell, X->s);
+      launch_schur_combine<T>(q, cv, P<T>(X->sig), (T)(-X->p.theta), (T)2, zp, g.ncell, X->s);
       break;
     case STOKES_P2:
       // x_u = A~^{-1} b_u; x_p = -S~^{-1}(D x_u + b_p)
@@ -490,7 +514,8 @@ void precond(stokes_ctx *X, const T *bu, const T *bp, T *zu, T *zp) {
       vel_sub<T>(X, bu, xs);
       launch_div<T>(g, xs, bp, (T)1, cv, X->s);
       neg_schur<T>(X, cv, zp);
-      launch_vel_residual<T>(g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), bu, xs, zp, tu, X->s);
+      launch_vel_residual<T>(g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), lam_of<T>(L), bu, xs,
+                             zp, tu, X->s);
       vel_sub<T>(X, tu, eu);
       launch_cast<T, T>(xs, zu, g.nvel, X->s);
       launch_axpy<T>((T)1, eu, zu, g.nvel, X->s);
@@ -517,8 +542,8 @@ void precond_from64(stokes_ctx *X, const double *v, void *z, bool have32 = false
 // y = M' x on the rescaled system (FP64)
 void apply_scaled(stokes_ctx *X, const double *x, double *y) {
   const Geo &g = X->lev[0].g;
-  launch_apply_m<double>(g, m_alpha_of(X), X->m_muc, X->m_mue, x, x + X->nvel, nullptr, nullptr, y,
-                         y + X->nvel, X->s);
+  launch_apply_m<double>(g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam, x, x + X->nvel, nullptr,
+                         nullptr, y, y + X->nvel, X->s);
 }
 
 double fetch(stokes_ctx *X, const double *dev, int count, double *dst) {
@@ -552,7 +577,8 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
   int it = 0, rc = STOKES_OK;
   for (;;) {
     // r = b - M x and its norm
-    launch_apply_m<double>(X->lev[0].g, m_alpha_of(X), X->m_muc, X->m_mue, X->x, X->x + nv, X->b,
+    launch_apply_m<double>(X->lev[0].g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam, X->x,
+                           X->x + nv, X->b,
                            X->b + nv, X->r, X->r + nv, X->s);
     launch_norm2(X->r, n, X->part, X->dsc + 0, X->s);
     const double rho = std::sqrt(fetch(X, X->dsc, 1, hb));
@@ -584,7 +610,8 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       if (flexible) {
         precond_from64(X, X->V[j], X->Z[j], j > 0);
         if (X->mg32)
-          launch_apply_m<float>(X->lev[0].g, m_alpha_of(X), X->m_muc, X->m_mue, P<float>(X->Z[j]),
+          launch_apply_m<float>(X->lev[0].g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam,
+                                P<float>(X->Z[j]),
                                 P<float>(X->Z[j]) + nv, nullptr, nullptr, X->w, X->w + nv, X->s);
         else
           apply_scaled(X, P<double>(X->Z[j]), X->w);
@@ -706,14 +733,14 @@ void finish_solution(stokes_ctx *X, const double *xs, double su, double sp, doub
 }
 
 int grad_impl(stokes_ctx *X, const double *u, const double *lam, double *dmu_cell,
-              double *dmu_edge, double *drho) {
+              double *dmu_edge, double *drho, double *dgamma) {
   const Geo &g = X->lev[0].g;
   double *de = dmu_edge ? dmu_edge : X->gedge;
   launch_grad_edges(g, u, lam, de, X->s);
-  if (dmu_cell || drho) {
+  if (dmu_cell || drho || dgamma) {
     // write into temporaries when a requested output is missing
     double *dc = dmu_cell ? dmu_cell : X->gcell;
-    launch_grad_cells(g, u, lam, X->p.theta, dc, drho, X->s);
+    launch_grad_cells(g, u, lam, X->p.theta, X->bulk, dc, drho, dgamma, X->s);
     if (dmu_cell && X->p.edge_avg != STOKES_EDGE_GIVEN)
       launch_grad_chain(g, de, X->m_mue, X->m_muc, X->p.edge_avg, dmu_cell, X->s);
   }
@@ -760,7 +787,8 @@ int mg_solve(stokes_ctx *X, bool vel, double tol, int max_cycles, int *cycles, d
     }
     c++;
     if (vel)
-      launch_vel_residual<double>(g, m_alpha_of(X), X->m_muc, X->m_mue, r, e, nullptr, res, X->s);
+      launch_vel_residual<double>(g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam, r, e, nullptr,
+                                  res, X->s);
     else
       launch_p_residual<double>(g, beta64, r, e, res, X->s);
     launch_norm2(res, n, X->part, X->dsc, X->s);
@@ -812,13 +840,14 @@ size_t stokes_workspace_bytes(const stokes_params *p) {
 }
 
 int stokes_create(const stokes_params *p, const double *rho, const double *mu,
-                  const double *mu_edges, void *workspace, size_t ws_bytes, void *hip_stream,
-                  stokes_ctx **out) {
+                  const double *mu_edges, const double *gamma, void *workspace, size_t ws_bytes,
+                  void *hip_stream, stokes_ctx **out) {
   if (!out) return STOKES_EINVAL;
   *out = nullptr;
   int nlev = 0;
   if (!valid_params(p, &nlev) || !rho || !mu || !workspace) return STOKES_EINVAL;
   if (p->edge_avg == STOKES_EDGE_GIVEN && !mu_edges) return STOKES_EINVAL;
+  if ((p->bulk != 0) != (gamma != nullptr)) return STOKES_EINVAL;
   if (((uintptr_t)workspace) % kAlign != 0) return STOKES_EINVAL;
   if (ws_bytes < stokes_workspace_bytes(p)) return STOKES_ENOMEM;
   stokes_ctx *X = new (std::nothrow) stokes_ctx();
@@ -828,6 +857,7 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
   X->d = p->dim;
   X->nlev = nlev;
   X->mg32 = (p->precision == STOKES_MG_FP32);
+  X->bulk = p->bulk;
   Carver cv(workspace);
   carve_all(p, nlev, cv, X);
   const Geo &g0 = X->lev[0].g;
@@ -862,6 +892,7 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
   // coefficient check and rescaling factor
   launch_fill<int>(X->dflag, 0, 1, s);
   launch_check_coefs(rho, mu, g0.ncell, X->dflag, s);
+  if (gamma) launch_check_coefs(rho, gamma, g0.ncell, X->dflag, s);  // gamma >= 0, finite
   launch_logsum(mu, g0.ncell, X->part, X->dsc, s);
   int flag = 0;
   (void)hipMemcpyAsync(&X->host[0], X->dsc, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -899,6 +930,14 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
                      P<double>(F.mue), P<double>(C.alpha), P<double>(C.beta), P<double>(C.muc),
                      P<double>(C.mue), s);
     }
+    if (X->bulk) {
+      // bulk coefficient: coarse cell = mean of its 2^d fine cells (like mu_cell)
+      launch_setup_bulk(gamma, mu, X->c, g0.ncell, P<double>(L0.lam), P<double>(X->sig), s);
+      (void)hipMemcpyAsync(X->m_lam, L0.lam, g0.ncell * 8, hipMemcpyDeviceToDevice, s);
+      for (int l = 1; l < nlev; l++)
+        launch_cell_restrict<double>(X->lev[l - 1].g, X->lev[l].g, P<double>(X->lev[l - 1].lam),
+                                     P<double>(X->lev[l].lam), s);
+    }
   } else {
     launch_setup_faces(g0, rho, p->theta, X->c, X->c64a[0], X->c64b[0], s);
     launch_setup_cells(g0, mu, X->c, X->c64m[0], s);
@@ -913,6 +952,14 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
       launch_cast<float, double>(X->c64m[l], P<float>(L.muc), L.g.ncell, s);
       launch_cast<float, double>(X->c64e[l], P<float>(L.mue), L.g.nedge, s);
     }
+    if (X->bulk) {
+      launch_setup_bulk(gamma, mu, X->c, g0.ncell, X->c64l[0], X->sig64, s);
+      for (int l = 1; l < nlev; l++)
+        launch_cell_restrict<double>(X->lev[l - 1].g, X->lev[l].g, X->c64l[l - 1], X->c64l[l], s);
+      for (int l = 0; l < nlev; l++)
+        launch_cast<float, double>(X->c64l[l], P<float>(X->lev[l].lam), X->lev[l].g.ncell, s);
+      launch_cast<float, double>(X->sig64, P<float>(X->sig), g0.ncell, s);
+    }
   }
   // algorithmic bytes of one finest-level velocity colour pass of component
   // k: read all velocity components, rhs_k, alpha_k, mu_cell and the d-1 edge
@@ -926,7 +973,9 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
     // reads: every velocity component, rhs_k, alpha_k (not when theta = 0),
     // mu_cell, the edge families touching k; writes: component k
     const double own = (p->theta == 0.0) ? 2.0 : 3.0;
-    X->gs_bytes[k] = tb * ((double)g0.nvel + own * (double)g0.fcnt[k] + (double)g0.ncell + e);
+    const double cells = X->bulk ? 2.0 : 1.0;  // mu_cell (and the bulk coefficient)
+    X->gs_bytes[k] =
+        tb * ((double)g0.nvel + own * (double)g0.fcnt[k] + cells * (double)g0.ncell + e);
   }
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
     (void)hipHostFree(X->host);
@@ -968,7 +1017,8 @@ int stokes_boundary_rhs(stokes_ctx *X, const double *un, const double *ut, doubl
   // tangential wall velocities in the no-slip ghosts
   launch_pack_walls(g, un, 1.0, X->t, X->s);
   launch_fill<double>(X->t + X->nvel, 0.0, X->ncell, X->s);
-  launch_apply_m_walls(g, m_alpha_of(X), X->m_muc, X->m_mue, X->t, X->t + X->nvel, ut, X->w,
+  launch_apply_m_walls(g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam, X->t, X->t + X->nvel, ut,
+                       X->w,
                        X->w + X->nvel, X->s);
   launch_pack_vel(g, X->w, 1.0 / X->c, cu, X->s);
   launch_scale(X->w + X->nvel, 1.0, cp, X->ncell, X->s);
@@ -1066,22 +1116,24 @@ int stokes_solve(stokes_ctx *X, const double *bu, const double *bp, double *xu, 
 }
 
 int stokes_grad(stokes_ctx *X, const double *xu, const double *lu, double *dmu_cell,
-                double *dmu_edge, double *drho_cell) {
+                double *dmu_edge, double *drho_cell, double *dgamma_cell) {
   if (!X || !xu || !lu) return STOKES_EINVAL;
+  if (dgamma_cell && !X->bulk) return STOKES_EINVAL;
   const Geo &g = X->lev[0].g;
   launch_pack_vel(g, xu, 1.0, X->t, X->s);
   launch_pack_vel(g, lu, 1.0, X->r, X->s);
-  grad_impl(X, X->t, X->r, dmu_cell, dmu_edge, drho_cell);
+  grad_impl(X, X->t, X->r, dmu_cell, dmu_edge, drho_cell, dgamma_cell);
   return finish(X, STOKES_OK);
 }
 
 int stokes_adjoint_solve(stokes_ctx *X, const double *xu, const double *xp, const double *gu,
                          const double *gp, double *lu, double *lp, double *dmu_cell,
-                         double *dmu_edge, double *drho_cell, double tol, int max_iter,
-                         stokes_stats *st) {
+                         double *dmu_edge, double *drho_cell, double *dgamma_cell, double tol,
+                         int max_iter, stokes_stats *st) {
   (void)xp;
   if (!X || !xu || !gu || !gp || !lu || !lp || !(tol > 0.0) || max_iter < 0)
     return STOKES_EINVAL;
+  if (dgamma_cell && !X->bulk) return STOKES_EINVAL;
   const Geo &g = X->lev[0].g;
   // M' = diag(c,1) M diag(1,1/c) is symmetric: lambda = diag(c,1) M'^{-1} (g_u, g_p / c)
   launch_pack_vel(g, gu, 1.0, X->b, X->s);
@@ -1096,7 +1148,7 @@ int stokes_adjoint_solve(stokes_ctx *X, const double *xu, const double *xp, cons
   rc = krylov(X, tol, max_iter, st);
   finish_solution(X, X->x, X->c, 1.0, lu, lp);
   launch_pack_vel(g, xu, 1.0, X->t, X->s);
-  grad_impl(X, X->t, lu, dmu_cell, dmu_edge, drho_cell);
+  grad_impl(X, X->t, lu, dmu_cell, dmu_edge, drho_cell, dgamma_cell);
   hip_ok(X, hipStreamSynchronize(X->s));
   return finish(X, rc);
 }

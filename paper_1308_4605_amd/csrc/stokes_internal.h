@@ -50,6 +50,9 @@ void launch_coarsen(const Geo &gf, const Geo &gc, const double *af, const double
                     const double *mcf, const double *mef, double *ac, double *bc, double *mcc,
                     double *mec, hipStream_t s);
 void launch_check_coefs(const double *rho, const double *mu, i64 n, int *flag, hipStream_t s);
+// bulk viscosity: lam = c (gamma - 2/3 mu) and sig = c mu + lam / 2 per cell
+void launch_setup_bulk(const double *gamma, const double *mu, double c, i64 n, double *lam,
+                       double *sig, hipStream_t s);
 
 // element-wise
 template <typename TO, typename TI>
@@ -65,25 +68,28 @@ void launch_axpy(T a, const T *x, T *y, i64 n, hipStream_t s);  // y += a x
 // saddle operator on the fine level in FP64:
 //   y_u = alpha u - L_mu u + G p, y_p = -D u            (b == nullptr)
 //   y = b - M x                                         (b != nullptr)
+// lam (may be null): bulk coefficient per cell, gamma - 2/3 mu (scaled)
 template <typename TI>
 void launch_apply_m(const Geo &g, const double *alpha, const double *muc, const double *mue,
-                    const TI *xu, const TI *xp, const double *bu, const double *bp, double *yu,
-                    double *yp, hipStream_t s);
+                    const double *lam, const TI *xu, const TI *xp, const double *bu,
+                    const double *bp, double *yu, double *yp, hipStream_t s);
 // boundary terms of prescribed wall velocities: M applied to the wall-data
 // field xu (normal values on wall faces, zero inside) with tangential wall
 // values gw (edge layout) in the no-slip ghosts
 void launch_apply_m_walls(const Geo &g, const double *alpha, const double *muc,
-                          const double *mue, const double *xu, const double *xp,
-                          const double *gw, double *yu, double *yp, hipStream_t s);
+                          const double *mue, const double *lam, const double *xu,
+                          const double *xp, const double *gw, double *yu, double *yp,
+                          hipStream_t s);
 void launch_pack_walls(const Geo &g, const double *in, double scale, double *out, hipStream_t s);
 
 // multigrid level kernels, T = float or double
+// (lam: bulk coefficient per cell or null, as for launch_apply_m)
 template <typename T>
 void launch_vel_gs(const Geo &g, int k, int colour, const T *alpha, const T *muc, const T *mue,
-                   const T *rhs, T *phi, hipStream_t s);
-template <typename T>
-void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mue, const T *rhs,
-                         const T *phi, const T *p, T *res, hipStream_t s);  // res = rhs - A phi - G p
+                   const T *lam, const T *rhs, T *phi, hipStream_t s);
+template <typename T>  // res = rhs - A phi - G p
+void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mue, const T *lam,
+                         const T *rhs, const T *phi, const T *p, T *res, hipStream_t s);
 template <typename T>
 void launch_face_restrict(const Geo &gf, const Geo &gc, const T *rf, T *rc, hipStream_t s);
 template <typename T>
@@ -109,12 +115,13 @@ struct TailLevels {
   int nu_pre, nu_post, nu_coarse;
   Geo g[kTailMax];
   const T *a[kTailMax], *b[kTailMax], *mc[kTailMax], *me[kTailMax];  // alpha, beta, mu_c, mu_e
+  const T *lam[kTailMax];  // bulk coefficient per cell (null: none)
   T *phi[kTailMax], *rhs[kTailMax], *res[kTailMax];
   // levels lds0..nl-1 live in dynamic LDS: byte offsets of
-  // {alpha or beta, mu_c, mu_e, phi, rhs, res}; lds_bytes in total
+  // {alpha or beta, mu_c, mu_e, phi, rhs, res, lam}; lds_bytes in total
   int lds0;
   unsigned lds_bytes;
-  unsigned off[kTailMax][6];
+  unsigned off[kTailMax][7];
 };
 constexpr unsigned kTailLds = 60 * 1024;  // dynamic LDS budget of a tail launch
 // fills lds0 / off / lds_bytes for the velocity (vel) or pressure tail
@@ -174,8 +181,9 @@ void launch_logsum(const double *mu, i64 n, double *partials, double *out2, hipS
 void launch_norm2(const double *a, i64 n, double *partials, double *nrm2, hipStream_t s);
 
 // gradient contraction (unscaled forward u and adjoint lambda)
-void launch_grad_cells(const Geo &g, const double *u, const double *lam, double theta,
-                       double *dmu_cell, double *drho, hipStream_t s);
+// bulk != 0: also the bulk-coefficient terms (dgamma may be null)
+void launch_grad_cells(const Geo &g, const double *u, const double *lam, double theta, int bulk,
+                       double *dmu_cell, double *drho, double *dgamma, hipStream_t s);
 void launch_grad_edges(const Geo &g, const double *u, const double *lam, double *dmu_edge,
                        hipStream_t s);
 void launch_grad_chain(const Geo &g, const double *dmu_edge, const double *mue_raw,

@@ -140,12 +140,16 @@ __device__ __forceinline__ bool box_thread(const Geo &g, int W, int &w, int &y, 
 // normal axis k (ukp, ukm) and, for each tangential axis l, the u_k values
 // above/below (ua[l], ub[l]) with the wall ghost already applied; u_l values
 // and the coefficients are read from the component arrays comp[l].
+// lam (may be null): gamma - 2/3 mu per cell; the normal stresses of the two
+// cells beside f then gain lam (div u) (bulk viscosity, Sec. 2).  The u_l
+// values the shear terms load are exactly the cells' tangential faces, so the
+// cell divergences cost no extra velocity loads.
 template <typename T, int DIM>
 __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T uf, T ukp, T ukm,
                                          const T (&ua)[3], const T (&ub)[3],
                                          const T *const *comp, const T *__restrict__ alpha,
                                          const T *__restrict__ muc, const T *__restrict__ mue,
-                                         T &Au, T &diag) {
+                                         const T *__restrict__ lam, T &Au, T &diag) {
   const T ih = (T)g.ih;
   const T ih2 = ih * ih;
   const i64 fq = fidx3(g, k, i);
@@ -160,6 +164,8 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
   T s = (tr - tl) * ih;
   const T al = alpha ? alpha[fq] : (T)0;  // no alpha array: theta = 0
   T dg = al + (T)2 * (mr + ml) * ih2;
+  // h * divergence of the cells right (r) and left (l) of f
+  T hdr = ukp - uf, hdl = uf - ukm;
 #pragma unroll
   for (int l = 0; l < DIM; l++) {
     if (l == k) continue;
@@ -187,6 +193,15 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
     s += (mhi * ghi - mlo * glo) * ih;
     const T ww = g.fs[l] ? (T)0 : (T)2;  // wall edge: one-sided (no-slip) or no flux
     dg += ((top ? ww : (T)1) * mhi + (bot ? ww : (T)1) * mlo) * ih2;
+    hdr += ulh_r - ull_r;
+    hdl += ulh_l - ull_l;
+  }
+  if (lam) {
+    t[k] = km;
+    const T lr = lam[cidx3(g, i)], ll = lam[cidx3(g, t)];
+    t[k] = i[k];
+    s += (lr * hdr - ll * hdl) * ih2;
+    dg += (lr + ll) * ih2;
   }
   Au = al * uf - s;
   diag = dg;
@@ -199,7 +214,8 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
 template <typename T, int DIM>
 __device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const T *__restrict__ u,
                                       const T *__restrict__ alpha, const T *__restrict__ muc,
-                                      const T *__restrict__ mue, T &Au, T &diag) {
+                                      const T *__restrict__ mue, const T *__restrict__ lam,
+                                      T &Au, T &diag) {
   const i64 fq = fidx3(g, k, i);
   const T uf = u[fq];
   int t[3] = {i[0], i[1], i[2]};
@@ -227,7 +243,7 @@ __device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const
     ub[l] = bot ? gs : vb;
   }
   const T *comp[3] = {u + g.foff[0], u + g.foff[1], u + g.foff[2]};
-  a_row_nb<T, DIM>(g, k, i, uf, ukp, ukm, ua, ub, comp, alpha, muc, mue, Au, diag);
+  a_row_nb<T, DIM>(g, k, i, uf, ukp, ukm, ua, ub, comp, alpha, muc, mue, lam, Au, diag);
 }
 
 __device__ __forceinline__ bool low_wall(const Geo &g, int k, const int i[3]) {
@@ -387,6 +403,24 @@ __global__ void k_check_coefs(const double *__restrict__ rho, const double *__re
   if (!ok) atomicOr(flag, 1);
 }
 
+// bulk coefficient of the stress, lam = c (gamma - 2/3 mu) per cell (Sec. 2);
+// sig = c mu + lam / 2 = c (gamma + 4/3 mu) / 2 is what the Schur
+// approximation multiplies by 2 (eq. Schur_app_bulk)
+__global__ void k_setup_bulk(const double *__restrict__ gamma, const double *__restrict__ mu,
+                             double c, i64 n, double *__restrict__ lam, double *__restrict__ sig) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double m = mu[t];
+  const double l = c * (gamma[t] - 2.0 / 3.0 * m);
+  lam[t] = l;
+  sig[t] = c * m + 0.5 * l;
+}
+void launch_setup_bulk(const double *gamma, const double *mu, double c, i64 n, double *lam,
+                       double *sig, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup_bulk, dim3(blocks_for(n)), dim3(kBlock), 0, s, gamma, mu, c, n, lam,
+                     sig);
+}
+
 void launch_setup_faces(const Geo &g, const double *rho, double theta, double c, double *alpha,
                         double *beta, hipStream_t s) {
   hipLaunchKernelGGL(k_setup_faces, dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, rho, theta,
@@ -496,6 +530,7 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
                                             const double *__restrict__ alpha,
                                             const double *__restrict__ muc,
                                             const double *__restrict__ mue,
+                                            const double *__restrict__ lam,
                                             const double *__restrict__ gw, double &Au) {
   const double ih = g.ih;
   const i64 fq = fidx3(g, k, i);
@@ -513,6 +548,7 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
   const double tr = 2.0 * mr * ((ukp - uf) * ih);
   const double tl = 2.0 * ml * ((uf - ukm) * ih);
   double s = (tr - tl) * ih;
+  double hdr = ukp - uf, hdl = uf - ukm;  // h * divergence of cells r and l
 #pragma unroll
   for (int l = 0; l < DIM; l++) {
     if (l == k) continue;
@@ -555,13 +591,21 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
       if (bot) glo = 0.0;
     }
     s += (mhi * ghi - mlo * glo) * ih;
+    hdr += ulh_r - ull_r;
+    hdl += ulh_l - ull_l;
+  }
+  if (lam) {  // bulk viscosity: lam (div u) on the two normal stresses
+    t[k] = km;
+    s += (lam[cidx3(g, i)] * hdr - lam[cidx3(g, t)] * hdl) * (ih * ih);
+    t[k] = i[k];
   }
   Au = (alpha ? alpha[fq] * uf : 0.0) - s;  // no alpha array: theta = 0
 }
 
 template <typename TI, int DIM, bool GW>
 __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double *__restrict__ muc,
-                          const double *__restrict__ mue, const TI *__restrict__ xu,
+                          const double *__restrict__ mue, const double *__restrict__ lam,
+                          const TI *__restrict__ xu,
                           const TI *__restrict__ xp, const double *__restrict__ bu,
                           const double *__restrict__ bp, const double *__restrict__ gw,
                           double *__restrict__ yu, double *__restrict__ yp) {
@@ -582,7 +626,7 @@ __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double 
       continue;
     }
     double Au;
-    a_row_mixed<TI, DIM, GW>(g, k, i, xu, alpha, muc, mue, gw, Au);
+    a_row_mixed<TI, DIM, GW>(g, k, i, xu, alpha, muc, mue, lam, gw, Au);
     int l[3] = {i[0], i[1], i[2]};
     l[k] = dn1(g, k, i[k]);
     const double gp = (pc - (double)xp[cidx3(g, l)]) * ih;
@@ -594,31 +638,33 @@ __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double 
 
 template <typename TI>
 void launch_apply_m(const Geo &g, const double *alpha, const double *muc, const double *mue,
-                    const TI *xu, const TI *xp, const double *bu, const double *bp, double *yu,
-                    double *yp, hipStream_t s) {
+                    const double *lam, const TI *xu, const TI *xp, const double *bu,
+                    const double *bp, double *yu, double *yp, hipStream_t s) {
   if (g.d == 3)
     hipLaunchKernelGGL((k_apply_m<TI, 3, false>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
-                       alpha, muc, mue, xu, xp, bu, bp, nullptr, yu, yp);
+                       alpha, muc, mue, lam, xu, xp, bu, bp, nullptr, yu, yp);
   else
     hipLaunchKernelGGL((k_apply_m<TI, 2, false>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
-                       alpha, muc, mue, xu, xp, bu, bp, nullptr, yu, yp);
+                       alpha, muc, mue, lam, xu, xp, bu, bp, nullptr, yu, yp);
 }
 template void launch_apply_m<double>(const Geo &, const double *, const double *, const double *,
                                      const double *, const double *, const double *,
-                                     const double *, double *, double *, hipStream_t);
+                                     const double *, const double *, double *, double *,
+                                     hipStream_t);
 template void launch_apply_m<float>(const Geo &, const double *, const double *, const double *,
-                                    const float *, const float *, const double *, const double *,
-                                    double *, double *, hipStream_t);
+                                    const double *, const float *, const float *, const double *,
+                                    const double *, double *, double *, hipStream_t);
 
 void launch_apply_m_walls(const Geo &g, const double *alpha, const double *muc,
-                          const double *mue, const double *xu, const double *xp,
-                          const double *gw, double *yu, double *yp, hipStream_t s) {
+                          const double *mue, const double *lam, const double *xu,
+                          const double *xp, const double *gw, double *yu, double *yp,
+                          hipStream_t s) {
   if (g.d == 3)
     hipLaunchKernelGGL((k_apply_m<double, 3, true>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s,
-                       g, alpha, muc, mue, xu, xp, nullptr, nullptr, gw, yu, yp);
+                       g, alpha, muc, mue, lam, xu, xp, nullptr, nullptr, gw, yu, yp);
   else
     hipLaunchKernelGGL((k_apply_m<double, 2, true>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s,
-                       g, alpha, muc, mue, xu, xp, nullptr, nullptr, gw, yu, yp);
+                       g, alpha, muc, mue, lam, xu, xp, nullptr, nullptr, gw, yu, yp);
 }
 
 // out = scale * in on the wall faces, 0 elsewhere (the wall-data field)
@@ -671,11 +717,11 @@ __host__ __device__ __forceinline__ i64 colour_threads(const Geo &g) {
 template <typename T, int DIM>
 __device__ __forceinline__ void gs_point(const Geo &g, int k, const int i[3],
                                          const T *__restrict__ alpha, const T *__restrict__ muc,
-                                         const T *__restrict__ mue, const T *__restrict__ rhs,
-                                         T *__restrict__ phi) {
+                                         const T *__restrict__ mue, const T *__restrict__ lam,
+                                         const T *__restrict__ rhs, T *__restrict__ phi) {
   if (low_wall(g, k, i)) return;
   T Au, dg;
-  a_row<T, DIM>(g, k, i, phi, alpha, muc, mue, Au, dg);
+  a_row<T, DIM>(g, k, i, phi, alpha, muc, mue, lam, Au, dg);
   const i64 fq = fidx3(g, k, i);
   phi[fq] += (rhs[fq] - Au) / dg;
 }
@@ -684,30 +730,31 @@ __device__ __forceinline__ void gs_point(const Geo &g, int k, const int i[3],
 template <typename T, int DIM>
 __device__ __forceinline__ void vel_gs_elem(const Geo &g, int k, int colour, i64 t,
                                             const T *__restrict__ alpha, const T *__restrict__ muc,
-                                            const T *__restrict__ mue, const T *__restrict__ rhs,
-                                            T *__restrict__ phi) {
+                                            const T *__restrict__ mue, const T *__restrict__ lam,
+                                            const T *__restrict__ rhs, T *__restrict__ phi) {
   int i[3];
   if (!colour_cell(g, t, colour, i)) return;
-  gs_point<T, DIM>(g, k, i, alpha, muc, mue, rhs, phi);
+  gs_point<T, DIM>(g, k, i, alpha, muc, mue, lam, rhs, phi);
 }
 
 template <typename T, int DIM, int K>
 __global__ void k_vel_gs(Geo g, int colour, const T *__restrict__ alpha,
                          const T *__restrict__ muc, const T *__restrict__ mue,
-                         const T *__restrict__ rhs, T *__restrict__ phi) {
+                         const T *__restrict__ lam, const T *__restrict__ rhs,
+                         T *__restrict__ phi) {
   int tx, i[3];
   if (!box_thread(g, (g.n[0] + 1) >> 1, tx, i[1], i[2])) return;
   i[0] = 2 * tx + ((i[1] + i[2] + colour) & 1);
-  if (i[0] < g.n[0]) gs_point<T, DIM>(g, K, i, alpha, muc, mue, rhs, phi);
+  if (i[0] < g.n[0]) gs_point<T, DIM>(g, K, i, alpha, muc, mue, lam, rhs, phi);
 }
 
 template <typename T>
 void launch_vel_gs(const Geo &g, int k, int colour, const T *alpha, const T *muc, const T *mue,
-                   const T *rhs, T *phi, hipStream_t s) {
+                   const T *lam, const T *rhs, T *phi, hipStream_t s) {
   const dim3 nb = box_blocks(g, (g.n[0] + 1) >> 1);
 #define GS_CASE(D, KK)                                                                       \
   hipLaunchKernelGGL((k_vel_gs<T, D, KK>), nb, dim3(kBlock), 0, s, g, colour, alpha, muc, \
-                     mue, rhs, phi)
+                     mue, lam, rhs, phi)
   if (g.d == 3) {
     if (k == 0) GS_CASE(3, 0);
     else if (k == 1) GS_CASE(3, 1);
@@ -725,6 +772,7 @@ __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i6
                                                 const T *__restrict__ alpha,
                                                 const T *__restrict__ muc,
                                                 const T *__restrict__ mue,
+                                                const T *__restrict__ lam,
                                                 const T *__restrict__ rhs,
                                                 const T *__restrict__ phi,
                                                 const T *__restrict__ p, T *__restrict__ res) {
@@ -732,7 +780,7 @@ __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i6
   for (int k = 0; k < DIM; k++) {
     if (low_wall(g, k, i)) continue;
     T Au, dg;
-    a_row<T, DIM>(g, k, i, phi, alpha, muc, mue, Au, dg);
+    a_row<T, DIM>(g, k, i, phi, alpha, muc, mue, lam, Au, dg);
     const i64 fq = fidx3(g, k, i);
     T r = rhs[fq] - Au;
     if (p) {
@@ -748,34 +796,35 @@ template <typename T, int DIM>
 __device__ __forceinline__ void vel_residual_elem(const Geo &g, i64 t, const T *__restrict__ alpha,
                                                   const T *__restrict__ muc,
                                                   const T *__restrict__ mue,
+                                                  const T *__restrict__ lam,
                                                   const T *__restrict__ rhs,
                                                   const T *__restrict__ phi,
                                                   const T *__restrict__ p, T *__restrict__ res) {
   if (t >= g.ncell) return;
   int i[3];
   cell_of(g, t, i);
-  vel_residual_at<T, DIM>(g, i, t, alpha, muc, mue, rhs, phi, p, res);
+  vel_residual_at<T, DIM>(g, i, t, alpha, muc, mue, lam, rhs, phi, p, res);
 }
 
 template <typename T, int DIM>
 __global__ void k_vel_residual(Geo g, const T *__restrict__ alpha, const T *__restrict__ muc,
-                               const T *__restrict__ mue, const T *__restrict__ rhs,
-                               const T *__restrict__ phi, const T *__restrict__ p,
-                               T *__restrict__ res) {
+                               const T *__restrict__ mue, const T *__restrict__ lam,
+                               const T *__restrict__ rhs, const T *__restrict__ phi,
+                               const T *__restrict__ p, T *__restrict__ res) {
   int i[3];
   if (!box_thread(g, g.n[0], i[0], i[1], i[2])) return;
-  vel_residual_at<T, DIM>(g, i, cidx3(g, i), alpha, muc, mue, rhs, phi, p, res);
+  vel_residual_at<T, DIM>(g, i, cidx3(g, i), alpha, muc, mue, lam, rhs, phi, p, res);
 }
 
 template <typename T>
-void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mue, const T *rhs,
-                         const T *phi, const T *p, T *res, hipStream_t s) {
+void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mue, const T *lam,
+                         const T *rhs, const T *phi, const T *p, T *res, hipStream_t s) {
   if (g.d == 3)
     hipLaunchKernelGGL((k_vel_residual<T, 3>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
-                       alpha, muc, mue, rhs, phi, p, res);
+                       alpha, muc, mue, lam, rhs, phi, p, res);
   else
     hipLaunchKernelGGL((k_vel_residual<T, 2>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
-                       alpha, muc, mue, rhs, phi, p, res);
+                       alpha, muc, mue, lam, rhs, phi, p, res);
 }
 
 // face restriction (Appendix C): normal weights 1/4, 1/2, 1/4 at fine faces
@@ -1109,13 +1158,13 @@ __device__ void tail_zero(T *dst, i64 n) {
 
 template <typename T, int DIM>
 __device__ void tail_vel_smooth(const Geo &g, const T *alpha, const T *muc, const T *mue,
-                                const T *rhs, T *phi, int sweeps) {
+                                const T *lam, const T *rhs, T *phi, int sweeps) {
   const i64 nt = colour_threads(g);
   for (int s = 0; s < sweeps; s++)
     for (int k = 0; k < DIM; k++)
       for (int colour = 0; colour < 2; colour++) {
         for (i64 t = threadIdx.x; t < nt; t += blockDim.x)
-          vel_gs_elem<T, DIM>(g, k, colour, t, alpha, muc, mue, rhs, phi);
+          vel_gs_elem<T, DIM>(g, k, colour, t, alpha, muc, mue, lam, rhs, phi);
         __syncthreads();
       }
 }
@@ -1127,7 +1176,7 @@ __device__ void tail_vel_smooth(const Geo &g, const T *alpha, const T *muc, cons
 // both through generic pointers.
 template <typename T>
 struct TailPtrs {
-  const T *a[kTailMax], *b[kTailMax], *mc[kTailMax], *me[kTailMax];
+  const T *a[kTailMax], *b[kTailMax], *mc[kTailMax], *me[kTailMax], *lam[kTailMax];
   T *phi[kTailMax], *rhs[kTailMax], *res[kTailMax];
 };
 
@@ -1140,6 +1189,7 @@ __device__ void tail_stage(const TailLevels<T> &L, unsigned char *lds, TailPtrs<
       P.b[l] = in ? (const T *)(lds + L.off[l][0]) : L.b[l];
       P.mc[l] = in ? (const T *)(lds + L.off[l][1]) : L.mc[l];
       P.me[l] = in ? (const T *)(lds + L.off[l][2]) : L.me[l];
+      P.lam[l] = (in && L.lam[l]) ? (const T *)(lds + L.off[l][6]) : L.lam[l];
       P.phi[l] = in ? (T *)(lds + L.off[l][3]) : L.phi[l];
       P.rhs[l] = in ? (T *)(lds + L.off[l][4]) : L.rhs[l];
       P.res[l] = in ? (T *)(lds + L.off[l][5]) : L.res[l];
@@ -1153,6 +1203,10 @@ __device__ void tail_stage(const TailLevels<T> &L, unsigned char *lds, TailPtrs<
         for (i64 t = threadIdx.x; t < g.nvel; t += blockDim.x) a[t] = L.a[l][t];
       for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x) mc[t] = L.mc[l][t];
       for (i64 t = threadIdx.x; t < g.nedge; t += blockDim.x) me[t] = L.me[l][t];
+      if (L.lam[l]) {
+        T *lm = (T *)(lds + L.off[l][6]);
+        for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x) lm[t] = L.lam[l][t];
+      }
     } else {
       T *b = (T *)(lds + L.off[l][0]);
       for (i64 t = threadIdx.x; t < g.nvel; t += blockDim.x) b[t] = L.b[l][t];
@@ -1170,9 +1224,10 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_vel(TailLevels<T> L) {
   for (int l = 0; l < nl - 1; l++) {
     const Geo &g = L.g[l];
     tail_zero<T>(P.phi[l], g.nvel);
-    tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.rhs[l], P.phi[l], L.nu_pre);
+    tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.lam[l], P.rhs[l], P.phi[l],
+                            L.nu_pre);
     for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x)
-      vel_residual_elem<T, DIM>(g, t, P.a[l], P.mc[l], P.me[l], P.rhs[l], P.phi[l],
+      vel_residual_elem<T, DIM>(g, t, P.a[l], P.mc[l], P.me[l], P.lam[l], P.rhs[l], P.phi[l],
                                 (const T *)nullptr, P.res[l]);
     __syncthreads();
     for (i64 t = threadIdx.x; t < L.g[l + 1].ncell; t += blockDim.x)
@@ -1189,7 +1244,8 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_vel(TailLevels<T> L) {
       else
         tail_copy<T>(P.rhs[l] + g.foff[k], P.res[l] + g.foff[k], g.fcnt[k]);
     }
-    tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.res[l], P.phi[l], L.nu_coarse);
+    tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.lam[l], P.res[l], P.phi[l],
+                            L.nu_coarse);
     for (int k = 0; k < g.d; k++)
       if ((L.singular >> k) & 1)
         tail_sub_mean<T>(P.phi[l] + g.foff[k], P.phi[l] + g.foff[k], g.fcnt[k]);
@@ -1199,7 +1255,8 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_vel(TailLevels<T> L) {
     for (i64 t = threadIdx.x; t < g.ncell; t += blockDim.x)
       face_prolong_elem<T, DIM>(L.g[l + 1], g, t, P.phi[l + 1], P.phi[l]);
     __syncthreads();
-    tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.rhs[l], P.phi[l], L.nu_post);
+    tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.lam[l], P.rhs[l], P.phi[l],
+                            L.nu_post);
   }
 }
 
@@ -1254,7 +1311,7 @@ void tail_plan_lds(TailLevels<T> &L, bool vel) {
   L.lds0 = L.nl;
   L.lds_bytes = 0;
   for (int l = 0; l < kTailMax; l++)
-    for (int q = 0; q < 6; q++) L.off[l][q] = 0;
+    for (int q = 0; q < 7; q++) L.off[l][q] = 0;
   unsigned total = 0;
   // from the coarsest level up; the first tail level keeps the caller's
   // buffers in global memory
@@ -1262,13 +1319,14 @@ void tail_plan_lds(TailLevels<T> &L, bool vel) {
     const Geo &g = L.g[l];
     const unsigned nv = (unsigned)g.nvel * sizeof(T), nc = (unsigned)g.ncell * sizeof(T);
     const unsigned ne = (unsigned)g.nedge * sizeof(T);
-    const unsigned sz[6] = {up(nv), vel ? up(nc) : 0u, vel ? up(ne) : 0u,
-                            up(vel ? nv : nc), up(vel ? nv : nc), up(vel ? nv : nc)};
+    const unsigned sz[7] = {up(nv), vel ? up(nc) : 0u, vel ? up(ne) : 0u,
+                            up(vel ? nv : nc), up(vel ? nv : nc), up(vel ? nv : nc),
+                            (vel && L.lam[l]) ? up(nc) : 0u};
     unsigned need = 0;
-    for (int q = 0; q < 6; q++) need += sz[q];
+    for (int q = 0; q < 7; q++) need += sz[q];
     if (total + need > kTailLds) break;
     unsigned o = total;
-    for (int q = 0; q < 6; q++) {
+    for (int q = 0; q < 7; q++) {
       L.off[l][q] = o;
       o += sz[q];
     }
@@ -1804,13 +1862,16 @@ __device__ __forceinline__ double dkl(const Geo &g, const double *__restrict__ u
   return (u[fidx3(g, k, f)] - u[fidx3(g, k, fb)]) / h;
 }
 
+// bulk != 0: the stress carries (gamma - 2/3 mu)(div u) I, whose coefficient
+// has derivative dgam = -(D lambda)(D u) per cell; -2/3 of it joins dmu.
 __global__ void k_grad_cells(Geo g, const double *__restrict__ u, const double *__restrict__ lam,
-                             double theta, double *__restrict__ dmu, double *__restrict__ drho) {
+                             double theta, int bulk, double *__restrict__ dmu,
+                             double *__restrict__ drho, double *__restrict__ dgam) {
   i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.ncell) return;
   int i[3];
   cell_of(g, t, i);
-  double s = 0.0, r = 0.0;
+  double s = 0.0, r = 0.0, divu = 0.0, divl = 0.0;
   for (int k = 0; k < g.d; k++) {
     int hi[3] = {i[0], i[1], i[2]};
     hi[k] = up1(g, k, i[k]);
@@ -1818,11 +1879,15 @@ __global__ void k_grad_cells(Geo g, const double *__restrict__ u, const double *
     const double du = (u[qh] - u[ql]) / g.h;
     const double dl = (lam[qh] - lam[ql]) / g.h;
     s += dl * du;
+    divu += du;
+    divl += dl;
     // density: both faces of the cell along k (wall faces hold 0)
     r += lam[ql] * u[ql] + lam[qh] * u[qh];
   }
-  if (dmu) dmu[t] = -2.0 * s;
+  const double dg = -divl * divu;
+  if (dmu) dmu[t] = bulk ? -2.0 * s - 2.0 / 3.0 * dg : -2.0 * s;
   if (drho) drho[t] = -theta * 0.5 * r;
+  if (dgam) dgam[t] = dg;
 }
 
 __global__ void k_grad_edges(Geo g, int m, const double *__restrict__ u,
@@ -1885,10 +1950,10 @@ __global__ void k_grad_chain(Geo g, const double *__restrict__ dme, const double
   dmu[t] += acc;
 }
 
-void launch_grad_cells(const Geo &g, const double *u, const double *lam, double theta,
-                       double *dmu_cell, double *drho, hipStream_t s) {
+void launch_grad_cells(const Geo &g, const double *u, const double *lam, double theta, int bulk,
+                       double *dmu_cell, double *drho, double *dgamma, hipStream_t s) {
   hipLaunchKernelGGL(k_grad_cells, dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, u, lam, theta,
-                     dmu_cell, drho);
+                     bulk, dmu_cell, drho, dgamma);
 }
 void launch_grad_edges(const Geo &g, const double *u, const double *lam, double *dmu_edge,
                        hipStream_t s) {
@@ -1909,9 +1974,9 @@ void launch_grad_chain(const Geo &g, const double *dmu_edge, const double *mue_r
 // ------------------------------------------------------------------------
 #define INST(T)                                                                                  \
   template void launch_vel_gs<T>(const Geo &, int, int, const T *, const T *, const T *,         \
-                                 const T *, T *, hipStream_t);                                   \
+                                 const T *, const T *, T *, hipStream_t);                        \
   template void launch_vel_residual<T>(const Geo &, const T *, const T *, const T *, const T *,  \
-                                       const T *, const T *, T *, hipStream_t);                  \
+                                       const T *, const T *, const T *, T *, hipStream_t);       \
   template void launch_face_restrict<T>(const Geo &, const Geo &, const T *, T *, hipStream_t);  \
   template void launch_face_prolong_add<T>(const Geo &, const Geo &, const T *, T *,             \
                                            hipStream_t);                                         \

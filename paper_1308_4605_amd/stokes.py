@@ -42,7 +42,7 @@ class StokesParams(ctypes.Structure):
                 ("precision", ctypes.c_int), ("krylov", ctypes.c_int), ("restart", ctypes.c_int),
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("nu_coarse", ctypes.c_int),
                 ("vcycles", ctypes.c_int), ("rescale_c", ctypes.c_double),
-                ("edge_avg", ctypes.c_int)]
+                ("edge_avg", ctypes.c_int), ("bulk", ctypes.c_int)]
 
 
 class StokesStats(ctypes.Structure):
@@ -79,7 +79,7 @@ def lib():
                                    ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int)]
         L.stokes_workspace_bytes.argtypes = [PP]
         L.stokes_workspace_bytes.restype = ctypes.c_size_t
-        L.stokes_create.argtypes = [PP, dp, dp, dp, dp, ctypes.c_size_t, vp,
+        L.stokes_create.argtypes = [PP, dp, dp, dp, dp, dp, ctypes.c_size_t, vp,
                                     ctypes.POINTER(ctypes.c_void_p)]
         L.stokes_apply.argtypes = [vp, dp, dp, dp, dp]
         L.stokes_precond.argtypes = [vp, dp, dp, dp, dp]
@@ -91,10 +91,10 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.stokes_solve.argtypes = [vp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(StokesStats)]
-        L.stokes_adjoint_solve.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+        L.stokes_adjoint_solve.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
                                            ctypes.c_double, ctypes.c_int,
                                            ctypes.POINTER(StokesStats)]
-        L.stokes_grad.argtypes = [vp, dp, dp, dp, dp, dp]
+        L.stokes_grad.argtypes = [vp, dp, dp, dp, dp, dp, dp]
         L.stokes_rescale.argtypes = [vp]
         L.stokes_rescale.restype = ctypes.c_double
         L.stokes_set_timing.argtypes = [vp, ctypes.c_int]
@@ -113,7 +113,8 @@ def strerror(code: int) -> str:
 
 
 def make_params(dim, n, bc, h, theta, precond=1, precision=0, krylov=0, restart=10, nu_pre=2,
-                nu_post=2, nu_coarse=8, vcycles=1, rescale_c=0.0, edge_avg=0, **_ignored):
+                nu_post=2, nu_coarse=8, vcycles=1, rescale_c=0.0, edge_avg=0, bulk=0,
+                **_ignored):
     p = StokesParams()
     p.dim = int(dim)
     n = tuple(n) + (1,) * (3 - len(n))
@@ -125,6 +126,7 @@ def make_params(dim, n, bc, h, theta, precond=1, precision=0, krylov=0, restart=
     p.precond, p.precision, p.krylov, p.restart = int(precond), int(precision), int(krylov), int(restart)
     p.nu_pre, p.nu_post, p.nu_coarse, p.vcycles = int(nu_pre), int(nu_post), int(nu_coarse), int(vcycles)
     p.rescale_c, p.edge_avg = float(rescale_c), int(edge_avg)
+    p.bulk = int(bulk)
     return p
 
 
@@ -155,13 +157,15 @@ class Stokes:
     """One solver context: coefficients, multigrid hierarchy and Krylov
     workspace on the current HIP device, all in one caller-owned workspace
     tensor.  Methods take and return torch float64 CUDA tensors in the ABI
-    layout (flat arrays)."""
+    layout (flat arrays).  gamma: bulk viscosity per cell (the stress with
+    (gamma - 2/3 mu)(div u) I), or None for the incompressible stress form."""
 
-    def __init__(self, params: dict, rho, mu, mu_edges=None, stream=None):
+    def __init__(self, params: dict, rho, mu, mu_edges=None, stream=None, gamma=None):
         import torch
 
-        self.params = dict(params)
-        self.p = make_params(**params)
+        self.params = dict(params, bulk=0 if gamma is None else 1)
+        self.bulk = gamma is not None
+        self.p = make_params(**self.params)
         self.nvel, self.ncell, self.nedge, self.nlevels = stokes_sizes(self.p)
         self.ws_bytes = stokes_workspace_bytes(self.p)
         dev = rho.device
@@ -170,7 +174,8 @@ class Stokes:
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         h = ctypes.c_void_p()
         rc = lib().stokes_create(ctypes.byref(self.p), _ptr(rho), _ptr(mu), _ptr(mu_edges),
-                                 ctypes.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                                 _ptr(gamma), ctypes.c_void_p(self.workspace.data_ptr()),
+                                 self.ws_bytes,
                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if rc:
             raise StokesError(rc, "stokes_create")
@@ -265,21 +270,30 @@ class Stokes:
     def adjoint(self, xu, xp, gu, gp, tol=1e-8, max_iter=1000, check=True):
         lu, lp = self._new(self.nvel), self._new(self.ncell)
         dmc, dme, drho = self._new(self.ncell), self._new(self.nedge), self._new(self.ncell)
+        dg = self._new(self.ncell) if self.bulk else None
         st = StokesStats()
         rc = lib().stokes_adjoint_solve(self._h, _ptr(xu), _ptr(xp), _ptr(gu), _ptr(gp), _ptr(lu),
-                                        _ptr(lp), _ptr(dmc), _ptr(dme), _ptr(drho), float(tol),
-                                        int(max_iter), ctypes.byref(st))
+                                        _ptr(lp), _ptr(dmc), _ptr(dme), _ptr(drho), _ptr(dg),
+                                        float(tol), int(max_iter), ctypes.byref(st))
         if check and rc:
             raise StokesError(rc, "stokes_adjoint_solve")
-        return dict(lu=lu, lp=lp, dmu_cell=dmc, dmu_edge=dme, drho_cell=drho,
-                    stats=st.as_dict(), rc=rc)
+        out = dict(lu=lu, lp=lp, dmu_cell=dmc, dmu_edge=dme, drho_cell=drho,
+                   stats=st.as_dict(), rc=rc)
+        if self.bulk:
+            out["dgamma_cell"] = dg
+        return out
 
     def grad(self, xu, lu):
         dmc, dme, drho = self._new(self.ncell), self._new(self.nedge), self._new(self.ncell)
-        rc = lib().stokes_grad(self._h, _ptr(xu), _ptr(lu), _ptr(dmc), _ptr(dme), _ptr(drho))
+        dg = self._new(self.ncell) if self.bulk else None
+        rc = lib().stokes_grad(self._h, _ptr(xu), _ptr(lu), _ptr(dmc), _ptr(dme), _ptr(drho),
+                               _ptr(dg))
         if rc:
             raise StokesError(rc, "stokes_grad")
-        return dict(dmu_cell=dmc, dmu_edge=dme, drho_cell=drho)
+        out = dict(dmu_cell=dmc, dmu_edge=dme, drho_cell=drho)
+        if self.bulk:
+            out["dgamma_cell"] = dg
+        return out
 
     def set_timing(self, enable: bool):
         rc = lib().stokes_set_timing(self._h, 1 if enable else 0)

@@ -475,6 +475,11 @@ def random_coefficients(seed, lay: Layout, mu_range=(0.5, 2.0), rho_range=(0.5, 
     return rho, mu
 
 
+def random_bulk_viscosity(seed, lay: Layout, gamma_range=(0.0, 2.0)):
+    """Bulk viscosity per cell for small tests: i.i.d. uniform, >= 0."""
+    return np.random.default_rng(seed).uniform(*gamma_range, lay.ncell)
+
+
 def random_velocity(seed, lay: Layout, remove_mean=False):
     r = np.random.default_rng(seed)
     u = r.standard_normal(lay.nvel)

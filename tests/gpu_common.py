@@ -38,12 +38,14 @@ def params(dim, n, bc, theta, **kw):
     return p, lay
 
 
-def pair(p, rho, mu, edges=None):
-    """GPU context and oracle context on identical inputs."""
+def pair(p, rho, mu, edges=None, gamma=None):
+    """GPU context and oracle context on identical inputs (gamma: bulk
+    viscosity or None)."""
     from paper_1308_4605_amd.stokes import Stokes
 
-    g = Stokes(p, T(rho), T(mu), None if edges is None else T(edges))
-    o = oracle.Oracle(rho=rho, mu=mu, edges=edges, **p)
+    g = Stokes(p, T(rho), T(mu), None if edges is None else T(edges),
+               gamma=None if gamma is None else T(gamma))
+    o = oracle.Oracle(rho=rho, mu=mu, edges=edges, gamma=gamma, **p)
     return g, o
 
 

@@ -67,7 +67,8 @@ def test_invalid_parameters_rejected_on_host(S, bad):
     assert rc == S.STOKES_EINVAL
     assert S.stokes_workspace_bytes(p) == 0
     h = ctypes.c_void_p()
-    rc = S.lib().stokes_create(ctypes.byref(p), None, None, None, None, 0, None, ctypes.byref(h))
+    rc = S.lib().stokes_create(ctypes.byref(p), None, None, None, None, None, 0, None,
+                               ctypes.byref(h))
     assert rc == S.STOKES_EINVAL and not h.value
 
 

@@ -1,0 +1,182 @@
+"""Bulk viscosity on the GPU (Sec. 2: the stress (gamma - 2/3 mu)(div u) I for
+div u = g != 0; eq. Schur_app_bulk: gamma + 4/3 mu in the Schur approximation)
+against the oracle on identical seeded inputs: the operator, the boundary
+terms and the gradient contraction at 1e-12, the FP64 subsolver and
+preconditioners at 1e-11, the FP32 preconditioner at 1e-4, solves with
+iteration counts within +-1 and the oracle-checked true residual, and the
+differentiable solve (autograd) against the oracle's FP64 adjoint."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import N, T, pair, params, rel, scaled_residual
+from paper_1308_4605_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+OPS = [
+    (2, (48, 32), (1, 1)), (2, (64, 32), (0, 1)), (2, (32, 32), (0, 0)), (2, (48, 32), (2, 1)),
+    (3, (16, 16, 16), (1, 1, 1)), (3, (16, 16, 16), (0, 0, 0)), (3, (48, 40, 8), (1, 0, 1)),
+    (3, (32, 16, 16), (2, 1, 0)), (3, (2, 2, 2), (0, 0, 0)),
+]
+
+
+def _coefs(lay, seed):
+    rho, mu = W.random_coefficients(seed, lay, mu_range=(0.2, 5.0), rho_range=(0.5, 2.0))
+    gamma = W.random_bulk_viscosity(seed + 100, lay, (0.0, 4.0))
+    return rho, mu, gamma
+
+
+@pytest.mark.parametrize("dim,n,bc", OPS)
+@pytest.mark.parametrize("theta", [0.0, 30.0])
+def test_bulk_apply_and_boundary_parity(dim, n, bc, theta):
+    print(f"bulk apply {dim} {n} {bc} theta={theta}", flush=True)
+    p, lay = params(dim, n, bc, theta)
+    rho, mu, gamma = _coefs(lay, 1)
+    g, o = pair(p, rho, mu, gamma=gamma)
+    xu = W.random_velocity(5, lay)
+    xp = W.random_cells(6, lay)
+    yu, yp = g.apply(T(xu), T(xp))
+    ou, op = o.apply(xu, xp)
+    assert rel(N(yu), ou) <= 1e-12
+    assert rel(N(yp), op) <= 1e-12
+    rng = np.random.default_rng(7)
+    un, ut = rng.standard_normal(lay.nvel), rng.standard_normal(lay.nedge)
+    cu, cp = g.boundary_rhs(T(un), T(ut))
+    ocu, ocp = o.boundary_rhs(un, ut)
+    assert rel(N(cu), ocu) <= 1e-12
+    assert rel(N(cp), ocp) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,n,bc", OPS)
+@pytest.mark.parametrize("theta", [0.0, 40.0])
+def test_bulk_subsolver_parity(dim, n, bc, theta):
+    print(f"bulk subsolve {dim} {n} {bc} theta={theta}", flush=True)
+    for precision, krylov, tol in ((W.FP64, W.GMRES_LEFT, 1e-11), (W.MG_FP32, W.FGMRES, 1e-4)):
+        p, lay = params(dim, n, bc, theta, precision=precision, krylov=krylov)
+        rho, mu, gamma = _coefs(lay, 2)
+        g, o = pair(p, rho, mu, gamma=gamma)
+        r = W.random_velocity(7, lay, remove_mean=lay.singular_components(theta))
+        assert rel(N(g.vel_subsolve(T(r))), o.vel_subsolve(r)) <= tol
+
+
+@pytest.mark.parametrize("dim,n,bc,theta", [(2, (48, 32), (1, 1), 25.0), (3, (16, 16, 16), (0, 0, 0), 0.0),
+                                            (3, (48, 40, 8), (1, 0, 1), 100.0),
+                                            (3, (32, 16, 16), (2, 0, 2), 0.0)])
+@pytest.mark.parametrize("precond", [W.P1, W.P2, W.P3, W.P4, W.P5])
+def test_bulk_precond_parity(dim, n, bc, theta, precond):
+    print(f"bulk precond P{precond} {dim} {n} {bc} theta={theta}", flush=True)
+    for precision, krylov, tol in ((W.FP64, W.GMRES_LEFT, 1e-11), (W.MG_FP32, W.FGMRES, 1e-4)):
+        p, lay = params(dim, n, bc, theta, precond=precond, precision=precision, krylov=krylov)
+        rho, mu, gamma = _coefs(lay, 3)
+        g, o = pair(p, rho, mu, gamma=gamma)
+        bu = W.random_velocity(9, lay, remove_mean=lay.singular_components(theta))
+        bp = W.random_cells(10, lay, remove_mean=True)
+        zu, zp = g.precond(T(bu), T(bp))
+        ou, op = o.precond(bu, bp)
+        assert rel(N(zu), ou) <= tol
+        assert rel(N(zp), op) <= tol
+
+
+@pytest.mark.parametrize("dim,n,bc,theta", [(2, (64, 64), (1, 1), 0.0), (3, (32, 32, 32), (1, 0, 1), 50.0),
+                                            (3, (32, 32, 32), (0, 0, 0), 0.0)])
+@pytest.mark.parametrize("precision", [W.FP64, W.MG_FP32])
+def test_bulk_compressible_solve_parity(dim, n, bc, theta, precision):
+    """Variable rho, mu, gamma; a compressible right-hand side (b_p = -g with
+    g of zero mean)."""
+    print(f"bulk solve {dim} {n} {bc} theta={theta} precision={precision}", flush=True)
+    krylov = W.FGMRES if precision == W.MG_FP32 else W.GMRES_LEFT
+    p, lay = params(dim, n, bc, theta, precond=W.P1, precision=precision, krylov=krylov)
+    rho, mu, gamma = _coefs(lay, 4)
+    g, _ = pair(p, rho, mu, gamma=gamma)
+    o = oracle.Oracle(rho=rho, mu=mu, gamma=gamma, **dict(p, precision=W.FP64))
+    bu = W.random_velocity(11, lay, remove_mean=lay.singular_components(theta))
+    bp = W.random_cells(12, lay, remove_mean=True)
+    xu, xp, st, rc = g.solve(T(bu), T(bp), tol=1e-9, max_iter=600)
+    ou, op, ost, orc = o.solve(bu, bp, tol=1e-9, max_iter=600)
+    print(f"  gpu {st['iters']} oracle {ost['iters']} iterations", flush=True)
+    assert rc == orc == 0
+    if precision == W.FP64:
+        assert abs(st["iters"] - ost["iters"]) <= 1
+    else:
+        assert st["iters"] <= ost["iters"] + 3
+    assert scaled_residual(o, o.c, bu, bp, N(xu), N(xp)) <= 1e-9 * (1 + 1e-6)
+    assert rel(N(xu), ou) <= 1e-6
+    assert rel(N(xp), op) <= 1e-6
+
+
+@pytest.mark.parametrize("dim,n,bc", [(2, (48, 32), (1, 1)), (3, (16, 16, 16), (2, 1, 0))])
+def test_bulk_grad_parity(dim, n, bc):
+    p, lay = params(dim, n, bc, 20.0)
+    rho, mu, gamma = _coefs(lay, 5)
+    g, o = pair(p, rho, mu, gamma=gamma)
+    u, lam = W.random_velocity(13, lay), W.random_velocity(14, lay)
+    gg = g.grad(T(u), T(lam))
+    og = o.grad(u, lam)
+    for k in ("dmu_cell", "dmu_edge", "drho_cell", "dgamma_cell"):
+        assert rel(N(gg[k]), og[k]) <= 1e-12, k
+
+
+def test_bulk_mg_solve_parity():
+    dim, n, bc = 3, (32, 32, 32), (1, 1, 1)
+    for precision, krylov in ((W.FP64, W.GMRES_LEFT), (W.MG_FP32, W.FGMRES)):
+        p, lay = params(dim, n, bc, 10.0, precision=precision, krylov=krylov)
+        rho, mu, gamma = _coefs(lay, 6)
+        g, _ = pair(p, rho, mu, gamma=gamma)
+        o = oracle.Oracle(rho=rho, mu=mu, gamma=gamma, **dict(p, precision=W.FP64))
+        r = W.random_velocity(15, lay)
+        e, cyc, q, rc = g.vel_mg_solve(T(r), tol=1e-10, max_cycles=300)
+        oe, ocyc, oq, orc = o.vel_mg_solve(r, tol=1e-10, max_cycles=300)
+        print(f"  precision {precision}: gpu {cyc} oracle {ocyc} cycles", flush=True)
+        assert rc == orc == 0
+        assert (abs(cyc - ocyc) <= 1) if precision == W.FP64 else (cyc <= ocyc + 3)
+        assert rel(N(e), oe) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.MG_FP32])
+def test_bulk_autograd_matches_oracle_adjoint(precision):
+    """dL/dgamma, dL/dmu, dL/dg and dL/df of L = 1/2 ||u - u_t||^2 +
+    1/2 ||p - p_t||^2 through the differentiable solve equal the oracle's FP64
+    adjoint (1e-6)."""
+    import torch
+
+    from paper_1308_4605_amd.autograd import stokes_solve
+
+    dim, n, bc = 3, (16, 16, 16), (1, 0, 1)
+    krylov = W.FGMRES if precision == W.MG_FP32 else W.GMRES_LEFT
+    p, lay = params(dim, n, bc, 20.0, precision=precision, krylov=krylov)
+    rho, mu, gamma = _coefs(lay, 8)
+    f = W.random_velocity(16, lay)
+    bp = W.random_cells(17, lay, remove_mean=True)
+    ut, pt = 0.01 * W.random_velocity(18, lay), 0.01 * W.random_cells(19, lay)
+    mu_t, gm_t = T(mu).requires_grad_(True), T(gamma).requires_grad_(True)
+    f_t, bp_t = T(f).requires_grad_(True), T(bp).requires_grad_(True)
+    u, pr = stokes_solve(mu_t, T(rho), f_t, p, tol=1e-12, max_iter=3000, gamma_cell=gm_t, b_p=bp_t)
+    L = 0.5 * torch.sum((u - T(ut)) ** 2) + 0.5 * torch.sum((pr - T(pt)) ** 2)
+    L.backward()
+    o = oracle.Oracle(rho=rho, mu=mu, gamma=gamma, **dict(p, precision=W.FP64, precond=W.P1))
+    ou, op, _, _ = o.solve(f, bp, tol=1e-12, max_iter=3000)
+    adj = o.adjoint(ou, op, ou - ut, op - pt, tol=1e-12, max_iter=3000)
+    assert rel(N(mu_t.grad), adj["dmu_cell"]) <= 1e-6
+    assert rel(N(gm_t.grad), adj["dgamma_cell"]) <= 1e-6
+    assert rel(N(f_t.grad), adj["lu"]) <= 1e-6
+    assert rel(N(bp_t.grad), adj["lp"]) <= 1e-6
+
+
+def test_bulk_at_128_cubed_layers():
+    """128^3 no-slip layers (viscosity contrast 1e4) with a bulk viscosity
+    field and a compressible right-hand side: the FP32-multigrid FGMRES
+    solution meets 1e-8 checked with the oracle's operator."""
+    w = W.layers_3d()
+    lay = w.layout
+    gamma = W.random_bulk_viscosity(20, lay, (0.0, 1.0)) * w.mu
+    bp = W.random_cells(21, lay, remove_mean=True) * 1e-2
+    for precision in (W.FP64, W.MG_FP32):
+        kry = W.FGMRES if precision == W.MG_FP32 else W.GMRES_LEFT
+        p = w.params(precision=precision, krylov=kry)
+        g, o = pair(p, w.rho, w.mu, gamma=gamma)
+        xu, xp, st, rc = g.solve(T(w.bu), T(bp), tol=1e-8, max_iter=500)
+        res = scaled_residual(o, o.c, w.bu, bp, N(xu), N(xp))
+        print(f"  precision {precision}: {st['iters']} iterations, oracle-checked {res:.2e}",
+              flush=True)
+        assert rc == 0 and res <= 1e-8 * (1 + 1e-6)
