@@ -71,11 +71,16 @@ enum {
   STOKES_EINCOMPAT = -7    /* right-hand side not orthogonal to the null space */
 };
 
-/* boundary condition per axis (both ends) */
-/* Boundary conditions per axis (Sec. 3.1).  No-slip: u = 0 on the wall, the
-   shear next to it one-sided.  Free-slip: zero normal velocity and no
-   tangential momentum flux through the wall. */
-enum { STOKES_PERIODIC = 0, STOKES_NOSLIP = 1, STOKES_FREESLIP = 2 };
+/* Boundary conditions (Sec. 3.1: a condition at each domain boundary),
+   given per axis a in bc[a].  No-slip: u = 0 on the wall, the shear next to
+   it one-sided.  Free-slip: zero normal velocity and no tangential momentum
+   flux through the wall.  Periodic applies to both ends of an axis; the two
+   walls of a wall axis may differ: STOKES_NOSLIP_FREESLIP is no-slip at the
+   low end (index 0) and free-slip at the high end (index n), and
+   STOKES_FREESLIP_NOSLIP the reverse (e.g. an open channel with a free
+   surface on top). */
+enum { STOKES_PERIODIC = 0, STOKES_NOSLIP = 1, STOKES_FREESLIP = 2, STOKES_NOSLIP_FREESLIP = 3,
+       STOKES_FREESLIP_NOSLIP = 4 };
 
 /* block preconditioners of Sec. 2: projection (eq. P1_practical), lower
    triangular (eq. CC_Pre_lower), upper triangular (eq. CC_Pre_upper),
@@ -99,7 +104,8 @@ typedef struct {
   int dim;          /* 2 or 3 */
   int n[3];         /* cells per axis (n[2] ignored in 2D) */
   double h;         /* grid spacing (> 0) */
-  int bc[3];        /* STOKES_PERIODIC, STOKES_NOSLIP or STOKES_FREESLIP per axis */
+  int bc[3];        /* STOKES_PERIODIC, STOKES_NOSLIP, STOKES_FREESLIP,
+                       STOKES_NOSLIP_FREESLIP or STOKES_FREESLIP_NOSLIP per axis */
   double theta;     /* >= 0 */
   int precond;      /* STOKES_P1..STOKES_P5 */
   int precision;    /* STOKES_FP64 or STOKES_MG_FP32 */
@@ -124,6 +130,13 @@ typedef struct {
                            pressure cycles): the paper's cost proxy (Sec. 4) */
   double rel_res_true;  /* ||b' - M' x'|| / ||b'|| of the rescaled system at exit */
   double rel_res_est;   /* last Givens estimate, as a true relative residual */
+  double rel_res_unscaled;  /* ||b - M x|| / ||b|| of the caller's (unscaled) system
+                               at exit (0 when the solve stopped on a breakdown or a
+                               non-finite value) */
+  int history_len;      /* entries written to the stokes_set_history buffer */
+  double t_total;       /* wall-clock seconds of the Krylov solve */
+  double t_precond;     /* GPU seconds in preconditioner applications (HIP events) */
+  double t_krylov;      /* t_total - t_precond: M applies, Arnoldi, host work */
 } stokes_stats;
 
 typedef struct stokes_ctx stokes_ctx;
@@ -185,7 +198,8 @@ int stokes_boundary_rhs(stokes_ctx *ctx, const double *un, const double *ut, dou
    same operator the Krylov solver applies.  Output pressure has zero mean;
    the output velocity components that are singular have zero mean (Sec. 3.2
    null-space care).  Component k of the velocity operator is singular when
-   theta = 0, axis k is periodic and no axis has no-slip walls. */
+   theta = 0, axis k is periodic and no wall (at either end of any axis) is
+   no-slip. */
 int stokes_precond(stokes_ctx *ctx, const double *bu, const double *bp, double *zu, double *zp);
 
 /* The two multigrid subsolvers alone (Sec. 3.2, Appendix C): e = A~^{-1} r
@@ -251,6 +265,14 @@ int stokes_adjoint_solve(stokes_ctx *ctx, const double *xu, const double *xp, co
    velocity lambda (same formulas as above).  Asynchronous. */
 int stokes_grad(stokes_ctx *ctx, const double *xu, const double *lu, double *dmu_cell,
                 double *dmu_edge, double *drho_cell, double *dgamma_cell);
+
+/* Residual history of the Krylov solves: buf (HOST memory, cap doubles,
+   owned by the caller, kept until replaced or the ctx is destroyed) receives
+   after every Arnoldi step of each later stokes_solve / stokes_adjoint_solve
+   its rel_res_est, from index 0, while fewer than cap entries are written
+   (stokes_stats.history_len counts them).  buf = NULL or cap = 0 turns the
+   history off. */
+int stokes_set_history(stokes_ctx *ctx, double *buf, int cap);
 
 /* Rescaling factor c in use (Sec. 3.3). */
 double stokes_rescale(const stokes_ctx *ctx);

@@ -47,7 +47,7 @@ typedef struct {
   int d;      /* dimension */
   int n[3];   /* cells per axis (n[2] = 1 for d = 2) */
   int ns[3];  /* 1: walls on this axis (no-slip or free-slip), 0: periodic */
-  int fs[3];  /* 1: the walls on this axis are free-slip */
+  int fs[3][2]; /* fs[a][0] / fs[a][1]: the low / high wall of axis a is free-slip */
   int sing;   /* bit k: velocity component k is singular (mean removed) */
   double h;   /* grid spacing */
 } grid_t;
@@ -231,7 +231,7 @@ static double dkl(const level_t *L, const double *u, int k, int l, const int e[3
 
 /* the edge lies on a free-slip wall of axis a */
 static int on_free_slip(const grid_t *g, int a, const int e[3]) {
-  return g->fs[a] && (e[a] == 0 || e[a] == g->n[a]);
+  return (e[a] == 0 && g->fs[a][0]) || (e[a] == g->n[a] && g->fs[a][1]);
 }
 
 /* shear rate gamma_kl = du_k/dx_l + du_l/dx_k at an edge; zero on a free-slip
@@ -304,9 +304,8 @@ static double a_diag(const level_t *L, const double *alpha, const double *mu_c,
     if (!g->ns[l]) ehi[l] = wrapi(ehi[l], g->n[l]);
     /* a no-slip wall edge carries the one-sided difference (weight 2), a
        free-slip wall edge no flux (weight 0) */
-    const double wwall = g->fs[l] ? 0.0 : 2.0;
-    double wlo = (g->ns[l] && f[l] == 0) ? wwall : 1.0;
-    double whi = (g->ns[l] && f[l] + 1 == g->n[l]) ? wwall : 1.0;
+    double wlo = (g->ns[l] && f[l] == 0) ? (g->fs[l][0] ? 0.0 : 2.0) : 1.0;
+    double whi = (g->ns[l] && f[l] + 1 == g->n[l]) ? (g->fs[l][1] ? 0.0 : 2.0) : 1.0;
     dg += (whi * mu_e[eidx(L, m, ehi)] + wlo * mu_e[eidx(L, m, elo)]) / h2;
   }
   return dg;
@@ -571,7 +570,7 @@ static int tang_weights(const grid_t *gc, int a, int j, int idx[2], double w[2])
   w[0] = 0.75;
   if (gc->ns[a] && (Jn < 0 || Jn >= gc->n[a])) {
     idx[1] = J;
-    w[1] = gc->fs[a] ? 0.25 : -0.25;
+    w[1] = gc->fs[a][Jn < 0 ? 0 : 1] ? 0.25 : -0.25;
   } else {
     idx[1] = gc->ns[a] ? Jn : wrapi(Jn, gc->n[a]);
     w[1] = 0.25;
@@ -1276,15 +1275,17 @@ int orc_create(const orc_params *p, const double *rho, const double *mu,
   int nmin = 1 << 30;
   for (int a = 0; a < 3; a++) {
     if (a < g.d) {
-      if (p->n[a] < 2 || p->bc[a] < ORC_PERIODIC || p->bc[a] > ORC_FREESLIP) return ORC_EINVAL;
+      if (p->n[a] < 2 || p->bc[a] < ORC_PERIODIC || p->bc[a] > ORC_FREESLIP_NOSLIP)
+        return ORC_EINVAL;
       g.n[a] = p->n[a];
       g.ns[a] = (p->bc[a] != ORC_PERIODIC);
-      g.fs[a] = (p->bc[a] == ORC_FREESLIP);
+      g.fs[a][0] = (p->bc[a] == ORC_FREESLIP || p->bc[a] == ORC_FREESLIP_NOSLIP);
+      g.fs[a][1] = (p->bc[a] == ORC_FREESLIP || p->bc[a] == ORC_NOSLIP_FREESLIP);
       if (g.n[a] < nmin) nmin = g.n[a];
     } else {
       g.n[a] = 1;
       g.ns[a] = 0;
-      g.fs[a] = 0;
+      g.fs[a][0] = g.fs[a][1] = 0;
     }
   }
   /* the smallest axis must be a power of two >= 2; every axis must halve
@@ -1338,7 +1339,7 @@ int orc_create(const orc_params *p, const double *rho, const double *mu,
   X->vel_singular = 0;
   if (p->theta == 0.0) {
     int noslip = 0;
-    for (int a = 0; a < g.d; a++) noslip |= (g.ns[a] && !g.fs[a]);
+    for (int a = 0; a < g.d; a++) noslip |= (g.ns[a] && (!g.fs[a][0] || !g.fs[a][1]));
     for (int k = 0; k < g.d; k++)
       if (!g.ns[k] && !noslip) X->vel_singular |= 1 << k;
   }

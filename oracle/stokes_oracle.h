@@ -10,14 +10,16 @@
  * Conventions (same data layout as the product ABI, defined independently):
  *   - axes 0,1,2 = x,y,z; arrays are C-ordered with x fastest;
  *   - d = 2 or 3; for d = 2, n[2] = 1 and there is no z component;
- *   - bc[a] = 0 periodic, 1 no-slip walls at both ends of axis a;
+ *   - bc[a] = 0 periodic, 1 no-slip walls at both ends of axis a, 2 free-slip
+ *     walls, 3 no-slip low / free-slip high, 4 free-slip low / no-slip high;
+ *   - w[a] = 1 when axis a has walls (bc[a] != 0), else 0;
  *   - velocity component k lives on faces normal to axis k; its array has
- *     n[a] entries along a != k and n[k] + bc[k] entries along k; wall faces
- *     (index 0 and n[k] on a no-slip axis) hold 0 and are not unknowns;
+ *     n[a] entries along a != k and n[k] + w[k] entries along k; wall faces
+ *     (index 0 and n[k] on a wall axis) hold 0 and are not unknowns;
  *   - the d velocity arrays are stored back to back in one buffer (x, y, z);
  *   - cell arrays (p, rho, mu) have n[0]*n[1]*n[2] entries;
  *   - edge viscosity: edge family m is parallel to axis m and carries the shear
- *     viscosity for the pair {k,l} = the other two axes; it has n[a] + bc[a]
+ *     viscosity for the pair {k,l} = the other two axes; it has n[a] + w[a]
  *     entries along a in {k,l} and n[m] along m.  In 2D only family m = 2 (the
  *     grid nodes) exists.  Families are stored back to back in the order
  *     m = 2, 1, 0 (3D) or m = 2 (2D).
@@ -31,7 +33,10 @@ extern "C" {
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ENOCONV = -4,
        ORC_EBREAKDOWN = -5, ORC_ENONFINITE = -6, ORC_EINCOMPAT = -7 };
-enum { ORC_PERIODIC = 0, ORC_NOSLIP = 1, ORC_FREESLIP = 2 };
+/* per axis; the last two mix the two walls of one axis: no-slip at the low
+   end and free-slip at the high end, or the reverse */
+enum { ORC_PERIODIC = 0, ORC_NOSLIP = 1, ORC_FREESLIP = 2, ORC_NOSLIP_FREESLIP = 3,
+       ORC_FREESLIP_NOSLIP = 4 };
 enum { ORC_P1 = 1, ORC_P2 = 2, ORC_P3 = 3, ORC_P4 = 4, ORC_P5 = 5 };
 enum { ORC_GMRES_LEFT = 0, ORC_FGMRES = 1 };
 enum { ORC_EDGE_ARITH = 0, ORC_EDGE_HARMONIC = 1, ORC_EDGE_GIVEN = 2 };

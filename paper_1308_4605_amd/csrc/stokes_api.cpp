@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -63,8 +64,7 @@ bool valid_params(const stokes_params *p, int *nlev_out) {
   int nmin = 1 << 30;
   for (int a = 0; a < p->dim; a++) {
     if (p->n[a] < 2 || p->n[a] > (1 << 20)) return false;
-    if (p->bc[a] != STOKES_PERIODIC && p->bc[a] != STOKES_NOSLIP && p->bc[a] != STOKES_FREESLIP)
-      return false;
+    if (p->bc[a] < STOKES_PERIODIC || p->bc[a] > STOKES_FREESLIP_NOSLIP) return false;
     if (p->n[a] < nmin) nmin = p->n[a];
   }
   // coarsen by 2 until the smallest axis has two cells (Appendix C)
@@ -132,6 +132,10 @@ struct stokes_ctx {
   long launches = 0;
   double bytes = 0.0;
   double gs_bytes[3] = {0, 0, 0};
+  // preconditioner timing for stokes_stats (two events around each application)
+  hipEvent_t pev[2] = {nullptr, nullptr};
+  double *hist = nullptr;  // residual history (caller's host buffer)
+  int hist_cap = 0;
   int err = 0;
 };
 
@@ -558,6 +562,44 @@ double fetch(stokes_ctx *X, const double *dev, int count, double *dst) {
 // below 1/sqrt(2) of its previous value; Givens rotations on the host; the
 // solve ends on the true residual, each cycle on the Givens estimate reduced
 // by the factor the true residual still lacks.
+// Preconditioner applications bracketed by the ctx's two events; the time is
+// folded in at the next synchronisation of the iteration (prec_fold).
+struct PrecClock {
+  stokes_ctx *X;
+  double ms = 0.0;
+  bool open = false;
+  void start() {
+    if (X->pev[0]) (void)hipEventRecord(X->pev[0], X->s);
+  }
+  void stop() {
+    if (X->pev[0]) {
+      (void)hipEventRecord(X->pev[1], X->s);
+      open = true;
+    }
+  }
+  void fold() {  // call after the stream has reached the stop event
+    if (!open) return;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, X->pev[0], X->pev[1]) == hipSuccess) ms += t;
+    open = false;
+  }
+};
+
+// ||b - M x|| / ||b|| of the caller's system, from the scaled residual and
+// right-hand side (r' = (c r_u, r_p), b' = (c b_u, b_p))
+double unscaled_rel(stokes_ctx *X) {
+  const i64 nv = X->nvel, nc = X->ncell;
+  double *hb = X->host;
+  launch_norm2(X->r, nv, X->part, X->dsc + 0, X->s);
+  launch_norm2(X->r + nv, nc, X->part, X->dsc + 1, X->s);
+  launch_norm2(X->b, nv, X->part, X->dsc + 2, X->s);
+  launch_norm2(X->b + nv, nc, X->part, X->dsc + 3, X->s);
+  fetch(X, X->dsc, 4, hb);
+  const double c2 = X->c * X->c;
+  const double num = hb[0] / c2 + hb[1], den = hb[2] / c2 + hb[3];
+  return den > 0.0 ? std::sqrt(num / den) : 0.0;
+}
+
 int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
   const int m = X->p.restart;
   const int flexible = (X->p.krylov == STOKES_FGMRES);
@@ -565,6 +607,21 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
   stokes_stats local;
   if (!st) st = &local;
   std::memset(st, 0, sizeof(*st));
+  double *const hist = X->hist;
+  const int hcap = X->hist_cap;
+  PrecClock pc{X};
+  const auto t0 = std::chrono::steady_clock::now();
+  struct Finish {  // wall and preconditioner times on every exit path
+    stokes_stats *st;
+    PrecClock &pc;
+    std::chrono::steady_clock::time_point t0;
+    ~Finish() {
+      pc.fold();
+      st->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      st->t_precond = pc.ms * 1e-3;
+      st->t_krylov = st->t_total - st->t_precond;
+    }
+  } fin{st, pc, t0};
   double *hb = X->host;
   launch_norm2(X->b, n, X->part, X->dsc + 0, X->s);
   const double nb = std::sqrt(fetch(X, X->dsc, 1, hb));
@@ -583,6 +640,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     launch_norm2(X->r, n, X->part, X->dsc + 0, X->s);
     const double rho = std::sqrt(fetch(X, X->dsc, 1, hb));
     if (X->err) return STOKES_EDEVICE;
+    pc.fold();
     st->rel_res_true = rho / nb;
     if (!std::isfinite(rho)) { rc = STOKES_ENONFINITE; break; }
     if (rho <= tol * nb) { rc = STOKES_OK; break; }
@@ -593,10 +651,13 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       beta = rho;
       launch_scale(X->r, 1.0 / beta, X->V[0], n, X->s);
     } else {
+      pc.start();
       precond<double>(X, X->r, X->r + nv, X->V[0], X->V[0] + nv);
+      pc.stop();
       st->precond_applies++;
       launch_norm2(X->V[0], n, X->part, X->dsc + 0, X->s);
       beta = std::sqrt(fetch(X, X->dsc, 1, hb));
+      pc.fold();
       if (!std::isfinite(beta)) { rc = STOKES_ENONFINITE; break; }
       if (beta == 0.0) { rc = STOKES_EBREAKDOWN; break; }
       launch_scale(X->V[0], 1.0 / beta, X->V[0], n, X->s);
@@ -608,7 +669,9 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     int jj = 0;
     for (int j = 0; j < m; j++) {
       if (flexible) {
+        pc.start();
         precond_from64(X, X->V[j], X->Z[j], j > 0);
+        pc.stop();
         if (X->mg32)
           launch_apply_m<float>(X->lev[0].g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam,
                                 P<float>(X->Z[j]),
@@ -617,7 +680,9 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
           apply_scaled(X, P<double>(X->Z[j]), X->w);
       } else {
         apply_scaled(X, X->V[j], X->t);
+        pc.start();
         precond<double>(X, X->t, X->t + nv, X->w, X->w + nv);
+        pc.stop();
       }
       st->precond_applies++;
       it++;
@@ -630,6 +695,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
                                hipMemcpyDeviceToHost, X->s));
       hip_ok(X, hipStreamSynchronize(X->s));
       if (X->err) return STOKES_EDEVICE;
+      pc.fold();
       double *hcol = &H[(size_t)j * (m + 1)];
       double q = 0.0;
       for (int i = 0; i <= j; i++) {
@@ -671,6 +737,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       jj = j + 1;
       const double est = std::fabs(g[j + 1]);
       st->rel_res_est = est / beta * (rho / nb);
+      if (hist && st->history_len < hcap) hist[st->history_len++] = st->rel_res_est;
       if (!std::isfinite(est)) break;
       if (hn == 0.0 || est <= target || it >= max_iter) break;
       // pass C: v_{j+1} = (w - V (h1 + h2)) / nu, plus the FP32 copy the next
@@ -698,6 +765,8 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
   const int vel_per = (X->p.precond == STOKES_P5) ? 2 : 1;
   const int p_per = (X->p.precond == STOKES_P1) ? 1 : (X->p.theta != 0.0 ? 1 : 0);
   st->scalar_vcycles = st->precond_applies * X->p.vcycles * (X->d * vel_per + p_per);
+  // X->r holds b' - M' x' of the final iterate unless the loop left early
+  if (rc == STOKES_OK || rc == STOKES_ENOCONV) st->rel_res_unscaled = unscaled_rel(X);
   return rc;
 }
 
@@ -871,7 +940,9 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
   X->vel_singular = 0;
   if (p->theta == 0.0) {
     int noslip = 0;
-    for (int a = 0; a < p->dim; a++) noslip |= (p->bc[a] == STOKES_NOSLIP);
+    for (int a = 0; a < p->dim; a++)
+      noslip |= (p->bc[a] == STOKES_NOSLIP || p->bc[a] == STOKES_NOSLIP_FREESLIP ||
+                 p->bc[a] == STOKES_FREESLIP_NOSLIP);
     for (int k = 0; k < p->dim; k++)
       if (p->bc[k] == STOKES_PERIODIC && !noslip) X->vel_singular |= 1 << k;
   }
@@ -982,6 +1053,10 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
     delete X;
     return STOKES_EDEVICE;
   }
+  if (hipEventCreate(&X->pev[0]) != hipSuccess || hipEventCreate(&X->pev[1]) != hipSuccess) {
+    if (X->pev[0]) (void)hipEventDestroy(X->pev[0]);
+    X->pev[0] = X->pev[1] = nullptr;  // statistics then report no preconditioner time
+  }
   *out = X;
   return STOKES_OK;
 }
@@ -990,6 +1065,8 @@ void stokes_destroy(stokes_ctx *X) {
   if (!X) return;
   if (X->s) (void)hipStreamSynchronize(X->s);
   for (auto e : X->ev) (void)hipEventDestroy(e);
+  for (auto e : X->pev)
+    if (e) (void)hipEventDestroy(e);
   if (X->host) (void)hipHostFree(X->host);
   delete X;
 }
@@ -1151,6 +1228,13 @@ int stokes_adjoint_solve(stokes_ctx *X, const double *xu, const double *xp, cons
   grad_impl(X, X->t, lu, dmu_cell, dmu_edge, drho_cell, dgamma_cell);
   hip_ok(X, hipStreamSynchronize(X->s));
   return finish(X, rc);
+}
+
+int stokes_set_history(stokes_ctx *X, double *buf, int cap) {
+  if (!X || cap < 0) return STOKES_EINVAL;
+  X->hist = (buf && cap > 0) ? buf : nullptr;
+  X->hist_cap = X->hist ? cap : 0;
+  return STOKES_OK;
 }
 
 int stokes_set_timing(stokes_ctx *X, int enable) {

@@ -21,7 +21,7 @@ struct Geo {
   int d;
   int n[3];
   int ns[3];  // walls on this axis (no-slip or free-slip)
-  int fs[3];  // the walls on this axis are free-slip
+  int fs[3];  // free-slip ends of this axis: bit 0 low end, bit 1 high end
   int sing;   // bit k: velocity component k has a constant null space
   double h, ih;  // spacing and its reciprocal
   i64 ncell, nvel, nedge;

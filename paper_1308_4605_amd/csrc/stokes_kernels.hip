@@ -37,7 +37,9 @@ Geo make_geo(int d, const int n[3], const int bc[3], double h) {
   for (int a = 0; a < 3; a++) {
     g.n[a] = (a < d) ? n[a] : 1;
     g.ns[a] = (a < d) ? (bc[a] != 0) : 0;
-    g.fs[a] = (a < d) ? (bc[a] == 2) : 0;
+    // free-slip ends: bit 0 the low end, bit 1 the high end
+    const int b = (a < d) ? bc[a] : 0;
+    g.fs[a] = (b == 2) ? 3 : (b == 3) ? 2 : (b == 4) ? 1 : 0;
   }
   g.sing = 0;
   g.ncell = (i64)g.n[0] * g.n[1] * g.n[2];
@@ -191,8 +193,9 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
     const T ghi = (ua[l] - uf) * ih + (ulh_r - ulh_l) * ih;
     const T glo = (uf - ub[l]) * ih + (ull_r - ull_l) * ih;
     s += (mhi * ghi - mlo * glo) * ih;
-    const T ww = g.fs[l] ? (T)0 : (T)2;  // wall edge: one-sided (no-slip) or no flux
-    dg += ((top ? ww : (T)1) * mhi + (bot ? ww : (T)1) * mlo) * ih2;
+    // wall edge: one-sided difference (no-slip, weight 2) or no flux (free-slip)
+    const T wt = (g.fs[l] & 2) ? (T)0 : (T)2, wb = (g.fs[l] & 1) ? (T)0 : (T)2;
+    dg += ((top ? wt : (T)1) * mhi + (bot ? wb : (T)1) * mlo) * ih2;
     hdr += ulh_r - ull_r;
     hdl += ulh_l - ull_l;
   }
@@ -238,9 +241,8 @@ __device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const
     const T vb = u[fidx3(g, k, t)];
     t[l] = i[l];
     // no-slip: odd ghost (zero wall value); free-slip: even ghost (no shear)
-    const T gs = g.fs[l] ? uf : -uf;
-    ua[l] = top ? gs : va;
-    ub[l] = bot ? gs : vb;
+    ua[l] = top ? ((g.fs[l] & 2) ? uf : -uf) : va;
+    ub[l] = bot ? ((g.fs[l] & 1) ? uf : -uf) : vb;
   }
   const T *comp[3] = {u + g.foff[0], u + g.foff[1], u + g.foff[2]};
   a_row_nb<T, DIM>(g, k, i, uf, ukp, ukm, ua, ub, comp, alpha, muc, mue, lam, Au, diag);
@@ -559,8 +561,9 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
     const int lm = dn1(g, l, i[l]);
     t[l] = top ? i[l] : lp;  // component k has no face at index n[l] along l
     const double va = (double)u[fidx3(g, k, t)];  // unconditional; ghost selected below
-    const double gsv = g.fs[l] ? uf : -uf;  // wall ghost: even (free-slip) or odd
-    double ua = top ? gsv : va;
+    // wall ghosts: even (free-slip end) or odd (no-slip end)
+    const bool fs_hi = g.fs[l] & 2, fs_lo = g.fs[l] & 1;
+    double ua = top ? (fs_hi ? uf : -uf) : va;
     t[l] = lp;
     const int ehi = eidx3(g, m, t);
     const double mhi = mue[ehi];
@@ -570,13 +573,13 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
     t[k] = i[k];
     t[l] = lm;
     const double vb = (double)u[fidx3(g, k, t)];
-    double ub = bot ? gsv : vb;
+    double ub = bot ? (fs_lo ? uf : -uf) : vb;
     t[l] = i[l];
     const int elo = eidx3(g, m, t);
     const double mlo = mue[elo];
-    if (GW && !g.fs[l]) {
-      if (top) ua = 2.0 * gw[ehi] - uf;
-      if (bot) ub = 2.0 * gw[elo] - uf;
+    if (GW) {
+      if (top && !fs_hi) ua = 2.0 * gw[ehi] - uf;
+      if (bot && !fs_lo) ub = 2.0 * gw[elo] - uf;
     }
     // with prescribed normal velocities on a free-slip wall the cross
     // derivative along the wall need not vanish; the whole flux does
@@ -586,9 +589,9 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
     t[k] = i[k];
     double ghi = (ua - uf) * ih + (ulh_r - ulh_l) * ih;
     double glo = (uf - ub) * ih + (ull_r - ull_l) * ih;
-    if (GW && g.fs[l]) {
-      if (top) ghi = 0.0;
-      if (bot) glo = 0.0;
+    if (GW) {
+      if (top && fs_hi) ghi = 0.0;
+      if (bot && fs_lo) glo = 0.0;
     }
     s += (mhi * ghi - mlo * glo) * ih;
     hdr += ulh_r - ull_r;
@@ -883,7 +886,8 @@ void launch_face_restrict(const Geo &gf, const Geo &gc, const T *rf, T *rc, hipS
 
 // tangential prolongation weights (Appendix C): 3/4 on the parent coarse
 // face, 1/4 on the next one away from the parent's centre; at a no-slip wall
-// the missing neighbour is the odd reflection -phi(J)
+// the missing neighbour is the odd reflection -phi(J), at a free-slip wall
+// the even one
 __device__ __forceinline__ void tang_w(const Geo &gc, int a, int j, int idx[2], double w[2]) {
   const int J = j >> 1;
   const int Jn = (j & 1) ? J + 1 : J - 1;
@@ -891,7 +895,8 @@ __device__ __forceinline__ void tang_w(const Geo &gc, int a, int j, int idx[2], 
   w[0] = 0.75;
   if (gc.ns[a] && (Jn < 0 || Jn >= gc.n[a])) {
     idx[1] = J;
-    w[1] = gc.fs[a] ? 0.25 : -0.25;  // even reflection at a free-slip wall
+    const int end = (Jn < 0) ? 1 : 2;  // low or high end of axis a
+    w[1] = (gc.fs[a] & end) ? 0.25 : -0.25;
   } else {
     int jj = Jn;
     if (!gc.ns[a]) {
@@ -1906,8 +1911,8 @@ __global__ void k_grad_edges(Geo g, int m, const double *__restrict__ u,
   const bool wall = (g.ns[k] && (e[k] == 0 || e[k] == g.n[k])) ||
                     (g.ns[l] && (e[l] == 0 || e[l] == g.n[l]));
   // no shear stress (and no dependence on mu_edge) on a free-slip wall
-  const bool free = (g.fs[k] && (e[k] == 0 || e[k] == g.n[k])) ||
-                    (g.fs[l] && (e[l] == 0 || e[l] == g.n[l]));
+  const bool free = ((g.fs[k] & 1) && e[k] == 0) || ((g.fs[k] & 2) && e[k] == g.n[k]) ||
+                    ((g.fs[l] & 1) && e[l] == 0) || ((g.fs[l] & 2) && e[l] == g.n[l]);
   const double gu = dkl(g, u, k, l, e) + dkl(g, u, l, k, e);
   const double gl = dkl(g, lam, k, l, e) + dkl(g, lam, l, k, e);
   dme[g.eoff[m] + t] = free ? 0.0 : -(wall ? 0.5 : 1.0) * gl * gu;

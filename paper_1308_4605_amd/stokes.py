@@ -32,6 +32,7 @@ ABI_FUNCTIONS = (
     "stokes_vel_subsolve", "stokes_p_subsolve", "stokes_vel_mg_solve", "stokes_p_mg_solve",
     "stokes_solve", "stokes_adjoint_solve",
     "stokes_grad", "stokes_rescale", "stokes_set_timing", "stokes_kernel_time", "stokes_destroy",
+    "stokes_set_history",
     "stokes_strerror",
 )
 
@@ -48,10 +49,16 @@ class StokesParams(ctypes.Structure):
 class StokesStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("precond_applies", ctypes.c_int), ("scalar_vcycles", ctypes.c_int),
-                ("rel_res_true", ctypes.c_double), ("rel_res_est", ctypes.c_double)]
+                ("rel_res_true", ctypes.c_double), ("rel_res_est", ctypes.c_double),
+                ("rel_res_unscaled", ctypes.c_double), ("history_len", ctypes.c_int),
+                ("t_total", ctypes.c_double), ("t_precond", ctypes.c_double),
+                ("t_krylov", ctypes.c_double)]
 
-    def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+    def as_dict(self, history=None):
+        out = {f: getattr(self, f) for f, _ in self._fields_}
+        if history is not None:
+            out["history"] = [history[i] for i in range(self.history_len)]
+        return out
 
 
 class StokesError(RuntimeError):
@@ -98,6 +105,7 @@ def lib():
         L.stokes_rescale.argtypes = [vp]
         L.stokes_rescale.restype = ctypes.c_double
         L.stokes_set_timing.argtypes = [vp, ctypes.c_int]
+        L.stokes_set_history.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
         L.stokes_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_long),
                                          ctypes.POINTER(ctypes.c_double)]
@@ -252,7 +260,10 @@ class Stokes:
         """Pressure multigrid run to ||r - L e|| <= tol ||r||: (e, cycles, rel_res, rc)."""
         return self._mg_solve("stokes_p_mg_solve", r, self.ncell, tol, max_cycles)
 
-    def solve(self, bu, bp, tol=1e-8, max_iter=1000, x0=None, check=True, out=None):
+    def solve(self, bu, bp, tol=1e-8, max_iter=1000, x0=None, check=True, out=None,
+              history=False):
+        """Returns (xu, xp, stats, rc); history=True adds the per-iteration
+        residual estimates to stats["history"]."""
         if out is not None:
             xu, xp = out
         else:
@@ -260,12 +271,19 @@ class Stokes:
         if x0 is not None:
             xu.copy_(x0[0])
             xp.copy_(x0[1])
-        st = StokesStats()
-        rc = lib().stokes_solve(self._h, _ptr(bu), _ptr(bp), _ptr(xu), _ptr(xp), float(tol),
-                                int(max_iter), 1 if x0 is not None else 0, ctypes.byref(st))
+        st, buf = StokesStats(), None
+        if history:
+            buf = (ctypes.c_double * (int(max_iter) + 1))()
+            lib().stokes_set_history(self._h, buf, int(max_iter) + 1)
+        try:
+            rc = lib().stokes_solve(self._h, _ptr(bu), _ptr(bp), _ptr(xu), _ptr(xp), float(tol),
+                                    int(max_iter), 1 if x0 is not None else 0, ctypes.byref(st))
+        finally:
+            if history:
+                lib().stokes_set_history(self._h, None, 0)
         if check and rc:
             raise StokesError(rc, "stokes_solve")
-        return xu, xp, st.as_dict(), rc
+        return xu, xp, st.as_dict(buf), rc
 
     def adjoint(self, xu, xp, gu, gp, tol=1e-8, max_iter=1000, check=True):
         lu, lp = self._new(self.nvel), self._new(self.ncell)

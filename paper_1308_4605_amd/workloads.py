@@ -22,6 +22,15 @@ import numpy as np
 PERIODIC = 0
 NOSLIP = 1
 FREESLIP = 2
+NOSLIP_FREESLIP = 3   # no-slip at the low end of the axis, free-slip at the high end
+FREESLIP_NOSLIP = 4   # free-slip low, no-slip high
+
+
+def end_is_noslip(bc, side):
+    """Whether the wall at the low (side 0) or high (side 1) end of an axis
+    with condition bc is no-slip."""
+    return bc == NOSLIP or (bc == NOSLIP_FREESLIP and side == 0) or (
+        bc == FREESLIP_NOSLIP and side == 1)
 
 P1, P2, P3, P4, P5 = 1, 2, 3, 4, 5
 GMRES_LEFT, FGMRES = 0, 1
@@ -138,7 +147,8 @@ class Layout:
     def singular_components(self, theta):
         """Velocity components with a constant null space: theta = 0, the
         component's own axis periodic and no axis with no-slip walls."""
-        if theta != 0.0 or any(self.bc[a] == NOSLIP for a in range(self.dim)):
+        if theta != 0.0 or any(end_is_noslip(self.bc[a], s) for a in range(self.dim)
+                               for s in (0, 1)):
             return []
         return [k for k in range(self.dim) if self.bc[k] == PERIODIC]
 

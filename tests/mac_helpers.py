@@ -58,6 +58,13 @@ def second_diff_1d(n, h, kind):
         A = sp.diags([np.ones(m - 1), -2 * np.ones(m), np.ones(m - 1)], [-1, 0, 1]).tolil()
         A[0, 0] = -1.0
         A[m - 1, m - 1] = -1.0
+    elif kind in ("wall_neumann_cc", "neumann_wall_cc"):
+        # zero value half a cell out at one end, zero flux at the other
+        m = n
+        A = sp.diags([np.ones(m - 1), -2 * np.ones(m), np.ones(m - 1)], [-1, 0, 1]).tolil()
+        lo, hi = (-3.0, -1.0) if kind == "wall_neumann_cc" else (-1.0, -3.0)
+        A[0, 0] = lo
+        A[m - 1, m - 1] = hi
     else:
         raise ValueError(kind)
     return (A.tocsr() / (h * h))
@@ -93,10 +100,11 @@ def textbook_vector_laplacian(lay: W.Layout, h):
                 mats.append(second_diff_1d(n, h, "periodic"))
             elif a == k:
                 mats.append(second_diff_1d(n, h, "dirichlet"))
-            elif lay.bc[a] == W.FREESLIP:
-                mats.append(second_diff_1d(n, h, "neumann_cc"))
             else:
-                mats.append(second_diff_1d(n, h, "wall_cc"))
+                lo, hi = (W.end_is_noslip(lay.bc[a], s) for s in (0, 1))
+                kind = {(True, True): "wall_cc", (False, False): "neumann_cc",
+                        (True, False): "wall_neumann_cc", (False, True): "neumann_wall_cc"}[(lo, hi)]
+                mats.append(second_diff_1d(n, h, kind))
         blocks.append(kron_sum(mats))
     return sp.block_diag(blocks, format="csr").toarray()
 

@@ -41,7 +41,8 @@ def test_library_exports_every_declared_function(S):
 @pytest.mark.parametrize("dim,n,bc", [(2, (32, 32), (0, 0)), (2, (1024, 1024), (1, 1)),
                                       (3, (128, 128, 128), (1, 1, 1)), (3, (256, 256, 256), (0, 0, 0)),
                                       (3, (48, 40, 8), (1, 0, 1)), (2, (2, 2), (1, 1)),
-                                      (3, (48, 40, 8), (2, 0, 1)), (2, (32, 16), (2, 2))])
+                                      (3, (48, 40, 8), (2, 0, 1)), (2, (32, 16), (2, 2)),
+                                      (2, (32, 16), (0, 3)), (3, (48, 40, 8), (4, 3, 1))])
 def test_sizes_match_layout(S, dim, n, bc):
     p = S.make_params(dim, n, bc, 1.0 / n[0], 0.0)
     nv, nc, ne, nl = S.stokes_sizes(p)
@@ -55,7 +56,7 @@ def test_sizes_match_layout(S, dim, n, bc):
 @pytest.mark.parametrize("bad", [
     dict(dim=4), dict(n=(12, 12)), dict(n=(32, 24)), dict(h=0.0), dict(theta=-1.0),
     dict(precond=6), dict(precision=1, krylov=0), dict(restart=0), dict(restart=33),
-    dict(nu_coarse=0), dict(vcycles=0), dict(edge_avg=3), dict(bc=(3, 0)),
+    dict(nu_coarse=0), dict(vcycles=0), dict(edge_avg=3), dict(bc=(5, 0)), dict(bc=(-1, 0)),
     dict(n=(96, 64)), dict(dim=3, n=(1024, 1024, 1024), bc=(0, 0, 0))])
 def test_invalid_parameters_rejected_on_host(S, bad):
     base = dict(dim=2, n=(32, 32), bc=(0, 0), h=1 / 32, theta=1.0)

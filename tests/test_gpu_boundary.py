@@ -9,12 +9,14 @@ import oracle
 from gpu_common import N, T, pair, params, rel, scaled_residual
 from paper_1308_4605_amd import workloads as W
 from test_oracle_boundary import _couette_exact, _edge_views
+from test_oracle_mixed_bc import _open_channel_exact
 
 pytestmark = pytest.mark.gpu
 
 GRIDS = [
     (2, (48, 32), (1, 1)), (2, (64, 32), (0, 1)), (2, (32, 32), (2, 1)),
     (3, (16, 16, 16), (1, 1, 1)), (3, (32, 16, 16), (1, 2, 0)), (3, (16, 32, 16), (0, 0, 1)),
+    (2, (64, 32), (0, 3)), (3, (16, 16, 32), (4, 0, 3)),
 ]
 
 
@@ -81,3 +83,33 @@ def test_lid_driven_cavity_parity(precision, krylov):
         assert abs(st["iters"] - ost["iters"]) <= 1
     assert scaled_residual(o, o.c, -ocu, -ocp, N(xu), N(xp)) <= 1e-9 * (1 + 1e-6)
     assert rel(N(xu), ou) <= 1e-6
+
+
+@pytest.mark.parametrize("bc_y", [W.NOSLIP_FREESLIP, W.FREESLIP_NOSLIP])
+@pytest.mark.parametrize("precision,krylov", [(W.FP64, W.GMRES_LEFT), (W.MG_FP32, W.FGMRES)])
+def test_open_channel_exact_gpu(bc_y, precision, krylov):
+    """A no-slip bed and a free-slip surface on one axis: the discrete
+    open-channel profile in closed form (test_oracle_mixed_bc.py)."""
+    n = (64, 256)
+    lay = W.make_layout(2, n, (W.PERIODIC, bc_y))
+    h = 1.0 / n[0]
+    rng = np.random.default_rng(75)
+    mu_nodes = rng.uniform(0.2, 5.0, n[1] + 1)
+    edges = np.repeat(mu_nodes[:, None], n[0], axis=1).ravel()
+    p, _ = params(2, n, (W.PERIODIC, bc_y), 0.0, precond=W.P2, precision=precision,
+                  krylov=krylov, edge_avg=W.EDGE_GIVEN)
+    g, _ = pair(p, np.ones(lay.ncell), np.ones(lay.ncell), edges)
+    f = 1.3
+    bu = np.zeros(lay.nvel)
+    lay.split_vel(bu)[0][...] = f
+    # the true residual of this right-hand side levels off near 5e-12 (FP64
+    # rounding, the oracle alike); 1e-10 already gives a 1e-13 profile error
+    xu, xp, st, rc = g.solve(T(bu), T(np.zeros(lay.ncell)), tol=1e-10, max_iter=1000)
+    assert rc == 0
+    ux, uy = lay.split_vel(N(xu))
+    uex = _open_channel_exact(mu_nodes, h, f, bc_y == W.NOSLIP_FREESLIP)
+    scale = np.abs(uex).max()
+    print(f"  precision {precision}: {st['iters']} iterations, max error "
+          f"{np.abs(ux - uex[:, None]).max() / scale:.2e}", flush=True)
+    assert np.abs(ux - uex[:, None]).max() <= 1e-9 * scale
+    assert np.abs(uy).max() <= 1e-9 * scale

@@ -31,6 +31,9 @@ OPS = [
     # free-slip walls (2), alone and mixed
     (2, (48, 32), (2, 2)), (2, (64, 32), (0, 2)), (3, (16, 16, 16), (2, 2, 2)),
     (3, (48, 40, 8), (2, 0, 1)), (3, (32, 16, 16), (2, 1, 0)),
+    # one axis with different walls: 3 = no-slip low / free-slip high, 4 = the reverse
+    (2, (64, 32), (0, 3)), (2, (48, 32), (4, 1)), (3, (32, 16, 16), (4, 0, 3)),
+    (3, (16, 16, 16), (3, 4, 2)),
 ]
 
 
@@ -75,7 +78,9 @@ def test_subsolver_parity(dim, n, bc, theta):
 @pytest.mark.parametrize("dim,n,bc,theta", [(2, (48, 32), (1, 1), 25.0), (3, (16, 16, 16), (0, 0, 0), 0.0),
                                             (3, (48, 40, 8), (1, 0, 1), 100.0), (2, (32, 32), (0, 0), 0.0),
                                             (2, (48, 32), (2, 2), 0.0), (3, (32, 16, 16), (2, 0, 2), 0.0),
-                                            (3, (16, 16, 16), (2, 1, 2), 40.0)])
+                                            (3, (16, 16, 16), (2, 1, 2), 40.0),
+                                            (2, (64, 32), (0, 3), 0.0),
+                                            (3, (32, 16, 16), (4, 0, 3), 20.0)])
 @pytest.mark.parametrize("precond", [W.P1, W.P2, W.P3, W.P4, W.P5])
 def test_precond_parity(dim, n, bc, theta, precond):
     print(f"precond P{precond} {dim} {n} {bc} theta={theta}", flush=True)
@@ -211,6 +216,8 @@ FREESLIP = [
     (2, (64, 64), (2, 2), 0.0),
     (3, (32, 32, 32), (2, 0, 2), 0.0),
     (3, (32, 32, 32), (2, 2, 1), 10.0),
+    (2, (64, 64), (0, 3), 0.0),
+    (3, (32, 32, 32), (0, 4, 0), 0.0),
 ]
 
 

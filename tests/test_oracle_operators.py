@@ -22,6 +22,11 @@ CASES = [
     (2, (8, 8), (1, 2)),
     (3, (4, 4, 4), (2, 2, 2)),
     (3, (4, 8, 4), (2, 0, 1)),
+    # the two walls of one axis differ (3: no-slip low / free-slip high, 4: the reverse)
+    (2, (8, 8), (0, 3)),
+    (2, (8, 8), (4, 3)),
+    (3, (4, 4, 4), (3, 0, 4)),
+    (3, (4, 8, 4), (1, 4, 3)),
 ]
 
 
@@ -180,7 +185,7 @@ def test_periodic_commuting_properties():
         assert rel(Lp @ D, D @ L) < 1e-13
 
 
-@pytest.mark.parametrize("bc", [(1, 0, 1), (2, 0, 1), (2, 2, 2)])
+@pytest.mark.parametrize("bc", [(1, 0, 1), (2, 0, 1), (2, 2, 2), (3, 0, 4), (4, 3, 1)])
 def test_energy_form_of_viscous_operator(bc):
     """-u^T L_mu u = sum_cells 2 mu_c sum_k (D^k u_k)^2 + sum_edges w_e mu_e
     gamma_e^2, with w_e = 1/2 on no-slip wall edges and no flux through

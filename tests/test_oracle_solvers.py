@@ -86,7 +86,7 @@ def test_gmres_matches_fft_exact_solution(dim, n, theta, precond):
     (2, (8, 8), (1, 1), 0.0), (2, (8, 8), (0, 0), 30.0), (2, (8, 8), (0, 1), 0.0),
     (2, (8, 8), (0, 0), 0.0), (3, (4, 4, 4), (1, 1, 1), 10.0), (3, (4, 4, 4), (1, 0, 0), 0.0),
     (2, (8, 8), (2, 2), 0.0), (2, (8, 8), (0, 2), 0.0), (3, (4, 4, 4), (2, 1, 2), 10.0),
-    (3, (4, 4, 4), (2, 2, 0), 0.0)])
+    (3, (4, 4, 4), (2, 2, 0), 0.0), (2, (8, 8), (0, 3), 0.0), (3, (4, 4, 4), (4, 2, 3), 10.0)])
 @pytest.mark.parametrize("precond,krylov", [(W.P1, W.GMRES_LEFT), (W.P2, W.GMRES_LEFT),
                                             (W.P3, W.GMRES_LEFT), (W.P5, W.GMRES_LEFT),
                                             (W.P1, W.FGMRES), (W.P4, W.FGMRES)])
