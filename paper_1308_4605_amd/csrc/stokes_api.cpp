@@ -558,10 +558,11 @@ double fetch(stokes_ctx *X, const double *dev, int count, double *dst) {
 
 // Restarted GMRES(m), left-preconditioned or flexible, on the rescaled system
 // b' -> x' held in X->b, X->x.  The same algorithm as the CPU oracle:
-// classical Gram-Schmidt with one re-orthogonalisation when the norm falls
-// below 1/sqrt(2) of its previous value; Givens rotations on the host; the
-// solve ends on the true residual, each cycle on the Givens estimate reduced
-// by the factor the true residual still lacks.
+// classical Gram-Schmidt applied twice (CGS2) in three streaming passes, the
+// new vector's norm from ||w'||^2 - ||h2||^2 unless the second pass removed
+// half or more of ||w'||^2 (then w'' is formed and measured); Givens
+// rotations on the host; the solve ends on the true residual, each cycle on
+// the Givens estimate reduced by the factor the true residual still lacks.
 // Preconditioner applications bracketed by the ctx's two events; the time is
 // folded in at the next synchronisation of the iteration (prec_fold).
 struct PrecClock {
