@@ -11,6 +11,9 @@ The JSON line also carries
   - roofline: the finest-level velocity Gauss-Seidel colour pass (the
     dominant kernel), algorithmic bytes per launch / average launch time,
     timed with HIP events on the solver's stream during the timed solves;
+  - vcycle_aggregate: whole finest-level V-cycles (velocity, pressure when
+    the preconditioner runs one), their algorithmic bytes over all levels /
+    their time, from HIP events on the solver's stream;
   - cpu_baseline: the FP64 CPU oracle on a bounded sample of the same
     workload (one Arnoldi step), scaled to solves/s with the iteration count
     of the FP64 solve.
@@ -171,7 +174,7 @@ def main():
             its.append(st["iters"])
         torch.cuda.synchronize()
         el = time.perf_counter() - t
-        kt = S.kernel_time() if timing else None
+        kt = (S.kernel_time(), S.vcycle_time(False), S.vcycle_time(True)) if timing else None
         if timing:
             S.set_timing(False)
         S.close()
@@ -185,8 +188,21 @@ def main():
 
     split = _split_baseline(torch, dev, Stokes, p32, rho, mu, bu, bp, args.tol, st["scalar_vcycles"])
 
-    ms_k, launches, bytes_k = kt
+    (ms_k, launches, bytes_k), vc_vel, vc_p = kt
     avg_ms = ms_k / max(launches, 1)
+
+    def vcycle_rate(t):
+        ms, cycles, nbytes = t
+        if cycles == 0:
+            return None
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"cycles": cycles, "avg_ms": ms / cycles, "alg_bytes_per_cycle": nbytes / cycles,
+                "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+    vcycles = {"velocity": vcycle_rate(vc_vel), "pressure": vcycle_rate(vc_p),
+               "note": "whole V-cycles from the finest level (all levels), HIP events on the "
+                       "solver stream; algorithmic bytes = every array each kernel reads or "
+                       "writes, once per kernel"}
     achieved = (bytes_k / max(launches, 1)) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
 
     fp64 = None
@@ -268,6 +284,7 @@ def main():
                      "copy_ceiling": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "avg_launch_us": 1e3 * avg_ms, "launches": launches,
                      "bytes_per_launch": bytes_k / max(launches, 1)},
+        "vcycle_aggregate": vcycles,
         "split_baseline": split,
         "adjoint": adjoint,
         "cpu_baseline": cpu,

@@ -285,6 +285,15 @@ double stokes_rescale(const stokes_ctx *ctx);
    synchronises the stream. */
 int stokes_set_timing(stokes_ctx *ctx, int enable);
 int stokes_kernel_time(stokes_ctx *ctx, double *ms_total, long *launches, double *bytes_total);
+/* With timing enabled, every V-cycle started from the finest level (in the
+   preconditioner, the subsolvers and the *_mg_solve calls) is also bracketed
+   by HIP events: pressure = 0 selects the velocity cycles, 1 the pressure
+   cycles.  Returns their accumulated milliseconds, their count and their
+   algorithmic bytes (each array a kernel of the cycle reads or writes counted
+   once, summed over the levels), for the aggregate V-cycle bandwidth.
+   Synchronises the stream. */
+int stokes_vcycle_time(stokes_ctx *ctx, int pressure, double *ms_total, long *cycles,
+                       double *bytes_total);
 
 void stokes_destroy(stokes_ctx *ctx);
 const char *stokes_strerror(int code);

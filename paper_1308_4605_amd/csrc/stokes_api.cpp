@@ -132,6 +132,13 @@ struct stokes_ctx {
   long launches = 0;
   double bytes = 0.0;
   double gs_bytes[3] = {0, 0, 0};
+  // timing of whole V-cycles from the finest level (index 0 velocity, 1
+  // pressure): event pairs, accumulated time, count and algorithmic bytes
+  std::vector<hipEvent_t> vev;
+  std::vector<int> vev_kind;
+  int vev_used = 0;
+  double vc_ms[2] = {0, 0}, vc_bytes[2] = {0, 0}, vc_cycle_bytes[2] = {0, 0};
+  long vc_count[2] = {0, 0};
   // preconditioner timing for stokes_stats (two events around each application)
   hipEvent_t pev[2] = {nullptr, nullptr};
   double *hist = nullptr;  // residual history (caller's host buffer)
@@ -265,6 +272,17 @@ int finish(stokes_ctx *X, int rc) {
 }
 
 // ---------------- timing ----------------
+void fold_vevents(stokes_ctx *X) {
+  if (X->vev_used == 0) return;
+  (void)hipStreamSynchronize(X->s);
+  for (int i = 0; i < X->vev_used; i++) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, X->vev[2 * i], X->vev[2 * i + 1]) == hipSuccess)
+      X->vc_ms[X->vev_kind[i]] += ms;
+  }
+  X->vev_used = 0;
+}
+
 void fold_events(stokes_ctx *X) {
   if (X->ev_used == 0) return;
   (void)hipStreamSynchronize(X->s);
@@ -294,6 +312,57 @@ inline const double *m_alpha_of(const stokes_ctx *X) {
 template <typename T>
 inline const T *lam_of(const Level &L) {
   return (const T *)L.lam;
+}
+
+// Algorithmic bytes of one V-cycle from the finest level (each array a
+// kernel reads or writes counted once per kernel, the same model as the
+// colour-pass figure), summed over the levels; s = bytes per value of the
+// hierarchy.  Velocity, per level: the zero fill of phi; each colour pass of
+// component k reads all components, rhs_k, alpha_k (theta != 0), mu_cell,
+// the bulk coefficient (if any) and the edge families touching k, and writes
+// component k; on all but the coarsest level the residual (rhs, phi, alpha,
+// mu_cell, edges, bulk -> res), the face restriction (res -> coarse rhs) and
+// the prolongation (coarse phi, phi -> phi).  Pressure alike with beta on
+// the faces and red-black passes over the cells.
+double vcycle_alg_bytes(const stokes_ctx *X, bool vel) {
+  const double s = X->mg32 ? 4.0 : 8.0;
+  const bool th = X->p.theta != 0.0;
+  double total = 0.0;
+  for (int l = 0; l < X->nlev; l++) {
+    const Geo &g = X->lev[l].g;
+    const double nv = (double)g.nvel, nc = (double)g.ncell, ne = (double)g.nedge;
+    const bool coarsest = (l == X->nlev - 1);
+    const int sweeps = coarsest ? X->p.nu_coarse : X->p.nu_pre + X->p.nu_post;
+    double b = 0.0;
+    if (vel) {
+      b += nv;  // zero fill
+      double sweep = 0.0;
+      for (int k = 0; k < g.d; k++) {
+        double e = 0.0;
+        for (int m = 0; m < 3; m++)
+          if ((m != k || g.d == 2) && g.ecnt[m] > 0) e += (double)g.ecnt[m];
+        sweep += 2.0 * (nv + (th ? 3.0 : 2.0) * (double)g.fcnt[k] + (X->bulk ? 2.0 : 1.0) * nc + e);
+      }
+      b += sweeps * sweep;
+      if (!coarsest) {
+        const double nvc = (double)X->lev[l + 1].g.nvel;
+        b += 3.0 * nv + (th ? nv : 0.0) + nc + ne + (X->bulk ? nc : 0.0);  // residual
+        b += nv + nvc;                                                    // restriction
+        b += nvc + 2.0 * nv;                                              // prolongation
+      }
+    } else {
+      b += nc;                                   // zero fill
+      b += sweeps * 2.0 * (nv + 3.0 * nc);       // beta, rhs, phi read; phi written
+      if (!coarsest) {
+        const double ncc = (double)X->lev[l + 1].g.ncell;
+        b += nv + 3.0 * nc;                      // residual
+        b += nc + ncc;                           // restriction
+        b += ncc + 2.0 * nc;                     // prolongation
+      }
+    }
+    total += s * b;
+  }
+  return total;
 }
 
 template <typename T>
@@ -431,6 +500,28 @@ void vcycle_p(stokes_ctx *X, int l, const T *rhs, T *phi) {
   for (int s = 0; s < X->p.nu_post; s++) sweep_p<T>(X, l, rhs, phi);
 }
 
+// A V-cycle from the finest level, bracketed by events when timing is on
+template <typename T>
+void vcycle_top(stokes_ctx *X, bool vel, const T *rhs, T *phi) {
+  const bool tm = X->timing != 0;
+  const int kind = vel ? 0 : 1;
+  if (tm) {
+    if (X->vev_used == kEventPool) fold_vevents(X);
+    (void)hipEventRecord(X->vev[2 * X->vev_used], X->s);
+  }
+  if (vel)
+    vcycle_vel<T>(X, 0, rhs, phi);
+  else
+    vcycle_p<T>(X, 0, rhs, phi);
+  if (tm) {
+    (void)hipEventRecord(X->vev[2 * X->vev_used + 1], X->s);
+    X->vev_kind[X->vev_used] = kind;
+    X->vev_used++;
+    X->vc_count[kind]++;
+    X->vc_bytes[kind] += X->vc_cycle_bytes[kind];
+  }
+}
+
 // A~^{-1} r: `vcycles` V-cycles, zero initial guess (Sec. 3.2)
 template <typename T>
 void vel_sub(stokes_ctx *X, const T *r, T *e) {
@@ -440,11 +531,11 @@ void vel_sub(stokes_ctx *X, const T *r, T *e) {
     launch_vel_remove_means<T>(L.g, r, P<T>(X->vs_r), X->part, X->dsc + 8, X->s);
     rr = P<T>(X->vs_r);
   }
-  vcycle_vel<T>(X, 0, rr, e);
+  vcycle_top<T>(X, true, rr, e);
   for (int v = 1; v < X->p.vcycles; v++) {
     launch_vel_residual<T>(L.g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), lam_of<T>(L), rr,
                            e, nullptr, P<T>(X->vs_t), X->s);
-    vcycle_vel<T>(X, 0, P<T>(X->vs_t), P<T>(X->vs_de));
+    vcycle_top<T>(X, true, P<T>(X->vs_t), P<T>(X->vs_de));
     launch_axpy<T>((T)1, P<T>(X->vs_de), e, L.g.nvel, X->s);
   }
   if (X->vel_singular) remove_vel_means<T>(X, L.g, e);
@@ -457,10 +548,10 @@ void p_sub(stokes_ctx *X, const T *r, T *e) {
   launch_cast<T, T>(r, P<T>(X->ps_r), L.g.ncell, X->s);
   remove_mean<T>(X, P<T>(X->ps_r), L.g.ncell, 18);
   const T *rr = P<T>(X->ps_r);
-  vcycle_p<T>(X, 0, rr, e);
+  vcycle_top<T>(X, false, rr, e);
   for (int v = 1; v < X->p.vcycles; v++) {
     launch_p_residual<T>(L.g, P<T>(L.beta), rr, e, P<T>(X->ps_t), X->s);
-    vcycle_p<T>(X, 0, P<T>(X->ps_t), P<T>(X->ps_de));
+    vcycle_top<T>(X, false, P<T>(X->ps_t), P<T>(X->ps_de));
     launch_axpy<T>((T)1, P<T>(X->ps_de), e, L.g.ncell, X->s);
   }
   remove_mean<T>(X, e, L.g.ncell, 19);
@@ -845,14 +936,12 @@ int mg_solve(stokes_ctx *X, bool vel, double tol, int max_cycles, int *cycles, d
     if (X->mg32) {
       float *pin = P<float>(X->pin), *pout = P<float>(X->pout);
       launch_cast<float, double>(res, pin, n, X->s);
-      if (vel) vcycle_vel<float>(X, 0, pin, pout);
-      else vcycle_p<float>(X, 0, pin, pout);
+      vcycle_top<float>(X, vel, pin, pout);
       const float *zs[1] = {pout};
       const double one = 1.0;
       launch_update_x<float>(e, zs, &one, 1, n, X->s);
     } else {
-      if (vel) vcycle_vel<double>(X, 0, res, de);
-      else vcycle_p<double>(X, 0, res, de);
+      vcycle_top<double>(X, vel, res, de);
       launch_axpy<double>(1.0, de, e, n, X->s);
     }
     c++;
@@ -1049,6 +1138,8 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
     X->gs_bytes[k] =
         tb * ((double)g0.nvel + own * (double)g0.fcnt[k] + cells * (double)g0.ncell + e);
   }
+  X->vc_cycle_bytes[0] = vcycle_alg_bytes(X, true);
+  X->vc_cycle_bytes[1] = vcycle_alg_bytes(X, false);
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
     (void)hipHostFree(X->host);
     delete X;
@@ -1066,6 +1157,7 @@ void stokes_destroy(stokes_ctx *X) {
   if (!X) return;
   if (X->s) (void)hipStreamSynchronize(X->s);
   for (auto e : X->ev) (void)hipEventDestroy(e);
+  for (auto e : X->vev) (void)hipEventDestroy(e);
   for (auto e : X->pev)
     if (e) (void)hipEventDestroy(e);
   if (X->host) (void)hipHostFree(X->host);
@@ -1244,12 +1336,31 @@ int stokes_set_timing(stokes_ctx *X, int enable) {
     X->ev.resize(2 * kEventPool);
     for (auto &e : X->ev)
       if (hipEventCreate(&e) != hipSuccess) return STOKES_EDEVICE;
+    X->vev.resize(2 * kEventPool);
+    X->vev_kind.resize(kEventPool);
+    for (auto &e : X->vev)
+      if (hipEventCreate(&e) != hipSuccess) return STOKES_EDEVICE;
   }
   fold_events(X);
+  fold_vevents(X);
   X->timing = enable ? 1 : 0;
   X->t_ms = 0.0;
   X->launches = 0;
   X->bytes = 0.0;
+  for (int k = 0; k < 2; k++) {
+    X->vc_ms[k] = X->vc_bytes[k] = 0.0;
+    X->vc_count[k] = 0;
+  }
+  return STOKES_OK;
+}
+
+int stokes_vcycle_time(stokes_ctx *X, int pressure, double *ms_total, long *cycles,
+                       double *bytes_total) {
+  if (!X || (pressure != 0 && pressure != 1)) return STOKES_EINVAL;
+  fold_vevents(X);
+  if (ms_total) *ms_total = X->vc_ms[pressure];
+  if (cycles) *cycles = X->vc_count[pressure];
+  if (bytes_total) *bytes_total = X->vc_bytes[pressure];
   return STOKES_OK;
 }
 

@@ -32,7 +32,7 @@ ABI_FUNCTIONS = (
     "stokes_vel_subsolve", "stokes_p_subsolve", "stokes_vel_mg_solve", "stokes_p_mg_solve",
     "stokes_solve", "stokes_adjoint_solve",
     "stokes_grad", "stokes_rescale", "stokes_set_timing", "stokes_kernel_time", "stokes_destroy",
-    "stokes_set_history",
+    "stokes_set_history", "stokes_vcycle_time",
     "stokes_strerror",
 )
 
@@ -106,6 +106,9 @@ def lib():
         L.stokes_rescale.restype = ctypes.c_double
         L.stokes_set_timing.argtypes = [vp, ctypes.c_int]
         L.stokes_set_history.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+        L.stokes_vcycle_time.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_long),
+                                         ctypes.POINTER(ctypes.c_double)]
         L.stokes_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_long),
                                          ctypes.POINTER(ctypes.c_double)]
@@ -317,6 +320,15 @@ class Stokes:
         rc = lib().stokes_set_timing(self._h, 1 if enable else 0)
         if rc:
             raise StokesError(rc, "stokes_set_timing")
+
+    def vcycle_time(self, pressure: bool):
+        """(ms, cycles, algorithmic bytes) of the timed finest-level V-cycles."""
+        ms, n, b = ctypes.c_double(), ctypes.c_long(), ctypes.c_double()
+        rc = lib().stokes_vcycle_time(self._h, 1 if pressure else 0, ctypes.byref(ms),
+                                      ctypes.byref(n), ctypes.byref(b))
+        if rc:
+            raise StokesError(rc, "stokes_vcycle_time")
+        return ms.value, n.value, b.value
 
     def kernel_time(self):
         ms, n, b = ctypes.c_double(), ctypes.c_long(), ctypes.c_double()

@@ -61,3 +61,57 @@ def test_autograd_given_edge_viscosity_matches_oracle():
     adj = o.adjoint(ou, op, ou - ut, np.zeros(lay.ncell), tol=1e-12, max_iter=3000)
     assert rel(N(e_t.grad), adj["dmu_edge"]) <= 1e-6
     assert rel(N(mu_t.grad), adj["dmu_cell"]) <= 1e-6
+
+
+
+def _vcycle_bytes_model(dim, n, bc, theta, vel, s=8, nu=(2, 2, 8)):
+    """The documented byte model of one finest-level V-cycle (stokes.h,
+    stokes_vcycle_time), from the array sizes of each level."""
+    total, levels = 0.0, []
+    m = list(n)
+    while True:
+        levels.append(W.make_layout(dim, tuple(m), bc))
+        if min(m) == 2:
+            break
+        m = [x // 2 for x in m]
+    for l, lay in enumerate(levels):
+        nv, nc, ne = lay.nvel, lay.ncell, lay.nedge
+        coarsest = l == len(levels) - 1
+        sweeps = nu[2] if coarsest else nu[0] + nu[1]
+        edges = {m_: int(np.prod(lay.edge_dims(m_)[:dim])) for m_ in lay.edge_families}
+        if vel:
+            b = nv
+            sw = 0.0
+            for k in range(dim):
+                e = sum(c for m_, c in edges.items() if m_ != k)
+                sw += 2 * (nv + (3 if theta else 2) * lay.face_counts[k] + nc + e)
+            b += sweeps * sw
+            if not coarsest:
+                nvc = levels[l + 1].nvel
+                b += 3 * nv + (nv if theta else 0) + nc + ne + nv + nvc + nvc + 2 * nv
+        else:
+            b = nc + sweeps * 2 * (nv + 3 * nc)
+            if not coarsest:
+                ncc = levels[l + 1].ncell
+                b += nv + 3 * nc + nc + ncc + ncc + 2 * nc
+        total += s * b
+    return total
+
+
+def test_vcycle_timing_counts_and_bytes():
+    """The V-cycle timer counts one velocity and one pressure cycle per P1
+    application and reports the bytes of the documented cycle model."""
+    dim, n, bc = 3, (32, 32, 32), (1, 1, 1)
+    p, lay = params(dim, n, bc, 10.0, precond=W.P1)
+    rho, mu = W.random_coefficients(98, lay)
+    g, _ = pair(p, rho, mu)
+    bu = W.random_velocity(99, lay)
+    g.set_timing(True)
+    g.precond(T(bu), T(np.zeros(lay.ncell)))
+    g.precond(T(bu), T(np.zeros(lay.ncell)))
+    msv, cv, bv = g.vcycle_time(False)
+    msp, cp, bpr = g.vcycle_time(True)
+    g.set_timing(False)
+    assert cv == 2 and cp == 2 and msv > 0 and msp > 0
+    assert bv / cv == pytest.approx(_vcycle_bytes_model(dim, n, bc, 10.0, True), rel=1e-12)
+    assert bpr / cp == pytest.approx(_vcycle_bytes_model(dim, n, bc, 10.0, False), rel=1e-12)
