@@ -100,3 +100,28 @@ def test_bubble_512_paper_bound(precision, krylov):
     assert rc == 0 and st["rel_res_true"] <= 1e-10
     assert st["iters"] <= g1["max_gmres_iterations"]
     assert st["scalar_vcycles"] <= g1["max_scalar_vcycles"]
+
+
+def test_restart_claims_512():
+    """Sec. 4.2.2 at the paper's size (2D bubble, 512^2, left GMRES): with
+    mu = 0, restart 5 hurts P3 and not P1, P2; in steady flow restart 5 is
+    never better than restart 10.  The 128^2 counts equal the oracle's (+-1)."""
+    from test_oracle_paper_claims import check_restart_claims, restart_study
+
+    def solve(w, P, m):
+        p = w.params(precond=P, restart=m, precision=W.FP64, krylov=W.GMRES_LEFT)
+        g, o = pair(p, w.rho, w.mu)
+        bu, bp = _rhs(o, w)
+        _, _, st, rc = g.solve(T(bu), T(bp), tol=1e-10, max_iter=600)
+        assert rc == 0
+        return st["iters"]
+
+    res = restart_study(2, 512, solve)
+    print(f"512^2 restart study (iters at restart 10, 5): {res}", flush=True)
+    check_restart_claims(res)
+    small = restart_study(2, 128, solve)
+    ref = restart_study(2, 128, lambda w, P, m: oracle.Oracle.from_workload(
+        w, precond=P, restart=m).solve(*_rhs(oracle.Oracle.from_workload(w), w), tol=1e-10,
+                                       max_iter=600)[2]["iters"])
+    for k in small:
+        assert abs(small[k][0] - ref[k][0]) <= 1 and abs(small[k][1] - ref[k][1]) <= 1, (k, small, ref)

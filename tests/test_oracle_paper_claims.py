@@ -76,3 +76,33 @@ def test_bubble_viscous_cfl_sweep(dim, n):
     res = {P: _cfl_sweep(dim, n, P, solve) for P in (W.P1, W.P2)}
     print(dim, n, res)
     check_cfl_claims(res)
+
+
+def restart_study(dim, n, solve):
+    """Iterations with restart 10 and 5 for P1-P3 on the inviscid
+    time-dependent bubble (mu = 0, theta h = 1) and on the steady bubble
+    (theta = 0).  solve(w, precond, restart) -> iterations."""
+    out = {}
+    wi = W.bubble(dim, n, 100.0, 100.0, theta=float(n))  # theta h = 1
+    wi.mu = np.zeros_like(wi.mu)
+    ws = W.bubble(dim, n, 100.0, 100.0)
+    for case, w in (("inviscid", wi), ("steady", ws)):
+        for P in (W.P1, W.P2, W.P3):
+            out[case, P] = (solve(w, P, 10), solve(w, P, 5))
+    return out
+
+
+def check_restart_claims(res):
+    g = GOLD["restarts"]
+    r = {k: v[1] / v[0] for k, v in res.items()}
+    assert r["inviscid", W.P3] >= g["p3_inviscid_min_ratio"], res
+    assert r["inviscid", W.P1] <= g["p1_p2_inviscid_max_ratio"], res
+    assert r["inviscid", W.P2] <= g["p1_p2_inviscid_max_ratio"], res
+    for P in (W.P1, W.P2, W.P3):
+        assert res["steady", P][1] >= res["steady", P][0], res
+
+
+def test_restart_claims_128():
+    """Sec. 4.2.2 at 128^2 (the GPU test runs the paper's 512^2)."""
+    res = restart_study(2, 128, lambda w, P, m: _solve(w, precond=P, restart=m)["iters"])
+    check_restart_claims(res)
