@@ -125,3 +125,52 @@ def test_restart_claims_512():
                                        max_iter=600)[2]["iters"])
     for k in small:
         assert abs(small[k][0] - ref[k][0]) <= 1 and abs(small[k][1] - ref[k][1]) <= 1, (k, small, ref)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 512), (3, 128)])
+def test_smoothing_sweeps_claims_box_sizes(dim, n):
+    """Sec. 4.1.1 at the paper's sizes: one to two sweeps is the large step,
+    later sweeps gain less; two sweeps reduce the residual tenfold per cycle
+    (FP64 stand-alone multigrid, constant coefficients, no-slip)."""
+    from paper_1308_4605_amd.stokes import Stokes
+    from test_oracle_paper_claims import check_sweep_claims, sweep_study
+
+    def mg(lay, nu, vel):
+        p = dict(dim=lay.dim, n=lay.n, bc=lay.bc, h=1.0 / lay.n[0], theta=0.0, precond=W.P1,
+                 precision=W.FP64, krylov=W.GMRES_LEFT, restart=10, nu_pre=nu, nu_post=nu,
+                 nu_coarse=8, vcycles=1, rescale_c=0.0, edge_avg=W.EDGE_ARITH)
+        S = Stokes(p, T(np.ones(lay.ncell)), T(np.ones(lay.ncell)))
+        if vel:
+            _, c, q, rc = S.vel_mg_solve(T(W.random_velocity(35, lay)), tol=1e-10, max_cycles=200)
+        else:
+            _, c, q, rc = S.p_mg_solve(T(W.random_cells(36, lay, remove_mean=True)), tol=1e-10,
+                                       max_cycles=200)
+        S.close()
+        assert rc == 0
+        return c, q
+
+    rates = sweep_study(dim, n, mg)
+    print(f"{dim}D {n}: per-cycle factors {rates}", flush=True)
+    check_sweep_claims(rates)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 512), (3, 128)])
+def test_vcycles_per_application_claims_box_sizes(dim, n):
+    """Sec. 4.1.2 at the paper's sizes: P1 with one V-cycle per subsolver
+    application is the cheapest in scalar V-cycles on the bubble problem, and
+    no worse than near-exact subsolvers on the periodic constant-coefficient
+    problem (left GMRES, restart 32, to 1e-10)."""
+    from test_oracle_paper_claims import check_vcycle_claims, vcycle_study
+
+    def solve(w, v):
+        p = w.params(precond=W.P1, vcycles=v, restart=32, precision=W.FP64,
+                     krylov=W.GMRES_LEFT)
+        g, o = pair(p, w.rho, w.mu)
+        bu, bp = _rhs(o, w)
+        _, _, st, rc = g.solve(T(bu), T(bp), tol=1e-10, max_iter=400)
+        assert rc == 0
+        return st["scalar_vcycles"]
+
+    sv = vcycle_study(dim, n, solve)
+    print(f"{dim}D {n}: scalar V-cycles {sv}", flush=True)
+    check_vcycle_claims(sv)

@@ -106,3 +106,74 @@ def test_restart_claims_128():
     """Sec. 4.2.2 at 128^2 (the GPU test runs the paper's 512^2)."""
     res = restart_study(2, 128, lambda w, P, m: _solve(w, precond=P, restart=m)["iters"])
     check_restart_claims(res)
+
+
+def sweep_study(dim, n, mg_solve):
+    """Per-cycle convergence factors of the velocity and pressure multigrid
+    solvers for 1-4 smoothing sweeps (constant coefficients, steady, no-slip).
+    mg_solve(lay, nu, vel) -> (cycles, rel_res)."""
+    lay = W.make_layout(dim, (n,) * dim, (W.NOSLIP,) * dim)
+    out = {}
+    for vel in (True, False):
+        for nu in GOLD["smoothing_sweeps"]["sweeps"]:
+            c, q = mg_solve(lay, nu, vel)
+            out[vel, nu] = q ** (1.0 / c)
+    return out
+
+
+def check_sweep_claims(rates):
+    for vel in (True, False):
+        lq = [np.log(rates[vel, nu]) for nu in GOLD["smoothing_sweeps"]["sweeps"]]
+        gains = [lq[i] - lq[i + 1] for i in range(len(lq) - 1)]
+        assert all(g > 0 for g in gains), (vel, rates)
+        assert gains[0] > max(gains[1:]), (vel, rates)
+        assert rates[vel, 2] <= 0.15, (vel, rates)
+
+
+def _oracle_mg(lay, nu, vel):
+    o = oracle.Oracle(lay.dim, lay.n, lay.bc, 1.0 / lay.n[0], 0.0, np.ones(lay.ncell),
+                      np.ones(lay.ncell), nu_pre=nu, nu_post=nu)
+    if vel:
+        _, c, q, rc = o.vel_mg_solve(W.random_velocity(35, lay), tol=1e-10, max_cycles=200)
+    else:
+        _, c, q, rc = o.p_mg_solve(W.random_cells(36, lay, remove_mean=True), tol=1e-10,
+                                   max_cycles=200)
+    assert rc == oracle.ORC_OK
+    return c, q
+
+
+@pytest.mark.parametrize("dim,n", [(2, 128), (3, 32)])
+def test_smoothing_sweeps_claims(dim, n):
+    """Sec. 4.1.1 at 128^2 / 32^3 (the GPU test runs 512^2 / 128^3)."""
+    check_sweep_claims(sweep_study(dim, n, _oracle_mg))
+
+
+def vcycle_study(dim, n, solve):
+    """Total scalar V-cycles of P1 for 1, 2, 4 V-cycles per application on
+    the bubble problem and on the periodic constant-coefficient problem.
+    solve(w, vcycles) -> scalar V-cycles."""
+    wb = W.bubble(dim, n, 100.0, 100.0)
+    lay = W.make_layout(dim, (n,) * dim, (W.PERIODIC,) * dim)
+    wc = W.Workload(f"{dim}d-periodic-constant", dim, lay.n, lay.bc, 1.0 / n, 0.0, W.P1,
+                    W.GMRES_LEFT, W.FP64, W.EDGE_ARITH, np.ones(lay.ncell), np.ones(lay.ncell),
+                    np.zeros(lay.nvel), np.zeros(lay.ncell))
+    wc.extra.update(x_u=W.random_velocity(37, lay, remove_mean=True),
+                    x_p=W.random_cells(38, lay))
+    out = {}
+    for name, w in (("bubble", wb), ("periodic", wc)):
+        for v in GOLD["vcycles_per_application"]["vcycles"]:
+            out[name, v] = solve(w, v)
+    return out
+
+
+def check_vcycle_claims(sv):
+    vs = GOLD["vcycles_per_application"]["vcycles"]
+    assert sv["bubble", 1] == min(sv["bubble", v] for v in vs), sv
+    assert sv["periodic", 1] <= min(sv["periodic", v] for v in vs), sv
+
+
+def test_vcycles_per_application_claims_128():
+    """Sec. 4.1.2 at 128^2 (the GPU test runs 512^2 and 128^3)."""
+    sv = vcycle_study(2, 128, lambda w, v: _solve(w, precond=W.P1, vcycles=v,
+                                                  restart=60)["scalar_vcycles"])
+    check_vcycle_claims(sv)
