@@ -423,6 +423,30 @@ def test_saddle_inertia_and_schur_clustering_32():
     assert lam[~zero].min() > 0.0 and lam.max() <= 1.0 + 1e-8
 
 
+def test_bubble_schur_spectrum_32():
+    """32^2 no-slip steady bubble, viscosity contrast 100 (App. B.1): about 87%
+    of the N_dof eigenvalues of the exactly-preconditioned operator lie in
+    (0.99, 1.01), and the rest stay near unity (tests/golden/spectrum_32.json)."""
+    import json, os
+
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "spectrum_32.json")))["bubble_contrast_100"]
+    w = W.bubble(2, 32, 100.0, 100.0)
+    lay = w.layout
+    o, lay, h = _mk(2, lay.n, lay.bc, 0.0, w.rho, w.mu, rescale_c=1.0)
+    M, nv = assemble(o, lay)
+    A, G, mD = M[:nv, :nv], M[:nv, nv:], M[nv:, :nv]
+    lam = np.linalg.eigvals(np.diag(2.0 * w.mu) @ (mD @ np.linalg.solve(A, G)))
+    assert np.abs(lam.imag).max() <= 1e-8 * np.abs(lam).max()
+    lam = lam.real
+    zero = np.abs(lam) < 1e-8
+    assert zero.sum() == 1
+    near = ((lam > 0.99) & (lam < 1.01)).sum() + nv
+    frac = near / (nv + lay.ncell)
+    assert abs(frac - gold["fraction_in_0.99_1.01"]) <= gold["fraction_tolerance"], frac
+    assert lam[~zero].min() > 0.2 and lam.max() < 2.0
+
+
 # ---------------------------------------------------------------------------
 # adjoint (M = M^T, Sec. 2)
 # ---------------------------------------------------------------------------
