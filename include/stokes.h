@@ -130,9 +130,11 @@ typedef struct {
                            pressure cycles): the paper's cost proxy (Sec. 4) */
   double rel_res_true;  /* ||b' - M' x'|| / ||b'|| of the rescaled system at exit */
   double rel_res_est;   /* last Givens estimate, as a true relative residual */
-  double rel_res_unscaled;  /* ||b - M x|| / ||b|| of the caller's (unscaled) system
-                               at exit (0 when the solve stopped on a breakdown or a
-                               non-finite value) */
+  double rel_res_unscaled;  /* stokes_solve: ||b - M x|| / ||b|| of the caller's
+                               (unscaled) system at exit; stokes_adjoint_solve: the
+                               same combination of the velocity and pressure blocks
+                               of its residual.  0 when the solve stopped on a
+                               breakdown or a non-finite value */
   int history_len;      /* entries written to the stokes_set_history buffer */
   double t_total;       /* wall-clock seconds of the Krylov solve */
   double t_precond;     /* GPU seconds in preconditioner applications (HIP events) */
