@@ -34,6 +34,8 @@ OPS = [
     # one axis with different walls: 3 = no-slip low / free-slip high, 4 = the reverse
     (2, (64, 32), (0, 3)), (2, (48, 32), (4, 1)), (3, (32, 16, 16), (4, 0, 3)),
     (3, (16, 16, 16), (3, 4, 2)),
+    # rows of >= 128 colour positions (two faces per thread), full and partial chunks
+    (2, (320, 64), (0, 1)), (2, (256, 32), (1, 0)), (3, (256, 16, 16), (1, 0, 2)),
 ]
 
 
