@@ -28,6 +28,7 @@ constexpr int kEventPool = 2048;
 
 struct Level {
   Geo g;
+  Geo gv;  // geometry of the velocity multigrid arrays (storage order, Geo::split)
   void *alpha, *beta, *muc, *mue;             // precision T of the hierarchy
   void *lam;                                  // bulk coefficient (null: none)
   void *phi_u, *rhs_u, *res_u, *phi_p, *rhs_p, *res_p;
@@ -95,6 +96,10 @@ struct stokes_ctx {
   int mg32 = 0;
   int vel_singular = 0;  // bit k: velocity component k has a constant null space
   int bulk = 0;          // stress with bulk viscosity (lam arrays present)
+  // the finest velocity level of an FP32 hierarchy in the colour-split
+  // storage order (vsplit): its V-cycle input / output and alpha in that order
+  int vsplit = 0;
+  void *vrs = nullptr, *ves = nullptr, *alpha_v = nullptr;
   int tail_l = -1;  // first level of the single-workgroup coarse tail (-1: none)
   double c = 1.0;
   Level lev[kMaxLev];
@@ -150,6 +155,18 @@ namespace {
 
 constexpr int kDscSlots = 256;  // device scalar slots
 
+// The velocity levels above the one-workgroup coarse tail of an FP32
+// hierarchy are stored colour-split when the finest rows are long (a wave
+// then reads 64 same-colour faces from one contiguous run instead of every
+// other face of 128): the same arithmetic with half the cache lines per
+// load.  FP64 passes already run at the copy bandwidth, and the two
+// reordering passes per cycle made them slower.
+bool use_vsplit(const stokes_params *p) {
+  i64 cells = 1;
+  for (int a = 0; a < p->dim; a++) cells *= p->n[a];
+  return p->precision == STOKES_MG_FP32 && p->n[0] >= 128 && cells > kTailCells;
+}
+
 void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
   const int d = p->dim;
   const size_t tb = (p->precision == STOKES_MG_FP32) ? sizeof(float) : sizeof(double);
@@ -166,6 +183,7 @@ void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
     Geo g = make_geo(d, nl, ns, p->h * (double)(1 << l));
     Level L;
     L.g = g;
+    L.gv = g;
     L.alpha = cv.take(g.nvel * tb);
     L.beta = cv.take(g.nvel * tb);
     L.muc = cv.take(g.ncell * tb);
@@ -214,6 +232,14 @@ void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
   void *ps_r = cv.take(nc * tb), *ps_t = cv.take(nc * tb), *ps_de = cv.take(nc * tb);
   double *ge = (double *)cv.take(ne * 8);
   double *gc = (double *)cv.take(nc * 8);
+  if (use_vsplit(p)) {
+    void *a = cv.take(nv * tb), *b = cv.take(nv * tb), *c = cv.take(nv * tb);
+    if (X) {
+      X->vrs = a;
+      X->ves = b;
+      X->alpha_v = c;
+    }
+  }
   double *part = (double *)cv.take((size_t)kRedBlocks * (kMaxRestart + 2) * 8);
   double *dsc = (double *)cv.take(kDscSlots * 8);
   int *dflag = (int *)cv.take(64);
@@ -313,6 +339,26 @@ template <typename T>
 inline const T *lam_of(const Level &L) {
   return (const T *)L.lam;
 }
+// alpha of the velocity multigrid on level l (the colour-split copy on a
+// split finest level)
+template <typename T>
+inline const T *valpha_of(const stokes_ctx *X, int l) {
+  if (X->p.theta == 0.0) return nullptr;
+  return (l == 0 && X->vsplit) ? (const T *)X->alpha_v : (const T *)X->lev[l].alpha;
+}
+// alpha in the velocity multigrid's storage order: a copy on the finest
+// level (its natural-order alpha also serves P5's residual), in place on the
+// other split levels (only the velocity multigrid reads them)
+template <typename T>
+void split_alpha(stokes_ctx *X) {
+  const Level &L0 = X->lev[0];
+  launch_vel_permute<T>(L0.g, L0.gv, P<T>(L0.alpha), P<T>(X->alpha_v), nullptr, X->s);
+  for (int l = 1; l < X->nlev && X->lev[l].gv.split; l++) {
+    Level &L = X->lev[l];
+    launch_vel_permute<T>(L.g, L.gv, P<T>(L.alpha), P<T>(X->vrs), nullptr, X->s);
+    launch_cast<T, T>(P<T>(X->vrs), P<T>(L.alpha), L.g.nvel, X->s);
+  }
+}
 
 // Algorithmic bytes of one V-cycle from the finest level (each array a
 // kernel reads or writes counted once per kernel, the same model as the
@@ -391,7 +437,7 @@ void smooth_vel(stokes_ctx *X, int l, const T *rhs, T *phi, int nsweeps) {
           if (X->ev_used == kEventPool) fold_events(X);
           (void)hipEventRecord(X->ev[2 * X->ev_used], X->s);
         }
-        launch_vel_gs<T>(L.g, k, colour, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue),
+        launch_vel_gs<T>(L.gv, k, colour, valpha_of<T>(X, l), P<T>(L.muc), P<T>(L.mue),
                          lam_of<T>(L), rhs, phi, X->s);
         if (tm) {
           (void)hipEventRecord(X->ev[2 * X->ev_used + 1], X->s);
@@ -428,8 +474,8 @@ TailLevels<T> tail_levels(stokes_ctx *X, int l0, const T *rhs, T *phi, bool vel)
       continue;
     }
     Level &L = X->lev[l];
-    t.g[i] = L.g;
-    t.a[i] = alpha_of<T>(X, L);
+    t.g[i] = vel ? L.gv : L.g;
+    t.a[i] = vel ? valpha_of<T>(X, l) : alpha_of<T>(X, L);
     t.b[i] = P<T>(L.beta);
     t.mc[i] = P<T>(L.muc);
     t.me[i] = P<T>(L.mue);
@@ -452,24 +498,24 @@ void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
     launch_tail_vel<T>(tail_levels<T>(X, l, rhs, phi, true), X->s);
     return;
   }
-  launch_fill<T>(phi, (T)0, L.g.nvel, X->s);
+  launch_fill<T>(phi, (T)0, L.gv.nvel, X->s);
   if (l == X->nlev - 1) {
     T *r = P<T>(L.res_u);
     if (X->vel_singular)
-      launch_vel_remove_means<T>(L.g, rhs, r, X->part, X->dsc + 8, X->s);
+      launch_vel_remove_means<T>(L.gv, rhs, r, X->part, X->dsc + 8, X->s);
     else
-      launch_cast<T, T>(rhs, r, L.g.nvel, X->s);
+      launch_cast<T, T>(rhs, r, L.gv.nvel, X->s);
     smooth_vel<T>(X, l, r, phi, X->p.nu_coarse);
-    if (X->vel_singular) remove_vel_means<T>(X, L.g, phi);
+    if (X->vel_singular) remove_vel_means<T>(X, L.gv, phi);
     return;
   }
   Level &C = X->lev[l + 1];
   smooth_vel<T>(X, l, rhs, phi, X->p.nu_pre);
-  launch_vel_residual<T>(L.g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), lam_of<T>(L), rhs,
+  launch_vel_residual<T>(L.gv, valpha_of<T>(X, l), P<T>(L.muc), P<T>(L.mue), lam_of<T>(L), rhs,
                          phi, nullptr, P<T>(L.res_u), X->s);
-  launch_face_restrict<T>(L.g, C.g, P<T>(L.res_u), P<T>(C.rhs_u), X->s);
+  launch_face_restrict<T>(L.gv, C.gv, P<T>(L.res_u), P<T>(C.rhs_u), X->s);
   vcycle_vel<T>(X, l + 1, P<T>(C.rhs_u), P<T>(C.phi_u));
-  launch_face_prolong_add<T>(C.g, L.g, P<T>(C.phi_u), phi, X->s);
+  launch_face_prolong_add<T>(C.gv, L.gv, P<T>(C.phi_u), phi, X->s);
   smooth_vel<T>(X, l, rhs, phi, X->p.nu_post);
 }
 
@@ -500,19 +546,33 @@ void vcycle_p(stokes_ctx *X, int l, const T *rhs, T *phi) {
   for (int s = 0; s < X->p.nu_post; s++) sweep_p<T>(X, l, rhs, phi);
 }
 
-// A V-cycle from the finest level, bracketed by events when timing is on
+// A V-cycle from the finest level, bracketed by events when timing is on.
+// means_in / means_out (velocity, colour-split finest level only): remove
+// the singular components' means from rhs on the way in and from the result
+// on the way out, inside the reordering passes.
 template <typename T>
-void vcycle_top(stokes_ctx *X, bool vel, const T *rhs, T *phi) {
+void vcycle_top(stokes_ctx *X, bool vel, const T *rhs, T *phi, bool means_in = false,
+                bool means_out = false) {
   const bool tm = X->timing != 0;
   const int kind = vel ? 0 : 1;
   if (tm) {
     if (X->vev_used == kEventPool) fold_vevents(X);
     (void)hipEventRecord(X->vev[2 * X->vev_used], X->s);
   }
-  if (vel)
+  if (vel && X->vsplit) {
+    // the finest level runs in the colour-split order: reorder in and out
+    const Level &L0 = X->lev[0];
+    double *sums = X->dsc + 8;
+    if (means_in) launch_vel_sums<T>(L0.g, rhs, X->part, sums, X->s);
+    launch_vel_permute<T>(L0.g, L0.gv, rhs, P<T>(X->vrs), means_in ? sums : nullptr, X->s);
+    vcycle_vel<T>(X, 0, P<T>(X->vrs), P<T>(X->ves));
+    if (means_out) launch_vel_sums<T>(L0.gv, P<T>(X->ves), X->part, sums, X->s);
+    launch_vel_permute<T>(L0.gv, L0.g, P<T>(X->ves), phi, means_out ? sums : nullptr, X->s);
+  } else if (vel) {
     vcycle_vel<T>(X, 0, rhs, phi);
-  else
+  } else {
     vcycle_p<T>(X, 0, rhs, phi);
+  }
   if (tm) {
     (void)hipEventRecord(X->vev[2 * X->vev_used + 1], X->s);
     X->vev_kind[X->vev_used] = kind;
@@ -526,6 +586,12 @@ void vcycle_top(stokes_ctx *X, bool vel, const T *rhs, T *phi) {
 template <typename T>
 void vel_sub(stokes_ctx *X, const T *r, T *e) {
   Level &L = X->lev[0];
+  if (X->vsplit && X->vel_singular && X->p.vcycles == 1) {
+    // one cycle on the colour-split finest level: the mean removals ride on
+    // the two reordering passes
+    vcycle_top<T>(X, true, r, e, true, true);
+    return;
+  }
   const T *rr = r;
   if (X->vel_singular) {
     launch_vel_remove_means<T>(L.g, r, P<T>(X->vs_r), X->part, X->dsc + 8, X->s);
@@ -1036,13 +1102,17 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
     for (int k = 0; k < p->dim; k++)
       if (p->bc[k] == STOKES_PERIODIC && !noslip) X->vel_singular |= 1 << k;
   }
-  for (int l = 0; l < nlev; l++) X->lev[l].g.sing = X->vel_singular;
+  for (int l = 0; l < nlev; l++) X->lev[l].g.sing = X->lev[l].gv.sing = X->vel_singular;
+  X->vsplit = use_vsplit(p) ? 1 : 0;
   // coarse tail: the levels small enough for one workgroup (at most kTailMax)
   for (int l = std::max(0, nlev - kTailMax); l < nlev; l++)
     if (X->lev[l].g.ncell <= kTailCells) {
       X->tail_l = l;
       break;
     }
+  // colour-split storage for the velocity levels below the coarse tail
+  if (X->vsplit)
+    for (int l = 0; l < nlev && (X->tail_l < 0 || l < X->tail_l); l++) X->lev[l].gv.split = 1;
   if (hipHostMalloc((void **)&X->host, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete X;
     return STOKES_EDEVICE;
@@ -1121,6 +1191,12 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
         launch_cast<float, double>(X->c64l[l], P<float>(X->lev[l].lam), X->lev[l].g.ncell, s);
       launch_cast<float, double>(X->sig64, P<float>(X->sig), g0.ncell, s);
     }
+  }
+  if (X->vsplit && p->theta != 0.0) {
+    if (X->mg32)
+      split_alpha<float>(X);
+    else
+      split_alpha<double>(X);
   }
   // algorithmic bytes of one finest-level velocity colour pass of component
   // k: read all velocity components, rhs_k, alpha_k, mu_cell and the d-1 edge

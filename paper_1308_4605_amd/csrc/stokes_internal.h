@@ -32,12 +32,23 @@ struct Geo {
   int ed[3][3];
   i64 ecnt[3];
   int xcd;  // stencil kernels: one band of rows per XCD
+  // velocity storage order along x: 0 natural; 1 split by the parity of the
+  // x index (even positions of a row first, then odd), so that the faces of
+  // one Gauss-Seidel colour lie contiguously in every row
+  int split;
 };
 
 // bc[a]: STOKES_PERIODIC, STOKES_NOSLIP or STOKES_FREESLIP per axis
 Geo make_geo(int d, const int n[3], const int bc[3], double h);
 
 // ---- launch wrappers (all asynchronous on stream s) ----------------------
+
+// velocity arrays between storage orders: out (order of gout) = in (order of
+// gin), same grid; with sums (per-component sums from launch_vel_sums), the
+// mean of each singular component is subtracted on the way
+template <typename T>
+void launch_vel_permute(const Geo &gin, const Geo &gout, const T *in, T *out, const double *sums,
+                        hipStream_t s);
 
 // coefficient setup (scaled by c): faces alpha = c*theta*rho_f, beta =
 // (1/rho_f)/c; cells mu_c = c*mu; edges = c * mean/harmonic/given.
@@ -149,6 +160,9 @@ void launch_sum(const T *a, i64 n, double *partials, double *out, hipStream_t s)
 template <typename T>
 void launch_sub_mean(T *a, i64 n, const double *sum, hipStream_t s);
 
+// sums[k] = sum of velocity component k (any storage order)
+template <typename T>
+void launch_vel_sums(const Geo &g, const T *in, double *partials, double *sums, hipStream_t s);
 // out = in minus each velocity component's mean (all axes periodic: every
 // face is an unknown); out may alias in
 template <typename T>

@@ -44,6 +44,7 @@ Geo make_geo(int d, const int n[3], const int bc[3], double h) {
   g.sing = 0;
   g.ncell = (i64)g.n[0] * g.n[1] * g.n[2];
   g.xcd = 1;
+  g.split = 0;
   i64 off = 0;
   for (int k = 0; k < 3; k++) {
     for (int a = 0; a < 3; a++) g.fd[k][a] = g.n[a] + ((a == k && k < d) ? g.ns[a] : 0);
@@ -80,8 +81,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Index arithmetic is 32-bit: stokes_create rejects grids whose face, cell
 // or edge storage exceeds 2^31 - 1 entries.
+// position of x index i in a velocity row of length L (Geo::split)
+__device__ __forceinline__ int xpos(const Geo &g, int L, int i) {
+  return g.split ? ((i & 1) ? ((L + 1) >> 1) + (i >> 1) : (i >> 1)) : i;
+}
 __device__ __forceinline__ int fidx(const Geo &g, int k, int i0, int i1, int i2) {
-  return (int)g.foff[k] + (i2 * g.fd[k][1] + i1) * g.fd[k][0] + i0;
+  const int L = g.fd[k][0];
+  return (int)g.foff[k] + (i2 * g.fd[k][1] + i1) * L + xpos(g, L, i0);
 }
 __device__ __forceinline__ int fidx3(const Geo &g, int k, const int i[3]) {
   return fidx(g, k, i[0], i[1], i[2]);
@@ -180,15 +186,15 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
     t[l] = lp;
     const T mhi = mue[eidx3(g, m, t)];
     // u_l on the two faces beside the upper edge (cells i[k] and i[k]-1 along k)
-    const T ulh_r = ul[(t[2] * f1 + t[1]) * f0 + t[0]];
+    const T ulh_r = ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = km;
-    const T ulh_l = ul[(t[2] * f1 + t[1]) * f0 + t[0]];
+    const T ulh_l = ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = i[k];
     t[l] = i[l];
     const T mlo = mue[eidx3(g, m, t)];
-    const T ull_r = ul[(t[2] * f1 + t[1]) * f0 + t[0]];
+    const T ull_r = ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = km;
-    const T ull_l = ul[(t[2] * f1 + t[1]) * f0 + t[0]];
+    const T ull_l = ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = i[k];
     const T ghi = (ua[l] - uf) * ih + (ulh_r - ulh_l) * ih;
     const T glo = (uf - ub[l]) * ih + (ull_r - ull_l) * ih;
@@ -688,6 +694,41 @@ void launch_pack_walls(const Geo &g, const double *in, double scale, double *out
   hipLaunchKernelGGL(k_pack_walls, dim3(blocks_for(g.nvel)), dim3(kBlock), 0, s, g, in, scale,
                      out);
 }
+
+// out = in with the velocity storage order of gout (in has that of gin);
+// with sums, the mean of each singular component (gin.sing) is subtracted
+template <typename T>
+__global__ void k_vel_permute(Geo gin, Geo gout, const T *__restrict__ in, T *__restrict__ out,
+                              const double *__restrict__ sums) {
+  const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gin.nvel) return;
+  int k = 0;
+  while (k + 1 < gin.d && t >= gin.foff[k + 1]) k++;
+  const unsigned L = (unsigned)gin.fd[k][0];
+  const unsigned r = (unsigned)(t - gin.foff[k]);
+  const unsigned row = r / L;
+  const int p = (int)(r - row * L);  // position in the row, order of gin
+  // x index of that position
+  int i0 = p;
+  if (gin.split) {
+    const int ne = (int)((L + 1) >> 1);
+    i0 = (p < ne) ? 2 * p : 2 * (p - ne) + 1;
+  }
+  const i64 base = gin.foff[k] + (i64)row * L;
+  const T mean =
+      (sums && ((gin.sing >> k) & 1)) ? (T)(sums[k] / (double)gin.fcnt[k]) : (T)0;
+  out[base + xpos(gout, (int)L, i0)] = in[t] - mean;
+}
+template <typename T>
+void launch_vel_permute(const Geo &gin, const Geo &gout, const T *in, T *out, const double *sums,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_vel_permute<T>, dim3(blocks_for(gin.nvel)), dim3(kBlock), 0, s, gin, gout,
+                     in, out, sums);
+}
+template void launch_vel_permute<float>(const Geo &, const Geo &, const float *, float *,
+                                        const double *, hipStream_t);
+template void launch_vel_permute<double>(const Geo &, const Geo &, const double *, double *,
+                                         const double *, hipStream_t);
 
 // ------------------------------------------------------------------------
 // velocity multigrid (Appendix C)
@@ -1569,14 +1610,25 @@ __global__ void k_vel_sub_means(Geo g, const T *__restrict__ in, T *__restrict__
 }
 
 template <typename T>
+void launch_vel_sums(const Geo &g, const T *in, double *partials, double *sums, hipStream_t s) {
+  i64 nmax = 0;
+  for (int k = 0; k < g.d; k++) nmax = g.fcnt[k] > nmax ? g.fcnt[k] : nmax;
+  const i64 nbx = (nmax + 4 * kBlock - 1) / (4 * kBlock);
+  const int nr = (int)(nbx < kRedBlocks ? (nbx < 1 ? 1 : nbx) : kRedBlocks);
+  hipLaunchKernelGGL(k_vel_sums_partial<T>, dim3(nr, g.d), dim3(kBlock), 0, s, g, in, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nr, 3, g.d, sums);
+}
+template void launch_vel_sums<float>(const Geo &, const float *, double *, double *, hipStream_t);
+template void launch_vel_sums<double>(const Geo &, const double *, double *, double *,
+                                      hipStream_t);
+
+template <typename T>
 void launch_vel_remove_means(const Geo &g, const T *in, T *out, double *partials, double *sums,
                              hipStream_t s) {
   i64 nmax = 0;
   for (int k = 0; k < g.d; k++) nmax = g.fcnt[k] > nmax ? g.fcnt[k] : nmax;
-  i64 nbx = (nmax + 4 * kBlock - 1) / (4 * kBlock);
-  const int nr = (int)(nbx < kRedBlocks ? (nbx < 1 ? 1 : nbx) : kRedBlocks);
-  hipLaunchKernelGGL(k_vel_sums_partial<T>, dim3(nr, g.d), dim3(kBlock), 0, s, g, in, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nr, 3, g.d, sums);
+  const i64 nbx = (nmax + 4 * kBlock - 1) / (4 * kBlock);
+  launch_vel_sums<T>(g, in, partials, sums, s);
   hipLaunchKernelGGL(k_vel_sub_means<T>, dim3((unsigned)(nbx < 1 ? 1 : nbx), g.d), dim3(kBlock),
                      0, s, g, in, out, sums);
 }

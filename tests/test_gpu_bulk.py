@@ -18,6 +18,7 @@ OPS = [
     (2, (48, 32), (1, 1)), (2, (64, 32), (0, 1)), (2, (32, 32), (0, 0)), (2, (48, 32), (2, 1)),
     (3, (16, 16, 16), (1, 1, 1)), (3, (16, 16, 16), (0, 0, 0)), (3, (48, 40, 8), (1, 0, 1)),
     (3, (32, 16, 16), (2, 1, 0)), (3, (2, 2, 2), (0, 0, 0)),
+    (2, (256, 32), (1, 1)),  # FP32: colour-split finest velocity level
 ]
 
 

@@ -247,3 +247,30 @@ def test_solve_parity_freeslip(dim, n, bc, theta, precond, precision, krylov):
         assert abs(st["iters"] - ost["iters"]) <= 1
     assert scaled_residual(o, o.c, bu, bp, N(xu), N(xp)) <= 1e-9 * (1 + 1e-6)
     assert rel(N(xu), ou) <= 1e-6
+
+
+LONG_ROWS = [
+    # dim, n, bc, theta: rows of >= 128 faces (the finest velocity level of an FP32 hierarchy
+    # is stored colour-split there), odd row lengths on x-walls, partial last waves
+    (2, (256, 32), (1, 1), 0.0), (2, (320, 64), (0, 1), 25.0), (3, (128, 16, 16), (1, 0, 2), 10.0),
+    (3, (256, 8, 8), (0, 0, 0), 0.0), (3, (128, 16, 16), (2, 1, 4), 0.0),
+]
+
+
+@pytest.mark.parametrize("dim,n,bc,theta", LONG_ROWS)
+@pytest.mark.parametrize("precond", [W.P1, W.P2, W.P5])
+def test_fp32_precond_parity_long_rows(dim, n, bc, theta, precond):
+    """FP32 preconditioner and velocity subsolver against the FP64 oracle (1e-4) on grids
+    whose finest velocity level runs in the colour-split storage order."""
+    print(f"fp32 long rows P{precond} {dim} {n} {bc} theta={theta}", flush=True)
+    p, lay = params(dim, n, bc, theta, precond=precond, precision=W.MG_FP32, krylov=W.FGMRES)
+    rho, mu = _coefs(lay, 5)
+    g, o = pair(p, rho, mu)
+    bu = W.random_velocity(15, lay, remove_mean=lay.singular_components(theta))
+    bp = W.random_cells(16, lay, remove_mean=True)
+    zu, zp = g.precond(T(bu), T(bp))
+    ou, op = o.precond(bu, bp)
+    assert rel(N(zu), ou) <= 1e-4
+    assert rel(N(zp), op) <= 1e-4
+    assert np.all(N(zu)[lay.wall_mask()] == 0.0)
+    assert rel(N(g.vel_subsolve(T(bu))), o.vel_subsolve(bu)) <= 1e-4
