@@ -85,6 +85,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ int xpos(const Geo &g, int L, int i) {
   return g.split ? ((i & 1) ? ((L + 1) >> 1) + (i >> 1) : (i >> 1)) : i;
 }
+// x index handled by thread w of a row of n0 cells: on split levels the
+// first half of the threads takes the even cells and the second half the odd
+// ones, so a wave touches one contiguous run of each split velocity row
+__device__ __forceinline__ int split_x(const Geo &g, int w) {
+  if (!g.split) return w;
+  const int half = (g.n[0] + 1) >> 1;
+  return (w < half) ? 2 * w : 2 * (w - half) + 1;
+}
 __device__ __forceinline__ int fidx(const Geo &g, int k, int i0, int i1, int i2) {
   const int L = g.fd[k][0];
   return (int)g.foff[k] + (i2 * g.fd[k][1] + i1) * L + xpos(g, L, i0);
@@ -700,24 +708,25 @@ void launch_pack_walls(const Geo &g, const double *in, double scale, double *out
 template <typename T>
 __global__ void k_vel_permute(Geo gin, Geo gout, const T *__restrict__ in, T *__restrict__ out,
                               const double *__restrict__ sums) {
+  // one thread per output position, so that the stores are contiguous
   const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= gin.nvel) return;
+  if (t >= gout.nvel) return;
   int k = 0;
-  while (k + 1 < gin.d && t >= gin.foff[k + 1]) k++;
-  const unsigned L = (unsigned)gin.fd[k][0];
-  const unsigned r = (unsigned)(t - gin.foff[k]);
+  while (k + 1 < gout.d && t >= gout.foff[k + 1]) k++;
+  const unsigned L = (unsigned)gout.fd[k][0];
+  const unsigned r = (unsigned)(t - gout.foff[k]);
   const unsigned row = r / L;
-  const int p = (int)(r - row * L);  // position in the row, order of gin
+  const int p = (int)(r - row * L);  // position in the row, order of gout
   // x index of that position
   int i0 = p;
-  if (gin.split) {
+  if (gout.split) {
     const int ne = (int)((L + 1) >> 1);
     i0 = (p < ne) ? 2 * p : 2 * (p - ne) + 1;
   }
-  const i64 base = gin.foff[k] + (i64)row * L;
+  const i64 base = gout.foff[k] + (i64)row * L;
   const T mean =
       (sums && ((gin.sing >> k) & 1)) ? (T)(sums[k] / (double)gin.fcnt[k]) : (T)0;
-  out[base + xpos(gout, (int)L, i0)] = in[t] - mean;
+  out[t] = in[base + xpos(gin, (int)L, i0)] - mean;
 }
 template <typename T>
 void launch_vel_permute(const Geo &gin, const Geo &gout, const T *in, T *out, const double *sums,
@@ -855,8 +864,9 @@ __global__ void k_vel_residual(Geo g, const T *__restrict__ alpha, const T *__re
                                const T *__restrict__ mue, const T *__restrict__ lam,
                                const T *__restrict__ rhs, const T *__restrict__ phi,
                                const T *__restrict__ p, T *__restrict__ res) {
-  int i[3];
-  if (!box_thread(g, g.n[0], i[0], i[1], i[2])) return;
+  int w, i[3];
+  if (!box_thread(g, g.n[0], w, i[1], i[2])) return;
+  i[0] = split_x(g, w);
   vel_residual_at<T, DIM>(g, i, cidx3(g, i), alpha, muc, mue, lam, rhs, phi, p, res);
 }
 
@@ -999,8 +1009,9 @@ __device__ __forceinline__ void face_prolong_elem(const Geo &gc, const Geo &gf, 
 template <typename T, int DIM>
 __global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
                                    T *__restrict__ phif) {
-  int f[3];
-  if (!box_thread(gf, gf.n[0], f[0], f[1], f[2])) return;
+  int w, f[3];
+  if (!box_thread(gf, gf.n[0], w, f[1], f[2])) return;
+  f[0] = split_x(gf, w);
   face_prolong_at<T, DIM>(gc, gf, f, ec, phif);
 }
 
