@@ -85,13 +85,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ int xpos(const Geo &g, int L, int i) {
   return g.split ? ((i & 1) ? ((L + 1) >> 1) + (i >> 1) : (i >> 1)) : i;
 }
-// x index handled by thread w of a row of n0 cells: on split levels the
-// first half of the threads takes the even cells and the second half the odd
-// ones, so a wave touches one contiguous run of each split velocity row
+// x index handled by thread w of a row of n0 cells.  On split levels the
+// row is cut into groups of G = min(64, largest power of two dividing n0)
+// threads; the first half of a group takes the group's even cells and the
+// second half its odd ones.  A wave's load from a split velocity array is
+// then two contiguous runs, and its load from a natural-order cell or edge
+// array covers the same cache lines as with the identity mapping.
 __device__ __forceinline__ int split_x(const Geo &g, int w) {
   if (!g.split) return w;
-  const int half = (g.n[0] + 1) >> 1;
-  return (w < half) ? 2 * w : 2 * (w - half) + 1;
+  const int n0 = g.n[0];
+  const int G = min(64, n0 & -n0);
+  if (G < 2) return w;
+  const int j = w & (G - 1), half = G >> 1;
+  return (w - j) + ((j < half) ? 2 * j : 2 * (j - half) + 1);
 }
 __device__ __forceinline__ int fidx(const Geo &g, int k, int i0, int i1, int i2) {
   const int L = g.fd[k][0];
@@ -704,35 +710,79 @@ void launch_pack_walls(const Geo &g, const double *in, double scale, double *out
 }
 
 // out = in with the velocity storage order of gout (in has that of gin);
-// with sums, the mean of each singular component (gin.sing) is subtracted
+// with sums, the mean of each singular component (gin.sing) is subtracted.
+// Thread p of a row of L faces moves the pair of x positions 2p, 2p+1: in
+// natural order the pair is adjacent, in split order it sits at p and
+// (L+1)/2 + p, so every load and store of a wave is contiguous.
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+  typedef float2 V;
+};
+template <>
+struct Pair<double> {
+  typedef double2 V;
+};
+__host__ __device__ inline i64 permute_pairs(const Geo &g, int k) {
+  return (i64)g.fd[k][1] * g.fd[k][2] * ((g.fd[k][0] + 1) >> 1);
+}
 template <typename T>
 __global__ void k_vel_permute(Geo gin, Geo gout, const T *__restrict__ in, T *__restrict__ out,
-                              const double *__restrict__ sums) {
-  // one thread per output position, so that the stores are contiguous
-  const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= gout.nvel) return;
+                              const double *__restrict__ sums, int in_al, int out_al) {
+  typedef typename Pair<T>::V V;
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   int k = 0;
-  while (k + 1 < gout.d && t >= gout.foff[k + 1]) k++;
-  const unsigned L = (unsigned)gout.fd[k][0];
-  const unsigned r = (unsigned)(t - gout.foff[k]);
-  const unsigned row = r / L;
-  const int p = (int)(r - row * L);  // position in the row, order of gout
-  // x index of that position
-  int i0 = p;
-  if (gout.split) {
-    const int ne = (int)((L + 1) >> 1);
-    i0 = (p < ne) ? 2 * p : 2 * (p - ne) + 1;
+  for (; k < gin.d; k++) {
+    const i64 np = permute_pairs(gin, k);
+    if (t < np) break;
+    t -= np;
   }
-  const i64 base = gout.foff[k] + (i64)row * L;
+  if (k == gin.d) return;
+  const unsigned L = (unsigned)gin.fd[k][0], ne = (L + 1) >> 1;
+  const unsigned row = (unsigned)t / ne;
+  const unsigned p = (unsigned)t - row * ne;
+  const i64 base = gin.foff[k] + (i64)row * L;
+  const bool two = 2 * p + 1 < L;
   const T mean =
       (sums && ((gin.sing >> k) & 1)) ? (T)(sums[k] / (double)gin.fcnt[k]) : (T)0;
-  out[t] = in[base + xpos(gin, (int)L, i0)] - mean;
+  T a, b = (T)0;
+  if (gin.split) {
+    a = in[base + p];
+    if (two) b = in[base + ne + p];
+  } else if (in_al && two && !(base & 1)) {
+    const V v = *reinterpret_cast<const V *>(in + base + 2 * p);
+    a = v.x;
+    b = v.y;
+  } else {
+    a = in[base + 2 * p];
+    if (two) b = in[base + 2 * p + 1];
+  }
+  a -= mean;
+  b -= mean;
+  if (gout.split) {
+    out[base + p] = a;
+    if (two) out[base + ne + p] = b;
+  } else if (out_al && two && !(base & 1)) {
+    V v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<V *>(out + base + 2 * p) = v;
+  } else {
+    out[base + 2 * p] = a;
+    if (two) out[base + 2 * p + 1] = b;
+  }
 }
 template <typename T>
 void launch_vel_permute(const Geo &gin, const Geo &gout, const T *in, T *out, const double *sums,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_vel_permute<T>, dim3(blocks_for(gin.nvel)), dim3(kBlock), 0, s, gin, gout,
-                     in, out, sums);
+  i64 np = 0;
+  for (int k = 0; k < gin.d; k++) np += permute_pairs(gin, k);
+  // pair loads and stores need the buffer itself aligned to a pair
+  const int in_al = ((uintptr_t)in % (2 * sizeof(T))) == 0;
+  const int out_al = ((uintptr_t)out % (2 * sizeof(T))) == 0;
+  hipLaunchKernelGGL(k_vel_permute<T>, dim3(blocks_for(np)), dim3(kBlock), 0, s, gin, gout, in,
+                     out, sums, in_al, out_al);
 }
 template void launch_vel_permute<float>(const Geo &, const Geo &, const float *, float *,
                                         const double *, hipStream_t);
