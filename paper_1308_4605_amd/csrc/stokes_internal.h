@@ -118,7 +118,7 @@ void launch_cell_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *pf, h
 // coarse tail of a V-cycle (levels l0..nlev-1) in one workgroup
 constexpr int kTailMax = 8;
 constexpr int kTailBlock = 1024;
-constexpr i64 kTailCells = 4096;  // largest level run inside the tail
+constexpr i64 kTailCells = 512;  // largest level run inside the tail
 template <typename T>
 struct TailLevels {
   int nl;        // number of levels in the tail (the last is the coarsest)
