@@ -425,19 +425,23 @@ void remove_vel_means(stokes_ctx *X, const Geo &g, T *u) {
 
 // nsweeps multicolour Gauss-Seidel sweeps of the velocity (Appendix C: per
 // sweep x-red, x-black, y-red, y-black[, z-red, z-black]), one launch per
-// colour, in place.
+// colour, in place.  from_zero: phi is the zero iterate but its memory has
+// not been cleared; the first sweep then reads the values not yet written as
+// zero.
 template <typename T>
-void smooth_vel(stokes_ctx *X, int l, const T *rhs, T *phi, int nsweeps) {
+void smooth_vel(stokes_ctx *X, int l, const T *rhs, T *phi, int nsweeps, bool from_zero = false) {
   Level &L = X->lev[l];
   for (int s = 0; s < nsweeps; s++)
     for (int k = 0; k < L.g.d; k++)
       for (int colour = 0; colour < 2; colour++) {
-        const bool tm = X->timing && l == 0;
+        const int first = from_zero && s == 0;
+        // the timed passes are the full ones (the first sweep reads less)
+        const bool tm = X->timing && l == 0 && !first;
         if (tm) {
           if (X->ev_used == kEventPool) fold_events(X);
           (void)hipEventRecord(X->ev[2 * X->ev_used], X->s);
         }
-        launch_vel_gs<T>(L.gv, k, colour, valpha_of<T>(X, l), P<T>(L.muc), P<T>(L.mue),
+        launch_vel_gs<T>(L.gv, k, colour, first, valpha_of<T>(X, l), P<T>(L.muc), P<T>(L.mue),
                          lam_of<T>(L), rhs, phi, X->s);
         if (tm) {
           (void)hipEventRecord(X->ev[2 * X->ev_used + 1], X->s);
@@ -498,19 +502,24 @@ void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
     launch_tail_vel<T>(tail_levels<T>(X, l, rhs, phi, true), X->s);
     return;
   }
-  launch_fill<T>(phi, (T)0, L.gv.nvel, X->s);
-  if (l == X->nlev - 1) {
+  const bool coarsest = l == X->nlev - 1;
+  // the first sweep writes every face of the zero iterate, so the clearing
+  // pass is needed only without a sweep or where the colouring does not
+  // hold across a periodic wrap
+  const bool zf = vel_gs_first_ok(L.gv) && (coarsest ? X->p.nu_coarse : X->p.nu_pre) > 0;
+  if (!zf) launch_fill<T>(phi, (T)0, L.gv.nvel, X->s);
+  if (coarsest) {
     T *r = P<T>(L.res_u);
     if (X->vel_singular)
       launch_vel_remove_means<T>(L.gv, rhs, r, X->part, X->dsc + 8, X->s);
     else
       launch_cast<T, T>(rhs, r, L.gv.nvel, X->s);
-    smooth_vel<T>(X, l, r, phi, X->p.nu_coarse);
+    smooth_vel<T>(X, l, r, phi, X->p.nu_coarse, zf);
     if (X->vel_singular) remove_vel_means<T>(X, L.gv, phi);
     return;
   }
   Level &C = X->lev[l + 1];
-  smooth_vel<T>(X, l, rhs, phi, X->p.nu_pre);
+  smooth_vel<T>(X, l, rhs, phi, X->p.nu_pre, zf);
   launch_vel_residual<T>(L.gv, valpha_of<T>(X, l), P<T>(L.muc), P<T>(L.mue), lam_of<T>(L), rhs,
                          phi, nullptr, P<T>(L.res_u), X->s);
   launch_face_restrict<T>(L.gv, C.gv, P<T>(L.res_u), P<T>(C.rhs_u), X->s);

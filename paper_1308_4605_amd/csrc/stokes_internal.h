@@ -95,9 +95,13 @@ void launch_pack_walls(const Geo &g, const double *in, double scale, double *out
 
 // multigrid level kernels, T = float or double
 // (lam: bulk coefficient per cell or null, as for launch_apply_m)
+// first != 0: a pass of the first sweep from a zero iterate whose memory has
+// not been cleared (allowed when vel_gs_first_ok(g); the sweep writes every
+// face, the wall faces included, before any pass reads it)
+bool vel_gs_first_ok(const Geo &g);
 template <typename T>
-void launch_vel_gs(const Geo &g, int k, int colour, const T *alpha, const T *muc, const T *mue,
-                   const T *lam, const T *rhs, T *phi, hipStream_t s);
+void launch_vel_gs(const Geo &g, int k, int colour, int first, const T *alpha, const T *muc,
+                   const T *mue, const T *lam, const T *rhs, T *phi, hipStream_t s);
 template <typename T>  // res = rhs - A phi - G p
 void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mue, const T *lam,
                          const T *rhs, const T *phi, const T *p, T *res, hipStream_t s);

@@ -166,7 +166,9 @@ __device__ __forceinline__ bool box_thread(const Geo &g, int W, int &w, int &y, 
 // cells beside f then gain lam (div u) (bulk viscosity, Sec. 2).  The u_l
 // values the shear terms load are exactly the cells' tangential faces, so the
 // cell divergences cost no extra velocity loads.
-template <typename T, int DIM>
+// Z != 0 (first sweep from a zero iterate): the components l > k have not
+// been written yet and are read as zero.
+template <typename T, int DIM, int Z = 0>
 __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T uf, T ukp, T ukm,
                                          const T (&ua)[3], const T (&ub)[3],
                                          const T *const *comp, const T *__restrict__ alpha,
@@ -200,15 +202,16 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
     t[l] = lp;
     const T mhi = mue[eidx3(g, m, t)];
     // u_l on the two faces beside the upper edge (cells i[k] and i[k]-1 along k)
-    const T ulh_r = ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
+    const bool lz = Z && l > k;
+    const T ulh_r = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = km;
-    const T ulh_l = ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
+    const T ulh_l = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = i[k];
     t[l] = i[l];
     const T mlo = mue[eidx3(g, m, t)];
-    const T ull_r = ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
+    const T ull_r = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = km;
-    const T ull_l = ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
+    const T ull_l = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = i[k];
     const T ghi = (ua[l] - uf) * ih + (ulh_r - ulh_l) * ih;
     const T glo = (uf - ub[l]) * ih + (ull_r - ull_l) * ih;
@@ -234,18 +237,24 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
 // from the concatenated velocity buffer u.  Returns (A u)_f and the diagonal
 // of A at f.  Tangential no-slip walls use the ghost value -u_f, which equals
 // the one-sided wall difference (u_f - 0)/(h/2).
-template <typename T, int DIM>
+// Z (first Gauss-Seidel sweep from a zero iterate, where memory has not been
+// cleared): bit 0 reads u_f as zero, bit 1 the other-colour neighbours of
+// component k as zero, and any nonzero Z reads the high wall face of
+// component k and the components after k as zero.  The values are those the
+// cleared iterate would hold, so the arithmetic is unchanged.
+template <typename T, int DIM, int Z = 0>
 __device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const T *__restrict__ u,
                                       const T *__restrict__ alpha, const T *__restrict__ muc,
                                       const T *__restrict__ mue, const T *__restrict__ lam,
                                       T &Au, T &diag) {
   const i64 fq = fidx3(g, k, i);
-  const T uf = u[fq];
+  const T uf = (Z & 1) ? (T)0 : u[fq];
   int t[3] = {i[0], i[1], i[2]};
   t[k] = up1(g, k, i[k]);
-  const T ukp = u[fidx3(g, k, t)];
+  const bool kz = (Z & 2) || (Z && g.ns[k] && i[k] + 1 == g.n[k]);
+  const T ukp = kz ? (T)0 : u[fidx3(g, k, t)];
   t[k] = dn1(g, k, i[k]);
-  const T ukm = u[fidx3(g, k, t)];
+  const T ukm = (Z & 2) ? (T)0 : u[fidx3(g, k, t)];
   t[k] = i[k];
   T ua[3] = {0, 0, 0}, ub[3] = {0, 0, 0};
 #pragma unroll
@@ -256,16 +265,16 @@ __device__ __forceinline__ void a_row(const Geo &g, int k, const int i[3], const
     // loads are unconditional (from an in-range index) so that all of them
     // issue before the first wait; the wall ghost -u_f is selected afterwards
     t[l] = top ? i[l] : up1(g, l, i[l]);  // component k has no face at index n[l] along l
-    const T va = u[fidx3(g, k, t)];
+    const T va = (Z & 2) ? (T)0 : u[fidx3(g, k, t)];
     t[l] = dn1(g, l, i[l]);
-    const T vb = u[fidx3(g, k, t)];
+    const T vb = (Z & 2) ? (T)0 : u[fidx3(g, k, t)];
     t[l] = i[l];
     // no-slip: odd ghost (zero wall value); free-slip: even ghost (no shear)
     ua[l] = top ? ((g.fs[l] & 2) ? uf : -uf) : va;
     ub[l] = bot ? ((g.fs[l] & 1) ? uf : -uf) : vb;
   }
   const T *comp[3] = {u + g.foff[0], u + g.foff[1], u + g.foff[2]};
-  a_row_nb<T, DIM>(g, k, i, uf, ukp, ukm, ua, ub, comp, alpha, muc, mue, lam, Au, diag);
+  a_row_nb<T, DIM, Z>(g, k, i, uf, ukp, ukm, ua, ub, comp, alpha, muc, mue, lam, Au, diag);
 }
 
 __device__ __forceinline__ bool low_wall(const Geo &g, int k, const int i[3]) {
@@ -816,17 +825,32 @@ __host__ __device__ __forceinline__ i64 colour_threads(const Geo &g) {
   return (i64)((g.n[0] + 1) >> 1) * g.n[1] * g.n[2];
 }
 
-// Gauss-Seidel update of one velocity face (component k, cell index i)
-template <typename T, int DIM>
+// Gauss-Seidel update of one velocity face (component k, cell index i).
+// Z != 0: a pass of the first sweep from a zero iterate whose memory has not
+// been cleared (Z = 3 colour 0, Z = 1 colour 1; the loads a_row skips for
+// that Z are the values not yet written in that sweep).
+template <typename T, int DIM, int Z = 0>
 __device__ __forceinline__ void gs_point(const Geo &g, int k, const int i[3],
                                          const T *__restrict__ alpha, const T *__restrict__ muc,
                                          const T *__restrict__ mue, const T *__restrict__ lam,
                                          const T *__restrict__ rhs, T *__restrict__ phi) {
-  if (low_wall(g, k, i)) return;
-  T Au, dg;
-  a_row<T, DIM>(g, k, i, phi, alpha, muc, mue, lam, Au, dg);
   const i64 fq = fidx3(g, k, i);
-  phi[fq] += (rhs[fq] - Au) / dg;
+  if (low_wall(g, k, i)) {
+    if (Z) phi[fq] = (T)0;  // wall faces hold zero; the first sweep writes them
+    return;
+  }
+  T Au, dg;
+  a_row<T, DIM, Z>(g, k, i, phi, alpha, muc, mue, lam, Au, dg);
+  if (Z) {
+    phi[fq] = (T)0 + (rhs[fq] - Au) / dg;
+    if (g.ns[k] && i[k] + 1 == g.n[k]) {
+      int t[3] = {i[0], i[1], i[2]};
+      t[k] = g.n[k];
+      phi[fidx3(g, k, t)] = (T)0;
+    }
+  } else {
+    phi[fq] += (rhs[fq] - Au) / dg;
+  }
 }
 
 // one face of one colour of the velocity Gauss-Seidel sweep
@@ -840,7 +864,7 @@ __device__ __forceinline__ void vel_gs_elem(const Geo &g, int k, int colour, i64
   gs_point<T, DIM>(g, k, i, alpha, muc, mue, lam, rhs, phi);
 }
 
-template <typename T, int DIM, int K>
+template <typename T, int DIM, int K, int Z>
 __global__ void k_vel_gs(Geo g, int colour, const T *__restrict__ alpha,
                          const T *__restrict__ muc, const T *__restrict__ mue,
                          const T *__restrict__ lam, const T *__restrict__ rhs,
@@ -848,24 +872,37 @@ __global__ void k_vel_gs(Geo g, int colour, const T *__restrict__ alpha,
   int tx, i[3];
   if (!box_thread(g, (g.n[0] + 1) >> 1, tx, i[1], i[2])) return;
   i[0] = 2 * tx + ((i[1] + i[2] + colour) & 1);
-  if (i[0] < g.n[0]) gs_point<T, DIM>(g, K, i, alpha, muc, mue, lam, rhs, phi);
+  if (i[0] < g.n[0]) gs_point<T, DIM, Z>(g, K, i, alpha, muc, mue, lam, rhs, phi);
+}
+
+bool vel_gs_first_ok(const Geo &g) {
+  // the colouring must hold across periodic wraps: every extent even
+  for (int a = 0; a < g.d; a++)
+    if (g.n[a] & 1) return false;
+  return true;
 }
 
 template <typename T>
-void launch_vel_gs(const Geo &g, int k, int colour, const T *alpha, const T *muc, const T *mue,
-                   const T *lam, const T *rhs, T *phi, hipStream_t s) {
+void launch_vel_gs(const Geo &g, int k, int colour, int first, const T *alpha, const T *muc,
+                   const T *mue, const T *lam, const T *rhs, T *phi, hipStream_t s) {
   const dim3 nb = box_blocks(g, (g.n[0] + 1) >> 1);
-#define GS_CASE(D, KK)                                                                       \
-  hipLaunchKernelGGL((k_vel_gs<T, D, KK>), nb, dim3(kBlock), 0, s, g, colour, alpha, muc, \
+  const int z = first ? (colour == 0 ? 3 : 1) : 0;
+#define GS_CASE(D, KK, ZZ)                                                                     \
+  hipLaunchKernelGGL((k_vel_gs<T, D, KK, ZZ>), nb, dim3(kBlock), 0, s, g, colour, alpha, muc, \
                      mue, lam, rhs, phi)
+#define GS_Z(D, KK)           \
+  if (z == 0) GS_CASE(D, KK, 0); \
+  else if (z == 1) GS_CASE(D, KK, 1); \
+  else GS_CASE(D, KK, 3)
   if (g.d == 3) {
-    if (k == 0) GS_CASE(3, 0);
-    else if (k == 1) GS_CASE(3, 1);
-    else GS_CASE(3, 2);
+    if (k == 0) { GS_Z(3, 0); }
+    else if (k == 1) { GS_Z(3, 1); }
+    else { GS_Z(3, 2); }
   } else {
-    if (k == 0) GS_CASE(2, 0);
-    else GS_CASE(2, 1);
+    if (k == 0) { GS_Z(2, 0); }
+    else { GS_Z(2, 1); }
   }
+#undef GS_Z
 #undef GS_CASE
 }
 
@@ -2091,7 +2128,7 @@ void launch_grad_chain(const Geo &g, const double *dmu_edge, const double *mue_r
 // explicit instantiations
 // ------------------------------------------------------------------------
 #define INST(T)                                                                                  \
-  template void launch_vel_gs<T>(const Geo &, int, int, const T *, const T *, const T *,         \
+  template void launch_vel_gs<T>(const Geo &, int, int, int, const T *, const T *, const T *,    \
                                  const T *, const T *, T *, hipStream_t);                        \
   template void launch_vel_residual<T>(const Geo &, const T *, const T *, const T *, const T *,  \
                                        const T *, const T *, const T *, T *, hipStream_t);       \
