@@ -368,7 +368,10 @@ void split_alpha(stokes_ctx *X) {
 // the bulk coefficient (if any) and the edge families touching k, and writes
 // component k; on all but the coarsest level the residual (rhs, phi, alpha,
 // mu_cell, edges, bulk -> res), the face restriction (res -> coarse rhs) and
-// the prolongation (coarse phi, phi -> phi).  Pressure alike with beta on
+// the prolongation (coarse phi, phi -> phi).  A velocity level above the
+// coarse tail that starts with a sweep has no fill, and the passes of its
+// first sweep read only the components already written in that sweep
+// (component k itself on its second colour).  Pressure alike with beta on
 // the faces and red-black passes over the cells.
 double vcycle_alg_bytes(const stokes_ctx *X, bool vel) {
   const double s = X->mg32 ? 4.0 : 8.0;
@@ -381,15 +384,23 @@ double vcycle_alg_bytes(const stokes_ctx *X, bool vel) {
     const int sweeps = coarsest ? X->p.nu_coarse : X->p.nu_pre + X->p.nu_post;
     double b = 0.0;
     if (vel) {
-      b += nv;  // zero fill
-      double sweep = 0.0;
+      const bool in_tail = X->tail_l >= 0 && l >= X->tail_l;
+      const int first_sweeps = coarsest ? X->p.nu_coarse : X->p.nu_pre;
+      const bool zf = !in_tail && vel_gs_first_ok(g) && first_sweeps > 0;
+      if (!zf) b += nv;  // zero fill
+      double sweep = 0.0, first = 0.0, done = 0.0;
       for (int k = 0; k < g.d; k++) {
         double e = 0.0;
         for (int m = 0; m < 3; m++)
           if ((m != k || g.d == 2) && g.ecnt[m] > 0) e += (double)g.ecnt[m];
-        sweep += 2.0 * (nv + (th ? 3.0 : 2.0) * (double)g.fcnt[k] + (X->bulk ? 2.0 : 1.0) * nc + e);
+        const double fk = (double)g.fcnt[k];
+        // rhs_k (alpha_k), mu_cell (bulk), edges; each pass also writes component k
+        const double coef = (th ? 2.0 : 1.0) * fk + (X->bulk ? 2.0 : 1.0) * nc + e;
+        sweep += 2.0 * (nv + coef + fk);
+        first += (done + coef + fk) + (done + fk + coef + fk);
+        done += fk;
       }
-      b += sweeps * sweep;
+      b += zf ? first + (sweeps - 1) * sweep : sweeps * sweep;
       if (!coarsest) {
         const double nvc = (double)X->lev[l + 1].g.nvel;
         b += 3.0 * nv + (th ? nv : 0.0) + nc + ne + (X->bulk ? nc : 0.0);  // residual

@@ -67,10 +67,11 @@ def test_autograd_given_edge_viscosity_matches_oracle():
 def _vcycle_bytes_model(dim, n, bc, theta, vel, s=8, nu=(2, 2, 8)):
     """The documented byte model of one finest-level V-cycle (stokes.h,
     stokes_vcycle_time), from the array sizes of each level."""
-    total, levels = 0.0, []
+    total, levels, dims = 0.0, [], []
     m = list(n)
     while True:
         levels.append(W.make_layout(dim, tuple(m), bc))
+        dims.append(tuple(m))
         if min(m) == 2:
             break
         m = [x // 2 for x in m]
@@ -80,12 +81,22 @@ def _vcycle_bytes_model(dim, n, bc, theta, vel, s=8, nu=(2, 2, 8)):
         sweeps = nu[2] if coarsest else nu[0] + nu[1]
         edges = {m_: int(np.prod(lay.edge_dims(m_)[:dim])) for m_ in lay.edge_families}
         if vel:
-            b = nv
-            sw = 0.0
+            # levels of at most 512 cells run in the single-workgroup tail, which
+            # clears phi; above it the first sweep starts from uncleared memory
+            # (every extent even) and reads only the components it has written
+            in_tail = nc <= 512
+            zf = (not in_tail) and all(x % 2 == 0 for x in dims[l]) and \
+                (nu[2] if coarsest else nu[0]) > 0
+            b = 0 if zf else nv
+            sw = first = done = 0.0
             for k in range(dim):
                 e = sum(c for m_, c in edges.items() if m_ != k)
-                sw += 2 * (nv + (3 if theta else 2) * lay.face_counts[k] + nc + e)
-            b += sweeps * sw
+                fk = lay.face_counts[k]
+                coef = (2 if theta else 1) * fk + nc + e
+                sw += 2 * (nv + coef + fk)
+                first += (done + coef + fk) + (done + fk + coef + fk)
+                done += fk
+            b += first + (sweeps - 1) * sw if zf else sweeps * sw
             if not coarsest:
                 nvc = levels[l + 1].nvel
                 b += 3 * nv + (nv if theta else 0) + nc + ne + nv + nvc + nvc + 2 * nv
