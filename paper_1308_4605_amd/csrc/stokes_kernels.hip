@@ -1093,22 +1093,106 @@ __device__ __forceinline__ void face_prolong_elem(const Geo &gc, const Geo &gf, 
   face_prolong_at<T, DIM>(gc, gf, f, ec, phif);
 }
 
+// Coarse index J of a tangential tap: periodic axes wrap; on a wall axis an
+// index past the end is clamped (that value is replaced by the wall ghost).
+__device__ __forceinline__ int tap_index(const Geo &gc, int a, int J) {
+  if (!gc.ns[a]) return (J < 0) ? J + gc.n[a] : (J >= gc.n[a]) ? J - gc.n[a] : J;
+  return (J < 0) ? 0 : (J >= gc.n[a]) ? gc.n[a] - 1 : J;
+}
+
+// Prolongation by coarse cell.  The thread of coarse cell C adds the
+// correction to the low faces of its 2^d fine cells.  For component k those
+// faces use the 2 (normal) x 3 x 3 (tangential offsets -1, 0, +1) coarse
+// values around C, loaded once.  At a wall end the tap past the wall is
+// (+1 free-slip, -1 no-slip) times the tap at C, so every fine face takes
+// weight 3/4 at offset 0 and 1/4 on its own side, with the same products and
+// order of operations as face_prolong_at (the sign moves through the
+// products exactly).
 template <typename T, int DIM>
 __global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
                                    T *__restrict__ phif) {
-  int w, f[3];
-  if (!box_thread(gf, gf.n[0], w, f[1], f[2])) return;
-  f[0] = split_x(gf, w);
-  face_prolong_at<T, DIM>(gc, gf, f, ec, phif);
+  int C[3];
+  if (!box_thread(gc, gc.n[0], C[0], C[1], C[2])) return;
+  constexpr int NB = (DIM == 3) ? 3 : 1;
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    const int ta = (k == 0) ? 1 : 0;
+    const int tb = (k == 2) ? 1 : 2;
+    T cv[2][3][NB];
+    int cf[3] = {0, 0, 0};
+#pragma unroll
+    for (int n = 0; n < 2; n++) {
+      cf[k] = C[k] + n;
+      if (!gc.ns[k] && cf[k] == gc.n[k]) cf[k] = 0;
+#pragma unroll
+      for (int s0 = 0; s0 < 3; s0++) {
+        cf[ta] = tap_index(gc, ta, C[ta] + s0 - 1);
+#pragma unroll
+        for (int s1 = 0; s1 < NB; s1++) {
+          if (DIM == 3) cf[tb] = tap_index(gc, tb, C[tb] + s1 - 1);
+          cv[n][s0][s1] = ec[fidx3(gc, k, cf)];
+        }
+      }
+    }
+    // wall ghosts, axis ta then tb (a corner takes both signs)
+    if (gc.ns[ta]) {
+      const T slo = (gc.fs[ta] & 1) ? (T)1 : (T)-1, shi = (gc.fs[ta] & 2) ? (T)1 : (T)-1;
+      const bool lo = C[ta] == 0, hi = C[ta] + 1 == gc.n[ta];
+#pragma unroll
+      for (int n = 0; n < 2; n++)
+#pragma unroll
+        for (int s1 = 0; s1 < NB; s1++) {
+          if (lo) cv[n][0][s1] = slo * cv[n][1][s1];
+          if (hi) cv[n][2][s1] = shi * cv[n][1][s1];
+        }
+    }
+    if (DIM == 3 && gc.ns[tb]) {
+      const T slo = (gc.fs[tb] & 1) ? (T)1 : (T)-1, shi = (gc.fs[tb] & 2) ? (T)1 : (T)-1;
+      const bool lo = C[tb] == 0, hi = C[tb] + 1 == gc.n[tb];
+#pragma unroll
+      for (int n = 0; n < 2; n++)
+#pragma unroll
+        for (int s0 = 0; s0 < 3; s0++) {
+          if (lo) cv[n][s0][0] = slo * cv[n][s0][1];
+          if (hi) cv[n][s0][NB - 1] = shi * cv[n][s0][1];
+        }
+    }
+#pragma unroll
+    for (int o2 = 0; o2 < (DIM == 3 ? 2 : 1); o2++)
+#pragma unroll
+      for (int o1 = 0; o1 < 2; o1++)
+#pragma unroll
+        for (int o0 = 0; o0 < 2; o0++) {
+          const int o[3] = {o0, o1, o2};
+          int f[3] = {2 * C[0] + o0, 2 * C[1] + o1, (DIM == 3) ? 2 * C[2] + o2 : 0};
+          if (low_wall(gf, k, f)) continue;
+          const int ok = o[k];
+          const T nw[2] = {ok ? (T)0.5 : (T)1, ok ? (T)0.5 : (T)0};
+          const int ns[2] = {0, ok};                  // normal slots of the two taps
+          const int s0i[2] = {1, o[ta] ? 2 : 0};      // tangential slots along ta
+          const int s1i[2] = {(DIM == 3) ? 1 : 0, o[tb] ? 2 : 0};
+          const double w0[2] = {0.75, 0.25};
+          const double w1[2] = {(DIM == 3) ? 0.75 : 1.0, (DIM == 3) ? 0.25 : 0.0};
+          T sum = 0;
+#pragma unroll
+          for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b0 = 0; b0 < 2; b0++)
+#pragma unroll
+              for (int b1 = 0; b1 < (DIM == 3 ? 2 : 1); b1++)
+                sum += nw[a] * (T)w0[b0] * (T)w1[b1] * cv[ns[a]][s0i[b0]][s1i[b1]];
+          phif[fidx3(gf, k, f)] += sum;
+        }
+  }
 }
 
 template <typename T>
 void launch_face_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *phif, hipStream_t s) {
   if (gf.d == 3)
-    hipLaunchKernelGGL((k_face_prolong_add<T, 3>), box_blocks(gf, gf.n[0]), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_face_prolong_add<T, 3>), box_blocks(gc, gc.n[0]), dim3(kBlock), 0, s,
                        gc, gf, ec, phif);
   else
-    hipLaunchKernelGGL((k_face_prolong_add<T, 2>), box_blocks(gf, gf.n[0]), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_face_prolong_add<T, 2>), box_blocks(gc, gc.n[0]), dim3(kBlock), 0, s,
                        gc, gf, ec, phif);
 }
 
