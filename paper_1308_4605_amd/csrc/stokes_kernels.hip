@@ -158,6 +158,50 @@ __device__ __forceinline__ bool box_thread(const Geo &g, int W, int &w, int &y, 
 // A = alpha - L_mu at one face (paper Sec. 3.1, eq. div_stress).  Returns
 // (A u)_f and the diagonal of A at f.  Tangential no-slip walls use the ghost
 // value -u_f, which equals the one-sided wall difference (u_f - 0)/(h/2).
+
+// Arithmetic of one row of A at face (k, i) from loaded values: u_f, its
+// neighbours along k (ukp, ukm) and, per tangential axis l, the u_k values
+// above/below (ua[l], ub[l], wall ghosts applied), the u_l values beside the
+// upper and lower edge on the right/left cell (ulh_r, ulh_l, ull_r, ull_l),
+// the edge viscosities (mhi, mlo), the cell viscosities right/left of f
+// (mr, ml), alpha at f and, with a bulk coefficient, lam right/left (lr, ll).
+template <typename T, int DIM>
+__device__ __forceinline__ void a_row_core(const Geo &g, int k, const int i[3], T uf, T ukp,
+                                           T ukm, const T (&ua)[3], const T (&ub)[3],
+                                           const T (&ulh_r)[3], const T (&ulh_l)[3],
+                                           const T (&ull_r)[3], const T (&ull_l)[3],
+                                           const T (&mhi)[3], const T (&mlo)[3], T mr, T ml,
+                                           T al, bool bulk, T lr, T ll, T &Au, T &diag) {
+  const T ih = (T)g.ih;
+  const T ih2 = ih * ih;
+  const T tr = (T)2 * mr * ((ukp - uf) * ih);
+  const T tl = (T)2 * ml * ((uf - ukm) * ih);
+  T s = (tr - tl) * ih;
+  T dg = al + (T)2 * (mr + ml) * ih2;
+  // h * divergence of the cells right (r) and left (l) of f
+  T hdr = ukp - uf, hdl = uf - ukm;
+#pragma unroll
+  for (int l = 0; l < DIM; l++) {
+    if (l == k) continue;
+    const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
+    const bool bot = g.ns[l] && (i[l] == 0);
+    const T ghi = (ua[l] - uf) * ih + (ulh_r[l] - ulh_l[l]) * ih;
+    const T glo = (uf - ub[l]) * ih + (ull_r[l] - ull_l[l]) * ih;
+    s += (mhi[l] * ghi - mlo[l] * glo) * ih;
+    // wall edge: one-sided difference (no-slip, weight 2) or no flux (free-slip)
+    const T wt = (g.fs[l] & 2) ? (T)0 : (T)2, wb = (g.fs[l] & 1) ? (T)0 : (T)2;
+    dg += ((top ? wt : (T)1) * mhi[l] + (bot ? wb : (T)1) * mlo[l]) * ih2;
+    hdr += ulh_r[l] - ull_r[l];
+    hdl += ulh_l[l] - ull_l[l];
+  }
+  if (bulk) {
+    s += (lr * hdr - ll * hdl) * ih2;
+    dg += (lr + ll) * ih2;
+  }
+  Au = al * uf - s;
+  diag = dg;
+}
+
 // Core of the row: the caller supplies u_f, its two neighbours along the
 // normal axis k (ukp, ukm) and, for each tangential axis l, the u_k values
 // above/below (ua[l], ub[l]) with the wall ghost already applied; u_l values
@@ -174,8 +218,6 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
                                          const T *const *comp, const T *__restrict__ alpha,
                                          const T *__restrict__ muc, const T *__restrict__ mue,
                                          const T *__restrict__ lam, T &Au, T &diag) {
-  const T ih = (T)g.ih;
-  const T ih2 = ih * ih;
   const i64 fq = fidx3(g, k, i);
   int t[3] = {i[0], i[1], i[2]};
   const int km = dn1(g, k, i[k]);
@@ -183,54 +225,40 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
   const T mr = muc[cidx3(g, i)];
   const T ml = muc[cidx3(g, t)];
   t[k] = i[k];
-  const T tr = (T)2 * mr * ((ukp - uf) * ih);
-  const T tl = (T)2 * ml * ((uf - ukm) * ih);
-  T s = (tr - tl) * ih;
   const T al = alpha ? alpha[fq] : (T)0;  // no alpha array: theta = 0
-  T dg = al + (T)2 * (mr + ml) * ih2;
-  // h * divergence of the cells right (r) and left (l) of f
-  T hdr = ukp - uf, hdl = uf - ukm;
+  T ulh_r[3] = {0, 0, 0}, ulh_l[3] = {0, 0, 0}, ull_r[3] = {0, 0, 0}, ull_l[3] = {0, 0, 0};
+  T mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0};
 #pragma unroll
   for (int l = 0; l < DIM; l++) {
     if (l == k) continue;
     const int m = 3 - k - l;
-    const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
-    const bool bot = g.ns[l] && (i[l] == 0);
     const int lp = up1(g, l, i[l]);
     const T *__restrict__ ul = comp[l];
     const int f0 = g.fd[l][0], f1 = g.fd[l][1];
-    t[l] = lp;
-    const T mhi = mue[eidx3(g, m, t)];
-    // u_l on the two faces beside the upper edge (cells i[k] and i[k]-1 along k)
     const bool lz = Z && l > k;
-    const T ulh_r = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
+    t[l] = lp;
+    mhi[l] = mue[eidx3(g, m, t)];
+    // u_l on the two faces beside the upper edge (cells i[k] and i[k]-1 along k)
+    ulh_r[l] = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = km;
-    const T ulh_l = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
+    ulh_l[l] = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = i[k];
     t[l] = i[l];
-    const T mlo = mue[eidx3(g, m, t)];
-    const T ull_r = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
+    mlo[l] = mue[eidx3(g, m, t)];
+    ull_r[l] = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = km;
-    const T ull_l = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
+    ull_l[l] = lz ? (T)0 : ul[(t[2] * f1 + t[1]) * f0 + xpos(g, f0, t[0])];
     t[k] = i[k];
-    const T ghi = (ua[l] - uf) * ih + (ulh_r - ulh_l) * ih;
-    const T glo = (uf - ub[l]) * ih + (ull_r - ull_l) * ih;
-    s += (mhi * ghi - mlo * glo) * ih;
-    // wall edge: one-sided difference (no-slip, weight 2) or no flux (free-slip)
-    const T wt = (g.fs[l] & 2) ? (T)0 : (T)2, wb = (g.fs[l] & 1) ? (T)0 : (T)2;
-    dg += ((top ? wt : (T)1) * mhi + (bot ? wb : (T)1) * mlo) * ih2;
-    hdr += ulh_r - ull_r;
-    hdl += ulh_l - ull_l;
   }
+  T lr = 0, ll = 0;
   if (lam) {
     t[k] = km;
-    const T lr = lam[cidx3(g, i)], ll = lam[cidx3(g, t)];
+    lr = lam[cidx3(g, i)];
+    ll = lam[cidx3(g, t)];
     t[k] = i[k];
-    s += (lr * hdr - ll * hdl) * ih2;
-    dg += (lr + ll) * ih2;
   }
-  Au = al * uf - s;
-  diag = dg;
+  a_row_core<T, DIM>(g, k, i, uf, ukp, ukm, ua, ub, ulh_r, ulh_l, ull_r, ull_l, mhi, mlo, mr, ml,
+                     al, lam != nullptr, lr, ll, Au, diag);
 }
 
 // A = alpha - L_mu at one face (paper Sec. 3.1, eq. div_stress), all values
@@ -906,7 +934,12 @@ void launch_vel_gs(const Geo &g, int k, int colour, int first, const T *alpha, c
 #undef GS_CASE
 }
 
-// res = rhs - A phi - G p (p may be null); cell-indexed over all components
+// res = rhs - A phi - G p (p may be null) at the low faces of cell i, all
+// components.  The rows share most of their velocity values, so those are
+// loaded once: per component c the value at i, at i +- e_a for every axis a,
+// and at i + e_c - e_k for k != c (27 loads in 3D instead of 45), and the
+// cell and edge viscosities around i likewise.  Each row then runs the
+// arithmetic of a_row_core, as the smoother does.
 template <typename T, int DIM>
 __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i64 t,
                                                 const T *__restrict__ alpha,
@@ -916,6 +949,116 @@ __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i6
                                                 const T *__restrict__ rhs,
                                                 const T *__restrict__ phi,
                                                 const T *__restrict__ p, T *__restrict__ res) {
+  int ip[3] = {0, 0, 0}, im[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    ip[a] = up1(g, a, i[a]);
+    im[a] = dn1(g, a, i[a]);
+  }
+  // V[c][0] at i, V[c][1 + 2a] at i + e_a, V[c][2 + 2a] at i - e_a;
+  // X[c][k] at i + e_c - e_k.  Component c has no face at index n[a] along a
+  // wall axis a != c: that load is clamped to i (the wall ghost replaces it).
+  T V[DIM][1 + 2 * DIM], X[DIM][DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; c++) {
+    int q[3] = {i[0], i[1], i[2]};
+    V[c][0] = phi[fidx3(g, c, q)];
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+      const bool top = a != c && g.ns[a] && (i[a] + 1 == g.n[a]);
+      q[a] = top ? i[a] : ip[a];
+      V[c][1 + 2 * a] = phi[fidx3(g, c, q)];
+      q[a] = im[a];
+      V[c][2 + 2 * a] = phi[fidx3(g, c, q)];
+      q[a] = i[a];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; k++) {
+      X[c][k] = (T)0;
+      if (k == c) continue;
+      q[c] = ip[c];
+      q[k] = im[k];
+      X[c][k] = phi[fidx3(g, c, q)];
+      q[c] = i[c];
+      q[k] = i[k];
+    }
+  }
+  // cell viscosity (and bulk coefficient) at i and at i - e_k
+  T mc[1 + DIM], lc[1 + DIM];
+  mc[0] = muc[t];
+  lc[0] = lam ? lam[t] : (T)0;
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    int q[3] = {i[0], i[1], i[2]};
+    q[k] = im[k];
+    const i64 cq = cidx3(g, q);
+    mc[1 + k] = muc[cq];
+    lc[1 + k] = lam ? lam[cq] : (T)0;
+  }
+  // edge family m at i (E0) and at i + e_a for the axes a != m (E1)
+  T E0[3] = {0, 0, 0}, E1[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int m = (DIM == 3 ? 0 : 2); m < 3; m++) {
+    E0[m] = mue[eidx3(g, m, i)];
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+      if (a == m) continue;
+      int q[3] = {i[0], i[1], i[2]};
+      q[a] = ip[a];
+      E1[m][a] = mue[eidx3(g, m, q)];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    if (low_wall(g, k, i)) continue;
+    const T uf = V[k][0];
+    T ua[3] = {0, 0, 0}, ub[3] = {0, 0, 0};
+    T ulh_r[3] = {0, 0, 0}, ulh_l[3] = {0, 0, 0}, ull_r[3] = {0, 0, 0}, ull_l[3] = {0, 0, 0};
+    T mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0};
+#pragma unroll
+    for (int l = 0; l < DIM; l++) {
+      if (l == k) continue;
+      const int m = 3 - k - l;
+      const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
+      const bool bot = g.ns[l] && (i[l] == 0);
+      // no-slip: odd ghost (zero wall value); free-slip: even ghost (no shear)
+      ua[l] = top ? ((g.fs[l] & 2) ? uf : -uf) : V[k][1 + 2 * l];
+      ub[l] = bot ? ((g.fs[l] & 1) ? uf : -uf) : V[k][2 + 2 * l];
+      ulh_r[l] = V[l][1 + 2 * l];
+      ulh_l[l] = X[l][k];
+      ull_r[l] = V[l][0];
+      ull_l[l] = V[l][2 + 2 * k];
+      mhi[l] = E1[m][l];
+      mlo[l] = E0[m];
+    }
+    const i64 fq = fidx3(g, k, i);
+    const T al = alpha ? alpha[fq] : (T)0;  // no alpha array: theta = 0
+    T Au, dg;
+    a_row_core<T, DIM>(g, k, i, uf, V[k][1 + 2 * k], V[k][2 + 2 * k], ua, ub, ulh_r, ulh_l, ull_r,
+                       ull_l, mhi, mlo, mc[0], mc[1 + k], al, lam != nullptr, lc[0], lc[1 + k],
+                       Au, dg);
+    T r = rhs[fq] - Au;
+    if (p) {
+      int l[3] = {i[0], i[1], i[2]};
+      l[k] = im[k];
+      r -= (p[t] - p[cidx3(g, l)]) * (T)g.ih;
+    }
+    res[fq] = r;
+  }
+}
+
+// The same residual one row at a time through a_row (fewer registers: the
+// form the single-workgroup coarse tail uses).
+template <typename T, int DIM>
+__device__ __forceinline__ void vel_residual_rows_at(const Geo &g, const int i[3], i64 t,
+                                                     const T *__restrict__ alpha,
+                                                     const T *__restrict__ muc,
+                                                     const T *__restrict__ mue,
+                                                     const T *__restrict__ lam,
+                                                     const T *__restrict__ rhs,
+                                                     const T *__restrict__ phi,
+                                                     const T *__restrict__ p,
+                                                     T *__restrict__ res) {
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
     if (low_wall(g, k, i)) continue;
@@ -943,7 +1086,7 @@ __device__ __forceinline__ void vel_residual_elem(const Geo &g, i64 t, const T *
   if (t >= g.ncell) return;
   int i[3];
   cell_of(g, t, i);
-  vel_residual_at<T, DIM>(g, i, t, alpha, muc, mue, lam, rhs, phi, p, res);
+  vel_residual_rows_at<T, DIM>(g, i, t, alpha, muc, mue, lam, rhs, phi, p, res);
 }
 
 template <typename T, int DIM>
