@@ -581,29 +581,18 @@ template void launch_axpy<double>(double, const double *, double *, i64, hipStre
 // saddle operator (FP64 arithmetic, input in TI)
 // ------------------------------------------------------------------------
 
-// GW: prescribed tangential wall velocities gw (edge layout) replace the
-// zero wall value of the no-slip ghost, 2 gw - u_f (boundary terms only).
-template <typename TI, int DIM, bool GW>
-__device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
-                                            const TI *__restrict__ u,
-                                            const double *__restrict__ alpha,
-                                            const double *__restrict__ muc,
-                                            const double *__restrict__ mue,
-                                            const double *__restrict__ lam,
-                                            const double *__restrict__ gw, double &Au) {
+// One row of A at face (k, i) in FP64 from loaded values (the names of
+// a_row_core).  GW: prescribed tangential wall velocities (gwhi, gwlo at the
+// upper/lower edge, edge layout) replace the zero wall value of the no-slip
+// ghost, 2 gw - u_f, and a free-slip wall's flux is zero (boundary terms only).
+template <int DIM, bool GW>
+__device__ __forceinline__ double a_row_mixed_core(
+    const Geo &g, int k, const int i[3], double uf, double ukp, double ukm, const double (&va)[3],
+    const double (&vb)[3], const double (&ulh_r)[3], const double (&ulh_l)[3],
+    const double (&ull_r)[3], const double (&ull_l)[3], const double (&mhi)[3],
+    const double (&mlo)[3], const double (&gwhi)[3], const double (&gwlo)[3], double mr,
+    double ml, double al, bool bulk, double lr, double ll) {
   const double ih = g.ih;
-  const i64 fq = fidx3(g, k, i);
-  const double uf = (double)u[fq];
-  int t[3] = {i[0], i[1], i[2]};
-  const int kp = up1(g, k, i[k]);
-  const int km = dn1(g, k, i[k]);
-  t[k] = kp;
-  const double ukp = (double)u[fidx3(g, k, t)];
-  t[k] = km;
-  const double ukm = (double)u[fidx3(g, k, t)];
-  const double mr = muc[cidx3(g, i)];
-  const double ml = muc[cidx3(g, t)];
-  t[k] = i[k];
   const double tr = 2.0 * mr * ((ukp - uf) * ih);
   const double tl = 2.0 * ml * ((uf - ukm) * ih);
   double s = (tr - tl) * ih;
@@ -611,57 +600,37 @@ __device__ __forceinline__ void a_row_mixed(const Geo &g, int k, const int i[3],
 #pragma unroll
   for (int l = 0; l < DIM; l++) {
     if (l == k) continue;
-    const int m = 3 - k - l;
     const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
     const bool bot = g.ns[l] && (i[l] == 0);
-    const int lp = up1(g, l, i[l]);
-    const int lm = dn1(g, l, i[l]);
-    t[l] = top ? i[l] : lp;  // component k has no face at index n[l] along l
-    const double va = (double)u[fidx3(g, k, t)];  // unconditional; ghost selected below
     // wall ghosts: even (free-slip end) or odd (no-slip end)
     const bool fs_hi = g.fs[l] & 2, fs_lo = g.fs[l] & 1;
-    double ua = top ? (fs_hi ? uf : -uf) : va;
-    t[l] = lp;
-    const int ehi = eidx3(g, m, t);
-    const double mhi = mue[ehi];
-    const double ulh_r = (double)u[fidx3(g, l, t)];
-    t[k] = km;
-    const double ulh_l = (double)u[fidx3(g, l, t)];
-    t[k] = i[k];
-    t[l] = lm;
-    const double vb = (double)u[fidx3(g, k, t)];
-    double ub = bot ? (fs_lo ? uf : -uf) : vb;
-    t[l] = i[l];
-    const int elo = eidx3(g, m, t);
-    const double mlo = mue[elo];
+    double ua = top ? (fs_hi ? uf : -uf) : va[l];
+    double ub = bot ? (fs_lo ? uf : -uf) : vb[l];
     if (GW) {
-      if (top && !fs_hi) ua = 2.0 * gw[ehi] - uf;
-      if (bot && !fs_lo) ub = 2.0 * gw[elo] - uf;
+      if (top && !fs_hi) ua = 2.0 * gwhi[l] - uf;
+      if (bot && !fs_lo) ub = 2.0 * gwlo[l] - uf;
     }
+    double ghi = (ua - uf) * ih + (ulh_r[l] - ulh_l[l]) * ih;
+    double glo = (uf - ub) * ih + (ull_r[l] - ull_l[l]) * ih;
     // with prescribed normal velocities on a free-slip wall the cross
     // derivative along the wall need not vanish; the whole flux does
-    const double ull_r = (double)u[fidx3(g, l, t)];
-    t[k] = km;
-    const double ull_l = (double)u[fidx3(g, l, t)];
-    t[k] = i[k];
-    double ghi = (ua - uf) * ih + (ulh_r - ulh_l) * ih;
-    double glo = (uf - ub) * ih + (ull_r - ull_l) * ih;
     if (GW) {
       if (top && fs_hi) ghi = 0.0;
       if (bot && fs_lo) glo = 0.0;
     }
-    s += (mhi * ghi - mlo * glo) * ih;
-    hdr += ulh_r - ull_r;
-    hdl += ulh_l - ull_l;
+    s += (mhi[l] * ghi - mlo[l] * glo) * ih;
+    hdr += ulh_r[l] - ull_r[l];
+    hdl += ulh_l[l] - ull_l[l];
   }
-  if (lam) {  // bulk viscosity: lam (div u) on the two normal stresses
-    t[k] = km;
-    s += (lam[cidx3(g, i)] * hdr - lam[cidx3(g, t)] * hdl) * (ih * ih);
-    t[k] = i[k];
-  }
-  Au = (alpha ? alpha[fq] * uf : 0.0) - s;  // no alpha array: theta = 0
+  if (bulk) s += (lr * hdr - ll * hdl) * (ih * ih);  // lam (div u) on the normal stresses
+  return al * uf - s;
 }
 
+// y = M x (or y = b - M x) at cell i: the velocity rows of the low faces of
+// all components, the pressure gradient, and the divergence row of the cell.
+// The rows share most of their velocity values, which are loaded once per
+// cell (per component c at i, at i +- e_a and at i + e_c - e_k), as are the
+// cell and edge coefficients.
 template <typename TI, int DIM, bool GW>
 __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double *__restrict__ muc,
                           const double *__restrict__ mue, const double *__restrict__ lam,
@@ -673,23 +642,104 @@ __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double 
   if (!box_thread(g, g.n[0], i[0], i[1], i[2])) return;
   const i64 t = cidx3(g, i);
   const double ih = g.ih;
-  const double pc = (double)xp[t];
+  int ip[3] = {0, 0, 0}, im[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    ip[a] = up1(g, a, i[a]);
+    im[a] = dn1(g, a, i[a]);
+  }
+  // V[c][0] at i, V[c][1 + 2a] at i + e_a, V[c][2 + 2a] at i - e_a; X[c][k]
+  // at i + e_c - e_k.  Component c has no face at index n[a] along a wall
+  // axis a != c: that load is clamped to i (the wall ghost replaces it).
+  double V[DIM][1 + 2 * DIM], X[DIM][DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; c++) {
+    int q[3] = {i[0], i[1], i[2]};
+    V[c][0] = (double)xu[fidx3(g, c, q)];
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+      const bool top = a != c && g.ns[a] && (i[a] + 1 == g.n[a]);
+      q[a] = top ? i[a] : ip[a];
+      V[c][1 + 2 * a] = (double)xu[fidx3(g, c, q)];
+      q[a] = im[a];
+      V[c][2 + 2 * a] = (double)xu[fidx3(g, c, q)];
+      q[a] = i[a];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; k++) {
+      X[c][k] = 0.0;
+      if (k == c) continue;
+      q[c] = ip[c];
+      q[k] = im[k];
+      X[c][k] = (double)xu[fidx3(g, c, q)];
+      q[c] = i[c];
+      q[k] = i[k];
+    }
+  }
+  // cell values at i and at i - e_k
+  double mc[1 + DIM], lc[1 + DIM], pc[1 + DIM];
+  mc[0] = muc[t];
+  lc[0] = lam ? lam[t] : 0.0;
+  pc[0] = (double)xp[t];
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    int q[3] = {i[0], i[1], i[2]};
+    q[k] = im[k];
+    const i64 cq = cidx3(g, q);
+    mc[1 + k] = muc[cq];
+    lc[1 + k] = lam ? lam[cq] : 0.0;
+    pc[1 + k] = (double)xp[cq];
+  }
+  // edge family m at i (E0) and at i + e_a for the axes a != m (E1), and the
+  // prescribed wall velocities at the same edges
+  double E0[3] = {0, 0, 0}, E1[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double G0[3] = {0, 0, 0}, G1[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int m = (DIM == 3 ? 0 : 2); m < 3; m++) {
+    const int e0 = eidx3(g, m, i);
+    E0[m] = mue[e0];
+    if (GW) G0[m] = gw[e0];
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+      if (a == m) continue;
+      int q[3] = {i[0], i[1], i[2]};
+      q[a] = ip[a];
+      const int e1 = eidx3(g, m, q);
+      E1[m][a] = mue[e1];
+      if (GW) G1[m][a] = gw[e1];
+    }
+  }
   double div = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
-    int r[3] = {i[0], i[1], i[2]};
-    r[k] = i[k] + 1;
-    if (!g.ns[k] && r[k] == g.n[k]) r[k] = 0;
-    div += ((double)xu[fidx3(g, k, r)] - (double)xu[fidx3(g, k, i)]) * ih;
-    const i64 q = fidx3(g, k, i);
-    if (low_wall(g, k, i)) {
-      continue;
+    // the face above along k: index i[k] + 1 (the wall face on a wall axis,
+    // wrapped on a periodic one)
+    div += (V[k][1 + 2 * k] - V[k][0]) * ih;
+    if (low_wall(g, k, i)) continue;
+    double va[3] = {0, 0, 0}, vb[3] = {0, 0, 0};
+    double ulh_r[3] = {0, 0, 0}, ulh_l[3] = {0, 0, 0}, ull_r[3] = {0, 0, 0}, ull_l[3] = {0, 0, 0};
+    double mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0}, gwhi[3] = {0, 0, 0}, gwlo[3] = {0, 0, 0};
+#pragma unroll
+    for (int l = 0; l < DIM; l++) {
+      if (l == k) continue;
+      const int m = 3 - k - l;
+      va[l] = V[k][1 + 2 * l];
+      vb[l] = V[k][2 + 2 * l];
+      ulh_r[l] = V[l][1 + 2 * l];
+      ulh_l[l] = X[l][k];
+      ull_r[l] = V[l][0];
+      ull_l[l] = V[l][2 + 2 * k];
+      mhi[l] = E1[m][l];
+      mlo[l] = E0[m];
+      gwhi[l] = G1[m][l];
+      gwlo[l] = G0[m];
     }
-    double Au;
-    a_row_mixed<TI, DIM, GW>(g, k, i, xu, alpha, muc, mue, lam, gw, Au);
-    int l[3] = {i[0], i[1], i[2]};
-    l[k] = dn1(g, k, i[k]);
-    const double gp = (pc - (double)xp[cidx3(g, l)]) * ih;
+    const i64 q = fidx3(g, k, i);
+    const double al = alpha ? alpha[q] : 0.0;  // no alpha array: theta = 0
+    const double Au = a_row_mixed_core<DIM, GW>(
+        g, k, i, V[k][0], V[k][1 + 2 * k], V[k][2 + 2 * k], va, vb, ulh_r, ulh_l, ull_r, ull_l,
+        mhi, mlo, gwhi, gwlo, mc[0], mc[1 + k], al, lam != nullptr, lc[0], lc[1 + k]);
+    const double gp = (pc[0] - pc[1 + k]) * ih;
     const double y = Au + gp;
     yu[q] = bu ? bu[q] - y : y;
   }
