@@ -13,6 +13,8 @@
 // wall values without branches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "stokes_internal.h"
 
 namespace stk {
@@ -2199,7 +2201,12 @@ void launch_cgs_next(const double *w, const double *const *v, const double *h1, 
                      double *nrm2, hipStream_t s) {
   PtrPack pk;
   for (int j = 0; j < nv; j++) pk.p[j] = v[j];
-  const int nb = arn_blocks(n);
+  // Without the norm there is nothing to reduce: one double2 per thread
+  // (the grid-stride loop then runs once), which streams faster than the
+  // fixed reduction grid.  With the norm the fixed grid keeps the partial
+  // sums, and so the result, independent of the launch.
+  const i64 pairs = std::max<i64>(1, ((n >> 1) + kArnBlock - 1) / kArnBlock);
+  const int nb = nrm2 ? arn_blocks(n) : (int)std::min<i64>(pairs, 0x7fffffff);
   ARN_DISPATCH(k_cgs_next, nv, w, pk, h1, h2, nv, inv_nu, n, out, out32,
                nrm2 ? partials : nullptr);
   if (nrm2) hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, nrm2);
