@@ -862,9 +862,71 @@ __global__ void k_vel_permute(Geo gin, Geo gout, const T *__restrict__ in, T *__
     if (two) out[base + 2 * p + 1] = b;
   }
 }
+// FP32 rows whose length is a multiple of 4: thread q of a row moves the
+// natural positions 4q..4q+3 (one float4) to the split positions 2q, 2q+1
+// and (L/2) + 2q, (L/2) + 2q + 1 (two float2), or back.
+__host__ __device__ inline i64 permute_quads(const Geo &g, int k) {
+  return (i64)g.fd[k][1] * g.fd[k][2] * (g.fd[k][0] >> 2);
+}
+__global__ void k_vel_permute4(Geo gin, Geo gout, const float *__restrict__ in,
+                               float *__restrict__ out, const double *__restrict__ sums) {
+  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  int k = 0;
+  for (; k < gin.d; k++) {
+    const i64 nq = permute_quads(gin, k);
+    if (t < nq) break;
+    t -= nq;
+  }
+  if (k == gin.d) return;
+  const unsigned L = (unsigned)gin.fd[k][0], nq = L >> 2, ne = L >> 1;
+  const unsigned row = (unsigned)t / nq;
+  const unsigned q = (unsigned)t - row * nq;
+  const i64 base = gin.foff[k] + (i64)row * L;
+  const float mean =
+      (sums && ((gin.sing >> k) & 1)) ? (float)(sums[k] / (double)gin.fcnt[k]) : 0.0f;
+  float x0, x1, x2, x3;  // natural positions 4q .. 4q+3
+  if (gin.split) {
+    const float2 e = *reinterpret_cast<const float2 *>(in + base + 2 * q);
+    const float2 o = *reinterpret_cast<const float2 *>(in + base + ne + 2 * q);
+    x0 = e.x;
+    x2 = e.y;
+    x1 = o.x;
+    x3 = o.y;
+  } else {
+    const float4 v = *reinterpret_cast<const float4 *>(in + base + 4 * q);
+    x0 = v.x;
+    x1 = v.y;
+    x2 = v.z;
+    x3 = v.w;
+  }
+  x0 -= mean;
+  x1 -= mean;
+  x2 -= mean;
+  x3 -= mean;
+  if (gout.split) {
+    *reinterpret_cast<float2 *>(out + base + 2 * q) = make_float2(x0, x2);
+    *reinterpret_cast<float2 *>(out + base + ne + 2 * q) = make_float2(x1, x3);
+  } else {
+    *reinterpret_cast<float4 *>(out + base + 4 * q) = make_float4(x0, x1, x2, x3);
+  }
+}
+
 template <typename T>
 void launch_vel_permute(const Geo &gin, const Geo &gout, const T *in, T *out, const double *sums,
                         hipStream_t s) {
+  if (sizeof(T) == 4 && ((uintptr_t)in % 16) == 0 && ((uintptr_t)out % 16) == 0) {
+    bool quads = true;
+    i64 nq = 0;
+    for (int k = 0; k < gin.d; k++) {
+      quads = quads && (gin.fd[k][0] % 4 == 0) && (gin.foff[k] % 4 == 0);
+      nq += permute_quads(gin, k);
+    }
+    if (quads) {
+      hipLaunchKernelGGL(k_vel_permute4, dim3(blocks_for(nq)), dim3(kBlock), 0, s, gin, gout,
+                         (const float *)in, (float *)out, sums);
+      return;
+    }
+  }
   i64 np = 0;
   for (int k = 0; k < gin.d; k++) np += permute_pairs(gin, k);
   // pair loads and stores need the buffer itself aligned to a pair
@@ -1948,12 +2010,28 @@ __global__ void k_vel_sums_partial(Geo g, const T *__restrict__ u, double *__res
   const T *__restrict__ c = u + g.foff[k];
   const i64 n = g.fcnt[k];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const i64 stride = (i64)gridDim.x * blockDim.x * 4;
-  for (i64 t0 = (i64)blockIdx.x * blockDim.x * 4 + threadIdx.x; t0 < n; t0 += stride) {
+  if (sizeof(T) == 4 && ((uintptr_t)c % 16) == 0) {
+    // FP32: one float4 per thread and iteration, the remainder below
+    const float4 *__restrict__ c4 = (const float4 *)c;
+    const i64 n4 = n >> 2;
+    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n4;
+         t += (i64)gridDim.x * blockDim.x) {
+      const float4 v = c4[t];
+      acc[0] += (double)v.x;
+      acc[1] += (double)v.y;
+      acc[2] += (double)v.z;
+      acc[3] += (double)v.w;
+    }
+    if (blockIdx.x == 0 && (i64)threadIdx.x < n - 4 * n4)
+      acc[0] += (double)c[4 * n4 + threadIdx.x];
+  } else {
+    const i64 stride = (i64)gridDim.x * blockDim.x * 4;
+    for (i64 t0 = (i64)blockIdx.x * blockDim.x * 4 + threadIdx.x; t0 < n; t0 += stride) {
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const i64 t = t0 + (i64)j * blockDim.x;
-      if (t < n) acc[j] += (double)c[t];
+      for (int j = 0; j < 4; j++) {
+        const i64 t = t0 + (i64)j * blockDim.x;
+        if (t < n) acc[j] += (double)c[t];
+      }
     }
   }
   double r = (acc[0] + acc[1]) + (acc[2] + acc[3]);
