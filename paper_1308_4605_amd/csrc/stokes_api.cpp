@@ -386,7 +386,7 @@ double vcycle_alg_bytes(const stokes_ctx *X, bool vel) {
     if (vel) {
       const bool in_tail = X->tail_l >= 0 && l >= X->tail_l;
       const int first_sweeps = coarsest ? X->p.nu_coarse : X->p.nu_pre;
-      const bool zf = !in_tail && vel_gs_first_ok(g) && first_sweeps > 0;
+      const bool zf = !in_tail && gs_first_ok(g) && first_sweeps > 0;
       if (!zf) b += nv;  // zero fill
       double sweep = 0.0, first = 0.0, done = 0.0;
       for (int k = 0; k < g.d; k++) {
@@ -408,8 +408,15 @@ double vcycle_alg_bytes(const stokes_ctx *X, bool vel) {
         b += nvc + 2.0 * nv;                                              // prolongation
       }
     } else {
-      b += nc;                                   // zero fill
-      b += sweeps * 2.0 * (nv + 3.0 * nc);       // beta, rhs, phi read; phi written
+      const bool in_tail = X->tail_l >= 0 && l >= X->tail_l;
+      const int first_sweeps = coarsest ? X->p.nu_coarse : X->p.nu_pre;
+      const bool zf = !in_tail && gs_first_ok(g) && first_sweeps > 0;
+      // beta, rhs, phi read and phi written per pass; the first sweep's first
+      // colour reads no phi, and there is no fill
+      if (zf)
+        b += (nv + 2.0 * nc) + (nv + 3.0 * nc) + (sweeps - 1) * 2.0 * (nv + 3.0 * nc);
+      else
+        b += nc + sweeps * 2.0 * (nv + 3.0 * nc);
       if (!coarsest) {
         const double ncc = (double)X->lev[l + 1].g.ncell;
         b += nv + 3.0 * nc;                      // residual
@@ -464,10 +471,10 @@ void smooth_vel(stokes_ctx *X, int l, const T *rhs, T *phi, int nsweeps, bool fr
 }
 
 template <typename T>
-void sweep_p(stokes_ctx *X, int l, const T *rhs, T *phi) {
+void sweep_p(stokes_ctx *X, int l, const T *rhs, T *phi, bool from_zero = false) {
   const Level &L = X->lev[l];
-  launch_p_gs<T>(L.g, 0, P<T>(L.beta), rhs, phi, X->s);
-  launch_p_gs<T>(L.g, 1, P<T>(L.beta), rhs, phi, X->s);
+  launch_p_gs<T>(L.g, 0, from_zero, P<T>(L.beta), rhs, phi, X->s);
+  launch_p_gs<T>(L.g, 1, from_zero, P<T>(L.beta), rhs, phi, X->s);
 }
 
 // levels tail_l..nlev-1 of a V-cycle in one launch; level tail_l works on
@@ -517,7 +524,7 @@ void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
   // the first sweep writes every face of the zero iterate, so the clearing
   // pass is needed only without a sweep or where the colouring does not
   // hold across a periodic wrap
-  const bool zf = vel_gs_first_ok(L.gv) && (coarsest ? X->p.nu_coarse : X->p.nu_pre) > 0;
+  const bool zf = gs_first_ok(L.gv) && (coarsest ? X->p.nu_coarse : X->p.nu_pre) > 0;
   if (!zf) launch_fill<T>(phi, (T)0, L.gv.nvel, X->s);
   if (coarsest) {
     T *r = P<T>(L.res_u);
@@ -548,17 +555,20 @@ void vcycle_p(stokes_ctx *X, int l, const T *rhs, T *phi) {
     launch_tail_p<T>(tail_levels<T>(X, l, rhs, phi, false), X->s);
     return;
   }
-  launch_fill<T>(phi, (T)0, L.g.ncell, X->s);
-  if (l == X->nlev - 1) {
+  const bool coarsest = l == X->nlev - 1;
+  // as for the velocity: the first sweep replaces the clearing pass
+  const bool zf = gs_first_ok(L.g) && (coarsest ? X->p.nu_coarse : X->p.nu_pre) > 0;
+  if (!zf) launch_fill<T>(phi, (T)0, L.g.ncell, X->s);
+  if (coarsest) {
     T *r = P<T>(L.res_p);
     launch_cast<T, T>(rhs, r, L.g.ncell, X->s);
     remove_mean<T>(X, r, L.g.ncell, 16);
-    for (int s = 0; s < X->p.nu_coarse; s++) sweep_p<T>(X, l, r, phi);
+    for (int s = 0; s < X->p.nu_coarse; s++) sweep_p<T>(X, l, r, phi, zf && s == 0);
     remove_mean<T>(X, phi, L.g.ncell, 17);
     return;
   }
   Level &C = X->lev[l + 1];
-  for (int s = 0; s < X->p.nu_pre; s++) sweep_p<T>(X, l, rhs, phi);
+  for (int s = 0; s < X->p.nu_pre; s++) sweep_p<T>(X, l, rhs, phi, zf && s == 0);
   launch_p_residual<T>(L.g, P<T>(L.beta), rhs, phi, P<T>(L.res_p), X->s);
   launch_cell_restrict<T>(L.g, C.g, P<T>(L.res_p), P<T>(C.rhs_p), X->s);
   vcycle_p<T>(X, l + 1, P<T>(C.rhs_p), P<T>(C.phi_p));

@@ -96,9 +96,10 @@ void launch_pack_walls(const Geo &g, const double *in, double scale, double *out
 // multigrid level kernels, T = float or double
 // (lam: bulk coefficient per cell or null, as for launch_apply_m)
 // first != 0: a pass of the first sweep from a zero iterate whose memory has
-// not been cleared (allowed when vel_gs_first_ok(g); the sweep writes every
-// face, the wall faces included, before any pass reads it)
-bool vel_gs_first_ok(const Geo &g);
+// not been cleared (allowed when gs_first_ok(g), i.e. every extent even so
+// that the colouring holds across periodic wraps; the sweep writes every
+// value, the velocity wall faces included, before any pass reads it)
+bool gs_first_ok(const Geo &g);
 template <typename T>
 void launch_vel_gs(const Geo &g, int k, int colour, int first, const T *alpha, const T *muc,
                    const T *mue, const T *lam, const T *rhs, T *phi, hipStream_t s);
@@ -109,8 +110,9 @@ template <typename T>
 void launch_face_restrict(const Geo &gf, const Geo &gc, const T *rf, T *rc, hipStream_t s);
 template <typename T>
 void launch_face_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *phif, hipStream_t s);
-template <typename T>
-void launch_p_gs(const Geo &g, int colour, const T *beta, const T *rhs, T *phi, hipStream_t s);
+template <typename T>  // first: as for launch_vel_gs
+void launch_p_gs(const Geo &g, int colour, int first, const T *beta, const T *rhs, T *phi,
+                 hipStream_t s);
 template <typename T>
 void launch_p_residual(const Geo &g, const T *beta, const T *rhs, const T *phi, T *res,
                        hipStream_t s);

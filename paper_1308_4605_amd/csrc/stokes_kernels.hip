@@ -1017,7 +1017,7 @@ __global__ void k_vel_gs(Geo g, int colour, const T *__restrict__ alpha,
   if (i[0] < g.n[0]) gs_point<T, DIM, Z>(g, K, i, alpha, muc, mue, lam, rhs, phi);
 }
 
-bool vel_gs_first_ok(const Geo &g) {
+bool gs_first_ok(const Geo &g) {
   // the colouring must hold across periodic wraps: every extent even
   for (int a = 0; a < g.d; a++)
     if (g.n[a] & 1) return false;
@@ -1457,11 +1457,14 @@ void launch_face_prolong_add(const Geo &gc, const Geo &gf, const T *ec, T *phif,
 // pressure multigrid: L_rho = D beta G with zero flux through walls
 // ------------------------------------------------------------------------
 
-template <typename T, int DIM>
+// Z (first red-black sweep from a zero iterate whose memory has not been
+// cleared): bit 0 reads the cell itself as zero, bit 1 its neighbours (the
+// other colour) as zero.
+template <typename T, int DIM, int Z = 0>
 __device__ __forceinline__ void p_row(const Geo &g, const int i[3], const T *__restrict__ beta,
                                       const T *__restrict__ p, T &Lp, T &diag) {
   const T ih = (T)g.ih;
-  const T pc = p[cidx3(g, i)];
+  const T pc = (Z & 1) ? (T)0 : p[cidx3(g, i)];
   T s = 0, dg = 0;
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
@@ -1474,10 +1477,10 @@ __device__ __forceinline__ void p_row(const Geo &g, const int i[3], const T *__r
     f[k] = wr ? i[k] : up1(g, k, i[k]);
     c[k] = f[k];
     const T br = beta[fidx3(g, k, f)];
-    const T pr = p[cidx3(g, c)];
+    const T pr = (Z & 2) ? (T)0 : p[cidx3(g, c)];
     c[k] = dn1(g, k, i[k]);
     const T bl = beta[fidx3(g, k, i)];
-    const T pl = p[cidx3(g, c)];
+    const T pl = (Z & 2) ? (T)0 : p[cidx3(g, c)];
     const T fr = wr ? (T)0 : br * ((pr - pc) * ih);
     const T fl = wl ? (T)0 : bl * ((pc - pl) * ih);
     dg -= (wr ? (T)0 : br) + (wl ? (T)0 : bl);
@@ -1487,31 +1490,44 @@ __device__ __forceinline__ void p_row(const Geo &g, const int i[3], const T *__r
   diag = dg * (ih * ih);
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, int Z = 0>
 __device__ __forceinline__ void p_gs_elem(const Geo &g, int colour, i64 t,
                                           const T *__restrict__ beta, const T *__restrict__ rhs,
                                           T *__restrict__ phi) {
   int i[3];
   if (!colour_cell(g, t, colour, i)) return;
   T Lp, dg;
-  p_row<T, DIM>(g, i, beta, phi, Lp, dg);
+  p_row<T, DIM, Z>(g, i, beta, phi, Lp, dg);
   const i64 c = cidx3(g, i);
-  phi[c] += (rhs[c] - Lp) / dg;
+  if (Z)
+    phi[c] = (T)0 + (rhs[c] - Lp) / dg;
+  else
+    phi[c] += (rhs[c] - Lp) / dg;
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, int Z>
 __global__ void k_p_gs(Geo g, int colour, const T *__restrict__ beta, const T *__restrict__ rhs,
                        T *__restrict__ phi) {
-  p_gs_elem<T, DIM>(g, colour, (i64)blockIdx.x * blockDim.x + threadIdx.x, beta, rhs, phi);
+  p_gs_elem<T, DIM, Z>(g, colour, (i64)blockIdx.x * blockDim.x + threadIdx.x, beta, rhs, phi);
 }
 
 template <typename T>
-void launch_p_gs(const Geo &g, int colour, const T *beta, const T *rhs, T *phi, hipStream_t s) {
+void launch_p_gs(const Geo &g, int colour, int first, const T *beta, const T *rhs, T *phi,
+                 hipStream_t s) {
   const unsigned nb = blocks_for(colour_threads(g));
-  if (g.d == 3)
-    hipLaunchKernelGGL((k_p_gs<T, 3>), dim3(nb), dim3(kBlock), 0, s, g, colour, beta, rhs, phi);
-  else
-    hipLaunchKernelGGL((k_p_gs<T, 2>), dim3(nb), dim3(kBlock), 0, s, g, colour, beta, rhs, phi);
+  const int z = first ? (colour == 0 ? 3 : 1) : 0;
+#define PGS(D, ZZ) \
+  hipLaunchKernelGGL((k_p_gs<T, D, ZZ>), dim3(nb), dim3(kBlock), 0, s, g, colour, beta, rhs, phi)
+  if (g.d == 3) {
+    if (z == 0) PGS(3, 0);
+    else if (z == 1) PGS(3, 1);
+    else PGS(3, 3);
+  } else {
+    if (z == 0) PGS(2, 0);
+    else if (z == 1) PGS(2, 1);
+    else PGS(2, 3);
+  }
+#undef PGS
 }
 
 template <typename T, int DIM>
@@ -2497,7 +2513,7 @@ void launch_grad_chain(const Geo &g, const double *dmu_edge, const double *mue_r
   template void launch_face_restrict<T>(const Geo &, const Geo &, const T *, T *, hipStream_t);  \
   template void launch_face_prolong_add<T>(const Geo &, const Geo &, const T *, T *,             \
                                            hipStream_t);                                         \
-  template void launch_p_gs<T>(const Geo &, int, const T *, const T *, T *, hipStream_t);        \
+  template void launch_p_gs<T>(const Geo &, int, int, const T *, const T *, T *, hipStream_t);   \
   template void launch_p_residual<T>(const Geo &, const T *, const T *, const T *, T *,          \
                                      hipStream_t);                                               \
   template void launch_cell_restrict<T>(const Geo &, const Geo &, const T *, T *, hipStream_t);  \

@@ -101,7 +101,12 @@ def _vcycle_bytes_model(dim, n, bc, theta, vel, s=8, nu=(2, 2, 8)):
                 nvc = levels[l + 1].nvel
                 b += 3 * nv + (nv if theta else 0) + nc + ne + nv + nvc + nvc + 2 * nv
         else:
-            b = nc + sweeps * 2 * (nv + 3 * nc)
+            zf = nc > 512 and all(x % 2 == 0 for x in dims[l]) and \
+                (nu[2] if coarsest else nu[0]) > 0
+            if zf:
+                b = (nv + 2 * nc) + (nv + 3 * nc) + (sweeps - 1) * 2 * (nv + 3 * nc)
+            else:
+                b = nc + sweeps * 2 * (nv + 3 * nc)
             if not coarsest:
                 ncc = levels[l + 1].ncell
                 b += nv + 3 * nc + nc + ncc + ncc + 2 * nc
