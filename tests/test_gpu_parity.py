@@ -274,3 +274,32 @@ def test_fp32_precond_parity_long_rows(dim, n, bc, theta, precond):
     assert rel(N(zp), op) <= 1e-4
     assert np.all(N(zu)[lay.wall_mask()] == 0.0)
     assert rel(N(g.vel_subsolve(T(bu))), o.vel_subsolve(bu)) <= 1e-4
+
+
+ODD_COARSE = [
+    # wall axes may coarsen to an odd extent; here the coarsest level (129 x 2 x 2 = 516 cells,
+    # 257 x 2 = 514 in 2D) is larger than the single-workgroup tail, so the grid kernels run on
+    # it and clear the iterate with a fill instead of starting the sweep from uncleared memory
+    (3, (516, 8, 8), (1, 0, 0), 0.0), (3, (516, 8, 8), (2, 1, 0), 10.0),
+    (2, (1028, 8), (3, 0), 0.0), (2, (1028, 8), (1, 1), 25.0),
+]
+
+
+@pytest.mark.parametrize("dim,n,bc,theta", ODD_COARSE)
+@pytest.mark.parametrize("precision", [W.FP64, W.MG_FP32])
+def test_precond_parity_odd_coarse_level(dim, n, bc, theta, precision):
+    """Preconditioner against the oracle on grids whose coarsest level has an odd extent and
+    runs outside the coarse tail (FP64 1e-11, FP32 multigrid 1e-4)."""
+    print(f"odd coarse {dim} {n} {bc} theta={theta} prec={precision}", flush=True)
+    kry = W.FGMRES if precision == W.MG_FP32 else W.GMRES_LEFT
+    p, lay = params(dim, n, bc, theta, precond=W.P1, precision=precision, krylov=kry)
+    rho, mu = _coefs(lay, 7)
+    g, o = pair(p, rho, mu)
+    bu = W.random_velocity(17, lay, remove_mean=lay.singular_components(theta))
+    bp = W.random_cells(18, lay, remove_mean=True)
+    zu, zp = g.precond(T(bu), T(bp))
+    ou, op = o.precond(bu, bp)
+    tol = 1e-11 if precision == W.FP64 else 1e-4
+    assert rel(N(zu), ou) <= tol
+    assert rel(N(zp), op) <= tol
+    assert np.all(N(zu)[lay.wall_mask()] == 0.0)
