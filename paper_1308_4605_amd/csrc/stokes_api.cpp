@@ -667,6 +667,20 @@ void neg_schur(stokes_ctx *X, const T *c, T *out) {
   }
 }
 
+// out = -S~^{-1}(sgn (D u + bp)): at theta = 0 the Schur approximation is
+// the cellwise scaling by -2 mu (or the bulk coefficient), applied in the
+// divergence pass itself
+template <typename T>
+void neg_schur_div(stokes_ctx *X, const T *u, const T *bp, T *out) {
+  const Geo &g = X->lev[0].g;
+  if (X->p.theta == 0.0) {
+    launch_div_scaled<T>(g, u, bp, (T)1, P<T>(X->sig), (T)-2, out, X->s);
+  } else {
+    launch_div<T>(g, u, bp, (T)1, P<T>(X->cv), X->s);
+    neg_schur<T>(X, P<T>(X->cv), out);
+  }
+}
+
 // z = P^{-1} b on the rescaled system (Sec. 2 block factorisations)
 template <typename T>
 void precond(stokes_ctx *X, const T *bu, const T *bp, T *zu, T *zp) {
@@ -686,8 +700,7 @@ void precond(stokes_ctx *X, const T *bu, const T *bp, T *zu, T *zp) {
     case STOKES_P2:
       // x_u = A~^{-1} b_u; x_p = -S~^{-1}(D x_u + b_p)
       vel_sub<T>(X, bu, zu);
-      launch_div<T>(g, zu, bp, (T)1, cv, X->s);
-      neg_schur<T>(X, cv, zp);
+      neg_schur_div<T>(X, zu, bp, zp);
       break;
     case STOKES_P3:
       // x_p = -S~^{-1} b_p; x_u = A~^{-1}(b_u - G x_p)
@@ -703,8 +716,7 @@ void precond(stokes_ctx *X, const T *bu, const T *bp, T *zu, T *zp) {
       // x* = A~^{-1} b_u; x_p = -S~^{-1}(D x* + b_p);
       // x_u = x* + A~^{-1}(b_u - G x_p - A x*)
       vel_sub<T>(X, bu, xs);
-      launch_div<T>(g, xs, bp, (T)1, cv, X->s);
-      neg_schur<T>(X, cv, zp);
+      neg_schur_div<T>(X, xs, bp, zp);
       launch_vel_residual<T>(g, alpha_of<T>(X, L), P<T>(L.muc), P<T>(L.mue), lam_of<T>(L), bu, xs,
                              zp, tu, X->s);
       vel_sub<T>(X, tu, eu);

@@ -152,6 +152,9 @@ void launch_tail_p(const TailLevels<T> &L, hipStream_t s);
 // preconditioner glue (level 0, precision T)
 template <typename T>  // out = sgn * (D u + bp)   (bp may be null)
 void launch_div(const Geo &g, const T *u, const T *bp, T sgn, T *out, hipStream_t s);
+template <typename T>  // out = b mu (sgn (D u + bp)): the divergence and a cellwise scaling
+void launch_div_scaled(const Geo &g, const T *u, const T *bp, T sgn, const T *mu, T b, T *out,
+                       hipStream_t s);
 template <typename T>  // zu = xs + beta * G q
 void launch_proj_update(const Geo &g, const T *xs, const T *beta, const T *q, T *zu, hipStream_t s);
 template <typename T>  // out = bu - G p

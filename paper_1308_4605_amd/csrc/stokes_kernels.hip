@@ -1864,11 +1864,10 @@ template void launch_tail_p<double>(const TailLevels<double> &, hipStream_t);
 
 template <typename T, int DIM>
 __global__ void k_div(Geo g, const T *__restrict__ u, const T *__restrict__ bp, T sgn,
-                      T *__restrict__ out) {
-  i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.ncell) return;
+                      const T *__restrict__ mu, T b, T *__restrict__ out) {
   int i[3];
-  cell_of(g, t, i);
+  if (!box_thread(g, g.n[0], i[0], i[1], i[2])) return;
+  const i64 t = cidx3(g, i);
   T s = 0;
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
@@ -1877,17 +1876,24 @@ __global__ void k_div(Geo g, const T *__restrict__ u, const T *__restrict__ bp, 
     s += (u[fidx3(g, k, r)] - u[fidx3(g, k, i)]) * (T)g.ih;
   }
   if (bp) s += bp[t];
-  out[t] = sgn * s;
+  const T c = sgn * s;
+  out[t] = mu ? b * mu[t] * c : c;
 }
 
 template <typename T>
 void launch_div(const Geo &g, const T *u, const T *bp, T sgn, T *out, hipStream_t s) {
+  launch_div_scaled<T>(g, u, bp, sgn, nullptr, (T)0, out, s);
+}
+
+template <typename T>
+void launch_div_scaled(const Geo &g, const T *u, const T *bp, T sgn, const T *mu, T b, T *out,
+                       hipStream_t s) {
   if (g.d == 3)
-    hipLaunchKernelGGL((k_div<T, 3>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, u, bp, sgn,
-                       out);
+    hipLaunchKernelGGL((k_div<T, 3>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g, u, bp, sgn,
+                       mu, b, out);
   else
-    hipLaunchKernelGGL((k_div<T, 2>), dim3(blocks_for(g.ncell)), dim3(kBlock), 0, s, g, u, bp, sgn,
-                       out);
+    hipLaunchKernelGGL((k_div<T, 2>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g, u, bp, sgn,
+                       mu, b, out);
 }
 
 // mode 0: zu = xs + beta * G q ; mode 1: out = bu - G q
@@ -2520,6 +2526,8 @@ void launch_grad_chain(const Geo &g, const double *dmu_edge, const double *mue_r
   template void launch_cell_prolong_add<T>(const Geo &, const Geo &, const T *, T *,             \
                                            hipStream_t);                                         \
   template void launch_div<T>(const Geo &, const T *, const T *, T, T *, hipStream_t);           \
+  template void launch_div_scaled<T>(const Geo &, const T *, const T *, T, const T *, T, T *,    \
+                                     hipStream_t);                                               \
   template void launch_proj_update<T>(const Geo &, const T *, const T *, const T *, T *,         \
                                       hipStream_t);                                              \
   template void launch_grad_sub<T>(const Geo &, const T *, const T *, T *, hipStream_t);         \
