@@ -114,10 +114,14 @@ def _vcycle_bytes_model(dim, n, bc, theta, vel, s=8, nu=(2, 2, 8)):
     return total
 
 
-def test_vcycle_timing_counts_and_bytes():
+@pytest.mark.parametrize("dim,n,bc", [
+    (3, (32, 32, 32), (1, 1, 1)),  # coarse tail below 16^3; first sweeps from uncleared memory
+    (3, (516, 8, 8), (1, 0, 0)),   # no tail; odd coarsest extent (129), which keeps the fill
+    (2, (256, 256), (0, 0)),       # periodic 2D, tail from 16^2
+])
+def test_vcycle_timing_counts_and_bytes(dim, n, bc):
     """The V-cycle timer counts one velocity and one pressure cycle per P1
     application and reports the bytes of the documented cycle model."""
-    dim, n, bc = 3, (32, 32, 32), (1, 1, 1)
     p, lay = params(dim, n, bc, 10.0, precond=W.P1)
     rho, mu = W.random_coefficients(98, lay)
     g, _ = pair(p, rho, mu)
