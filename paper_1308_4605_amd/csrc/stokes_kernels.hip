@@ -6,11 +6,12 @@
 // Conventions: cell-indexed launches cover the cells of a level; a thread at
 // cell (i0,i1,i2) handles the face of component k whose index is the same
 // triple (the face on the low side of the cell along k).  That visits every
-// face with index < n[k] along k; the high wall faces (index n[k] on a
-// no-slip axis) are never written, and internal vectors keep 0 there.  Low
-// wall faces (index 0 on a no-slip axis) are skipped.  All internal velocity
-// vectors therefore hold 0 on every wall face, which lets the stencils read
-// wall values without branches.
+// face with index < n[k] along k; the high wall faces (index n[k] on a wall
+// axis) are written only with 0 (by the first smoothing sweep from an
+// uncleared iterate), and the low wall faces (index 0) are skipped except
+// for that same zero write.  All internal velocity vectors therefore hold 0
+// on every wall face, which lets the stencils read wall values without
+// branches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -2120,7 +2121,8 @@ struct PtrPack {
 
 // ---- Arnoldi by classical Gram-Schmidt applied twice (CGS2) -------------
 // Three streaming passes over [w, v_0..v_j] with double2 loads, a fixed grid
-// and per-block partial sums (bitwise reproducible):
+// and per-block partial sums (bitwise reproducible); pass C without a norm to
+// reduce runs one double2 per thread instead:
 //   A: h1 = V^T w
 //   B: w' = w - V h1 formed on the fly (not stored): h2 = V^T w', s2 = (w', w')
 //   C: v_next = (w - V (h1 + h2)) * inv_nu, optionally also as FP32 (the
