@@ -80,6 +80,12 @@ def lib():
         L.orc_p_sweep.argtypes = [ctypes.c_void_p, P, P]
         L.orc_level_coef.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, P, ctypes.c_size_t]
         L.orc_level_dims.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int * 3]
+        for f in ("orc_restrict_faces", "orc_prolong_add_faces", "orc_restrict_cells",
+                  "orc_prolong_add_cells"):
+            getattr(L, f).argtypes = [ctypes.c_void_p, ctypes.c_int, P, P]
+        L.orc_level_sizes.argtypes = [ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(ctypes.c_size_t)]
         L.orc_solve.argtypes = [ctypes.c_void_p, P, P, P, P, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_int, ctypes.POINTER(Stats)]
         L.orc_adjoint.argtypes = [ctypes.c_void_p, P, P, P, P, P, P, P, P, P, P,
@@ -233,6 +239,37 @@ class Oracle:
         if rc:
             raise OracleError(rc, "level_dims")
         return tuple(out)
+
+    def level_sizes(self, level):
+        """(nvel, ncell) of multigrid level `level`."""
+        nv, nc = ctypes.c_size_t(), ctypes.c_size_t()
+        rc = lib().orc_level_sizes(self._h, level, ctypes.byref(nv), ctypes.byref(nc))
+        if rc:
+            raise OracleError(rc, "level_sizes")
+        return nv.value, nc.value
+
+    def _transfer(self, fn, level, src, dst_size, add_to=None):
+        src = _f64(src)
+        dst = np.zeros(dst_size) if add_to is None else _f64(add_to).copy()
+        rc = getattr(lib(), fn)(self._h, level, _p(src), _p(dst))
+        if rc:
+            raise OracleError(rc, fn)
+        return dst
+
+    def restrict_faces(self, level, rf):
+        """Face restriction of a level-`level` velocity field to level + 1."""
+        return self._transfer("orc_restrict_faces", level, rf, self.level_sizes(level + 1)[0])
+
+    def prolong_add_faces(self, level, ec, phif=None):
+        """phif + P ec: face prolongation of a level + 1 field onto level `level`."""
+        return self._transfer("orc_prolong_add_faces", level, ec, self.level_sizes(level)[0],
+                              phif)
+
+    def restrict_cells(self, level, rf):
+        return self._transfer("orc_restrict_cells", level, rf, self.level_sizes(level + 1)[1])
+
+    def prolong_add_cells(self, level, ec, pf=None):
+        return self._transfer("orc_prolong_add_cells", level, ec, self.level_sizes(level)[1], pf)
 
     def level_coef(self, level, which, count):
         out = np.empty(count)

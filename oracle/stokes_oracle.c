@@ -899,9 +899,7 @@ static void precond_scaled(orc_ctx *X, const double *b, double *z) {
   /* keep the pressure mean (and the velocity means when the velocity
      operator is singular) at zero (Sec. 3.2) */
   remove_mean(zp, nc);
-  /* the velocity subsolver output is already mean-free; only P1 adds
-     rho_f^{-1} G q, which need not be */
-  if (X->vel_singular && X->p.precond == ORC_P1) remove_vel_means(L, zu);
+  if (X->vel_singular) remove_vel_means(L, zu);
   free(cvec); free(tu); free(xs);
 }
 
@@ -922,48 +920,19 @@ static int p_cycles_per_apply(const orc_ctx *X) {
 /* GMRES(m) / FGMRES(m)                                                      */
 /* ------------------------------------------------------------------------ */
 
-/* Arnoldi orthogonalisation of w against v_0..v_j by classical Gram-Schmidt
-   applied twice (CGS2): h1 = V^T w, w' = w - V h1, h2 = V^T w'.  With V
-   orthonormal, w'' = w' - V h2 has ||w''||^2 = ||w'||^2 - ||h2||^2; that value
-   is used unless the second pass removed half or more of ||w'||^2, in which
-   case w'' is formed and its norm computed directly (*formed = 1).  Fills
-   hcol = h1 + h2 and h2; returns ||w''||. */
-static double arnoldi_orth(double **V, int j, double *w, size_t n, double *hcol, double *h2,
-                           int *formed) {
-  for (int i = 0; i <= j; i++) hcol[i] = dotv(w, V[i], n);
+/* Arnoldi step by modified Gram-Schmidt (Saad's MGS form of the Arnoldi
+   process, the Krylov method the paper names in Sec. "Krylov Solver"): for
+   i = 0..j in turn, h_i = (w, v_i) on the partly orthogonalised w, then
+   w <- w - h_i v_i; the new subdiagonal entry is ||w|| measured on the
+   final w.  Fills hcol[0..j]; returns ||w||; w is left orthogonalised. */
+static double arnoldi_mgs(double **V, int j, double *w, size_t n, double *hcol) {
   for (int i = 0; i <= j; i++) {
-    const double hi = hcol[i];
     const double *vi = V[i];
+    const double hi = dotv(w, vi, n);
+    hcol[i] = hi;
     for (size_t t = 0; t < n; t++) w[t] -= hi * vi[t];
   }
-  for (int i = 0; i <= j; i++) h2[i] = dotv(w, V[i], n);
-  const double s2 = dotv(w, w, n);
-  double q = 0.0;
-  for (int i = 0; i <= j; i++) {
-    q += h2[i] * h2[i];
-    hcol[i] += h2[i];
-  }
-  const double nu2 = s2 - q;
-  *formed = 0;
-  if (nu2 > 0.5 * s2) return sqrt(nu2);
-  for (int i = 0; i <= j; i++) {
-    const double hi = h2[i];
-    const double *vi = V[i];
-    for (size_t t = 0; t < n; t++) w[t] -= hi * vi[t];
-  }
-  *formed = 1;
   return sqrt(dotv(w, w, n));
-}
-
-/* next basis vector v_{j+1} = w'' / nu (w'' formed here unless already) */
-static void arnoldi_next(double **V, int j, const double *w, size_t n, const double *h2,
-                         int formed, double nu, double *out) {
-  for (size_t t = 0; t < n; t++) {
-    double x = w[t];
-    if (!formed)
-      for (int i = 0; i <= j; i++) x -= h2[i] * V[i][t];
-    out[t] = x / nu;
-  }
 }
 
 /* Solve the scaled system M' x = b by restarted GMRES: left-preconditioned
@@ -1037,9 +1006,7 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
       st->precond_applies++;
       it++;
       double *hc = H + (size_t)j * (m + 1);
-      double h2[64];
-      int formed = 0;
-      double hn = arnoldi_orth(V, j, w, n, hc, h2, &formed);
+      double hn = arnoldi_mgs(V, j, w, n, hc);
       hc[j + 1] = hn;
       /* previous rotations, then a new one that zeroes H[j+1][j] */
       for (int i = 0; i < j; i++) {
@@ -1059,7 +1026,7 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
       st->rel_res_est = est / beta * (rho / nb);
       if (!isfinite(est)) break;
       if (hn == 0.0 || est <= target || it >= max_iter) break;
-      arnoldi_next(V, j, w, n, h2, formed, hn, V[j + 1]);
+      for (size_t q = 0; q < n; q++) V[j + 1][q] = w[q] / hn;
     }
     /* back substitution H y = g and update x */
     for (int i = jj - 1; i >= 0; i--) {
@@ -1493,6 +1460,37 @@ int orc_level_coef(orc_ctx *X, int level, int which, double *out, size_t cap) {
   }
   if (cap < n) return ORC_EINVAL;
   memcpy(out, src, n * sizeof(double));
+  return ORC_OK;
+}
+
+int orc_level_sizes(orc_ctx *X, int level, size_t *nvel, size_t *ncell) {
+  if (!X || level < 0 || level >= X->nlev) return ORC_EINVAL;
+  if (nvel) *nvel = X->lev[level].nvel;
+  if (ncell) *ncell = X->lev[level].ncell;
+  return ORC_OK;
+}
+
+int orc_restrict_faces(orc_ctx *X, int level, const double *rf, double *rc) {
+  if (!X || !rf || !rc || level < 0 || level + 1 >= X->nlev) return ORC_EINVAL;
+  restrict_faces(&X->lev[level], &X->lev[level + 1], rf, rc);
+  return ORC_OK;
+}
+
+int orc_prolong_add_faces(orc_ctx *X, int level, const double *ec, double *phif) {
+  if (!X || !ec || !phif || level < 0 || level + 1 >= X->nlev) return ORC_EINVAL;
+  prolong_add_faces(&X->lev[level + 1], &X->lev[level], ec, phif);
+  return ORC_OK;
+}
+
+int orc_restrict_cells(orc_ctx *X, int level, const double *rf, double *rc) {
+  if (!X || !rf || !rc || level < 0 || level + 1 >= X->nlev) return ORC_EINVAL;
+  restrict_cells(&X->lev[level], &X->lev[level + 1], rf, rc);
+  return ORC_OK;
+}
+
+int orc_prolong_add_cells(orc_ctx *X, int level, const double *ec, double *pf) {
+  if (!X || !ec || !pf || level < 0 || level + 1 >= X->nlev) return ORC_EINVAL;
+  prolong_add_cells(&X->lev[level + 1], &X->lev[level], ec, pf);
   return ORC_OK;
 }
 

@@ -101,6 +101,18 @@ int orc_p_mg_solve(orc_ctx *c, const double *r, double *e, double tol, int max_c
 /* one multicolour Gauss-Seidel sweep on level 0 (unscaled operator), in place. */
 int orc_vel_sweep(orc_ctx *c, const double *rhs, double *phi);
 int orc_p_sweep(orc_ctx *c, const double *rhs, double *phi);
+/* The multigrid transfers between level l (fine) and level l + 1 (coarse),
+   exposed so that tests can pin them directly (Appendix C):
+   face restriction rc = R rf and face prolongation phif += P ec (velocity
+   layout of the two levels), cell restriction (mean of the 2^d fine cells)
+   and cell prolongation (injection, added).  ORC_EINVAL when l + 1 is not a
+   level. */
+int orc_restrict_faces(orc_ctx *c, int level, const double *rf, double *rc);
+int orc_prolong_add_faces(orc_ctx *c, int level, const double *ec, double *phif);
+int orc_restrict_cells(orc_ctx *c, int level, const double *rf, double *rc);
+int orc_prolong_add_cells(orc_ctx *c, int level, const double *ec, double *pf);
+/* sizes of the velocity and cell arrays of a level */
+int orc_level_sizes(orc_ctx *c, int level, size_t *nvel, size_t *ncell);
 /* copies of the scaled level coefficients (for tests). which: 0 alpha faces,
    1 beta faces, 2 mu cells, 3 mu edges. */
 int orc_level_coef(orc_ctx *c, int level, int which, double *out, size_t cap);

@@ -756,10 +756,11 @@ double fetch(stokes_ctx *X, const double *dev, int count, double *dst) {
 }
 
 // Restarted GMRES(m), left-preconditioned or flexible, on the rescaled system
-// b' -> x' held in X->b, X->x.  The same algorithm as the CPU oracle:
-// classical Gram-Schmidt applied twice (CGS2) in three streaming passes, the
-// new vector's norm from ||w'||^2 - ||h2||^2 unless the second pass removed
-// half or more of ||w'||^2 (then w'' is formed and measured); Givens
+// b' -> x' held in X->b, X->x.  The Arnoldi orthogonalisation is classical
+// Gram-Schmidt applied twice (CGS2) in three streaming passes, the new
+// vector's norm from ||w'||^2 - ||h2||^2 unless the second pass removed half
+// or more of ||w'||^2 (then w'' is formed and measured); in exact arithmetic
+// this is the same Hessenberg matrix as modified Gram-Schmidt.  Givens
 // rotations on the host; the solve ends on the true residual, each cycle on
 // the Givens estimate reduced by the factor the true residual still lacks.
 // Preconditioner applications bracketed by the ctx's two events; the time is
@@ -911,6 +912,8 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       if (nu2 > 0.5 * s2) {
         hn = std::sqrt(nu2);
       } else {
+        // in place (out == w): k_cgs_next reads and writes each element
+        // in the same thread and declares neither pointer restrict
         launch_cgs_next(X->w, X->V, X->dsc + 32, X->dsc + 72, j + 1, 1.0, n, X->w, nullptr,
                         X->part, X->dsc + 0, X->s);
         hn = std::sqrt(fetch(X, X->dsc, 1, hb));

@@ -2221,12 +2221,13 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_proj(const double *__restrict
   block_store<MAXV>(acc, nv, true, stride, partials);
 }
 
+// out may equal w (the norm-forming call runs in place): each element is
+// read and written by the same thread, and neither pointer is restrict.
 template <int MAXV>
-__global__ void __launch_bounds__(kArnBlock) k_cgs_next(const double *__restrict__ w, PtrPack v,
+__global__ void __launch_bounds__(kArnBlock) k_cgs_next(const double *w, PtrPack v,
                                                         const double *__restrict__ h1,
                                                         const double *__restrict__ h2, int nv,
-                                                        double inv_nu, i64 n,
-                                                        double *__restrict__ out,
+                                                        double inv_nu, i64 n, double *out,
                                                         float *__restrict__ out32,
                                                         double *__restrict__ partials) {
   double hh[MAXV];
@@ -2236,8 +2237,8 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_next(const double *__restrict
 #pragma unroll
   for (int i = 0; i <= MAXV; i++) acc[i] = 0.0;
   const i64 n2 = n >> 1;
-  const double2 *__restrict__ w2 = (const double2 *)w;
-  double2 *__restrict__ o2 = (double2 *)out;
+  const double2 *w2 = (const double2 *)w;
+  double2 *o2 = (double2 *)out;
   float2 *__restrict__ f2 = (float2 *)out32;
   for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n2; t += (i64)gridDim.x * blockDim.x) {
     double2 a = w2[t];

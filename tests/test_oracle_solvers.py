@@ -244,12 +244,17 @@ def _vcycle_reduction(o, lay, r, cycles, op, sub):
     return out
 
 
-# per-cycle contraction bounds: the paper states at least one order of
-# magnitude per V-cycle and about a dozen cycles to near roundoff (Sec. 4.1.1,
-# read off its figure for 512^2 and 128^3).  The 2D rate measured here is
-# <= 0.1; the 3D rate (tensor-product readings of the 12-point restriction and
-# the 3D prolongation) settles at about 0.14, so 3D is held to 0.15 per cycle
-# and both to 1e-10 after 12 cycles.
+# Per-cycle contraction bounds.  The paper states at least one order of
+# magnitude per V-cycle and about a dozen cycles to near roundoff (subsection
+# "The effect of the number of smoothing sweeps", read off its figure for
+# 512^2 and 128^3).  The paper pin here is the dozen cycles: both dimensions
+# must reach 1e-10 after 12 cycles.  The per-cycle bounds are regression
+# bounds measured on this oracle, not paper values: 2D stays <= 0.1; 3D
+# starts near 0.03 and settles at about 0.14 (geometric mean over 12 cycles
+# 0.11).  The transfers themselves are pinned directly in
+# test_oracle_transfers.py; the alternatives tried for 3D (full-weighting
+# tangential restriction, reversed colour order after coarse correction) both
+# contract more slowly (0.19 and 0.22), so the tensor readings stand.
 RATE = {2: 0.105, 3: 0.15}
 
 
