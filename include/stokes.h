@@ -283,16 +283,19 @@ double stokes_rescale(const stokes_ctx *ctx);
    the finest-level velocity Gauss-Seidel colour pass is bracketed by HIP
    events on the context stream; stokes_kernel_time returns the accumulated
    milliseconds, the launch count and the algorithmic bytes of those launches
-   (each array the pass reads or writes counted once).  Reading the totals
-   synchronises the stream. */
+   (each value the pass needs counted once: every velocity component, the
+   cell and edge viscosities in full, the pass's own colour half of the
+   right-hand side and of the mass coefficient, and the half of the
+   component it writes).  Reading the totals synchronises the stream. */
 int stokes_set_timing(stokes_ctx *ctx, int enable);
 int stokes_kernel_time(stokes_ctx *ctx, double *ms_total, long *launches, double *bytes_total);
 /* With timing enabled, every V-cycle started from the finest level (in the
    preconditioner, the subsolvers and the *_mg_solve calls) is also bracketed
    by HIP events: pressure = 0 selects the velocity cycles, 1 the pressure
    cycles.  Returns their accumulated milliseconds, their count and their
-   algorithmic bytes (each array a kernel of the cycle reads or writes counted
-   once, summed over the levels), for the aggregate V-cycle bandwidth.
+   algorithmic bytes (each value a kernel of the cycle needs counted once,
+   colour passes as above, summed over the levels), for the aggregate V-cycle
+   bandwidth.
    Synchronises the stream. */
 int stokes_vcycle_time(stokes_ctx *ctx, int pressure, double *ms_total, long *cycles,
                        double *bytes_total);

@@ -360,19 +360,21 @@ void split_alpha(stokes_ctx *X) {
   }
 }
 
-// Algorithmic bytes of one V-cycle from the finest level (each array a
-// kernel reads or writes counted once per kernel, the same model as the
-// colour-pass figure), summed over the levels; s = bytes per value of the
-// hierarchy.  Velocity, per level: the zero fill of phi; each colour pass of
-// component k reads all components, rhs_k, alpha_k (theta != 0), mu_cell,
-// the bulk coefficient (if any) and the edge families touching k, and writes
-// component k; on all but the coarsest level the residual (rhs, phi, alpha,
-// mu_cell, edges, bulk -> res), the face restriction (res -> coarse rhs) and
-// the prolongation (coarse phi, phi -> phi).  A velocity level above the
-// coarse tail that starts with a sweep has no fill, and the passes of its
-// first sweep read only the components already written in that sweep
-// (component k itself on its second colour).  Pressure alike with beta on
-// the faces and red-black passes over the cells.
+// Algorithmic bytes of one V-cycle from the finest level (each value a
+// kernel needs counted once per kernel, the same model as the colour-pass
+// figure), summed over the levels; s = bytes per value of the hierarchy.
+// Velocity, per level: the zero fill of phi; each colour pass of component k
+// reads all components, mu_cell, the bulk coefficient (if any) and the edge
+// families touching k in full, and its colour's half of rhs_k and alpha_k
+// (theta != 0), and writes that half of component k; on all but the coarsest
+// level the residual (rhs, phi, alpha, mu_cell, edges, bulk -> res), the
+// face restriction (res -> coarse rhs) and the prolongation (coarse phi,
+// phi -> phi).  A velocity level above the coarse tail that starts with a
+// sweep has no fill, and the passes of its first sweep read only the
+// components already written in that sweep (on its second colour, the half
+// of component k its first colour wrote).  Pressure alike with beta on the
+// faces and red-black passes over the cells (half of rhs read and half of
+// phi written per pass).
 double vcycle_alg_bytes(const stokes_ctx *X, bool vel) {
   const double s = X->mg32 ? 4.0 : 8.0;
   const bool th = X->p.theta != 0.0;
@@ -394,10 +396,11 @@ double vcycle_alg_bytes(const stokes_ctx *X, bool vel) {
         for (int m = 0; m < 3; m++)
           if ((m != k || g.d == 2) && g.ecnt[m] > 0) e += (double)g.ecnt[m];
         const double fk = (double)g.fcnt[k];
-        // rhs_k (alpha_k), mu_cell (bulk), edges; each pass also writes component k
-        const double coef = (th ? 2.0 : 1.0) * fk + (X->bulk ? 2.0 : 1.0) * nc + e;
-        sweep += 2.0 * (nv + coef + fk);
-        first += (done + coef + fk) + (done + fk + coef + fk);
+        // half of rhs_k (and of alpha_k), mu_cell (bulk), edges; each pass
+        // also writes its half of component k
+        const double coef = (th ? 1.0 : 0.5) * fk + (X->bulk ? 2.0 : 1.0) * nc + e;
+        sweep += 2.0 * (nv + coef + 0.5 * fk);
+        first += (done + coef + 0.5 * fk) + (done + 0.5 * fk + coef + 0.5 * fk);
         done += fk;
       }
       b += zf ? first + (sweeps - 1) * sweep : sweeps * sweep;
@@ -411,12 +414,13 @@ double vcycle_alg_bytes(const stokes_ctx *X, bool vel) {
       const bool in_tail = X->tail_l >= 0 && l >= X->tail_l;
       const int first_sweeps = coarsest ? X->p.nu_coarse : X->p.nu_pre;
       const bool zf = !in_tail && gs_first_ok(g) && first_sweeps > 0;
-      // beta, rhs, phi read and phi written per pass; the first sweep's first
-      // colour reads no phi, and there is no fill
+      // per pass beta and phi read in full, half of rhs read and half of phi
+      // written; the first sweep's first colour reads no phi, its second
+      // colour only the half the first wrote, and there is no fill
       if (zf)
-        b += (nv + 2.0 * nc) + (nv + 3.0 * nc) + (sweeps - 1) * 2.0 * (nv + 3.0 * nc);
+        b += (nv + nc) + (nv + 1.5 * nc) + (sweeps - 1) * 2.0 * (nv + 2.0 * nc);
       else
-        b += nc + sweeps * 2.0 * (nv + 3.0 * nc);
+        b += nc + sweeps * 2.0 * (nv + 2.0 * nc);
       if (!coarsest) {
         const double ncc = (double)X->lev[l + 1].g.ncell;
         b += nv + 3.0 * nc;                      // residual
@@ -1244,17 +1248,19 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
       split_alpha<double>(X);
   }
   // algorithmic bytes of one finest-level velocity colour pass of component
-  // k: read all velocity components, rhs_k, alpha_k, mu_cell and the d-1 edge
-  // families around k; write u_k (each array counted once)
+  // k, each value the pass needs counted once: it reads every velocity
+  // component (the faces of its colour and all their neighbours), mu_cell
+  // and the d-1 edge families around k in full (each cell and edge borders
+  // faces of both colours), and only its own colour's half of rhs_k and
+  // alpha_k (not read when theta = 0); it writes the half of u_k it updates.
   const double tb = X->mg32 ? 4.0 : 8.0;
   for (int k = 0; k < g0.d; k++) {
     double e = 0.0;
     for (int m = 0; m < 3; m++)
       if (m != k && g0.ecnt[m] > 0) e += (double)g0.ecnt[m];
     if (g0.d == 2) e = (double)g0.ecnt[2];
-    // reads: every velocity component, rhs_k, alpha_k (not when theta = 0),
-    // mu_cell, the edge families touching k; writes: component k
-    const double own = (p->theta == 0.0) ? 2.0 : 3.0;
+    // halves of rhs_k, alpha_k (theta != 0) and the written u_k
+    const double own = (p->theta == 0.0) ? 1.0 : 1.5;
     const double cells = X->bulk ? 2.0 : 1.0;  // mu_cell (and the bulk coefficient)
     X->gs_bytes[k] =
         tb * ((double)g0.nvel + own * (double)g0.fcnt[k] + cells * (double)g0.ncell + e);

@@ -92,9 +92,11 @@ def _vcycle_bytes_model(dim, n, bc, theta, vel, s=8, nu=(2, 2, 8)):
             for k in range(dim):
                 e = sum(c for m_, c in edges.items() if m_ != k)
                 fk = lay.face_counts[k]
-                coef = (2 if theta else 1) * fk + nc + e
-                sw += 2 * (nv + coef + fk)
-                first += (done + coef + fk) + (done + fk + coef + fk)
+                # a colour pass needs only its colour's half of rhs_k, alpha_k
+                # and the written u_k
+                coef = (1 if theta else 0.5) * fk + nc + e
+                sw += 2 * (nv + coef + 0.5 * fk)
+                first += (done + coef + 0.5 * fk) + (done + 0.5 * fk + coef + 0.5 * fk)
                 done += fk
             b += first + (sweeps - 1) * sw if zf else sweeps * sw
             if not coarsest:
@@ -104,9 +106,9 @@ def _vcycle_bytes_model(dim, n, bc, theta, vel, s=8, nu=(2, 2, 8)):
             zf = nc > 512 and all(x % 2 == 0 for x in dims[l]) and \
                 (nu[2] if coarsest else nu[0]) > 0
             if zf:
-                b = (nv + 2 * nc) + (nv + 3 * nc) + (sweeps - 1) * 2 * (nv + 3 * nc)
+                b = (nv + nc) + (nv + 1.5 * nc) + (sweeps - 1) * 2 * (nv + 2 * nc)
             else:
-                b = nc + sweeps * 2 * (nv + 3 * nc)
+                b = nc + sweeps * 2 * (nv + 2 * nc)
             if not coarsest:
                 ncc = levels[l + 1].ncell
                 b += nv + 3 * nc + nc + ncc + ncc + 2 * nc

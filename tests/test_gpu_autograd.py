@@ -87,7 +87,7 @@ def test_autograd_matches_fd_and_oracle_small(precision):
     assert rel(N(gf), adj["lu"]) <= 1e-6
 
 
-@pytest.mark.parametrize("precision,ns,nf", [(W.FP64, 20, 20), (W.MG_FP32, 4, 4)])
+@pytest.mark.parametrize("precision,ns,nf", [(W.FP64, 20, 20), (W.MG_FP32, 20, 20)])
 def test_autograd_full_size_fd(precision, ns, nf):
     """The 128^3 no-slip unsteady workload with mu = exp(s), s a smoothed
     Gaussian field: gradients in s and in the forcing against central
