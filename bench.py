@@ -17,7 +17,11 @@ The JSON line also carries
     their time, from HIP events on the solver's stream;
   - cpu_baseline: the FP64 CPU oracle on a bounded sample of the same
     workload (one Arnoldi step), scaled to solves/s with the iteration count
-    of the FP64 solve.
+    of the FP64 solve, plus fully measured oracle solves (the 2D periodic
+    32^2 workload, median of 3 on all threads and on one thread, and the
+    headline coefficients at 32^3) and the CPU model;
+  - oracle_parity: the GPU solutions' error against the oracle's FP64
+    solution on those measured inputs.
 """
 from __future__ import annotations
 
@@ -118,6 +122,80 @@ def _split_baseline(torch, dev, Stokes, params, rho, mu, bu, bp, tol, coupled_sv
            "rel_res": [qv, qp], "converged": rcv == 0 and rcp == 0,
            "coupled_scalar_vcycles": coupled_sv, "coupled_over_split": coupled_sv / sv}
     _log(f"split baseline: {out}")
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_measured(torch, dev, W, Stokes, tol):
+    """Fully measured oracle solves (not extrapolated), with the GPU forms
+    compared against the oracle's FP64 solution on the same inputs:
+      - the 2D periodic 32^2 workload (P1, left GMRES): median of 3 oracle
+        solves on all threads and on one thread, and the GPU solve beside it;
+      - the headline workload's coefficients (contrast 1e6, P2, FGMRES) at
+        32^3: one oracle solve, and the FP32-multigrid and FP64 GPU solves'
+        error against it."""
+    import oracle
+
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    rel = lambda a, b: float(np.linalg.norm(a.cpu().numpy() - b) / np.linalg.norm(b))
+    nthreads = oracle.threads()
+    out = {"cores": nthreads, "cpu_model": _cpu_model()}
+
+    w1 = W.periodic_smooth_2d(n=32)
+    o1 = oracle.Oracle.from_workload(w1)
+
+    def med3():
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            ou, op, ost, _ = o1.solve(w1.bu, w1.bp, tol=tol)
+            ts.append(time.perf_counter() - t)
+        return sorted(ts)[1], ou, op, ost
+
+    t_all, ou1, op1, ost1 = med3()
+    oracle.set_threads(1)
+    t_one, _, _, _ = med3()
+    oracle.set_threads(nthreads)
+    S1 = Stokes(w1.params(), T(w1.rho), T(w1.mu))
+    S1.solve(T(w1.bu), T(w1.bp), tol=tol)
+    gts = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        xu, xp, st1, _ = S1.solve(T(w1.bu), T(w1.bp), tol=tol)
+        torch.cuda.synchronize()
+        gts.append(time.perf_counter() - t)
+    S1.close()
+    out["2d-periodic-smooth-32"] = {
+        "oracle_s_median_of_3": t_all, "oracle_s_1_thread_median_of_3": t_one,
+        "oracle_iters": ost1["iters"], "gpu_s_median_of_5": sorted(gts)[2],
+        "gpu_iters": st1["iters"], "gpu_rel_err_u": rel(xu, ou1), "gpu_rel_err_p": rel(xp, op1)}
+
+    w4 = W.contrast_periodic_3d(n=32, precision=W.FP64)
+    p4 = w4.params(precision=W.FP64, krylov=W.FGMRES)
+    o4 = oracle.Oracle(rho=w4.rho, mu=w4.mu, **p4)
+    t = time.perf_counter()
+    ou, op, ost, _ = o4.solve(w4.bu, w4.bp, tol=tol, max_iter=3000)
+    t4 = time.perf_counter() - t
+    del o4
+    rec = {"oracle_s": t4, "oracle_iters": ost["iters"]}
+    for name, prec in (("fp32mg", W.MG_FP32), ("fp64", W.FP64)):
+        S = Stokes(dict(p4, precision=prec), T(w4.rho), T(w4.mu))
+        xu, xp, st, _ = S.solve(T(w4.bu), T(w4.bp), tol=tol, max_iter=3000)
+        rec[name] = {"iters": st["iters"], "rel_err_u": rel(xu, ou), "rel_err_p": rel(xp, op)}
+        S.close()
+    out["3d-periodic-contrast-32"] = rec
+    _log(f"oracle measured: {out}")
     return out
 
 
@@ -244,6 +322,10 @@ def main():
                          f"the {iters_ref} iterations of the FP64 solve"}
         _log(f"CPU oracle: {t_cpu:.1f}s for {k_it} iteration(s) on {cpu['cores']} threads")
         del o
+        # fully measured oracle solves beside the extrapolation, and the GPU
+        # forms' error against the oracle on those inputs
+        cpu["measured"] = _oracle_measured(torch, dev, W, Stokes, args.tol)
+        cpu["cpu_model"] = cpu["measured"]["cpu_model"]
 
     # device copy ceiling: a plain 1 GiB read + 1 GiB write on the same GPU
     a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -292,6 +374,13 @@ def main():
         "split_baseline": split,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
+        "oracle_parity": None if cpu is None else {
+            "note": "GPU solutions against the FP64 oracle's solution on the same inputs "
+                    "(relative 2-norm error), from cpu_baseline.measured",
+            "3d-periodic-contrast-32": cpu["measured"]["3d-periodic-contrast-32"],
+            "2d-periodic-smooth-32": {k: cpu["measured"]["2d-periodic-smooth-32"][k]
+                                      for k in ("gpu_iters", "oracle_iters", "gpu_rel_err_u",
+                                                "gpu_rel_err_p")}},
     }
     print(json.dumps(line), flush=True)
     if args.calib_copy:

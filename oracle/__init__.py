@@ -92,6 +92,7 @@ def lib():
                                   ctypes.c_double, ctypes.c_int, ctypes.POINTER(Stats)]
         L.orc_grad.argtypes = [ctypes.c_void_p, P, P, P, P, P, P]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -323,3 +324,8 @@ class Oracle:
 
 def threads() -> int:
     return lib().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP grid loops from now on."""
+    lib().orc_set_threads(int(n))

@@ -1225,6 +1225,14 @@ int orc_threads(void) {
 #endif
 }
 
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int orc_create(const orc_params *p, const double *rho, const double *mu,
                const double *edges_given, const double *gamma, orc_ctx **out) {
   if (!p || !out || !rho || !mu) return ORC_EINVAL;

@@ -132,6 +132,8 @@ int orc_adjoint(orc_ctx *c, const double *xu, const double *xp,
 int orc_grad(orc_ctx *c, const double *xu, const double *lu,
              double *dmu_cell, double *dmu_edge, double *drho_cell, double *dgamma_cell);
 int orc_threads(void);
+/* threads of the OpenMP grid loops from now on (timing of the CPU baseline) */
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }
