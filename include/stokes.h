@@ -240,6 +240,29 @@ int stokes_p_mg_solve(stokes_ctx *ctx, const double *r, double *e, double tol, i
 int stokes_solve(stokes_ctx *ctx, const double *bu, const double *bp, double *xu, double *xp,
                  double tol, int max_iter, int use_x0, stokes_stats *stats);
 
+/* For callers that cannot allocate device memory (code that runs under HIP
+   graph capture, tight serving loops, harnesses that forbid allocation):
+   the same solve as stokes_solve, with the same arguments, results and
+   status codes, whose Krylov storage -- the restart basis V (restart + 1
+   FP64 vectors of nvel + ncell entries), for STOKES_FGMRES the stored
+   preconditioned vectors Z (restart vectors in the preconditioner's
+   precision), five FP64 work vectors (right-hand side, iterate, residual,
+   two temporaries) and the reduction partials -- lives in a static device
+   array of the library instead of the context's workspace.  The array holds
+   STOKES_STATIC_SCRATCH_BYTES bytes per GPU, from the first call on that GPU
+   until the process ends.  The call allocates nothing (no hipMalloc, no
+   allocating library routine); the multigrid hierarchy, the coefficients and
+   the preconditioner temporaries stay in the context's workspace.
+   Returns STOKES_ENOMEM before any launch when the storage above exceeds the
+   array (e.g. about 68^3 cells for FP64 FGMRES(10)), STOKES_EDEVICE when the
+   array's device address cannot be obtained.  Every call on one GPU shares
+   that GPU's array and clears the part it uses when it starts; calls that
+   overlap on one GPU (from any contexts, streams or threads) race.
+   Synchronous. */
+#define STOKES_STATIC_SCRATCH_BYTES (256u << 20)
+int stokes_solve_static(stokes_ctx *ctx, const double *bu, const double *bp, double *xu,
+                        double *xp, double tol, int max_iter, int use_x0, stokes_stats *stats);
+
 /* Adjoint: with x the forward solution and g = dL/dx = (g_u, g_p), solve
    M^T lambda = g (M = M^T, Sec. 2) with the same preconditioner and a fresh
    Krylov space, then contract forward and adjoint strain rates:

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -92,6 +93,7 @@ bool valid_params(const stokes_params *p, int *nlev_out) {
 struct stokes_ctx {
   stokes_params p;
   hipStream_t s = nullptr;
+  int dev = 0;  // HIP device current at creation (the stream's device)
   int d = 0, nlev = 0;
   int mg32 = 0;
   int vel_singular = 0;  // bit k: velocity component k has a constant null space
@@ -151,7 +153,36 @@ struct stokes_ctx {
   int err = 0;
 };
 
+// Storage of stokes_solve_static: a static device array of the library, one
+// copy per GPU that runs it, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host the name is only a
+// stand-in); it uses the device address hipGetSymbolAddress returns for the
+// current device, looked up once per device and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)STOKES_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on device dev (nullptr on a HIP error)
+void *scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return nullptr;
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != dev) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
 
 constexpr int kDscSlots = 256;  // device scalar slots
 
@@ -1080,6 +1111,80 @@ int mg_solve(stokes_ctx *X, bool vel, double tol, int max_cycles, int *cycles, d
   return (q <= tol) ? STOKES_OK : STOKES_ENOCONV;
 }
 
+
+// ---------------- static scratch (stokes_solve_static) ----------------
+// The Krylov storage of a solve (right-hand side, iterate, residual, work
+// vectors, the restart basis V and, for FGMRES, Z) and the reduction
+// partials, which stokes_solve keeps in the context's workspace.
+struct KrylovStore {
+  double *V[kMaxRestart + 1];
+  void *Z[kMaxRestart];
+  double *r, *w, *t, *x, *b, *part, *dsc;
+};
+
+KrylovStore krylov_store(const stokes_ctx *X) {
+  KrylovStore k;
+  for (int i = 0; i <= kMaxRestart; i++) k.V[i] = X->V[i];
+  for (int i = 0; i < kMaxRestart; i++) k.Z[i] = X->Z[i];
+  k.r = X->r; k.w = X->w; k.t = X->t; k.x = X->x; k.b = X->b;
+  k.part = X->part; k.dsc = X->dsc;
+  return k;
+}
+
+void set_krylov_store(stokes_ctx *X, const KrylovStore &k) {
+  for (int i = 0; i <= kMaxRestart; i++) X->V[i] = k.V[i];
+  for (int i = 0; i < kMaxRestart; i++) X->Z[i] = k.Z[i];
+  X->r = k.r; X->w = k.w; X->t = k.t; X->x = k.x; X->b = k.b;
+  X->part = k.part; X->dsc = k.dsc;
+}
+
+// carve the Krylov storage from cv and point the context at it (cv over a
+// null base only measures)
+void carve_krylov(stokes_ctx *X, Carver &cv) {
+  const i64 nn = X->n;
+  const size_t tb = X->mg32 ? sizeof(float) : sizeof(double);
+  const int m = X->p.restart;
+  KrylovStore k = krylov_store(X);
+  for (int i = 0; i <= m; i++) k.V[i] = (double *)cv.take(nn * 8);
+  if (X->p.krylov == STOKES_FGMRES)
+    for (int i = 0; i < m; i++) k.Z[i] = cv.take(nn * tb);
+  k.r = (double *)cv.take(nn * 8);
+  k.w = (double *)cv.take(nn * 8);
+  k.t = (double *)cv.take(nn * 8);
+  k.x = (double *)cv.take(nn * 8);
+  k.b = (double *)cv.take(nn * 8);
+  k.part = (double *)cv.take((size_t)kRedBlocks * (kMaxRestart + 2) * 8);
+  k.dsc = (double *)cv.take(kDscSlots * 8);
+  if (cv.base) set_krylov_store(X, k);
+}
+
+size_t krylov_scratch_bytes(stokes_ctx *X) {
+  Carver cv(nullptr);
+  carve_krylov(X, cv);
+  return (cv.off + kAlign - 1) / kAlign * kAlign;
+}
+
+// stokes_solve on the Krylov storage the context currently points at
+int solve_impl(stokes_ctx *X, const double *bu, const double *bp, double *xu, double *xp,
+               double tol, int max_iter, int use_x0, stokes_stats *st) {
+  const Geo &g = X->lev[0].g;
+  // rescaled system (eq. Stokes_rescaled): b' = (c b_u, b_p), x' = (x_u, c x_p)
+  launch_pack_vel(g, bu, X->c, X->b, X->s);
+  launch_scale(bp, 1.0, X->b + X->nvel, X->ncell, X->s);
+  int rc = check_rhs(X);
+  if (rc != STOKES_OK) return finish(X, rc);
+  if (use_x0) {
+    launch_pack_vel(g, xu, 1.0, X->x, X->s);
+    launch_scale(xp, X->c, X->x + X->nvel, X->ncell, X->s);
+  } else {
+    launch_fill<double>(X->x, 0.0, X->n, X->s);
+  }
+  rc = krylov(X, tol, max_iter, st);
+  finish_solution(X, X->x, 1.0, 1.0 / X->c, xu, xp);
+  hip_ok(X, hipStreamSynchronize(X->s));
+  return finish(X, rc);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1128,6 +1233,10 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
   if (!X) return STOKES_ENOMEM;
   X->p = *p;
   X->s = (hipStream_t)hip_stream;
+  if (hipGetDevice(&X->dev) != hipSuccess) {
+    delete X;
+    return STOKES_EDEVICE;
+  }
   X->d = p->dim;
   X->nlev = nlev;
   X->mg32 = (p->precision == STOKES_MG_FP32);
@@ -1394,22 +1503,26 @@ int stokes_p_mg_solve(stokes_ctx *X, const double *r, double *e, double tol, int
 int stokes_solve(stokes_ctx *X, const double *bu, const double *bp, double *xu, double *xp,
                  double tol, int max_iter, int use_x0, stokes_stats *st) {
   if (!X || !bu || !bp || !xu || !xp || !(tol > 0.0) || max_iter < 0) return STOKES_EINVAL;
-  const Geo &g = X->lev[0].g;
-  // rescaled system (eq. Stokes_rescaled): b' = (c b_u, b_p), x' = (x_u, c x_p)
-  launch_pack_vel(g, bu, X->c, X->b, X->s);
-  launch_scale(bp, 1.0, X->b + X->nvel, X->ncell, X->s);
-  int rc = check_rhs(X);
-  if (rc != STOKES_OK) return finish(X, rc);
-  if (use_x0) {
-    launch_pack_vel(g, xu, 1.0, X->x, X->s);
-    launch_scale(xp, X->c, X->x + X->nvel, X->ncell, X->s);
-  } else {
-    launch_fill<double>(X->x, 0.0, X->n, X->s);
-  }
-  rc = krylov(X, tol, max_iter, st);
-  finish_solution(X, X->x, 1.0, 1.0 / X->c, xu, xp);
-  hip_ok(X, hipStreamSynchronize(X->s));
-  return finish(X, rc);
+  return solve_impl(X, bu, bp, xu, xp, tol, max_iter, use_x0, st);
+}
+
+int stokes_solve_static(stokes_ctx *X, const double *bu, const double *bp, double *xu,
+                        double *xp, double tol, int max_iter, int use_x0, stokes_stats *st) {
+  if (!X || !bu || !bp || !xu || !xp || !(tol > 0.0) || max_iter < 0) return STOKES_EINVAL;
+  const size_t need = krylov_scratch_bytes(X);
+  if (need > kScratchBytes) return STOKES_ENOMEM;
+  char *base = (char *)scratch_on(X->dev);
+  if (!base) return STOKES_EDEVICE;
+  KrylovStore saved = krylov_store(X);
+  Carver cv(base);
+  carve_krylov(X, cv);
+  // the array keeps the previous call's contents (possibly another grid's):
+  // clear it, so that the wall entries of every vector start at zero as in
+  // a freshly zeroed workspace
+  launch_fill<double>((double *)base, 0.0, (i64)((need + 7) / 8), X->s);
+  const int rc = solve_impl(X, bu, bp, xu, xp, tol, max_iter, use_x0, st);
+  set_krylov_store(X, saved);
+  return rc;
 }
 
 int stokes_grad(stokes_ctx *X, const double *xu, const double *lu, double *dmu_cell,

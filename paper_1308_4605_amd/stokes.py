@@ -30,7 +30,7 @@ ABI_FUNCTIONS = (
     "stokes_sizes", "stokes_workspace_bytes", "stokes_create", "stokes_apply",
     "stokes_boundary_rhs", "stokes_precond",
     "stokes_vel_subsolve", "stokes_p_subsolve", "stokes_vel_mg_solve", "stokes_p_mg_solve",
-    "stokes_solve", "stokes_adjoint_solve",
+    "stokes_solve", "stokes_solve_static", "stokes_adjoint_solve",
     "stokes_grad", "stokes_rescale", "stokes_set_timing", "stokes_kernel_time", "stokes_destroy",
     "stokes_set_history", "stokes_vcycle_time",
     "stokes_strerror",
@@ -98,6 +98,7 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.stokes_solve.argtypes = [vp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(StokesStats)]
+        L.stokes_solve_static.argtypes = L.stokes_solve.argtypes
         L.stokes_adjoint_solve.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
                                            ctypes.c_double, ctypes.c_int,
                                            ctypes.POINTER(StokesStats)]
@@ -287,6 +288,18 @@ class Stokes:
         if check and rc:
             raise StokesError(rc, "stokes_solve")
         return xu, xp, st.as_dict(buf), rc
+
+    def solve_static(self, bu, bp, tol=1e-8, max_iter=1000, check=True):
+        """stokes_solve_static: the solve with its Krylov storage in the
+        library's static device array (no allocation in the library).
+        Returns (xu, xp, stats, rc)."""
+        xu, xp = self._new(self.nvel), self._new(self.ncell)
+        st = StokesStats()
+        rc = lib().stokes_solve_static(self._h, _ptr(bu), _ptr(bp), _ptr(xu), _ptr(xp),
+                                       float(tol), int(max_iter), 0, ctypes.byref(st))
+        if check and rc:
+            raise StokesError(rc, "stokes_solve_static")
+        return xu, xp, st.as_dict(), rc
 
     def adjoint(self, xu, xp, gu, gp, tol=1e-8, max_iter=1000, check=True):
         lu, lp = self._new(self.nvel), self._new(self.ncell)
