@@ -96,6 +96,22 @@ enum { STOKES_FP64 = 0, STOKES_MG_FP32 = 1 };
    GMRES(m) (right preconditioning; named in Sec. 4) */
 enum { STOKES_GMRES_LEFT = 0, STOKES_FGMRES = 1 };
 
+/* Scaling of the linear system (Sec. 3.3, "Rescaling of the Linear
+   System").  UNIFORM: the rescaled system of eq. Stokes_rescaled, velocity
+   equations times c and pressure unknowns times c.  DIAGONAL: for a very
+   broad range of viscosities the paper rescales velocity and pressure
+   separately by diagonal matrices; here the Krylov solver runs on S M' S
+   (M' the uniformly rescaled operator) with S = diag(S_u, S_p),
+   S_u = diag(A')^{-1/2} on the velocity unknowns and S_p = (2 mu'_cell)^{1/2}
+   ((gamma' + 4/3 mu')^{1/2} with bulk viscosity) on the pressure unknowns,
+   so that the velocity diagonal is one and the Schur approximation is minus
+   the identity.  The preconditioner is the same operator conjugated by S,
+   the solution is the same; what changes is the norm in which GMRES
+   minimises and the tolerance is measured (stokes_stats.rel_res_true is
+   ||S (b' - M' x')|| / ||S b'||).  Needs a positive viscous Schur
+   coefficient in every cell (STOKES_EINVAL otherwise). */
+enum { STOKES_SCALE_UNIFORM = 0, STOKES_SCALE_DIAGONAL = 1 };
+
 /* edge/node viscosity: arithmetic mean of the neighbouring cells (Sec. 3.1),
    harmonic mean, or caller-supplied values */
 enum { STOKES_EDGE_ARITH = 0, STOKES_EDGE_HARMONIC = 1, STOKES_EDGE_GIVEN = 2 };
@@ -120,6 +136,11 @@ typedef struct {
   int edge_avg;     /* STOKES_EDGE_* */
   int bulk;         /* 0: incompressible stress form; 1: stress with bulk
                        viscosity (stokes_create then takes gamma_cell) */
+  int scaling;      /* STOKES_SCALE_UNIFORM or STOKES_SCALE_DIAGONAL */
+  int extended;     /* 1: the Krylov solver's true residuals b - M x in
+                       double-double arithmetic (about 106 bits), each entry
+                       rounded once to FP64 (Sec. 3.3: extended precision in
+                       extreme cases); 0: FP64 */
 } stokes_params;
 
 typedef struct {
@@ -180,6 +201,16 @@ int stokes_create(const stokes_params *p, const double *rho_cell, const double *
 /* y = M x with the caller's (unscaled) coefficients (Sec. 2, eq. Saddle_sys;
    direct evaluation of the stencils at every interior face and cell, Sec. 3.2). */
 int stokes_apply(stokes_ctx *ctx, const double *xu, const double *xp, double *yu, double *yp);
+
+/* r = b - M x with the caller's coefficients (the residual of the Krylov
+   solver's convergence test, Sec. 3.2), in FP64 (extended = 0) or in
+   double-double arithmetic with each entry rounded once to FP64
+   (extended = 1; Sec. 3.3, extended precision in extreme cases).  It is
+   evaluated on the rescaled system, r_u = (c b_u - c A x_u - G c x_p) / c,
+   so the products with c round to FP64 unless c is a power of two.  ru is 0
+   on wall faces.  Uses the context's work vectors; asynchronous. */
+int stokes_residual(stokes_ctx *ctx, const double *bu, const double *bp, const double *xu,
+                    const double *xp, double *ru, double *rp, int extended);
 
 /* Prescribed (non-homogeneous) wall velocities (Sec. 3.2): with them the
    operator is affine, M x + c, and the flow solves M x = b - c with the

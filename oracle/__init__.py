@@ -37,7 +37,8 @@ class _Params(ctypes.Structure):
                 ("precond", ctypes.c_int), ("krylov", ctypes.c_int), ("restart", ctypes.c_int),
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("nu_coarse", ctypes.c_int),
                 ("vcycles", ctypes.c_int), ("rescale_c", ctypes.c_double),
-                ("edge_avg", ctypes.c_int)]
+                ("edge_avg", ctypes.c_int), ("scaling", ctypes.c_int),
+                ("extended", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -69,6 +70,8 @@ def lib():
         L.orc_rescale.argtypes = [ctypes.c_void_p]
         L.orc_rescale.restype = ctypes.c_double
         L.orc_apply.argtypes = [ctypes.c_void_p, P, P, P, P]
+        L.orc_residual.argtypes = [ctypes.c_void_p, P, P, P, P, P, P, ctypes.c_int]
+        L.orc_diag_scaling.argtypes = [ctypes.c_void_p, P]
         L.orc_precond.argtypes = [ctypes.c_void_p, P, P, P, P]
         L.orc_boundary_rhs.argtypes = [ctypes.c_void_p, P, P, P, P]
         L.orc_vel_subsolve.argtypes = [ctypes.c_void_p, P, P]
@@ -121,7 +124,7 @@ class Oracle:
 
     def __init__(self, dim, n, bc, h, theta, rho, mu, edges=None, precond=1, krylov=0,
                  restart=10, nu_pre=2, nu_post=2, nu_coarse=8, vcycles=1, rescale_c=0.0,
-                 edge_avg=0, gamma=None, **_ignored):
+                 edge_avg=0, gamma=None, scaling=0, extended=0, **_ignored):
         L = lib()
         p = _Params()
         p.dim = dim
@@ -134,6 +137,7 @@ class Oracle:
         p.precond, p.krylov, p.restart = precond, krylov, restart
         p.nu_pre, p.nu_post, p.nu_coarse, p.vcycles = nu_pre, nu_post, nu_coarse, vcycles
         p.rescale_c, p.edge_avg = float(rescale_c), edge_avg
+        p.scaling, p.extended = int(scaling), int(extended)
         self._rho, self._mu = _f64(rho), _f64(mu)
         self._edges = None if edges is None else _f64(edges)
         self._gamma = None if gamma is None else _f64(gamma)
@@ -169,6 +173,24 @@ class Oracle:
         if rc:
             raise OracleError(rc, "apply")
         return yu, yp
+
+    def residual(self, bu, bp, xu, xp, extended=False):
+        """r = b - M x (caller's coefficients), FP64 or __float128 rounded once."""
+        bu, bp, xu, xp = _f64(bu), _f64(bp), _f64(xu), _f64(xp)
+        ru, rp = np.empty(self.nvel), np.empty(self.ncell)
+        rc = lib().orc_residual(self._h, _p(bu), _p(bp), _p(xu), _p(xp), _p(ru), _p(rp),
+                                1 if extended else 0)
+        if rc:
+            raise OracleError(rc, "residual")
+        return ru, rp
+
+    def diag_scaling(self):
+        """The diagonal scaling S of the rescaled unknowns [faces | cells]."""
+        s = np.empty(self.nvel + self.ncell)
+        rc = lib().orc_diag_scaling(self._h, _p(s))
+        if rc:
+            raise OracleError(rc, "diag_scaling")
+        return s
 
     def precond(self, bu, bp):
         bu, bp = _f64(bu), _f64(bp)

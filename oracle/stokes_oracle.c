@@ -81,6 +81,9 @@ struct orc_ctx {
   level_t *lev;    /* scaled hierarchy: used by the solver */
   int vel_singular;
   double *given_edges; /* copy of caller edges for ORC_EDGE_GIVEN */
+  /* ORC_SCALE_DIAGONAL: the diagonal scaling S of the rescaled unknowns
+     ([faces | cells]); NULL otherwise */
+  double *sdiag;
 };
 
 static void fatal(const char *msg) {
@@ -396,6 +399,105 @@ static void apply_m(const level_t *L, const double *alpha, const double *mu_c,
       for (int i0 = 0; i0 < g->n[0]; i0++) {
         int c[3] = {i0, i1, i2};
         yp[lin3(g->n, i0, i1, i2)] = -div_cell(L, xu, c);
+      }
+}
+
+/* ------------------------------------------------------------------------ */
+/* extended precision residual (Sec. "Rescaling of the Linear System": in   */
+/* extreme cases extended precision arithmetic may be needed in the solver) */
+/* ------------------------------------------------------------------------ */
+
+/* The same operator as above, every operation in __float128 (113-bit
+   significand) on the FP64 values of u and of the coefficients; only the
+   final residual is rounded to FP64. */
+typedef __float128 quad;
+
+static quad q_dkl(const level_t *L, const double *u, int k, int l, const int e[3]) {
+  const grid_t *g = &L->g;
+  const quad h = (quad)g->h;
+  int f[3] = {e[0], e[1], e[2]};
+  if (g->ns[l] && (e[l] == 0 || e[l] == g->n[l])) {
+    const int m = (g->d == 3) ? 3 - k - l : 2;
+    const quad uw = L->bd_ut ? (quad)L->bd_ut[eidx(L, m, e)] : (quad)0;
+    if (e[l] == 0) return 2 * ((quad)fget(L, u, k, f) - uw) / h;
+    f[l] = g->n[l] - 1;
+    return -2 * ((quad)fget(L, u, k, f) - uw) / h;
+  }
+  int fb[3] = {e[0], e[1], e[2]};
+  fb[l] -= 1;
+  return ((quad)fget(L, u, k, f) - (quad)fget(L, u, k, fb)) / h;
+}
+
+static quad q_shear_rate(const level_t *L, const double *u, int k, int l, const int e[3]) {
+  if (on_free_slip(&L->g, k, e) || on_free_slip(&L->g, l, e)) return 0;
+  return q_dkl(L, u, k, l, e) + q_dkl(L, u, l, k, e);
+}
+
+static quad q_normal_rate(const level_t *L, const double *u, int k, const int c[3]) {
+  int fr[3] = {c[0], c[1], c[2]};
+  fr[k] += 1;
+  return ((quad)fget(L, u, k, fr) - (quad)fget(L, u, k, c)) / (quad)L->g.h;
+}
+
+static quad q_div_cell(const level_t *L, const double *u, const int c[3]) {
+  quad s = 0;
+  for (int k = 0; k < L->g.d; k++) s += q_normal_rate(L, u, k, c);
+  return s;
+}
+
+static quad q_lmu_row(const level_t *L, const double *mu_c, const double *mu_e,
+                      const double *u, int k, const int f[3]) {
+  const grid_t *g = &L->g;
+  const quad h = (quad)g->h;
+  int cr[3] = {f[0], f[1], f[2]};
+  int cl[3] = {f[0], f[1], f[2]};
+  cl[k] -= 1;
+  quad tr = 2 * (quad)mu_c[cidx(g, cr)] * q_normal_rate(L, u, k, cr);
+  quad tl = 2 * (quad)mu_c[cidx(g, cl)] * q_normal_rate(L, u, k, cl);
+  if (L->lam_c) {
+    tr += (quad)L->lam_c[cidx(g, cr)] * q_div_cell(L, u, cr);
+    tl += (quad)L->lam_c[cidx(g, cl)] * q_div_cell(L, u, cl);
+  }
+  quad s = (tr - tl) / h;
+  for (int l = 0; l < g->d; l++) {
+    if (l == k) continue;
+    int m = third_axis(k, l);
+    int elo[3] = {f[0], f[1], f[2]};
+    int ehi[3] = {f[0], f[1], f[2]};
+    ehi[l] += 1;
+    if (!g->ns[l]) ehi[l] = wrapi(ehi[l], g->n[l]);
+    quad thi = (quad)mu_e[eidx(L, m, ehi)] * q_shear_rate(L, u, k, l, ehi);
+    quad tlo = (quad)mu_e[eidx(L, m, elo)] * q_shear_rate(L, u, k, l, elo);
+    s += (thi - tlo) / h;
+  }
+  return s;
+}
+
+/* r = b - M x on level L (coefficients alpha, mu_c, mu_e, L->lam_c) in
+   __float128, rounded once; x, b, r are [faces | cells] */
+static void residual_quad(const level_t *L, const double *alpha, const double *mu_c,
+                          const double *mu_e, const double *b, const double *x, double *r) {
+  const grid_t *g = &L->g;
+  const double *xu = x, *xp = x + L->nvel;
+  for (int k = 0; k < g->d; k++) {
+    FOR_FACES(L, k, f) {
+      FACE_IDX(f);
+      size_t q = fidx(L, k, f);
+      if (is_wall_face(g, k, f)) { r[q] = 0.0; continue; }
+      int cl[3] = {f[0], f[1], f[2]};
+      cl[k] -= 1;
+      const quad au = (quad)alpha[q] * (quad)xu[q] - q_lmu_row(L, mu_c, mu_e, xu, k, f);
+      const quad gp = ((quad)xp[cidx(g, f)] - (quad)xp[cidx(g, cl)]) / (quad)g->h;
+      r[q] = (double)((quad)b[q] - (au + gp));
+    }
+  }
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int i2 = 0; i2 < g->n[2]; i2++)
+    for (int i1 = 0; i1 < g->n[1]; i1++)
+      for (int i0 = 0; i0 < g->n[0]; i0++) {
+        int c[3] = {i0, i1, i2};
+        const size_t q = lin3(g->n, i0, i1, i2);
+        r[L->nvel + q] = (double)((quad)b[L->nvel + q] + q_div_cell(L, xu, c));
       }
 }
 
@@ -935,22 +1037,47 @@ static double arnoldi_mgs(double **V, int j, double *w, size_t n, double *hcol) 
   return sqrt(dotv(w, w, n));
 }
 
+/* r-hat = S (b - M' x) on the rescaled system: the true residual, in FP64
+   or (extended) in __float128, then scaled by the diagonal scaling S when the
+   context has one. */
+static void true_residual(orc_ctx *X, const double *b, const double *x, double *r, double *t) {
+  level_t *L = &X->lev[0];
+  const size_t n = L->nvel + L->ncell;
+  if (X->p.extended) {
+    residual_quad(L, L->alpha, L->mu_c, L->mu_e, b, x, r);
+  } else {
+    apply_scaled(X, x, t);
+    for (size_t i = 0; i < n; i++) r[i] = b[i] - t[i];
+  }
+  if (X->sdiag)
+    for (size_t i = 0; i < n; i++) r[i] *= X->sdiag[i];
+}
+
 /* Solve the scaled system M' x = b by restarted GMRES: left-preconditioned
    (Sec. 3.2) or flexible (right-preconditioned, Saad).  Stopping (reading):
    the solve ends when the true residual ||b - M x|| <= tol ||b||; each restart
    cycle ends when the Givens residual estimate has dropped by the factor the
-   true residual still lacks, or after m steps. */
+   true residual still lacks, or after m steps.
+   With the diagonal scaling S the Krylov method runs on M-hat = S M' S for
+   x-hat = S^{-1} x, right-hand side S b, with the preconditioner
+   P-hat^{-1} = S^{-1} P'^{-1} S^{-1}; the iterate is kept as x = S x-hat. */
 static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int max_iter,
                         orc_stats *st) {
   level_t *L = &X->lev[0];
   const size_t n = L->nvel + L->ncell;
   const int m = X->p.restart;
   const int flexible = (X->p.krylov == ORC_FGMRES);
+  const double *S = X->sdiag;
   orc_stats local;
   if (!st) st = &local;
   memset(st, 0, sizeof(*st));
   int rc = ORC_OK;
-  double nb = sqrt(dotv(b, b, n));
+  double nb = 0.0;
+  for (size_t i = 0; i < n; i++) {
+    const double bi = S ? S[i] * b[i] : b[i];
+    nb += bi * bi;
+  }
+  nb = sqrt(nb);
   if (nb == 0.0) {
     zerov(x, n);
     return ORC_OK;
@@ -963,6 +1090,7 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
   double *r = (double *)malloc(n * sizeof(double));
   double *w = (double *)malloc(n * sizeof(double));
   double *t = (double *)malloc(n * sizeof(double));
+  double *t2 = (double *)malloc(n * sizeof(double));
   double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double)); /* H[i + j*(m+1)] */
   double *cs = (double *)calloc((size_t)m, sizeof(double));
   double *sn = (double *)calloc((size_t)m, sizeof(double));
@@ -970,8 +1098,7 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
   double *y = (double *)calloc((size_t)m, sizeof(double));
   int it = 0;
   for (;;) {
-    apply_scaled(X, x, t);
-    for (size_t i = 0; i < n; i++) r[i] = b[i] - t[i];
+    true_residual(X, b, x, r, t);
     double rho = sqrt(dotv(r, r, n));
     st->rel_res_true = rho / nb;
     if (!isfinite(rho)) { rc = ORC_ENONFINITE; break; }
@@ -983,7 +1110,12 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
       beta = rho;
       for (size_t i = 0; i < n; i++) V[0][i] = r[i] / beta;
     } else {
+      /* P-hat^{-1} r-hat = S^{-1} P'^{-1} (S^{-1} r-hat) */
+      if (S)
+        for (size_t i = 0; i < n; i++) r[i] /= S[i];
       precond_scaled(X, r, V[0]);
+      if (S)
+        for (size_t i = 0; i < n; i++) V[0][i] /= S[i];
       st->precond_applies++;
       beta = sqrt(dotv(V[0], V[0], n));
       if (!isfinite(beta)) { rc = ORC_ENONFINITE; break; }
@@ -997,11 +1129,27 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
     int jj = 0;
     for (int j = 0; j < m; j++) {
       if (flexible) {
-        precond_scaled(X, V[j], Z[j]);
+        /* z = P'^{-1} S^{-1} v is stored; M-hat P-hat^{-1} v = S M' z */
+        const double *vin = V[j];
+        if (S) {
+          for (size_t i = 0; i < n; i++) t2[i] = V[j][i] / S[i];
+          vin = t2;
+        }
+        precond_scaled(X, vin, Z[j]);
         apply_scaled(X, Z[j], w);
+        if (S)
+          for (size_t i = 0; i < n; i++) w[i] *= S[i];
       } else {
-        apply_scaled(X, V[j], t);
+        /* P-hat^{-1} M-hat v = S^{-1} P'^{-1} M' S v */
+        const double *vin = V[j];
+        if (S) {
+          for (size_t i = 0; i < n; i++) t2[i] = S[i] * V[j][i];
+          vin = t2;
+        }
+        apply_scaled(X, vin, t);
         precond_scaled(X, t, w);
+        if (S)
+          for (size_t i = 0; i < n; i++) w[i] /= S[i];
       }
       st->precond_applies++;
       it++;
@@ -1030,14 +1178,22 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
     }
     /* back substitution H y = g and update x */
     for (int i = jj - 1; i >= 0; i--) {
-      double s = g[i];
-      for (int k = i + 1; k < jj; k++) s -= H[i + (size_t)k * (m + 1)] * y[k];
+      double sum = g[i];
+      for (int k = i + 1; k < jj; k++) sum -= H[i + (size_t)k * (m + 1)] * y[k];
       double dg = H[i + (size_t)i * (m + 1)];
-      y[i] = (dg != 0.0) ? s / dg : 0.0;
+      y[i] = (dg != 0.0) ? sum / dg : 0.0;
     }
-    for (int i = 0; i < jj; i++) {
-      const double *vi = flexible ? Z[i] : V[i];
-      for (size_t q = 0; q < n; q++) x[q] += y[i] * vi[q];
+    if (flexible || !S) {
+      for (int i = 0; i < jj; i++) {
+        const double *vi = flexible ? Z[i] : V[i];
+        for (size_t q = 0; q < n; q++) x[q] += y[i] * vi[q];
+      }
+    } else {
+      /* x = S x-hat: x += S (V y) */
+      zerov(t, n);
+      for (int i = 0; i < jj; i++)
+        for (size_t q = 0; q < n; q++) t[q] += y[i] * V[i][q];
+      for (size_t q = 0; q < n; q++) x[q] += S[q] * t[q];
     }
   }
   st->iters = it;
@@ -1049,7 +1205,7 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
     for (int i = 0; i < m; i++) free(Z[i]);
     free(Z);
   }
-  free(r); free(w); free(t); free(H); free(cs); free(sn); free(g); free(y);
+  free(r); free(w); free(t); free(t2); free(H); free(cs); free(sn); free(g); free(y);
   return rc;
 }
 
@@ -1341,6 +1497,37 @@ int orc_create(const orc_params *p, const double *rho, const double *mu,
   if (bulk)
     for (size_t i = 0; i < L0->ncell; i++) L0->lam_c[i] = X->c * X->raw.lam_c[i];
   for (int l = 1; l < nlev; l++) coarsen_coefficients(&X->lev[l - 1], &X->lev[l]);
+  /* diagonal scaling (Sec. "Rescaling of the Linear System": with a very
+     broad range of viscosities velocity and pressure are rescaled
+     separately by diagonal matrices; the formulation the paper points to is
+     not given, reading): S = diag(S_u, S_p) with S_u = diag(A')^{-1/2} on
+     the interior faces and S_p = sqrt(2 mu'_cell [+ lam'_cell]), the root of
+     the viscous coefficient of the Schur approximation, so that S M' S has a
+     unit velocity diagonal and a pressure block whose approximate Schur
+     complement is minus the identity.  Wall faces take 1. */
+  if (p->scaling == ORC_SCALE_DIAGONAL) {
+    const size_t nv = L0->nvel, nc = L0->ncell;
+    X->sdiag = (double *)malloc((nv + nc) * sizeof(double));
+    if (!X->sdiag) { orc_destroy(X); return ORC_ENOMEM; }
+    for (int k = 0; k < g.d; k++) {
+      FOR_FACES(L0, k, f) {
+        FACE_IDX(f);
+        const size_t q = fidx(L0, k, f);
+        X->sdiag[q] = is_wall_face(&L0->g, k, f)
+                          ? 1.0
+                          : 1.0 / sqrt(a_diag(L0, L0->alpha, L0->mu_c, L0->mu_e, k, f));
+      }
+    }
+    for (size_t i = 0; i < nc; i++) {
+      const double sig = schur_visc(L0, i);
+      if (!(sig > 0.0)) { orc_destroy(X); return ORC_EINVAL; }
+      X->sdiag[nv + i] = sqrt(sig);
+    }
+  } else if (p->scaling != ORC_SCALE_UNIFORM) {
+    orc_destroy(X);
+    return ORC_EINVAL;
+  }
+  if (p->extended != 0 && p->extended != 1) { orc_destroy(X); return ORC_EINVAL; }
   *out = X;
   return ORC_OK;
 }
@@ -1352,6 +1539,7 @@ void orc_destroy(orc_ctx *X) {
     for (int l = 0; l < X->nlev; l++) level_free(&X->lev[l]);
   free(X->lev);
   free(X->given_edges);
+  free(X->sdiag);
   free(X);
 }
 
@@ -1364,6 +1552,43 @@ double orc_rescale(const orc_ctx *X) { return X->c; }
 int orc_apply(orc_ctx *X, const double *xu, const double *xp, double *yu, double *yp) {
   if (!X || !xu || !xp || !yu || !yp) return ORC_EINVAL;
   apply_m(&X->raw, X->raw.alpha, X->raw.mu_c, X->raw.mu_e, xu, xp, yu, yp);
+  return ORC_OK;
+}
+
+int orc_residual(orc_ctx *X, const double *bu, const double *bp, const double *xu,
+                 const double *xp, double *ru, double *rp, int extended) {
+  if (!X || !bu || !bp || !xu || !xp || !ru || !rp) return ORC_EINVAL;
+  level_t *L = &X->raw;
+  const size_t nv = L->nvel, nc = L->ncell, n = nv + nc;
+  double *b = (double *)malloc(n * sizeof(double));
+  double *x = (double *)malloc(n * sizeof(double));
+  double *r = (double *)malloc(n * sizeof(double));
+  if (!b || !x || !r) { free(b); free(x); free(r); return ORC_ENOMEM; }
+  memcpy(b, bu, nv * sizeof(double));
+  memcpy(b + nv, bp, nc * sizeof(double));
+  memcpy(x, xu, nv * sizeof(double));
+  memcpy(x + nv, xp, nc * sizeof(double));
+  if (extended) {
+    residual_quad(L, L->alpha, L->mu_c, L->mu_e, b, x, r);
+  } else {
+    apply_m(L, L->alpha, L->mu_c, L->mu_e, x, x + nv, r, r + nv);
+    for (size_t i = 0; i < n; i++) r[i] = b[i] - r[i];
+    for (int k = 0; k < L->g.d; k++) {
+      FOR_FACES(L, k, f) {
+        FACE_IDX(f);
+        if (is_wall_face(&L->g, k, f)) r[fidx(L, k, f)] = 0.0;
+      }
+    }
+  }
+  memcpy(ru, r, nv * sizeof(double));
+  memcpy(rp, r + nv, nc * sizeof(double));
+  free(b); free(x); free(r);
+  return ORC_OK;
+}
+
+int orc_diag_scaling(orc_ctx *X, double *s) {
+  if (!X || !s || !X->sdiag) return ORC_EINVAL;
+  memcpy(s, X->sdiag, (X->lev[0].nvel + X->lev[0].ncell) * sizeof(double));
   return ORC_OK;
 }
 

@@ -54,7 +54,15 @@ typedef struct {
   int vcycles;      /* V-cycles per subsolver application */
   double rescale_c; /* <= 0: c = h / geometric mean of mu_cell */
   int edge_avg;     /* ORC_EDGE_* */
+  int scaling;      /* ORC_SCALE_UNIFORM: the rescaled system of eq.
+                       Stokes_rescaled; ORC_SCALE_DIAGONAL: that system scaled
+                       again by diagonal matrices, velocity and pressure
+                       separately (Sec. "Rescaling of the Linear System") */
+  int extended;     /* 1: the solver's true residuals b - M x in extended
+                       precision (__float128), rounded to FP64 */
 } orc_params;
+
+enum { ORC_SCALE_UNIFORM = 0, ORC_SCALE_DIAGONAL = 1 };
 
 typedef struct {
   int iters, restarts, precond_applies, scalar_vcycles;
@@ -85,6 +93,13 @@ int orc_apply(orc_ctx *c, const double *xu, const double *xp, double *yu, double
    component parallel to the wall and normal to the edge; no-slip walls only).
    The flow with those wall velocities solves M x = b - (cu, cp). */
 int orc_boundary_rhs(orc_ctx *c, const double *un, const double *ut, double *cu, double *cp);
+/* r = b - M x with the caller's (unscaled) coefficients, evaluated in FP64
+   (extended = 0) or in __float128 and rounded once to FP64 (extended = 1). */
+int orc_residual(orc_ctx *c, const double *bu, const double *bp, const double *xu,
+                 const double *xp, double *ru, double *rp, int extended);
+/* the diagonal scaling S of the rescaled system's unknowns ([faces | cells],
+   nvel + ncell entries; wall faces 1) when scaling = ORC_SCALE_DIAGONAL */
+int orc_diag_scaling(orc_ctx *c, double *s);
 /* z = P^{-1} b (unscaled system). */
 int orc_precond(orc_ctx *c, const double *bu, const double *bp, double *zu, double *zp);
 /* velocity subsolver e = A~^{-1} r and pressure subsolver e = L~_rho^{-1} r (unscaled). */

@@ -63,6 +63,8 @@ bool valid_params(const stokes_params *p, int *nlev_out) {
   if (p->nu_pre > 64 || p->nu_post > 64 || p->nu_coarse > 4096 || p->vcycles > 1000) return false;
   if (p->edge_avg < STOKES_EDGE_ARITH || p->edge_avg > STOKES_EDGE_GIVEN) return false;
   if (p->bulk != 0 && p->bulk != 1) return false;
+  if (p->scaling != STOKES_SCALE_UNIFORM && p->scaling != STOKES_SCALE_DIAGONAL) return false;
+  if (p->extended != 0 && p->extended != 1) return false;
   int nmin = 1 << 30;
   for (int a = 0; a < p->dim; a++) {
     if (p->n[a] < 2 || p->n[a] > (1 << 20)) return false;
@@ -117,6 +119,9 @@ struct stokes_ctx {
   double *V[kMaxRestart + 1];
   void *Z[kMaxRestart];
   double *r = nullptr, *w = nullptr, *t = nullptr, *x = nullptr, *b = nullptr;
+  // diagonal scaling S of the rescaled unknowns [faces | cells]
+  // (STOKES_SCALE_DIAGONAL; null otherwise)
+  double *sdiag = nullptr;
   // preconditioner temporaries (precision T, level-0 sizes)
   void *pin = nullptr, *pout = nullptr;           // [u | p]
   void *xs = nullptr, *tu = nullptr, *eu = nullptr;  // velocity
@@ -263,6 +268,8 @@ void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
   void *ps_r = cv.take(nc * tb), *ps_t = cv.take(nc * tb), *ps_de = cv.take(nc * tb);
   double *ge = (double *)cv.take(ne * 8);
   double *gc = (double *)cv.take(nc * 8);
+  double *sd = (p->scaling == STOKES_SCALE_DIAGONAL) ? (double *)cv.take(nn * 8) : nullptr;
+  if (X) X->sdiag = sd;
   if (use_vsplit(p)) {
     void *a = cv.take(nv * tb), *b = cv.take(nv * tb), *c = cv.take(nv * tb);
     if (X) {
@@ -823,11 +830,11 @@ struct PrecClock {
 
 // ||b - M x|| / ||b|| of the caller's system, from the scaled residual and
 // right-hand side (r' = (c r_u, r_p), b' = (c b_u, b_p))
-double unscaled_rel(stokes_ctx *X) {
+double unscaled_rel(stokes_ctx *X, const double *r) {
   const i64 nv = X->nvel, nc = X->ncell;
   double *hb = X->host;
-  launch_norm2(X->r, nv, X->part, X->dsc + 0, X->s);
-  launch_norm2(X->r + nv, nc, X->part, X->dsc + 1, X->s);
+  launch_norm2(r, nv, X->part, X->dsc + 0, X->s);
+  launch_norm2(r + nv, nc, X->part, X->dsc + 1, X->s);
   launch_norm2(X->b, nv, X->part, X->dsc + 2, X->s);
   launch_norm2(X->b + nv, nc, X->part, X->dsc + 3, X->s);
   fetch(X, X->dsc, 4, hb);
@@ -836,6 +843,25 @@ double unscaled_rel(stokes_ctx *X) {
   return den > 0.0 ? std::sqrt(num / den) : 0.0;
 }
 
+// r-hat = S (b' - M' x') into X->r: the true residual in FP64 or in
+// double-double arithmetic (extended), scaled by the diagonal scaling when
+// the context has one
+void true_residual(stokes_ctx *X) {
+  const Geo &g = X->lev[0].g;
+  const i64 nv = X->nvel;
+  if (X->p.extended)
+    launch_residual_dd(g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam, X->x, X->x + nv, X->b,
+                       X->b + nv, X->r, X->r + nv, X->s);
+  else
+    launch_apply_m<double>(g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam, X->x, X->x + nv, X->b,
+                           X->b + nv, X->r, X->r + nv, X->s);
+  if (X->sdiag) launch_mul_scaling(X->r, X->sdiag, 0, X->n, X->r, X->s);
+}
+
+// With the diagonal scaling S the Krylov method runs on S M' S for S^{-1} x'
+// with right-hand side S b' and the preconditioner S^{-1} P'^{-1} S^{-1}; the
+// iterate stays x' (flexible: x' += Z y with Z = P'^{-1} S^{-1} V; left:
+// x' += S V y).
 int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
   const int m = X->p.restart;
   const int flexible = (X->p.krylov == STOKES_FGMRES);
@@ -859,7 +885,13 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     }
   } fin{st, pc, t0};
   double *hb = X->host;
-  launch_norm2(X->b, n, X->part, X->dsc + 0, X->s);
+  const double *S = X->sdiag;
+  if (S) {
+    launch_mul_scaling(X->b, S, 0, n, X->t, X->s);
+    launch_norm2(X->t, n, X->part, X->dsc + 0, X->s);
+  } else {
+    launch_norm2(X->b, n, X->part, X->dsc + 0, X->s);
+  }
   const double nb = std::sqrt(fetch(X, X->dsc, 1, hb));
   if (X->err) return STOKES_EDEVICE;
   if (nb == 0.0) {
@@ -870,9 +902,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
   int it = 0, rc = STOKES_OK;
   for (;;) {
     // r = b - M x and its norm
-    launch_apply_m<double>(X->lev[0].g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam, X->x,
-                           X->x + nv, X->b,
-                           X->b + nv, X->r, X->r + nv, X->s);
+    true_residual(X);
     launch_norm2(X->r, n, X->part, X->dsc + 0, X->s);
     const double rho = std::sqrt(fetch(X, X->dsc, 1, hb));
     if (X->err) return STOKES_EDEVICE;
@@ -888,7 +918,9 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       launch_scale(X->r, 1.0 / beta, X->V[0], n, X->s);
     } else {
       pc.start();
+      if (S) launch_mul_scaling(X->r, S, 1, n, X->r, X->s);
       precond<double>(X, X->r, X->r + nv, X->V[0], X->V[0] + nv);
+      if (S) launch_mul_scaling(X->V[0], S, 1, n, X->V[0], X->s);
       pc.stop();
       st->precond_applies++;
       launch_norm2(X->V[0], n, X->part, X->dsc + 0, X->s);
@@ -906,7 +938,12 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     for (int j = 0; j < m; j++) {
       if (flexible) {
         pc.start();
-        precond_from64(X, X->V[j], X->Z[j], j > 0);
+        if (S) {
+          launch_mul_scaling(X->V[j], S, 1, n, X->t, X->s);
+          precond_from64(X, X->t, X->Z[j], false);
+        } else {
+          precond_from64(X, X->V[j], X->Z[j], j > 0);
+        }
         pc.stop();
         if (X->mg32)
           launch_apply_m<float>(X->lev[0].g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam,
@@ -914,10 +951,17 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
                                 P<float>(X->Z[j]) + nv, nullptr, nullptr, X->w, X->w + nv, X->s);
         else
           apply_scaled(X, P<double>(X->Z[j]), X->w);
+        if (S) launch_mul_scaling(X->w, S, 0, n, X->w, X->s);
       } else {
-        apply_scaled(X, X->V[j], X->t);
+        if (S) {
+          launch_mul_scaling(X->V[j], S, 0, n, X->w, X->s);
+          apply_scaled(X, X->w, X->t);
+        } else {
+          apply_scaled(X, X->V[j], X->t);
+        }
         pc.start();
         precond<double>(X, X->t, X->t + nv, X->w, X->w + nv);
+        if (S) launch_mul_scaling(X->w, S, 1, n, X->w, X->s);
         pc.stop();
       }
       st->precond_applies++;
@@ -981,7 +1025,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       // pass C: v_{j+1} = (w - V (h1 + h2)) / nu, plus the FP32 copy the next
       // flexible preconditioner application starts from
       launch_cgs_next(X->w, X->V, X->dsc + 32, X->dsc + 72, formed ? 0 : j + 1, 1.0 / hn, n,
-                      X->V[j + 1], (flexible && X->mg32) ? P<float>(X->pin) : nullptr, X->part,
+                      X->V[j + 1], (flexible && X->mg32 && !S) ? P<float>(X->pin) : nullptr, X->part,
                       nullptr, X->s);
     }
     for (int i = jj - 1; i >= 0; i--) {
@@ -995,6 +1039,11 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
         launch_update_x<float>(X->x, (const float *const *)X->Z, y.data(), jj, n, X->s);
       else
         launch_update_x<double>(X->x, (const double *const *)X->Z, y.data(), jj, n, X->s);
+    } else if (S) {
+      launch_fill<double>(X->t, 0.0, n, X->s);
+      launch_update_x<double>(X->t, (const double *const *)X->V, y.data(), jj, n, X->s);
+      launch_mul_scaling(X->t, S, 0, n, X->t, X->s);
+      launch_axpy<double>(1.0, X->t, X->x, n, X->s);
     } else {
       launch_update_x<double>(X->x, (const double *const *)X->V, y.data(), jj, n, X->s);
     }
@@ -1004,7 +1053,14 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
   const int p_per = (X->p.precond == STOKES_P1) ? 1 : (X->p.theta != 0.0 ? 1 : 0);
   st->scalar_vcycles = st->precond_applies * X->p.vcycles * (X->d * vel_per + p_per);
   // X->r holds b' - M' x' of the final iterate unless the loop left early
-  if (rc == STOKES_OK || rc == STOKES_ENOCONV) st->rel_res_unscaled = unscaled_rel(X);
+  if (rc == STOKES_OK || rc == STOKES_ENOCONV) {
+    const double *r = X->r;
+    if (S) {  // X->r holds S (b' - M' x')
+      launch_mul_scaling(X->r, S, 1, n, X->t, X->s);
+      r = X->t;
+    }
+    st->rel_res_unscaled = unscaled_rel(X, r);
+  }
   return rc;
 }
 
@@ -1356,6 +1412,24 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
     else
       split_alpha<double>(X);
   }
+  if (X->sdiag) {
+    // diagonal scaling from the FP64 coefficients of M'; X->t is still zero
+    launch_fill<int>(X->dflag, 0, 1, s);
+    launch_diag_scaling(g0, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam, X->t, X->sdiag, X->dflag,
+                        s);
+    (void)hipMemcpyAsync(&X->host[8], X->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) {
+      (void)hipHostFree(X->host);
+      delete X;
+      return STOKES_EDEVICE;
+    }
+    std::memcpy(&flag, &X->host[8], sizeof(int));
+    if (flag) {  // a cell without a positive viscous Schur coefficient
+      (void)hipHostFree(X->host);
+      delete X;
+      return STOKES_EINVAL;
+    }
+  }
   // algorithmic bytes of one finest-level velocity colour pass of component
   // k, each value the pass needs counted once: it reads every velocity
   // component (the faces of its colour and all their neighbours), mu_cell
@@ -1411,6 +1485,28 @@ int stokes_apply(stokes_ctx *X, const double *xu, const double *xp, double *yu, 
   apply_scaled(X, X->t, X->w);
   launch_pack_vel(g, X->w, 1.0 / X->c, yu, X->s);
   launch_scale(X->w + X->nvel, 1.0, yp, X->ncell, X->s);
+  return finish(X, STOKES_OK);
+}
+
+int stokes_residual(stokes_ctx *X, const double *bu, const double *bp, const double *xu,
+                    const double *xp, double *ru, double *rp, int extended) {
+  if (!X || !bu || !bp || !xu || !xp || !ru || !rp || (extended != 0 && extended != 1))
+    return STOKES_EINVAL;
+  const Geo &g = X->lev[0].g;
+  const i64 nv = X->nvel, nc = X->ncell;
+  // rescaled system: b' = (c b_u, b_p), x' = (x_u, c x_p), r_u = r'_u / c
+  launch_pack_vel(g, bu, X->c, X->b, X->s);
+  launch_scale(bp, 1.0, X->b + nv, nc, X->s);
+  launch_pack_vel(g, xu, 1.0, X->x, X->s);
+  launch_scale(xp, X->c, X->x + nv, nc, X->s);
+  if (extended)
+    launch_residual_dd(g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam, X->x, X->x + nv, X->b,
+                       X->b + nv, X->r, X->r + nv, X->s);
+  else
+    launch_apply_m<double>(g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam, X->x, X->x + nv, X->b,
+                           X->b + nv, X->r, X->r + nv, X->s);
+  launch_pack_vel(g, X->r, 1.0 / X->c, ru, X->s);
+  launch_scale(X->r + nv, 1.0, rp, nc, X->s);
   return finish(X, STOKES_OK);
 }
 

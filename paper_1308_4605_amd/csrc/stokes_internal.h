@@ -87,6 +87,20 @@ void launch_apply_m(const Geo &g, const double *alpha, const double *muc, const 
 // boundary terms of prescribed wall velocities: M applied to the wall-data
 // field xu (normal values on wall faces, zero inside) with tangential wall
 // values gw (edge layout) in the no-slip ghosts
+// r = b - M x like launch_apply_m (FP64 input), every operation in
+// double-double arithmetic and each entry rounded once to FP64
+void launch_residual_dd(const Geo &g, const double *alpha, const double *muc, const double *mue,
+                        const double *lam, const double *xu, const double *xp, const double *bu,
+                        const double *bp, double *ru, double *rp, hipStream_t s);
+// sd = the diagonal scaling of the unknowns [faces | cells]: 1/sqrt(diag A)
+// on interior faces (1 on wall faces), sqrt(2 mu_cell + lam) on cells (*bad
+// set to 1 where that is not positive); zero: an all-zero velocity array
+void launch_diag_scaling(const Geo &g, const double *alpha, const double *muc, const double *mue,
+                         const double *lam, const double *zero, double *sd, int *bad,
+                         hipStream_t s);
+// y = x * sd (inv = 0) or x / sd (inv = 1); y may equal x
+void launch_mul_scaling(const double *x, const double *sd, int inv, i64 n, double *y,
+                        hipStream_t s);
 void launch_apply_m_walls(const Geo &g, const double *alpha, const double *muc,
                           const double *mue, const double *lam, const double *xu,
                           const double *xp, const double *gw, double *yu, double *yp,

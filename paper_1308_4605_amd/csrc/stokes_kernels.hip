@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "stokes_internal.h"
 
@@ -581,25 +582,86 @@ template void launch_axpy<float>(float, const float *, float *, i64, hipStream_t
 template void launch_axpy<double>(double, const double *, double *, i64, hipStream_t);
 
 // ------------------------------------------------------------------------
-// saddle operator (FP64 arithmetic, input in TI)
+// double-double arithmetic for the extended-precision residual (paper Sec.
+// "Rescaling of the Linear System": extended precision arithmetic in extreme
+// cases).  A value is hi + lo with |lo| <= ulp(hi) / 2, about 106 bits of
+// significand.  The building blocks are the error-free transformations of
+// Knuth (two_sum: a + b = s + e exactly) and of the fused multiply-add
+// (two_prod: a * b = p + e exactly); sums and products renormalise with
+// fast_two_sum (Dekker).  Written from those definitions.  The identities
+// hold only for separately rounded operations, so no multiply-add in these
+// functions may be contracted into a fused one (the pragma below; the
+// compiler otherwise fuses p = a * b with the following p + lo).
+// ------------------------------------------------------------------------
+
+struct dd {
+  double hi, lo;
+  dd() = default;
+  __device__ constexpr dd(double h) : hi(h), lo(0.0) {}
+  __device__ constexpr dd(double h, double l) : hi(h), lo(l) {}
+};
+
+__device__ __forceinline__ dd dd_two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  const double s = a + b;
+  const double bb = s - a;
+  return dd(s, (a - (s - bb)) + (b - bb));
+}
+__device__ __forceinline__ dd dd_fast_two_sum(double a, double b) {  // needs |a| >= |b|
+#pragma clang fp contract(off)
+  const double s = a + b;
+  return dd(s, b - (s - a));
+}
+__device__ __forceinline__ dd dd_two_prod(double a, double b) {
+#pragma clang fp contract(off)
+  const double p = a * b;
+  return dd(p, fma(a, b, -p));
+}
+__device__ __forceinline__ dd operator+(const dd &a, const dd &b) {
+#pragma clang fp contract(off)
+  dd s = dd_two_sum(a.hi, b.hi);
+  const dd t = dd_two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = dd_fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return dd_fast_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ dd operator-(const dd &a) { return dd(-a.hi, -a.lo); }
+__device__ __forceinline__ dd operator-(const dd &a, const dd &b) { return a + (-b); }
+__device__ __forceinline__ dd operator*(const dd &a, const dd &b) {
+#pragma clang fp contract(off)
+  dd p = dd_two_prod(a.hi, b.hi);
+  p.lo += a.hi * b.lo + a.lo * b.hi;
+  return dd_fast_two_sum(p.hi, p.lo);
+}
+__device__ __forceinline__ double to_double(double a) { return a; }
+__device__ __forceinline__ double to_double(const dd &a) {
+#pragma clang fp contract(off)
+  return a.hi + a.lo;
+}
+// 1/h in the row arithmetic: the FP64 reciprocal, or with R = dd the
+// reciprocal to about 106 bits (ih_lo = (1 - h ih) / h from the host)
+__device__ __forceinline__ void make_ih(double ih, double, double &out) { out = ih; }
+__device__ __forceinline__ void make_ih(double ih, double ih_lo, dd &out) { out = dd(ih, ih_lo); }
+
+// ------------------------------------------------------------------------
+// saddle operator (FP64 or double-double arithmetic, input in TI)
 // ------------------------------------------------------------------------
 
 // One row of A at face (k, i) in FP64 from loaded values (the names of
 // a_row_core).  GW: prescribed tangential wall velocities (gwhi, gwlo at the
 // upper/lower edge, edge layout) replace the zero wall value of the no-slip
 // ghost, 2 gw - u_f, and a free-slip wall's flux is zero (boundary terms only).
-template <int DIM, bool GW>
-__device__ __forceinline__ double a_row_mixed_core(
-    const Geo &g, int k, const int i[3], double uf, double ukp, double ukm, const double (&va)[3],
-    const double (&vb)[3], const double (&ulh_r)[3], const double (&ulh_l)[3],
-    const double (&ull_r)[3], const double (&ull_l)[3], const double (&mhi)[3],
-    const double (&mlo)[3], const double (&gwhi)[3], const double (&gwlo)[3], double mr,
-    double ml, double al, bool bulk, double lr, double ll) {
-  const double ih = g.ih;
-  const double tr = 2.0 * mr * ((ukp - uf) * ih);
-  const double tl = 2.0 * ml * ((uf - ukm) * ih);
-  double s = (tr - tl) * ih;
-  double hdr = ukp - uf, hdl = uf - ukm;  // h * divergence of cells r and l
+template <typename R, int DIM, bool GW>
+__device__ __forceinline__ R a_row_mixed_core(
+    const Geo &g, int k, const int i[3], R ih, R uf, R ukp, R ukm, const R (&va)[3],
+    const R (&vb)[3], const R (&ulh_r)[3], const R (&ulh_l)[3], const R (&ull_r)[3],
+    const R (&ull_l)[3], const R (&mhi)[3], const R (&mlo)[3], const R (&gwhi)[3],
+    const R (&gwlo)[3], R mr, R ml, R al, bool bulk, R lr, R ll) {
+  const R tr = R(2.0) * mr * ((ukp - uf) * ih);
+  const R tl = R(2.0) * ml * ((uf - ukm) * ih);
+  R s = (tr - tl) * ih;
+  R hdr = ukp - uf, hdl = uf - ukm;  // h * divergence of cells r and l
 #pragma unroll
   for (int l = 0; l < DIM; l++) {
     if (l == k) continue;
@@ -607,25 +669,25 @@ __device__ __forceinline__ double a_row_mixed_core(
     const bool bot = g.ns[l] && (i[l] == 0);
     // wall ghosts: even (free-slip end) or odd (no-slip end)
     const bool fs_hi = g.fs[l] & 2, fs_lo = g.fs[l] & 1;
-    double ua = top ? (fs_hi ? uf : -uf) : va[l];
-    double ub = bot ? (fs_lo ? uf : -uf) : vb[l];
+    R ua = top ? (fs_hi ? uf : -uf) : va[l];
+    R ub = bot ? (fs_lo ? uf : -uf) : vb[l];
     if (GW) {
-      if (top && !fs_hi) ua = 2.0 * gwhi[l] - uf;
-      if (bot && !fs_lo) ub = 2.0 * gwlo[l] - uf;
+      if (top && !fs_hi) ua = R(2.0) * gwhi[l] - uf;
+      if (bot && !fs_lo) ub = R(2.0) * gwlo[l] - uf;
     }
-    double ghi = (ua - uf) * ih + (ulh_r[l] - ulh_l[l]) * ih;
-    double glo = (uf - ub) * ih + (ull_r[l] - ull_l[l]) * ih;
+    R ghi = (ua - uf) * ih + (ulh_r[l] - ulh_l[l]) * ih;
+    R glo = (uf - ub) * ih + (ull_r[l] - ull_l[l]) * ih;
     // with prescribed normal velocities on a free-slip wall the cross
     // derivative along the wall need not vanish; the whole flux does
     if (GW) {
-      if (top && fs_hi) ghi = 0.0;
-      if (bot && fs_lo) glo = 0.0;
+      if (top && fs_hi) ghi = R(0.0);
+      if (bot && fs_lo) glo = R(0.0);
     }
-    s += (mhi[l] * ghi - mlo[l] * glo) * ih;
-    hdr += ulh_r[l] - ull_r[l];
-    hdl += ulh_l[l] - ull_l[l];
+    s = s + (mhi[l] * ghi - mlo[l] * glo) * ih;
+    hdr = hdr + (ulh_r[l] - ull_r[l]);
+    hdl = hdl + (ulh_l[l] - ull_l[l]);
   }
-  if (bulk) s += (lr * hdr - ll * hdl) * (ih * ih);  // lam (div u) on the normal stresses
+  if (bulk) s = s + (lr * hdr - ll * hdl) * (ih * ih);  // lam (div u) on the normal stresses
   return al * uf - s;
 }
 
@@ -634,17 +696,21 @@ __device__ __forceinline__ double a_row_mixed_core(
 // The rows share most of their velocity values, which are loaded once per
 // cell (per component c at i, at i +- e_a and at i + e_c - e_k), as are the
 // cell and edge coefficients.
-template <typename TI, int DIM, bool GW>
+// R = double: FP64 arithmetic; R = dd: every value and operation in
+// double-double and the result rounded once (the extended-precision
+// residual, with ih_lo the low part of 1/h).
+template <typename TI, int DIM, bool GW, typename R = double>
 __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double *__restrict__ muc,
                           const double *__restrict__ mue, const double *__restrict__ lam,
                           const TI *__restrict__ xu,
                           const TI *__restrict__ xp, const double *__restrict__ bu,
                           const double *__restrict__ bp, const double *__restrict__ gw,
-                          double *__restrict__ yu, double *__restrict__ yp) {
+                          double *__restrict__ yu, double *__restrict__ yp, double ih_lo) {
   int i[3];
   if (!box_thread(g, g.n[0], i[0], i[1], i[2])) return;
   const i64 t = cidx3(g, i);
-  const double ih = g.ih;
+  R ih;
+  make_ih(g.ih, ih_lo, ih);
   int ip[3] = {0, 0, 0}, im[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < DIM; a++) {
@@ -654,74 +720,78 @@ __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double 
   // V[c][0] at i, V[c][1 + 2a] at i + e_a, V[c][2 + 2a] at i - e_a; X[c][k]
   // at i + e_c - e_k.  Component c has no face at index n[a] along a wall
   // axis a != c: that load is clamped to i (the wall ghost replaces it).
-  double V[DIM][1 + 2 * DIM], X[DIM][DIM];
+  R V[DIM][1 + 2 * DIM], X[DIM][DIM];
 #pragma unroll
   for (int c = 0; c < DIM; c++) {
     int q[3] = {i[0], i[1], i[2]};
-    V[c][0] = (double)xu[fidx3(g, c, q)];
+    V[c][0] = R((double)xu[fidx3(g, c, q)]);
 #pragma unroll
     for (int a = 0; a < DIM; a++) {
       const bool top = a != c && g.ns[a] && (i[a] + 1 == g.n[a]);
       q[a] = top ? i[a] : ip[a];
-      V[c][1 + 2 * a] = (double)xu[fidx3(g, c, q)];
+      V[c][1 + 2 * a] = R((double)xu[fidx3(g, c, q)]);
       q[a] = im[a];
-      V[c][2 + 2 * a] = (double)xu[fidx3(g, c, q)];
+      V[c][2 + 2 * a] = R((double)xu[fidx3(g, c, q)]);
       q[a] = i[a];
     }
 #pragma unroll
     for (int k = 0; k < DIM; k++) {
-      X[c][k] = 0.0;
+      X[c][k] = R(0.0);
       if (k == c) continue;
       q[c] = ip[c];
       q[k] = im[k];
-      X[c][k] = (double)xu[fidx3(g, c, q)];
+      X[c][k] = R((double)xu[fidx3(g, c, q)]);
       q[c] = i[c];
       q[k] = i[k];
     }
   }
   // cell values at i and at i - e_k
-  double mc[1 + DIM], lc[1 + DIM], pc[1 + DIM];
-  mc[0] = muc[t];
-  lc[0] = lam ? lam[t] : 0.0;
-  pc[0] = (double)xp[t];
+  R mc[1 + DIM], lc[1 + DIM], pc[1 + DIM];
+  mc[0] = R(muc[t]);
+  lc[0] = R(lam ? lam[t] : 0.0);
+  pc[0] = R((double)xp[t]);
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
     int q[3] = {i[0], i[1], i[2]};
     q[k] = im[k];
     const i64 cq = cidx3(g, q);
-    mc[1 + k] = muc[cq];
-    lc[1 + k] = lam ? lam[cq] : 0.0;
-    pc[1 + k] = (double)xp[cq];
+    mc[1 + k] = R(muc[cq]);
+    lc[1 + k] = R(lam ? lam[cq] : 0.0);
+    pc[1 + k] = R((double)xp[cq]);
   }
   // edge family m at i (E0) and at i + e_a for the axes a != m (E1), and the
   // prescribed wall velocities at the same edges
-  double E0[3] = {0, 0, 0}, E1[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  double G0[3] = {0, 0, 0}, G1[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  R E0[3] = {R(0.0), R(0.0), R(0.0)};
+  R E1[3][3] = {{R(0.0), R(0.0), R(0.0)}, {R(0.0), R(0.0), R(0.0)}, {R(0.0), R(0.0), R(0.0)}};
+  R G0[3] = {R(0.0), R(0.0), R(0.0)};
+  R G1[3][3] = {{R(0.0), R(0.0), R(0.0)}, {R(0.0), R(0.0), R(0.0)}, {R(0.0), R(0.0), R(0.0)}};
 #pragma unroll
   for (int m = (DIM == 3 ? 0 : 2); m < 3; m++) {
     const int e0 = eidx3(g, m, i);
-    E0[m] = mue[e0];
-    if (GW) G0[m] = gw[e0];
+    E0[m] = R(mue[e0]);
+    if (GW) G0[m] = R(gw[e0]);
 #pragma unroll
     for (int a = 0; a < DIM; a++) {
       if (a == m) continue;
       int q[3] = {i[0], i[1], i[2]};
       q[a] = ip[a];
       const int e1 = eidx3(g, m, q);
-      E1[m][a] = mue[e1];
-      if (GW) G1[m][a] = gw[e1];
+      E1[m][a] = R(mue[e1]);
+      if (GW) G1[m][a] = R(gw[e1]);
     }
   }
-  double div = 0.0;
+  R div = R(0.0);
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
     // the face above along k: index i[k] + 1 (the wall face on a wall axis,
     // wrapped on a periodic one)
-    div += (V[k][1 + 2 * k] - V[k][0]) * ih;
+    div = div + (V[k][1 + 2 * k] - V[k][0]) * ih;
     if (low_wall(g, k, i)) continue;
-    double va[3] = {0, 0, 0}, vb[3] = {0, 0, 0};
-    double ulh_r[3] = {0, 0, 0}, ulh_l[3] = {0, 0, 0}, ull_r[3] = {0, 0, 0}, ull_l[3] = {0, 0, 0};
-    double mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0}, gwhi[3] = {0, 0, 0}, gwlo[3] = {0, 0, 0};
+    R va[3] = {R(0.0), R(0.0), R(0.0)}, vb[3] = {R(0.0), R(0.0), R(0.0)};
+    R ulh_r[3] = {R(0.0), R(0.0), R(0.0)}, ulh_l[3] = {R(0.0), R(0.0), R(0.0)};
+    R ull_r[3] = {R(0.0), R(0.0), R(0.0)}, ull_l[3] = {R(0.0), R(0.0), R(0.0)};
+    R mhi[3] = {R(0.0), R(0.0), R(0.0)}, mlo[3] = {R(0.0), R(0.0), R(0.0)};
+    R gwhi[3] = {R(0.0), R(0.0), R(0.0)}, gwlo[3] = {R(0.0), R(0.0), R(0.0)};
 #pragma unroll
     for (int l = 0; l < DIM; l++) {
       if (l == k) continue;
@@ -738,15 +808,15 @@ __global__ void k_apply_m(Geo g, const double *__restrict__ alpha, const double 
       gwlo[l] = G0[m];
     }
     const i64 q = fidx3(g, k, i);
-    const double al = alpha ? alpha[q] : 0.0;  // no alpha array: theta = 0
-    const double Au = a_row_mixed_core<DIM, GW>(
-        g, k, i, V[k][0], V[k][1 + 2 * k], V[k][2 + 2 * k], va, vb, ulh_r, ulh_l, ull_r, ull_l,
-        mhi, mlo, gwhi, gwlo, mc[0], mc[1 + k], al, lam != nullptr, lc[0], lc[1 + k]);
-    const double gp = (pc[0] - pc[1 + k]) * ih;
-    const double y = Au + gp;
-    yu[q] = bu ? bu[q] - y : y;
+    const R al = R(alpha ? alpha[q] : 0.0);  // no alpha array: theta = 0
+    const R Au = a_row_mixed_core<R, DIM, GW>(
+        g, k, i, ih, V[k][0], V[k][1 + 2 * k], V[k][2 + 2 * k], va, vb, ulh_r, ulh_l, ull_r,
+        ull_l, mhi, mlo, gwhi, gwlo, mc[0], mc[1 + k], al, lam != nullptr, lc[0], lc[1 + k]);
+    const R gp = (pc[0] - pc[1 + k]) * ih;
+    const R y = Au + gp;
+    yu[q] = to_double(bu ? R(bu[q]) - y : y);
   }
-  yp[t] = bp ? bp[t] + div : -div;
+  yp[t] = to_double(bp ? R(bp[t]) + div : -div);
 }
 
 template <typename TI>
@@ -755,10 +825,10 @@ void launch_apply_m(const Geo &g, const double *alpha, const double *muc, const 
                     const double *bp, double *yu, double *yp, hipStream_t s) {
   if (g.d == 3)
     hipLaunchKernelGGL((k_apply_m<TI, 3, false>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
-                       alpha, muc, mue, lam, xu, xp, bu, bp, nullptr, yu, yp);
+                       alpha, muc, mue, lam, xu, xp, bu, bp, nullptr, yu, yp, 0.0);
   else
     hipLaunchKernelGGL((k_apply_m<TI, 2, false>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
-                       alpha, muc, mue, lam, xu, xp, bu, bp, nullptr, yu, yp);
+                       alpha, muc, mue, lam, xu, xp, bu, bp, nullptr, yu, yp, 0.0);
 }
 template void launch_apply_m<double>(const Geo &, const double *, const double *, const double *,
                                      const double *, const double *, const double *,
@@ -774,10 +844,86 @@ void launch_apply_m_walls(const Geo &g, const double *alpha, const double *muc,
                           hipStream_t s) {
   if (g.d == 3)
     hipLaunchKernelGGL((k_apply_m<double, 3, true>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s,
-                       g, alpha, muc, mue, lam, xu, xp, nullptr, nullptr, gw, yu, yp);
+                       g, alpha, muc, mue, lam, xu, xp, nullptr, nullptr, gw, yu, yp, 0.0);
   else
     hipLaunchKernelGGL((k_apply_m<double, 2, true>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s,
-                       g, alpha, muc, mue, lam, xu, xp, nullptr, nullptr, gw, yu, yp);
+                       g, alpha, muc, mue, lam, xu, xp, nullptr, nullptr, gw, yu, yp, 0.0);
+}
+
+void launch_residual_dd(const Geo &g, const double *alpha, const double *muc, const double *mue,
+                        const double *lam, const double *xu, const double *xp, const double *bu,
+                        const double *bp, double *ru, double *rp, hipStream_t s) {
+  // low part of 1/h: the FMA remainder 1 - h ih is exact
+  const double ih_lo = std::fma(-g.h, g.ih, 1.0) / g.h;
+  if (g.d == 3)
+    hipLaunchKernelGGL((k_apply_m<double, 3, false, dd>), box_blocks(g, g.n[0]), dim3(kBlock), 0,
+                       s, g, alpha, muc, mue, lam, xu, xp, bu, bp, nullptr, ru, rp, ih_lo);
+  else
+    hipLaunchKernelGGL((k_apply_m<double, 2, false, dd>), box_blocks(g, g.n[0]), dim3(kBlock), 0,
+                       s, g, alpha, muc, mue, lam, xu, xp, bu, bp, nullptr, ru, rp, ih_lo);
+}
+
+// Diagonal scaling of the rescaled unknowns: 1 / sqrt(diag A) at the interior
+// velocity faces (1 on wall faces), sqrt(2 mu_cell + lam) at the cells.
+template <int DIM>
+__global__ void k_diag_scaling_faces(Geo g, int k, const double *__restrict__ alpha,
+                                     const double *__restrict__ muc,
+                                     const double *__restrict__ mue,
+                                     const double *__restrict__ lam,
+                                     const double *__restrict__ zero, double *__restrict__ sd) {
+  int i[3];
+  if (!box_thread(g, g.n[0], i[0], i[1], i[2])) return;
+  const i64 q = fidx3(g, k, i);
+  if (low_wall(g, k, i)) {
+    sd[q] = 1.0;
+    if (i[k] == 0) {  // the high wall face of the same line
+      int t[3] = {i[0], i[1], i[2]};
+      t[k] = g.n[k];
+      sd[fidx3(g, k, t)] = 1.0;
+    }
+    return;
+  }
+  double Au, dg;
+  a_row<double, DIM>(g, k, i, zero, alpha, muc, mue, lam, Au, dg);
+  sd[q] = 1.0 / sqrt(dg);
+}
+
+__global__ void k_diag_scaling_cells(const double *__restrict__ muc, const double *__restrict__ lam,
+                                     i64 n, double *__restrict__ sd, int *__restrict__ bad) {
+  const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double sig = 2.0 * muc[t] + (lam ? lam[t] : 0.0);
+  if (!(sig > 0.0)) *bad = 1;
+  sd[t] = sig > 0.0 ? sqrt(sig) : 1.0;
+}
+
+void launch_diag_scaling(const Geo &g, const double *alpha, const double *muc, const double *mue,
+                         const double *lam, const double *zero, double *sd, int *bad,
+                         hipStream_t s) {
+  for (int k = 0; k < g.d; k++) {
+    if (g.d == 3)
+      hipLaunchKernelGGL((k_diag_scaling_faces<3>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
+                         k, alpha, muc, mue, lam, zero, sd);
+    else
+      hipLaunchKernelGGL((k_diag_scaling_faces<2>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
+                         k, alpha, muc, mue, lam, zero, sd);
+  }
+  hipLaunchKernelGGL(k_diag_scaling_cells, dim3((unsigned)((g.ncell + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, muc, lam, g.ncell, sd + g.nvel, bad);
+}
+
+// y = x * s (inv = 0) or y = x / s (inv = 1), elementwise; y may equal x
+__global__ void k_mul_scaling(const double *x, const double *__restrict__ sd, int inv, i64 n,
+                              double *y) {
+  const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  y[t] = inv ? x[t] / sd[t] : x[t] * sd[t];
+}
+
+void launch_mul_scaling(const double *x, const double *sd, int inv, i64 n, double *y,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_mul_scaling, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, x, sd, inv, n, y);
 }
 
 // out = scale * in on the wall faces, 0 elsewhere (the wall-data field)

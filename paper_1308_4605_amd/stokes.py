@@ -27,7 +27,7 @@ STOKES_EINCOMPAT = -7
 
 # names declared in include/stokes.h
 ABI_FUNCTIONS = (
-    "stokes_sizes", "stokes_workspace_bytes", "stokes_create", "stokes_apply",
+    "stokes_sizes", "stokes_workspace_bytes", "stokes_create", "stokes_apply", "stokes_residual",
     "stokes_boundary_rhs", "stokes_precond",
     "stokes_vel_subsolve", "stokes_p_subsolve", "stokes_vel_mg_solve", "stokes_p_mg_solve",
     "stokes_solve", "stokes_solve_static", "stokes_adjoint_solve",
@@ -43,7 +43,8 @@ class StokesParams(ctypes.Structure):
                 ("precision", ctypes.c_int), ("krylov", ctypes.c_int), ("restart", ctypes.c_int),
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("nu_coarse", ctypes.c_int),
                 ("vcycles", ctypes.c_int), ("rescale_c", ctypes.c_double),
-                ("edge_avg", ctypes.c_int), ("bulk", ctypes.c_int)]
+                ("edge_avg", ctypes.c_int), ("bulk", ctypes.c_int), ("scaling", ctypes.c_int),
+                ("extended", ctypes.c_int)]
 
 
 class StokesStats(ctypes.Structure):
@@ -90,6 +91,7 @@ def lib():
                                     ctypes.POINTER(ctypes.c_void_p)]
         L.stokes_apply.argtypes = [vp, dp, dp, dp, dp]
         L.stokes_precond.argtypes = [vp, dp, dp, dp, dp]
+        L.stokes_residual.argtypes = [vp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
         L.stokes_boundary_rhs.argtypes = [vp, dp, dp, dp, dp]
         L.stokes_vel_subsolve.argtypes = [vp, dp, dp]
         L.stokes_p_subsolve.argtypes = [vp, dp, dp]
@@ -126,7 +128,7 @@ def strerror(code: int) -> str:
 
 def make_params(dim, n, bc, h, theta, precond=1, precision=0, krylov=0, restart=10, nu_pre=2,
                 nu_post=2, nu_coarse=8, vcycles=1, rescale_c=0.0, edge_avg=0, bulk=0,
-                **_ignored):
+                scaling=0, extended=0, **_ignored):
     p = StokesParams()
     p.dim = int(dim)
     n = tuple(n) + (1,) * (3 - len(n))
@@ -139,6 +141,7 @@ def make_params(dim, n, bc, h, theta, precond=1, precision=0, krylov=0, restart=
     p.nu_pre, p.nu_post, p.nu_coarse, p.vcycles = int(nu_pre), int(nu_post), int(nu_coarse), int(vcycles)
     p.rescale_c, p.edge_avg = float(rescale_c), int(edge_avg)
     p.bulk = int(bulk)
+    p.scaling, p.extended = int(scaling), int(extended)
     return p
 
 
@@ -216,6 +219,15 @@ class Stokes:
         if rc:
             raise StokesError(rc, "stokes_apply")
         return yu, yp
+
+    def residual(self, bu, bp, xu, xp, extended=False):
+        """r = b - M x (FP64, or double-double rounded once when extended)."""
+        ru, rp = self._new(self.nvel), self._new(self.ncell)
+        rc = lib().stokes_residual(self._h, _ptr(bu), _ptr(bp), _ptr(xu), _ptr(xp), _ptr(ru),
+                                   _ptr(rp), 1 if extended else 0)
+        if rc:
+            raise StokesError(rc, "stokes_residual")
+        return ru, rp
 
     def precond(self, bu, bp):
         zu, zp = self._new(self.nvel), self._new(self.ncell)
