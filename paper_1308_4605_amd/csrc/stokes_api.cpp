@@ -190,6 +190,7 @@ void *scratch_on(int dev) {
 }
 
 constexpr int kDscSlots = 256;  // device scalar slots
+constexpr int kZeroSlots = 216;  // dsc[216..255] stay zero (cleared with the workspace)
 
 // The velocity levels above the one-workgroup coarse tail of an FP32
 // hierarchy are stored colour-split when the finest rows are long (a wave
@@ -898,7 +899,11 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     launch_fill<double>(X->x, 0.0, n, X->s);
     return STOKES_OK;
   }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hc2(m + 2);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  // unrotated Hessenberg columns (left GMRES), the correction of the
+  // provisional basis vector (c, 1 / alpha) for this step and the next
+  std::vector<double> Hraw((size_t)(m + 1) * m), colbuf(m + 2), cprev(m + 2), cnext(m + 2);
+  double iaprev = 1.0, ianext = 1.0;
   int it = 0, rc = STOKES_OK;
   for (;;) {
     // r = b - M x and its norm
@@ -932,6 +937,8 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     }
     const double target = beta * tol * nb / rho;
     std::fill(H.begin(), H.end(), 0.0);
+    std::fill(Hraw.begin(), Hraw.end(), 0.0);
+    iaprev = 1.0;  // V[0] is exactly normalised
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jj = 0;
@@ -966,39 +973,74 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       }
       st->precond_applies++;
       it++;
-      // CGS2: pass A (h1 = V^T w), pass B (w' = w - V h1; h2 = V^T w'; s2 = (w',w'))
-      launch_cgs_dots(X->w, X->V, j + 1, n, X->part, X->dsc + 32, X->s);
-      launch_cgs_proj(X->w, X->V, X->dsc + 32, j + 1, n, X->part, X->dsc + 72, X->s);
-      hip_ok(X, hipMemcpyAsync(hb + 32, X->dsc + 32, (j + 1) * sizeof(double),
+      // Arnoldi step, two passes with the second Gram-Schmidt pass lagged by
+      // one step.  V[j] holds the provisional vt_j, v_j = (vt_j - V c) * ia.
+      // Pass R: dots of w with v_0..v_{j-1}, vt_j, and (w, w).  Pass U:
+      // finalise v_j, project w once (coefficients d and f), write the next
+      // provisional vector (and its FP32 copy for the next flexible
+      // preconditioner application) and reduce its dots with v_0..v_j.
+      launch_cgs_dots(X->w, X->V, j + 1, n, X->part, X->dsc + 32, X->s, true);
+      launch_dcgs_update(X->w, X->V, j, cprev.data(), iaprev, X->dsc + 32, n, X->V[j + 1],
+                         (flexible && X->mg32 && !S) ? P<float>(X->pin) : nullptr, X->dsc + 30,
+                         X->part, X->dsc + 72, X->s);
+      hip_ok(X, hipMemcpyAsync(hb + 30, X->dsc + 30, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                               X->s));
+      hip_ok(X, hipMemcpyAsync(hb + 32, X->dsc + 32, (j + 2) * sizeof(double),
                                hipMemcpyDeviceToHost, X->s));
       hip_ok(X, hipMemcpyAsync(hb + 72, X->dsc + 72, (j + 2) * sizeof(double),
                                hipMemcpyDeviceToHost, X->s));
       hip_ok(X, hipStreamSynchronize(X->s));
       if (X->err) return STOKES_EDEVICE;
       pc.fold();
-      double *hcol = &H[(size_t)j * (m + 1)];
-      double q = 0.0;
-      for (int i = 0; i <= j; i++) {
-        q += hb[72 + i] * hb[72 + i];
-        hcol[i] = hb[32 + i] + hb[72 + i];
+      const double f = hb[30], nu = hb[31];
+      // projection of the new Krylov vector onto the final v_0..v_j:
+      // (d_0..d_{j-1}, f); vt_{j+1} = (w - V (d, f)) / nu
+      std::vector<double> &col = colbuf;
+      for (int i = 0; i < j; i++) col[i] = hb[32 + i];
+      col[j] = f;
+      double sc = nu;  // weight of vt_{j+1} in the column
+      if (!flexible) {
+        // left GMRES applied the operator to vt_j = alpha_j v_j + V c: by
+        // linearity the column of v_j is (V^T w - Hraw c) / alpha_j
+        for (int i = 0; i <= j; i++) {
+          double acc = col[i];
+          for (int l = 0; l < j; l++) acc -= cprev[l] * Hraw[i + (size_t)l * (m + 1)];
+          col[i] = acc * iaprev;
+        }
+        sc = nu * iaprev;
       }
-      const double s2 = hb[72 + j + 1];
-      const double nu2 = s2 - q;
-      // ||w - V h2||^2 = s2 - ||h2||^2 while V is orthonormal; form it
-      // explicitly when the second pass removed half or more of s2
-      bool formed = false;
-      double hn;
-      if (nu2 > 0.5 * s2) {
-        hn = std::sqrt(nu2);
+      // second pass of vt_{j+1}: vt_{j+1} = alpha v_{j+1} + V c'
+      double cc = 0.0;
+      for (int i = 0; i <= j; i++) cc += hb[72 + i] * hb[72 + i];
+      const double vv = hb[72 + j + 1];
+      double alpha;
+      if (vv - cc > 0.5 * vv) {
+        alpha = std::sqrt(vv - cc);
+        for (int i = 0; i <= j; i++) cnext[i] = hb[72 + i];
+        ianext = 1.0 / alpha;
       } else {
-        // in place (out == w): k_cgs_next reads and writes each element
-        // in the same thread and declares neither pointer restrict
-        launch_cgs_next(X->w, X->V, X->dsc + 32, X->dsc + 72, j + 1, 1.0, n, X->w, nullptr,
-                        X->part, X->dsc + 0, X->s);
-        hn = std::sqrt(fetch(X, X->dsc, 1, hb));
-        formed = true;
+        // the lagged pass would remove half or more of vt_{j+1}: apply it
+        // now and measure the result (FP32 copy rewritten)
+        launch_cgs_next(X->V[j + 1], X->V, X->dsc + 72, X->dsc + kZeroSlots, j + 1, 1.0, n,
+                        X->V[j + 1], nullptr, X->part, X->dsc + 0, X->s);
+        alpha = std::sqrt(fetch(X, X->dsc, 1, hb));
+        if (X->err) return STOKES_EDEVICE;
+        if (alpha > 0.0)
+          launch_cgs_next(X->V[j + 1], X->V, nullptr, nullptr, 0, 1.0 / alpha, n, X->V[j + 1],
+                          (flexible && X->mg32 && !S) ? P<float>(X->pin) : nullptr, X->part,
+                          nullptr, X->s);
+        for (int i = 0; i <= j; i++) cnext[i] = 0.0;
+        ianext = 1.0;
       }
-      hcol[j + 1] = hn;
+      // either way vt_{j+1} = alpha v_{j+1} + V c': the column gains sc c'
+      for (int i = 0; i <= j; i++) col[i] += sc * hb[72 + i];
+      col[j + 1] = sc * alpha;
+      for (int i = 0; i <= j + 1; i++) Hraw[i + (size_t)j * (m + 1)] = col[i];
+      std::swap(cprev, cnext);
+      iaprev = ianext;
+      double *hcol = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i <= j + 1; i++) hcol[i] = col[i];
+      const double hn = hcol[j + 1];
       for (int i = 0; i < j; i++) {
         const double a = hcol[i], bb = hcol[i + 1];
         hcol[i] = cs[i] * a + sn[i] * bb;
@@ -1022,11 +1064,6 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       if (hist && st->history_len < hcap) hist[st->history_len++] = st->rel_res_est;
       if (!std::isfinite(est)) break;
       if (hn == 0.0 || est <= target || it >= max_iter) break;
-      // pass C: v_{j+1} = (w - V (h1 + h2)) / nu, plus the FP32 copy the next
-      // flexible preconditioner application starts from
-      launch_cgs_next(X->w, X->V, X->dsc + 32, X->dsc + 72, formed ? 0 : j + 1, 1.0 / hn, n,
-                      X->V[j + 1], (flexible && X->mg32 && !S) ? P<float>(X->pin) : nullptr, X->part,
-                      nullptr, X->s);
     }
     for (int i = jj - 1; i >= 0; i--) {
       double s = g[i];

@@ -196,8 +196,9 @@ void launch_vel_remove_means(const Geo &g, const T *in, T *out, double *partials
 constexpr int kRedBlocks = 2048;
 // Arnoldi by classical Gram-Schmidt applied twice (CGS2), three passes:
 //   h[i] = (w, v_i), i < nv
+//   (with_norm: h[nv] = (w, w))
 void launch_cgs_dots(const double *w, const double *const *v, int nv, i64 n, double *partials,
-                     double *h, hipStream_t s);
+                     double *h, hipStream_t s, bool with_norm = false);
 //   w' = w - sum_i h_i v_i (not stored); h2s2[i] = (w', v_i) for i < nv,
 //   h2s2[nv] = (w', w')
 void launch_cgs_proj(const double *w, const double *const *v, const double *h, int nv, i64 n,
@@ -208,6 +209,15 @@ void launch_cgs_proj(const double *w, const double *const *v, const double *h, i
 void launch_cgs_next(const double *w, const double *const *v, const double *h1, const double *h2,
                      int nv, double inv_nu, i64 n, double *out, float *out32, double *partials,
                      double *nrm2, hipStream_t s);
+// Arnoldi step with lagged reorthogonalisation (second pass of the
+// two-pass form): v[0..j-1] final, v[j] provisional with
+// v_j = (v[j] - sum_i c_i v_i) * ia; dots = {(w, v_i), i < j; (w, v[j]);
+// (w, w)} from launch_cgs_dots.  Finalises v[j] in place, writes the next
+// provisional vector to vnext (and as FP32 to out32 when given), stores
+// {f, nu} in coef_out and red = {(vnext, v_i), i <= j; (vnext, vnext)}.
+void launch_dcgs_update(const double *w, double *const *v, int j, const double *c, double ia,
+                        const double *dots, i64 n, double *vnext, float *out32,
+                        double *coef_out, double *partials, double *red, hipStream_t s);
 // x += sum_i y_i z_i with z in precision TZ (y: host array, passed by value)
 template <typename TZ>
 void launch_update_x(double *x, const TZ *const *z, const double *y, int nz, i64 n,

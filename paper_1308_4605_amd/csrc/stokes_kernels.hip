@@ -2265,6 +2265,12 @@ struct PtrPack {
   const void *p[34];
 };
 
+struct CoefPack {
+  double c[34];
+};
+// index of 1 / alpha in the coefficient pack of k_dcgs_update
+constexpr int kMaxArnC = 33;
+
 // ---- Arnoldi by classical Gram-Schmidt applied twice (CGS2) -------------
 // Three streaming passes over [w, v_0..v_j] with double2 loads, a fixed grid
 // and per-block partial sums (bitwise reproducible); pass C without a norm to
@@ -2302,9 +2308,10 @@ __device__ __forceinline__ void block_store(double (&acc)[MAXV + 1], int nv, boo
   }
 }
 
+// with_norm: slot nv also receives (w, w)
 template <int MAXV>
 __global__ void __launch_bounds__(kArnBlock) k_cgs_dots(const double *__restrict__ w, PtrPack v,
-                                                        int nv, i64 n, int stride,
+                                                        int nv, i64 n, int stride, int with_norm,
                                                         double *__restrict__ partials) {
   double acc[MAXV + 1];
 #pragma unroll
@@ -2320,12 +2327,14 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_dots(const double *__restrict
         acc[i] += a.x * b.x + a.y * b.y;
       }
     }
+    if (with_norm) acc[MAXV] += a.x * a.x + a.y * a.y;
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
     const double a = w[n - 1];
     for (int i = 0; i < nv; i++) acc[i] += a * ((const double *)v.p[i])[n - 1];
+    if (with_norm) acc[MAXV] += a * a;
   }
-  block_store<MAXV>(acc, nv, false, stride, partials);
+  block_store<MAXV>(acc, nv, with_norm != 0, stride, partials);
 }
 
 template <int MAXV>
@@ -2413,6 +2422,118 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_next(const double *w, PtrPack
   if (partials) block_store<MAXV>(acc, 0, true, 1, partials);
 }
 
+// ---- Arnoldi with lagged reorthogonalisation (two passes per step) -------
+// Step j holds the final orthonormal v_0..v_{j-1} and a provisional vt_j
+// with v_j = (vt_j - sum_{i<j} c_i v_i) * ia (c, ia = 1 / alpha from the
+// previous step's reduction).  The new Krylov vector w (the operator
+// applied to vt_j) has been reduced against the stored vectors:
+// dots = {(w, v_i) for i < j, (w, vt_j), (w, w)}.  This pass then
+//   - finalises v_j in place,
+//   - projects w once against v_0..v_j with the coefficients d_i = (w, v_i)
+//     and f = (w, v_j) = ((w, vt_j) - sum_i c_i d_i) * ia,
+//   - writes the next provisional vector vt_{j+1} = (w - V d - f v_j) / nu
+//     with nu^2 = (w, w) - |d|^2 - f^2 (clamped: nu only scales vt_{j+1}),
+//     also as FP32 when out32 is given,
+//   - reduces (vt_{j+1}, v_i) for i <= j and (vt_{j+1}, vt_{j+1}): the
+//     second Gram-Schmidt pass of vt_{j+1}, applied by the next step.
+// Block 0 stores f and nu in coef_out[0..1] for the Hessenberg matrix.
+// Each element is read and written by one thread (v.p[j] is updated in place).
+template <int MAXV>
+__global__ void __launch_bounds__(kArnBlock) k_dcgs_update(const double *__restrict__ w, PtrPack v,
+                                                           int j, CoefPack cf,
+                                                           const double *__restrict__ dots,
+                                                           i64 n, double *vnext, float *out32,
+                                                           double *__restrict__ coef_out,
+                                                           double *__restrict__ partials) {
+  // coefficients (the same few values in every thread)
+  const double ia = cf.c[kMaxArnC];
+  double c[MAXV], d[MAXV];
+  double cd = 0.0, dd2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < MAXV; i++) {
+    c[i] = (i < j) ? cf.c[i] : 0.0;
+    d[i] = (i < j) ? dots[i] : 0.0;
+    cd += c[i] * d[i];
+    dd2 += d[i] * d[i];
+  }
+  const double f = (dots[j] - cd) * ia;
+  const double q = dots[j + 1];
+  double nu2 = q - dd2 - f * f;
+  // nu only scales the provisional vector (the next reduction measures it);
+  // keep it positive when cancellation leaves nothing reliable
+  const double floor2 = q * 0x1p-60;
+  const double nu = (nu2 > floor2) ? sqrt(nu2) : (q > 0.0 ? sqrt(floor2) : 1.0);
+  const double inu = 1.0 / nu;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    coef_out[0] = f;
+    coef_out[1] = nu;
+  }
+  double acc[MAXV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXV; i++) acc[i] = 0.0;
+  const i64 n2 = n >> 1;
+  const double2 *w2 = (const double2 *)w;
+  double2 *vj2 = (double2 *)v.p[j];
+  double2 *vn2 = (double2 *)vnext;
+  float2 *f2 = (float2 *)out32;
+  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n2; t += (i64)gridDim.x * blockDim.x) {
+    const double2 a = w2[t];
+    double2 vj = vj2[t];
+    double2 b[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; i++) {
+      if (i < j) {
+        b[i] = ((const double2 *)v.p[i])[t];
+        vj.x -= c[i] * b[i].x;
+        vj.y -= c[i] * b[i].y;
+      }
+    }
+    vj.x *= ia;
+    vj.y *= ia;
+    double2 wp = a;
+#pragma unroll
+    for (int i = 0; i < MAXV; i++) {
+      if (i < j) {
+        wp.x -= d[i] * b[i].x;
+        wp.y -= d[i] * b[i].y;
+      }
+    }
+    wp.x = (wp.x - f * vj.x) * inu;
+    wp.y = (wp.y - f * vj.y) * inu;
+    vj2[t] = vj;
+    vn2[t] = wp;
+    if (out32) f2[t] = make_float2((float)wp.x, (float)wp.y);
+    // slot i < j: (vt_{j+1}, v_i); slot j: (vt_{j+1}, v_j) (compile-time
+    // register indices, the slot chosen by predicate)
+#pragma unroll
+    for (int i = 0; i < MAXV; i++) {
+      if (i < j) acc[i] += b[i].x * wp.x + b[i].y * wp.y;
+      if (i == j) acc[i] += vj.x * wp.x + vj.y * wp.y;
+    }
+    acc[MAXV] += wp.x * wp.x + wp.y * wp.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const i64 e = n - 1;
+    double vj = ((const double *)v.p[j])[e];
+    for (int i = 0; i < j; i++) vj -= cf.c[i] * ((const double *)v.p[i])[e];
+    vj *= ia;
+    double wp = w[e];
+    for (int i = 0; i < j; i++) wp -= dots[i] * ((const double *)v.p[i])[e];
+    wp = (wp - f * vj) * inu;
+    ((double *)v.p[j])[e] = vj;
+    vnext[e] = wp;
+    if (out32) out32[e] = (float)wp;
+#pragma unroll
+    for (int i = 0; i < MAXV; i++) {
+      if (i < j) acc[i] += ((const double *)v.p[i])[e] * wp;
+      if (i == j) acc[i] += vj * wp;
+    }
+    acc[MAXV] += wp * wp;
+  }
+  // slots 0..j: (vt_{j+1}, v_i); slot j + 1: (vt_{j+1}, vt_{j+1})
+  block_store<MAXV>(acc, j + 1, true, j + 2, partials);
+}
+
 static int arn_blocks(i64 n) {
   i64 b = ((n >> 1) + kArnBlock - 1) / kArnBlock;
   if (b > kArnGrid) b = kArnGrid;
@@ -2428,12 +2549,13 @@ static int arn_blocks(i64 n) {
   } while (0)
 
 void launch_cgs_dots(const double *w, const double *const *v, int nv, i64 n, double *partials,
-                     double *h, hipStream_t s) {
+                     double *h, hipStream_t s, bool with_norm) {
   PtrPack pk;
   for (int j = 0; j < nv; j++) pk.p[j] = v[j];
   const int nb = arn_blocks(n);
-  ARN_DISPATCH(k_cgs_dots, nv, w, pk, nv, n, nv, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, nv, nv, h);
+  const int nout = nv + (with_norm ? 1 : 0);
+  ARN_DISPATCH(k_cgs_dots, nv, w, pk, nv, n, nout, with_norm ? 1 : 0, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, nout, nout, h);
 }
 
 void launch_cgs_proj(const double *w, const double *const *v, const double *h, int nv, i64 n,
@@ -2460,11 +2582,21 @@ void launch_cgs_next(const double *w, const double *const *v, const double *h1, 
                nrm2 ? partials : nullptr);
   if (nrm2) hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, nrm2);
 }
+void launch_dcgs_update(const double *w, double *const *v, int j, const double *c, double ia,
+                        const double *dots, i64 n, double *vnext, float *out32,
+                        double *coef_out, double *partials, double *red, hipStream_t s) {
+  PtrPack pk;
+  for (int i = 0; i <= j; i++) pk.p[i] = v[i];
+  CoefPack cf;
+  for (int i = 0; i < 34; i++) cf.c[i] = 0.0;
+  for (int i = 0; i < j; i++) cf.c[i] = c[i];
+  cf.c[kMaxArnC] = ia;
+  const int nb = arn_blocks(n);
+  ARN_DISPATCH(k_dcgs_update, j + 1, w, pk, j, cf, dots, n, vnext, out32, coef_out, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, j + 2, j + 2, red);
+}
 #undef ARN_DISPATCH
 
-struct CoefPack {
-  double c[34];
-};
 
 template <typename TZ>
 __global__ void k_update_x(double *__restrict__ x, PtrPack z, CoefPack y, int nz, i64 n) {
