@@ -122,6 +122,9 @@ struct stokes_ctx {
   // diagonal scaling S of the rescaled unknowns [faces | cells]
   // (STOKES_SCALE_DIAGONAL; null otherwise)
   double *sdiag = nullptr;
+  // device copy of the Arnoldi basis transform T (upper triangular,
+  // row-major, row stride restart + 1)
+  double *tmat = nullptr;
   // preconditioner temporaries (precision T, level-0 sizes)
   void *pin = nullptr, *pout = nullptr;           // [u | p]
   void *xs = nullptr, *tu = nullptr, *eu = nullptr;  // velocity
@@ -271,6 +274,8 @@ void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
   double *gc = (double *)cv.take(nc * 8);
   double *sd = (p->scaling == STOKES_SCALE_DIAGONAL) ? (double *)cv.take(nn * 8) : nullptr;
   if (X) X->sdiag = sd;
+  double *tm = (double *)cv.take((size_t)(kMaxRestart + 1) * (kMaxRestart + 1) * 8);
+  if (X) X->tmat = tm;
   if (use_vsplit(p)) {
     void *a = cv.take(nv * tb), *b = cv.take(nv * tb), *c = cv.take(nv * tb);
     if (X) {
@@ -902,7 +907,8 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   // unrotated Hessenberg columns (left GMRES), the correction of the
   // provisional basis vector (c, 1 / alpha) for this step and the next
-  std::vector<double> Hraw((size_t)(m + 1) * m), colbuf(m + 2), cprev(m + 2), cnext(m + 2);
+  std::vector<double> Hraw((size_t)(m + 1) * m), colbuf(m + 2), cprev(m + 2), cnext(m + 2),
+      tc(m + 2), Tm((size_t)(m + 1) * (m + 1)), ty(m + 1);
   double iaprev = 1.0, ianext = 1.0;
   int it = 0, rc = STOKES_OK;
   for (;;) {
@@ -938,11 +944,24 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     const double target = beta * tol * nb / rho;
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(Hraw.begin(), Hraw.end(), 0.0);
-    iaprev = 1.0;  // V[0] is exactly normalised
+    // V[0] is exactly normalised: T = I so far
+    std::fill(Tm.begin(), Tm.end(), 0.0);
+    for (int i = 0; i <= m; i++) Tm[(size_t)i * (m + 1) + i] = 1.0;
+    iaprev = 1.0;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jj = 0;
     for (int j = 0; j < m; j++) {
+      if (j + 1 > 12) {
+        // the basis transform outgrows the kernel arguments: stage it in
+        // device memory now, while the stream is idle after the last step
+        const int ld = m + 1;
+        double *tpin = hb + 2048;
+        for (int r = 0; r <= j; r++)
+          for (int cidx = 0; cidx <= j; cidx++) tpin[r * ld + cidx] = Tm[r * ld + cidx];
+        hip_ok(X, hipMemcpyAsync(X->tmat, tpin, (size_t)(j + 1) * ld * sizeof(double),
+                                 hipMemcpyHostToDevice, X->s));
+      }
       if (flexible) {
         pc.start();
         if (S) {
@@ -973,35 +992,35 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
       }
       st->precond_applies++;
       it++;
-      // Arnoldi step, two passes with the second Gram-Schmidt pass lagged by
-      // one step.  V[j] holds the provisional vt_j, v_j = (vt_j - V c) * ia.
-      // Pass R: dots of w with v_0..v_{j-1}, vt_j, and (w, w).  Pass U:
-      // finalise v_j, project w once (coefficients d and f), write the next
-      // provisional vector (and its FP32 copy for the next flexible
-      // preconditioner application) and reduce its dots with v_0..v_j.
+      // Arnoldi step in two passes, the second Gram-Schmidt pass of each new
+      // vector lagged into the transform T of the stored once-orthogonalised
+      // vectors (orthonormal basis = V T).  Pass R: dots of w with the stored
+      // v_0..v_j and (w, w).  Pass U: project w on the orthonormal basis,
+      // write the next stored vector (and its FP32 copy for the next
+      // flexible preconditioner application) and reduce its dots with the
+      // stored vectors.
+      const int ld = m + 1;
       launch_cgs_dots(X->w, X->V, j + 1, n, X->part, X->dsc + 32, X->s, true);
-      launch_dcgs_update(X->w, X->V, j, cprev.data(), iaprev, X->dsc + 32, n, X->V[j + 1],
-                         (flexible && X->mg32 && !S) ? P<float>(X->pin) : nullptr, X->dsc + 30,
+      launch_dcgs_update(X->w, X->V, j, X->dsc + 32, Tm.data(), X->tmat, ld, n, X->V[j + 1],
+                         (flexible && X->mg32 && !S) ? P<float>(X->pin) : nullptr, X->dsc + 110,
                          X->part, X->dsc + 72, X->s);
-      hip_ok(X, hipMemcpyAsync(hb + 30, X->dsc + 30, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                               X->s));
-      hip_ok(X, hipMemcpyAsync(hb + 32, X->dsc + 32, (j + 2) * sizeof(double),
+      hip_ok(X, hipMemcpyAsync(hb + 110, X->dsc + 110, (j + 2) * sizeof(double),
                                hipMemcpyDeviceToHost, X->s));
       hip_ok(X, hipMemcpyAsync(hb + 72, X->dsc + 72, (j + 2) * sizeof(double),
                                hipMemcpyDeviceToHost, X->s));
       hip_ok(X, hipStreamSynchronize(X->s));
       if (X->err) return STOKES_EDEVICE;
       pc.fold();
-      const double f = hb[30], nu = hb[31];
-      // projection of the new Krylov vector onto the final v_0..v_j:
-      // (d_0..d_{j-1}, f); vt_{j+1} = (w - V (d, f)) / nu
+      const double nu = hb[110 + j + 1];
+      // d = projections of w on the orthonormal basis (computed by pass U);
+      // the next stored vector is (w - V d) / nu
       std::vector<double> &col = colbuf;
-      for (int i = 0; i < j; i++) col[i] = hb[32 + i];
-      col[j] = f;
-      double sc = nu;  // weight of vt_{j+1} in the column
+      for (int i = 0; i <= j; i++) col[i] = hb[110 + i];
+      double sc = nu;  // weight of the stored vector in the column
       if (!flexible) {
-        // left GMRES applied the operator to vt_j = alpha_j v_j + V c: by
-        // linearity the column of v_j is (V^T w - Hraw c) / alpha_j
+        // left GMRES applied the operator to the stored v_j = alpha_j u_j +
+        // U c (u the orthonormal basis): by linearity the column of u_j is
+        // (U^T w - Hraw c) / alpha_j
         for (int i = 0; i <= j; i++) {
           double acc = col[i];
           for (int l = 0; l < j; l++) acc -= cprev[l] * Hraw[i + (size_t)l * (m + 1)];
@@ -1009,19 +1028,39 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
         }
         sc = nu * iaprev;
       }
-      // second pass of vt_{j+1}: vt_{j+1} = alpha v_{j+1} + V c'
+      // second pass of the stored vector: its dots with the orthonormal basis
+      // c' = T^T (V^T v_{j+1}), and alpha^2 = |v_{j+1}|^2 - |c'|^2
       double cc = 0.0;
-      for (int i = 0; i <= j; i++) cc += hb[72 + i] * hb[72 + i];
+      for (int i = 0; i <= j; i++) {
+        double acc = 0.0;
+        for (int l = 0; l <= i; l++) acc += Tm[l * ld + i] * hb[72 + l];
+        cnext[i] = acc;
+        cc += acc * acc;
+      }
       const double vv = hb[72 + j + 1];
+      // T c' (the coefficients of U c' on the stored vectors)
+      for (int l = 0; l <= j; l++) {
+        double acc = 0.0;
+        for (int i = l; i <= j; i++) acc += Tm[l * ld + i] * cnext[i];
+        tc[l] = acc;
+      }
       double alpha;
+      for (int l = 0; l <= j + 1; l++) Tm[l * ld + j + 1] = 0.0;
       if (vv - cc > 0.5 * vv) {
         alpha = std::sqrt(vv - cc);
-        for (int i = 0; i <= j; i++) cnext[i] = hb[72 + i];
+        // u_{j+1} = (v_{j+1} - V T c') / alpha
+        for (int l = 0; l <= j; l++) Tm[l * ld + j + 1] = -tc[l] / alpha;
+        Tm[(j + 1) * ld + j + 1] = 1.0 / alpha;
         ianext = 1.0 / alpha;
       } else {
-        // the lagged pass would remove half or more of vt_{j+1}: apply it
-        // now and measure the result (FP32 copy rewritten)
-        launch_cgs_next(X->V[j + 1], X->V, X->dsc + 72, X->dsc + kZeroSlots, j + 1, 1.0, n,
+        // the lagged pass would remove half or more of the stored vector:
+        // apply it now, measure and normalise the result (FP32 copy
+        // rewritten), which is then stored orthonormal
+        double *cpin = hb + 1024;
+        for (int l = 0; l <= j; l++) cpin[l] = tc[l];
+        hip_ok(X, hipMemcpyAsync(X->dsc + 150, cpin, (j + 1) * sizeof(double),
+                                 hipMemcpyHostToDevice, X->s));
+        launch_cgs_next(X->V[j + 1], X->V, X->dsc + 150, X->dsc + kZeroSlots, j + 1, 1.0, n,
                         X->V[j + 1], nullptr, X->part, X->dsc + 0, X->s);
         alpha = std::sqrt(fetch(X, X->dsc, 1, hb));
         if (X->err) return STOKES_EDEVICE;
@@ -1029,13 +1068,16 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
           launch_cgs_next(X->V[j + 1], X->V, nullptr, nullptr, 0, 1.0 / alpha, n, X->V[j + 1],
                           (flexible && X->mg32 && !S) ? P<float>(X->pin) : nullptr, X->part,
                           nullptr, X->s);
-        for (int i = 0; i <= j; i++) cnext[i] = 0.0;
+        Tm[(j + 1) * ld + j + 1] = 1.0;
+        // the operator of the next left-GMRES step sees the final vector
         ianext = 1.0;
       }
-      // either way vt_{j+1} = alpha v_{j+1} + V c': the column gains sc c'
-      for (int i = 0; i <= j; i++) col[i] += sc * hb[72 + i];
+      // either way v_{j+1} = alpha u_{j+1} + U c': the column gains sc c'
+      for (int i = 0; i <= j; i++) col[i] += sc * cnext[i];
       col[j + 1] = sc * alpha;
       for (int i = 0; i <= j + 1; i++) Hraw[i + (size_t)j * (m + 1)] = col[i];
+      if (!(vv - cc > 0.5 * vv))
+        for (int i = 0; i <= j; i++) cnext[i] = 0.0;
       std::swap(cprev, cnext);
       iaprev = ianext;
       double *hcol = &H[(size_t)j * (m + 1)];
@@ -1076,13 +1118,22 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
         launch_update_x<float>(X->x, (const float *const *)X->Z, y.data(), jj, n, X->s);
       else
         launch_update_x<double>(X->x, (const double *const *)X->Z, y.data(), jj, n, X->s);
-    } else if (S) {
-      launch_fill<double>(X->t, 0.0, n, X->s);
-      launch_update_x<double>(X->t, (const double *const *)X->V, y.data(), jj, n, X->s);
-      launch_mul_scaling(X->t, S, 0, n, X->t, X->s);
-      launch_axpy<double>(1.0, X->t, X->x, n, X->s);
     } else {
-      launch_update_x<double>(X->x, (const double *const *)X->V, y.data(), jj, n, X->s);
+      // x += U y with the orthonormal basis U = V T: coefficients T y on the
+      // stored vectors
+      for (int l = 0; l < jj; l++) {
+        double acc = 0.0;
+        for (int i = l; i < jj; i++) acc += Tm[(size_t)l * (m + 1) + i] * y[i];
+        ty[l] = acc;
+      }
+      if (S) {
+        launch_fill<double>(X->t, 0.0, n, X->s);
+        launch_update_x<double>(X->t, (const double *const *)X->V, ty.data(), jj, n, X->s);
+        launch_mul_scaling(X->t, S, 0, n, X->t, X->s);
+        launch_axpy<double>(1.0, X->t, X->x, n, X->s);
+      } else {
+        launch_update_x<double>(X->x, (const double *const *)X->V, ty.data(), jj, n, X->s);
+      }
     }
   }
   st->iters = it;

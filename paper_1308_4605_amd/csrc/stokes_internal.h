@@ -210,14 +210,18 @@ void launch_cgs_next(const double *w, const double *const *v, const double *h1, 
                      int nv, double inv_nu, i64 n, double *out, float *out32, double *partials,
                      double *nrm2, hipStream_t s);
 // Arnoldi step with lagged reorthogonalisation (second pass of the
-// two-pass form): v[0..j-1] final, v[j] provisional with
-// v_j = (v[j] - sum_i c_i v_i) * ia; dots = {(w, v_i), i < j; (w, v[j]);
-// (w, w)} from launch_cgs_dots.  Finalises v[j] in place, writes the next
-// provisional vector to vnext (and as FP32 to out32 when given), stores
-// {f, nu} in coef_out and red = {(vnext, v_i), i <= j; (vnext, vnext)}.
-void launch_dcgs_update(const double *w, double *const *v, int j, const double *c, double ia,
-                        const double *dots, i64 n, double *vnext, float *out32,
-                        double *coef_out, double *partials, double *red, hipStream_t s);
+// two-pass form): the stored v[0..j] are once-orthogonalised vectors whose
+// orthonormal basis is V = v T (T upper triangular, row-major, row stride
+// ld, on the device); dots = {(w, v_l), l <= j; (w, w)} from
+// launch_cgs_dots.  Writes vnext = (w - v T d) / nu with d = T^T dots (also
+// as FP32 to out32 when given), coef_out = {d_0..d_j, nu} and
+// red = {(vnext, v_l), l <= j; (vnext, vnext)}.  T (row-major, row stride
+// ld) is read from the host array tm_host into the kernel arguments while
+// j < 12, else from the device copy tm_dev, which must then hold it.
+void launch_dcgs_update(const double *w, const double *const *v, int j, const double *dots,
+                        const double *tm_host, const double *tm_dev, int ld, i64 n,
+                        double *vnext, float *out32, double *coef_out, double *partials,
+                        double *red, hipStream_t s);
 // x += sum_i y_i z_i with z in precision TZ (y: host array, passed by value)
 template <typename TZ>
 void launch_update_x(double *x, const TZ *const *z, const double *y, int nz, i64 n,

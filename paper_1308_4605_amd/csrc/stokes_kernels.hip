@@ -2268,8 +2268,7 @@ struct PtrPack {
 struct CoefPack {
   double c[34];
 };
-// index of 1 / alpha in the coefficient pack of k_dcgs_update
-constexpr int kMaxArnC = 33;
+
 
 // ---- Arnoldi by classical Gram-Schmidt applied twice (CGS2) -------------
 // Three streaming passes over [w, v_0..v_j] with double2 loads, a fixed grid
@@ -2423,114 +2422,108 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_next(const double *w, PtrPack
 }
 
 // ---- Arnoldi with lagged reorthogonalisation (two passes per step) -------
-// Step j holds the final orthonormal v_0..v_{j-1} and a provisional vt_j
-// with v_j = (vt_j - sum_{i<j} c_i v_i) * ia (c, ia = 1 / alpha from the
-// previous step's reduction).  The new Krylov vector w (the operator
-// applied to vt_j) has been reduced against the stored vectors:
-// dots = {(w, v_i) for i < j, (w, vt_j), (w, w)}.  This pass then
-//   - finalises v_j in place,
-//   - projects w once against v_0..v_j with the coefficients d_i = (w, v_i)
-//     and f = (w, v_j) = ((w, vt_j) - sum_i c_i d_i) * ia,
-//   - writes the next provisional vector vt_{j+1} = (w - V d - f v_j) / nu
-//     with nu^2 = (w, w) - |d|^2 - f^2 (clamped: nu only scales vt_{j+1}),
-//     also as FP32 when out32 is given,
-//   - reduces (vt_{j+1}, v_i) for i <= j and (vt_{j+1}, vt_{j+1}): the
-//     second Gram-Schmidt pass of vt_{j+1}, applied by the next step.
-// Block 0 stores f and nu in coef_out[0..1] for the Hessenberg matrix.
-// Each element is read and written by one thread (v.p[j] is updated in place).
+// The stored basis vectors vt_0..vt_j are the once-orthogonalised ones; the
+// orthonormal basis is V = Vt T with T upper triangular (the second
+// Gram-Schmidt pass of each vector, applied to coefficients instead of
+// being written back).  T is row-major with row stride ld.  Given
+// dots = {(w, vt_l) for l <= j, (w, w)} (the first pass), this pass forms
+//   d = T^T (Vt^T w)          the projections of w on the orthonormal basis,
+//   nu^2 = (w, w) - |d|^2     (clamped: nu only scales the new vector),
+//   vt_{j+1} = (w - Vt (T d)) / nu, also as FP32 when out32 is given,
+// and reduces (vt_{j+1}, vt_l) for l <= j and (vt_{j+1}, vt_{j+1}), from
+// which the next step finds the new column of T.  Block 0 stores d and nu
+// in coef_out[0..j+1].
+// T travels as a kernel argument (column-packed upper triangle) when it has
+// at most kTriDim rows, else through device memory (tm, row stride ld).
+constexpr int kTriDim = 12;
+struct TriPack {
+  double t[kTriDim * (kTriDim + 1) / 2];
+};
+
 template <int MAXV>
 __global__ void __launch_bounds__(kArnBlock) k_dcgs_update(const double *__restrict__ w, PtrPack v,
-                                                           int j, CoefPack cf,
-                                                           const double *__restrict__ dots,
-                                                           i64 n, double *vnext, float *out32,
+                                                           int j, const double *__restrict__ dots,
+                                                           TriPack tp,
+                                                           const double *__restrict__ tm, int ld,
+                                                           i64 n, double *__restrict__ vnext,
+                                                           float *__restrict__ out32,
                                                            double *__restrict__ coef_out,
                                                            double *__restrict__ partials) {
-  // coefficients (the same few values in every thread)
-  const double ia = cf.c[kMaxArnC];
-  double c[MAXV], d[MAXV];
-  double cd = 0.0, dd2 = 0.0;
+  // T(l, i), l <= i
+  auto T = [&](int l, int i) -> double {
+    return tm ? tm[l * ld + i] : tp.t[i * (i + 1) / 2 + l];
+  };
+  // coefficients (the same few values in every thread), over compile-time
+  // register indices
+  double d[MAXV], g[MAXV];
+  double dd2 = 0.0;
 #pragma unroll
   for (int i = 0; i < MAXV; i++) {
-    c[i] = (i < j) ? cf.c[i] : 0.0;
-    d[i] = (i < j) ? dots[i] : 0.0;
-    cd += c[i] * d[i];
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < MAXV; l++)
+      if (l <= i && i <= j) acc += T(l, i) * dots[l];
+    d[i] = (i <= j) ? acc : 0.0;
     dd2 += d[i] * d[i];
   }
-  const double f = (dots[j] - cd) * ia;
+  // g = T d (T is upper triangular)
+#pragma unroll
+  for (int l = 0; l < MAXV; l++) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXV; i++)
+      if (i >= l && i <= j) acc += T(l, i) * d[i];
+    g[l] = (l <= j) ? acc : 0.0;
+  }
   const double q = dots[j + 1];
-  double nu2 = q - dd2 - f * f;
-  // nu only scales the provisional vector (the next reduction measures it);
-  // keep it positive when cancellation leaves nothing reliable
+  const double nu2 = q - dd2;
   const double floor2 = q * 0x1p-60;
   const double nu = (nu2 > floor2) ? sqrt(nu2) : (q > 0.0 ? sqrt(floor2) : 1.0);
   const double inu = 1.0 / nu;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    coef_out[0] = f;
-    coef_out[1] = nu;
+    for (int i = 0; i <= j && i < MAXV; i++) coef_out[i] = d[i];
+    coef_out[j + 1] = nu;
   }
   double acc[MAXV + 1];
 #pragma unroll
   for (int i = 0; i <= MAXV; i++) acc[i] = 0.0;
   const i64 n2 = n >> 1;
-  const double2 *w2 = (const double2 *)w;
-  double2 *vj2 = (double2 *)v.p[j];
-  double2 *vn2 = (double2 *)vnext;
-  float2 *f2 = (float2 *)out32;
+  const double2 *__restrict__ w2 = (const double2 *)w;
+  double2 *__restrict__ vn2 = (double2 *)vnext;
+  float2 *__restrict__ f2 = (float2 *)out32;
   for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n2; t += (i64)gridDim.x * blockDim.x) {
-    const double2 a = w2[t];
-    double2 vj = vj2[t];
+    double2 wp = w2[t];
     double2 b[MAXV];
 #pragma unroll
     for (int i = 0; i < MAXV; i++) {
-      if (i < j) {
+      if (i <= j) {
         b[i] = ((const double2 *)v.p[i])[t];
-        vj.x -= c[i] * b[i].x;
-        vj.y -= c[i] * b[i].y;
+        wp.x -= g[i] * b[i].x;
+        wp.y -= g[i] * b[i].y;
       }
     }
-    vj.x *= ia;
-    vj.y *= ia;
-    double2 wp = a;
-#pragma unroll
-    for (int i = 0; i < MAXV; i++) {
-      if (i < j) {
-        wp.x -= d[i] * b[i].x;
-        wp.y -= d[i] * b[i].y;
-      }
-    }
-    wp.x = (wp.x - f * vj.x) * inu;
-    wp.y = (wp.y - f * vj.y) * inu;
-    vj2[t] = vj;
+    wp.x *= inu;
+    wp.y *= inu;
     vn2[t] = wp;
     if (out32) f2[t] = make_float2((float)wp.x, (float)wp.y);
-    // slot i < j: (vt_{j+1}, v_i); slot j: (vt_{j+1}, v_j) (compile-time
-    // register indices, the slot chosen by predicate)
 #pragma unroll
-    for (int i = 0; i < MAXV; i++) {
-      if (i < j) acc[i] += b[i].x * wp.x + b[i].y * wp.y;
-      if (i == j) acc[i] += vj.x * wp.x + vj.y * wp.y;
-    }
+    for (int i = 0; i < MAXV; i++)
+      if (i <= j) acc[i] += b[i].x * wp.x + b[i].y * wp.y;
     acc[MAXV] += wp.x * wp.x + wp.y * wp.y;
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
     const i64 e = n - 1;
-    double vj = ((const double *)v.p[j])[e];
-    for (int i = 0; i < j; i++) vj -= cf.c[i] * ((const double *)v.p[i])[e];
-    vj *= ia;
     double wp = w[e];
-    for (int i = 0; i < j; i++) wp -= dots[i] * ((const double *)v.p[i])[e];
-    wp = (wp - f * vj) * inu;
-    ((double *)v.p[j])[e] = vj;
+    for (int i = 0; i <= j && i < MAXV; i++) wp -= g[i] * ((const double *)v.p[i])[e];
+    wp *= inu;
     vnext[e] = wp;
     if (out32) out32[e] = (float)wp;
 #pragma unroll
-    for (int i = 0; i < MAXV; i++) {
-      if (i < j) acc[i] += ((const double *)v.p[i])[e] * wp;
-      if (i == j) acc[i] += vj * wp;
-    }
+    for (int i = 0; i < MAXV; i++)
+      if (i <= j) acc[i] += ((const double *)v.p[i])[e] * wp;
     acc[MAXV] += wp * wp;
   }
-  // slots 0..j: (vt_{j+1}, v_i); slot j + 1: (vt_{j+1}, vt_{j+1})
+  // slots 0..j: (vt_{j+1}, vt_l); slot j + 1: (vt_{j+1}, vt_{j+1})
   block_store<MAXV>(acc, j + 1, true, j + 2, partials);
 }
 
@@ -2582,17 +2575,24 @@ void launch_cgs_next(const double *w, const double *const *v, const double *h1, 
                nrm2 ? partials : nullptr);
   if (nrm2) hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, nrm2);
 }
-void launch_dcgs_update(const double *w, double *const *v, int j, const double *c, double ia,
-                        const double *dots, i64 n, double *vnext, float *out32,
-                        double *coef_out, double *partials, double *red, hipStream_t s) {
+void launch_dcgs_update(const double *w, const double *const *v, int j, const double *dots,
+                        const double *tm_host, const double *tm_dev, int ld, i64 n,
+                        double *vnext, float *out32, double *coef_out, double *partials,
+                        double *red, hipStream_t s) {
   PtrPack pk;
   for (int i = 0; i <= j; i++) pk.p[i] = v[i];
-  CoefPack cf;
-  for (int i = 0; i < 34; i++) cf.c[i] = 0.0;
-  for (int i = 0; i < j; i++) cf.c[i] = c[i];
-  cf.c[kMaxArnC] = ia;
+  TriPack tp;
+  for (int i = 0; i < kTriDim * (kTriDim + 1) / 2; i++) tp.t[i] = 0.0;
+  const double *tm = nullptr;
+  if (j + 1 <= kTriDim) {
+    for (int i = 0; i <= j; i++)
+      for (int l = 0; l <= i; l++) tp.t[i * (i + 1) / 2 + l] = tm_host[l * ld + i];
+  } else {
+    tm = tm_dev;
+  }
   const int nb = arn_blocks(n);
-  ARN_DISPATCH(k_dcgs_update, j + 1, w, pk, j, cf, dots, n, vnext, out32, coef_out, partials);
+  ARN_DISPATCH(k_dcgs_update, j + 1, w, pk, j, dots, tp, tm, ld, n, vnext, out32, coef_out,
+               partials);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, j + 2, j + 2, red);
 }
 #undef ARN_DISPATCH

@@ -303,3 +303,20 @@ def test_precond_parity_odd_coarse_level(dim, n, bc, theta, precision):
     assert rel(N(zu), ou) <= tol
     assert rel(N(zp), op) <= tol
     assert np.all(N(zu)[lay.wall_mask()] == 0.0)
+
+
+@pytest.mark.parametrize("krylov", [W.GMRES_LEFT, W.FGMRES])
+@pytest.mark.parametrize("restart", [16, 32])
+def test_solve_parity_long_restart(krylov, restart):
+    """Restart lengths beyond 12 (the GPU Arnoldi then keeps its basis
+    transform in device memory instead of the kernel arguments)."""
+    print(f"long restart {restart} krylov={krylov}", flush=True)
+    w = W.contrast_periodic_3d(n=32, contrast=1e3, precision=W.FP64)
+    p = w.params(krylov=krylov, precision=W.FP64, restart=restart)
+    g, o = pair(p, w.rho, w.mu)
+    xu, xp, st, rc = g.solve(T(w.bu), T(w.bp), tol=1e-8, max_iter=500)
+    ou, op, ost, orc = o.solve(w.bu, w.bp, tol=1e-8, max_iter=500)
+    print(f"  gpu iters {st['iters']} oracle iters {ost['iters']}", flush=True)
+    assert rc == 0 and orc == 0
+    assert abs(st["iters"] - ost["iters"]) <= 1
+    assert rel(N(xu), ou) <= 1e-5 and rel(N(xp), op) <= 1e-5
