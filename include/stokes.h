@@ -5,15 +5,15 @@
  * Finite-Volume Stokes Solvers" (arXiv:1308.4605), each built from one
  * geometric-multigrid V-cycle for the velocity and one for the pressure.
  *
- * Problem (paper Sec. 2, eq. Saddle_sys, discretised as in Sec. 3.1):
+ * Problem (paper Sec. "Preconditioners", eq. Saddle_sys, discretised as in Sec. "Staggered-grid Discretization"):
  *     M x = b,   M = [[A, G], [-D, 0]],   A = theta rho_f - L_mu,
  * x = (face velocities u, cell pressure p), b = (b_u, b_p) with b_p = -g.
  * D and G are the staggered divergence and gradient, rho_f the mean of the two
  * cells sharing a face, L_mu the stress-form viscous operator
  * div(mu (grad u + grad u^T)) with cell viscosity on the normal stresses and
  * edge (3D) / node (2D) viscosity on the shear stresses.  theta = 0 is steady
- * Stokes flow, theta ~ 1/dt unsteady (Sec. 2).  With bulk viscosity gamma
- * (flows with div u = g != 0, Sec. 2) the stress gains
+ * Stokes flow, theta ~ 1/dt unsteady (Sec. "Preconditioners").  With bulk viscosity gamma
+ * (flows with div u = g != 0, Sec. "Preconditioners") the stress gains
  * (gamma - 2/3 mu)(div u) I, added to the normal stresses of each cell.
  *
  * ------------------------------------------------------------------------
@@ -71,7 +71,7 @@ enum {
   STOKES_EINCOMPAT = -7    /* right-hand side not orthogonal to the null space */
 };
 
-/* Boundary conditions (Sec. 3.1: a condition at each domain boundary),
+/* Boundary conditions (Sec. "Staggered-grid Discretization": a condition at each domain boundary),
    given per axis a in bc[a].  No-slip: u = 0 on the wall, the shear next to
    it one-sided.  Free-slip: zero normal velocity and no tangential momentum
    flux through the wall.  Periodic applies to both ends of an axis; the two
@@ -82,9 +82,9 @@ enum {
 enum { STOKES_PERIODIC = 0, STOKES_NOSLIP = 1, STOKES_FREESLIP = 2, STOKES_NOSLIP_FREESLIP = 3,
        STOKES_FREESLIP_NOSLIP = 4 };
 
-/* block preconditioners of Sec. 2: projection (eq. P1_practical), lower
+/* block preconditioners of Sec. "Preconditioners": projection (eq. P1_practical), lower
    triangular (eq. CC_Pre_lower), upper triangular (eq. CC_Pre_upper),
-   block diagonal (eq. CC_Pre_diagonal), Uzawa-like (Sec. 2.4) */
+   block diagonal (eq. CC_Pre_diagonal), Uzawa-like (Sec. "Other preconditioners") */
 enum { STOKES_P1 = 1, STOKES_P2 = 2, STOKES_P3 = 3, STOKES_P4 = 4, STOKES_P5 = 5 };
 
 /* precision of the preconditioner (multigrid, transfers, coefficients and the
@@ -92,11 +92,11 @@ enum { STOKES_P1 = 1, STOKES_P2 = 2, STOKES_P3 = 3, STOKES_P4 = 4, STOKES_P5 = 5
    stay FP64.  STOKES_MG_FP32 requires STOKES_FGMRES. */
 enum { STOKES_FP64 = 0, STOKES_MG_FP32 = 1 };
 
-/* Krylov method: left-preconditioned GMRES(m) (Sec. 3.2, Sec. 4) or flexible
-   GMRES(m) (right preconditioning; named in Sec. 4) */
+/* Krylov method: left-preconditioned GMRES(m) (Sec. "Krylov Solver", Sec. "Results") or flexible
+   GMRES(m) (right preconditioning; named in Sec. "Results") */
 enum { STOKES_GMRES_LEFT = 0, STOKES_FGMRES = 1 };
 
-/* Scaling of the linear system (Sec. 3.3, "Rescaling of the Linear
+/* Scaling of the linear system (Sec. "Rescaling of the Linear System", "Rescaling of the Linear
    System").  UNIFORM: the rescaled system of eq. Stokes_rescaled, velocity
    equations times c and pressure unknowns times c.  DIAGONAL: for a very
    broad range of viscosities the paper rescales velocity and pressure
@@ -112,7 +112,7 @@ enum { STOKES_GMRES_LEFT = 0, STOKES_FGMRES = 1 };
    coefficient in every cell (STOKES_EINVAL otherwise). */
 enum { STOKES_SCALE_UNIFORM = 0, STOKES_SCALE_DIAGONAL = 1 };
 
-/* edge/node viscosity: arithmetic mean of the neighbouring cells (Sec. 3.1),
+/* edge/node viscosity: arithmetic mean of the neighbouring cells (Sec. "Staggered-grid Discretization"),
    harmonic mean, or caller-supplied values */
 enum { STOKES_EDGE_ARITH = 0, STOKES_EDGE_HARMONIC = 1, STOKES_EDGE_GIVEN = 2 };
 
@@ -139,7 +139,7 @@ typedef struct {
   int scaling;      /* STOKES_SCALE_UNIFORM or STOKES_SCALE_DIAGONAL */
   int extended;     /* 1: the Krylov solver's true residuals b - M x in
                        double-double arithmetic (about 106 bits), each entry
-                       rounded once to FP64 (Sec. 3.3: extended precision in
+                       rounded once to FP64 (Sec. "Rescaling of the Linear System": extended precision in
                        extreme cases); 0: FP64 */
 } stokes_params;
 
@@ -148,7 +148,7 @@ typedef struct {
   int restarts;         /* restart cycles started */
   int precond_applies;  /* preconditioner applications */
   int scalar_vcycles;   /* precond_applies * vcycles * (d * velocity cycles +
-                           pressure cycles): the paper's cost proxy (Sec. 4) */
+                           pressure cycles): the paper's cost proxy (Sec. "Results") */
   double rel_res_true;  /* ||b' - M' x'|| / ||b'|| of the rescaled system at exit */
   double rel_res_est;   /* last Givens estimate, as a true relative residual */
   double rel_res_unscaled;  /* stokes_solve: ||b - M x|| / ||b|| of the caller's
@@ -181,13 +181,13 @@ int stokes_sizes(const stokes_params *p, size_t *nvel, size_t *ncell, size_t *ne
 size_t stokes_workspace_bytes(const stokes_params *p);
 
 /* Build the context: face density, rho-weighted coefficients, edge viscosity
-   (Sec. 3.1), the rescaling c ~ h/mu0 (Sec. 3.3) and the coarse-level
+   (Sec. "Staggered-grid Discretization"), the rescaling c ~ h/mu0 (Sec. "Rescaling of the Linear System") and the coarse-level
    coefficients (Appendix C), all on the device.
    rho_cell, mu_cell: cell fields (rho > 0, mu >= 0, finite);
    mu_edges: edge viscosity for STOKES_EDGE_GIVEN, else NULL;
    gamma_cell: bulk viscosity per cell (>= 0, finite) when p->bulk = 1, else
      NULL (STOKES_EINVAL otherwise).  With it the stress carries
-     (gamma - 2/3 mu)(div u) I (Sec. 2), coarse levels take the mean of the
+     (gamma - 2/3 mu)(div u) I (Sec. "Preconditioners"), coarse levels take the mean of the
      fine cells' gamma - 2/3 mu, and the Schur approximation uses
      gamma + 4/3 mu in place of 2 mu (eq. Schur_app_bulk);
    workspace: device buffer of ws_bytes >= stokes_workspace_bytes(p);
@@ -198,21 +198,21 @@ int stokes_create(const stokes_params *p, const double *rho_cell, const double *
                   const double *mu_edges, const double *gamma_cell, void *workspace,
                   size_t ws_bytes, void *hip_stream, stokes_ctx **out);
 
-/* y = M x with the caller's (unscaled) coefficients (Sec. 2, eq. Saddle_sys;
-   direct evaluation of the stencils at every interior face and cell, Sec. 3.2). */
+/* y = M x with the caller's (unscaled) coefficients (Sec. "Preconditioners", eq. Saddle_sys;
+   direct evaluation of the stencils at every interior face and cell, Sec. "Krylov Solver"). */
 int stokes_apply(stokes_ctx *ctx, const double *xu, const double *xp, double *yu, double *yp);
 
 /* r = b - M x with the caller's coefficients (the residual of the Krylov
-   solver's convergence test, Sec. 3.2), in FP64 (extended = 0) or in
+   solver's convergence test, Sec. "Krylov Solver"), in FP64 (extended = 0) or in
    double-double arithmetic with each entry rounded once to FP64
-   (extended = 1; Sec. 3.3, extended precision in extreme cases).  It is
+   (extended = 1; Sec. "Rescaling of the Linear System", extended precision in extreme cases).  It is
    evaluated on the rescaled system, r_u = (c b_u - c A x_u - G c x_p) / c,
    so the products with c round to FP64 unless c is a power of two.  ru is 0
    on wall faces.  Uses the context's work vectors; asynchronous. */
 int stokes_residual(stokes_ctx *ctx, const double *bu, const double *bp, const double *xu,
                     const double *xp, double *ru, double *rp, int extended);
 
-/* Prescribed (non-homogeneous) wall velocities (Sec. 3.2): with them the
+/* Prescribed (non-homogeneous) wall velocities (Sec. "Krylov Solver"): with them the
    operator is affine, M x + c, and the flow solves M x = b - c with the
    homogeneous M used everywhere else.  This computes c = (cu, cp): M applied
    to the field that is zero at the unknowns and carries
@@ -227,15 +227,15 @@ int stokes_residual(stokes_ctx *ctx, const double *bu, const double *bp, const d
 int stokes_boundary_rhs(stokes_ctx *ctx, const double *un, const double *ut, double *cu,
                         double *cp);
 
-/* z = P^{-1} b for the configured preconditioner and precision (Sec. 2), the
+/* z = P^{-1} b for the configured preconditioner and precision (Sec. "Preconditioners"), the
    same operator the Krylov solver applies.  Output pressure has zero mean;
-   the output velocity components that are singular have zero mean (Sec. 3.2
+   the output velocity components that are singular have zero mean (Sec. "Krylov Solver"
    null-space care).  Component k of the velocity operator is singular when
    theta = 0, axis k is periodic and no wall (at either end of any axis) is
    no-slip. */
 int stokes_precond(stokes_ctx *ctx, const double *bu, const double *bp, double *zu, double *zp);
 
-/* The two multigrid subsolvers alone (Sec. 3.2, Appendix C): e = A~^{-1} r
+/* The two multigrid subsolvers alone (Sec. "Krylov Solver", Appendix C): e = A~^{-1} r
    (velocity, `vcycles` V-cycles from zero) and e = L~_rho^{-1} r (pressure,
    L_rho = D rho_f^{-1} G; r must have zero mean; e has zero mean). */
 int stokes_vel_subsolve(stokes_ctx *ctx, const double *r, double *e);
@@ -243,7 +243,7 @@ int stokes_p_subsolve(stokes_ctx *ctx, const double *r, double *e);
 
 /* The same two multigrid solvers run to convergence on their own, the cost
    reference of a split (projection-like) method in the study of V-cycles per
-   subsolve (Sec. 4.3.1): starting from e = 0, each cycle adds one V-cycle
+   subsolve (Sec. "The effect of the number of multigrid cycles"): starting from e = 0, each cycle adds one V-cycle
    applied to the current residual, e <- e + V(r - A e), until
    ||r - A e|| <= tol ||r|| or max_cycles cycles.  A is the velocity operator
    theta rho - L_mu (vel) or L_rho (p), unscaled as for the subsolvers; r is
@@ -261,8 +261,8 @@ int stokes_p_mg_solve(stokes_ctx *ctx, const double *r, double *e, double tol, i
                       int *cycles, double *rel_res);
 
 /* Solve M x = b until the true relative residual of the rescaled system
-   ||b' - M' x'|| <= tol ||b'|| (Sec. 3.2 "true residual"), at most max_iter
-   Arnoldi steps.  use_x0 != 0 starts from the given x (a restart, Sec. 4.2.2),
+   ||b' - M' x'|| <= tol ||b'|| (Sec. "Krylov Solver" "true residual"), at most max_iter
+   Arnoldi steps.  use_x0 != 0 starts from the given x (a restart, Sec. "The effect of restarts"),
    else from 0.  x is the solution of the unscaled system with p of zero mean
    (and zero-mean velocity components when the velocity operator is singular).
    b_p must have zero mean (STOKES_EINCOMPAT otherwise), as must each singular
@@ -295,7 +295,7 @@ int stokes_solve_static(stokes_ctx *ctx, const double *bu, const double *bp, dou
                         double *xp, double tol, int max_iter, int use_x0, stokes_stats *stats);
 
 /* Adjoint: with x the forward solution and g = dL/dx = (g_u, g_p), solve
-   M^T lambda = g (M = M^T, Sec. 2) with the same preconditioner and a fresh
+   M^T lambda = g (M = M^T, Sec. "Preconditioners") with the same preconditioner and a fresh
    Krylov space, then contract forward and adjoint strain rates:
      dL/db        = lambda                              (lu, lp),
      dL/dmu_cell  = -2 sum_k (D^k lambda_k)(D^k u_k)  + chain through the
@@ -330,7 +330,7 @@ int stokes_grad(stokes_ctx *ctx, const double *xu, const double *lu, double *dmu
    history off. */
 int stokes_set_history(stokes_ctx *ctx, double *buf, int cap);
 
-/* Rescaling factor c in use (Sec. 3.3). */
+/* Rescaling factor c in use (Sec. "Rescaling of the Linear System"). */
 double stokes_rescale(const stokes_ctx *ctx);
 
 /* Per-kernel timing for the roofline report.  When enabled, every launch of

@@ -8,20 +8,20 @@
  *
  * What each part follows (sections/equations of the paper):
  *   - saddle-point system M = [[A, G], [-D, 0]], A = theta*rho - L_mu
- *     (Sec. 2, eq. Saddle_sys);
- *   - MAC divergence D, gradient G (Sec. 3.1), stress-form viscous operator
- *     L_mu (Sec. 3.1, eq. div_stress) with one-sided wall differences and
+ *     (Sec. "Preconditioners", eq. Saddle_sys);
+ *   - MAC divergence D, gradient G (Sec. "Staggered-grid Discretization"), stress-form viscous operator
+ *     L_mu (Sec. "Staggered-grid Discretization", eq. div_stress) with one-sided wall differences and
  *     face density rho_f = mean of the two cells, node/edge viscosity = mean of
- *     the neighbouring cells (Sec. 3.1);
- *   - Schur approximation S~^{-1} = -theta L~_rho^{-1} + 2 mu (Sec. 2,
+ *     the neighbouring cells (Sec. "Staggered-grid Discretization");
+ *   - Schur approximation S~^{-1} = -theta L~_rho^{-1} + 2 mu (Sec. "Preconditioners",
  *     eq. Schur_app_varDen_varVis) and preconditioners P1 (eq. P1_practical),
  *     P2 (eq. CC_Pre_lower), P3 (eq. CC_Pre_upper), P4 (eq. CC_Pre_diagonal),
- *     P5 (Sec. 2.4, the three-step Uzawa-like recipe);
+ *     P5 (Sec. "Other preconditioners", the three-step Uzawa-like recipe);
  *   - multigrid V-cycles with multicolour Gauss-Seidel, restriction,
  *     prolongation and coefficient coarsening (Appendix C);
- *   - zero initial guess for subsolvers and null-space handling (Sec. 3.2);
- *   - rescaling by c ~ h/mu0 (Sec. 3.3, eq. Stokes_rescaled);
- *   - GMRES(m) with left preconditioning and FGMRES(m) (Sec. 3.2 and Sec. 4
+ *   - zero initial guess for subsolvers and null-space handling (Sec. "Krylov Solver");
+ *   - rescaling by c ~ h/mu0 (Sec. "Rescaling of the Linear System", eq. Stokes_rescaled);
+ *   - GMRES(m) with left preconditioning and FGMRES(m) (Sec. "Krylov Solver" and Sec. "Results"
  *     opening paragraphs; Saad's algorithms).
  * Readings of passages the paper leaves open are listed in the repository's
  * design notes; each is marked "reading" below where it is applied.
@@ -62,7 +62,7 @@ typedef struct {
   double *mu_c;  /* cell viscosity (ncell) */
   double *mu_e;  /* edge viscosity (nedge) */
   /* gamma - 2/3 mu per cell: the coefficient of (div u) I in the stress
-     when bulk viscosity is included (Sec. 2); NULL = incompressible form */
+     when bulk viscosity is included (Sec. "Preconditioners"); NULL = incompressible form */
   double *lam_c;
   /* V-cycle work arrays */
   double *phi_u, *rhs_u, *res_u;
@@ -75,7 +75,7 @@ typedef struct {
 
 struct orc_ctx {
   orc_params p;
-  double c;        /* rescale factor (Sec. 3.3) */
+  double c;        /* rescale factor (Sec. "Rescaling of the Linear System") */
   int nlev;
   level_t raw;     /* unscaled fine coefficients: used by orc_apply */
   level_t *lev;    /* scaled hierarchy: used by the solver */
@@ -206,14 +206,14 @@ static size_t eidx(const level_t *L, int m, const int e_in[3]) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* discrete operators (Sec. 3.1)                                             */
+/* discrete operators (Sec. "Staggered-grid Discretization")                                             */
 /* ------------------------------------------------------------------------ */
 
 /* derivative of u_k along axis l at the edge point e (e is a node along k and
    l).  Centred difference of the two faces above/below the edge; at a no-slip
    wall along l the one-sided difference (u_adjacent - 0)/(h/2) is used, the
    wall value of the tangential velocity being 0 (reading of the one-sided wall
-   rule of Sec. 3.1). */
+   rule of Sec. "Staggered-grid Discretization"). */
 static double dkl(const level_t *L, const double *u, int k, int l, const int e[3]) {
   const grid_t *g = &L->g;
   const double h = g->h;
@@ -238,7 +238,7 @@ static int on_free_slip(const grid_t *g, int a, const int e[3]) {
 }
 
 /* shear rate gamma_kl = du_k/dx_l + du_l/dx_k at an edge; zero on a free-slip
-   wall, where the tangential momentum flux vanishes (Sec. 3.1) */
+   wall, where the tangential momentum flux vanishes (Sec. "Staggered-grid Discretization") */
 static double shear_rate(const level_t *L, const double *u, int k, int l, const int e[3]) {
   if (on_free_slip(&L->g, k, e) || on_free_slip(&L->g, l, e)) return 0.0;
   return dkl(L, u, k, l, e) + dkl(L, u, l, k, e);
@@ -343,7 +343,7 @@ static double p_flux(const level_t *L, const double *beta, const double *p, int 
   return beta[fidx(L, k, ff)] * grad_face(L, p, k, ff);
 }
 
-/* (L_rho p)_c = D (beta G p), L_rho = D rho^{-1} G (Sec. 2) */
+/* (L_rho p)_c = D (beta G p), L_rho = D rho^{-1} G (Sec. "Preconditioners") */
 static double lrho_cell(const level_t *L, const double *beta, const double *p, const int c[3]) {
   double s = 0.0;
   for (int k = 0; k < L->g.d; k++) {
@@ -768,7 +768,7 @@ static void vcycle_vel(orc_ctx *X, int l, const double *rhs, double *phi) {
 
 /* pressure (cell-centred Poisson) V-cycle; the operator is always singular
    (periodic or natural boundaries), so the coarsest problem is made
-   consistent by removing the mean (Sec. 3.2 null-space care; reading). */
+   consistent by removing the mean (Sec. "Krylov Solver" null-space care; reading). */
 static void vcycle_p(orc_ctx *X, int l, const double *rhs, double *phi) {
   level_t *L = &X->lev[l];
   zerov(phi, L->ncell);
@@ -789,7 +789,7 @@ static void vcycle_p(orc_ctx *X, int l, const double *rhs, double *phi) {
   for (int s = 0; s < X->p.nu_post; s++) p_sweep(L, L->beta, rhs, phi);
 }
 
-/* A~^{-1} r on the scaled system: `vcycles` V-cycles from zero (Sec. 3.2:
+/* A~^{-1} r on the scaled system: `vcycles` V-cycles from zero (Sec. "Krylov Solver":
    zero initial guess), mean handling for the periodic steady null space. */
 static void vel_sub(orc_ctx *X, const double *r_in, double *e) {
   level_t *L = &X->lev[0];
@@ -836,7 +836,7 @@ static void p_sub(orc_ctx *X, const double *r_in, double *e) {
   free(r); free(t); free(de);
 }
 
-/* Stand-alone multigrid on one subproblem of the scaled system (Sec. 4.3.1:
+/* Stand-alone multigrid on one subproblem of the scaled system (Sec. "The effect of the number of multigrid cycles":
    the velocity and pressure multigrid solvers run to convergence are the
    reference cost of a split, projection-like method).  Starting from e = 0,
    each cycle applies one V-cycle to the current residual and adds the
@@ -888,7 +888,7 @@ static int mg_solve(orc_ctx *X, int vel, const double *r_in, double *e, double t
 }
 
 /* ------------------------------------------------------------------------ */
-/* preconditioners (Sec. 2)                                                  */
+/* preconditioners (Sec. "Preconditioners")                                                  */
 /* ------------------------------------------------------------------------ */
 
 static void div_all(const level_t *L, const double *u, double *out) {
@@ -999,7 +999,7 @@ static void precond_scaled(orc_ctx *X, const double *b, double *z) {
     break;
   }
   /* keep the pressure mean (and the velocity means when the velocity
-     operator is singular) at zero (Sec. 3.2) */
+     operator is singular) at zero (Sec. "Krylov Solver") */
   remove_mean(zp, nc);
   if (X->vel_singular) remove_vel_means(L, zu);
   free(cvec); free(tu); free(xs);
@@ -1054,7 +1054,7 @@ static void true_residual(orc_ctx *X, const double *b, const double *x, double *
 }
 
 /* Solve the scaled system M' x = b by restarted GMRES: left-preconditioned
-   (Sec. 3.2) or flexible (right-preconditioned, Saad).  Stopping (reading):
+   (Sec. "Krylov Solver") or flexible (right-preconditioned, Saad).  Stopping (reading):
    the solve ends when the true residual ||b - M x|| <= tol ||b||; each restart
    cycle ends when the Givens residual estimate has dropped by the factor the
    true residual still lacks, or after m steps.
@@ -1210,7 +1210,7 @@ static int krylov_solve(orc_ctx *X, const double *b, double *x, double tol, int 
 }
 
 /* ------------------------------------------------------------------------ */
-/* setup (Sec. 3.1 coefficients, Sec. 3.3 rescaling, Appendix C coarsening)  */
+/* setup (Sec. "Staggered-grid Discretization" coefficients, Sec. "Rescaling of the Linear System" rescaling, Appendix C coarsening)  */
 /* ------------------------------------------------------------------------ */
 
 static int level_alloc(level_t *L, int work, int bulk) {
@@ -1449,12 +1449,12 @@ int orc_create(const orc_params *p, const double *rho, const double *mu,
     }
   }
   fine_coefficients(X, &X->raw, rho, mu, edges_given);
-  /* stress with bulk viscosity (Sec. 2): the (div u) I coefficient is
+  /* stress with bulk viscosity (Sec. "Preconditioners"): the (div u) I coefficient is
      gamma - 2/3 mu per cell */
   if (bulk)
     for (size_t i = 0; i < X->raw.ncell; i++) X->raw.lam_c[i] = gamma[i] - 2.0 / 3.0 * mu[i];
   /* rescale factor c = h / mu_ref, mu_ref = geometric mean of the positive
-     cell viscosities (Sec. 3.3, reading of "typical magnitude") */
+     cell viscosities (Sec. "Rescaling of the Linear System", reading of "typical magnitude") */
   if (p->rescale_c > 0.0) {
     X->c = p->rescale_c;
   } else {
@@ -1727,7 +1727,7 @@ int orc_prolong_add_cells(orc_ctx *X, int level, const double *ec, double *pf) {
   return ORC_OK;
 }
 
-/* mean-compatibility of the right-hand side with the null space (Sec. 3.2) */
+/* mean-compatibility of the right-hand side with the null space (Sec. "Krylov Solver") */
 static int rhs_compatible(const orc_ctx *X, const double *bu, const double *bp) {
   const level_t *L = &X->raw;
   double s = 0.0, s2 = 0.0;
@@ -1773,7 +1773,7 @@ int orc_solve(orc_ctx *X, const double *bu, const double *bp, double *xu, double
 }
 
 /* Gradient of L(x(mu, rho)) given the forward solution x and the adjoint
-   lambda (M lambda = dL/dx; M is symmetric, Sec. 2).  With the symmetric form
+   lambda (M lambda = dL/dx; M is symmetric, Sec. "Preconditioners").  With the symmetric form
    -L_mu = B^T W B (B: cell normal rates and edge shear rates; W: 2 mu_cell and
    w_e mu_edge with w_e = 1/2 on no-slip wall edges, 1 elsewhere):
      dL/dmu_cell = -2 sum_k (D^k lambda_k)(D^k x_k),

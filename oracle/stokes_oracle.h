@@ -72,7 +72,7 @@ typedef struct {
 typedef struct orc_ctx orc_ctx;
 
 /* gamma_cell: bulk viscosity per cell (>= 0), or NULL.  Given, the stress
-   is mu (grad u + grad u^T) + (gamma - 2/3 mu)(div u) I (Sec. 2, the form
+   is mu (grad u + grad u^T) + (gamma - 2/3 mu)(div u) I (Sec. "Preconditioners", the form
    for div u = g != 0) and the Schur approximation uses gamma + 4/3 mu in place
    of 2 mu (eq. Schur_app_bulk).  NULL: the incompressible stress form. */
 int    orc_create(const orc_params *p, const double *rho_cell, const double *mu_cell,
@@ -87,7 +87,7 @@ double orc_rescale(const orc_ctx *c);
 /* y = M x with the unscaled coefficients. */
 int orc_apply(orc_ctx *c, const double *xu, const double *xp, double *yu, double *yp);
 /* Boundary terms of the affine operator for prescribed wall velocities
-   (Sec. 3.2): (cu, cp) = M applied to the field that is zero at the unknowns
+   (Sec. "Krylov Solver"): (cu, cp) = M applied to the field that is zero at the unknowns
    and holds un on the wall faces (normal velocity; interior entries of un
    are ignored) and ut on the wall edges (tangential velocity of the
    component parallel to the wall and normal to the edge; no-slip walls only).

@@ -660,7 +660,7 @@ void vcycle_top(stokes_ctx *X, bool vel, const T *rhs, T *phi, bool means_in = f
   }
 }
 
-// A~^{-1} r: `vcycles` V-cycles, zero initial guess (Sec. 3.2)
+// A~^{-1} r: `vcycles` V-cycles, zero initial guess (Sec. "Krylov Solver")
 template <typename T>
 void vel_sub(stokes_ctx *X, const T *r, T *e) {
   Level &L = X->lev[0];
@@ -729,7 +729,7 @@ void neg_schur_div(stokes_ctx *X, const T *u, const T *bp, T *out) {
   }
 }
 
-// z = P^{-1} b on the rescaled system (Sec. 2 block factorisations)
+// z = P^{-1} b on the rescaled system (Sec. "Preconditioners" block factorisations)
 template <typename T>
 void precond(stokes_ctx *X, const T *bu, const T *bp, T *zu, T *zp) {
   Level &L = X->lev[0];
@@ -1152,7 +1152,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
   return rc;
 }
 
-// compatibility of b' with the null space (Sec. 3.2); b' in X->b
+// compatibility of b' with the null space (Sec. "Krylov Solver"); b' in X->b
 int check_rhs(stokes_ctx *X) {
   const Geo &g = X->lev[0].g;
   double *hb = X->host;

@@ -159,7 +159,7 @@ __device__ __forceinline__ bool box_thread(const Geo &g, int W, int &w, int &y, 
 }
 
 // ------------------------------------------------------------------------
-// A = alpha - L_mu at one face (paper Sec. 3.1, eq. div_stress).  Returns
+// A = alpha - L_mu at one face (paper Sec. "Staggered-grid Discretization", eq. div_stress).  Returns
 // (A u)_f and the diagonal of A at f.  Tangential no-slip walls use the ghost
 // value -u_f, which equals the one-sided wall difference (u_f - 0)/(h/2).
 
@@ -211,7 +211,7 @@ __device__ __forceinline__ void a_row_core(const Geo &g, int k, const int i[3], 
 // above/below (ua[l], ub[l]) with the wall ghost already applied; u_l values
 // and the coefficients are read from the component arrays comp[l].
 // lam (may be null): gamma - 2/3 mu per cell; the normal stresses of the two
-// cells beside f then gain lam (div u) (bulk viscosity, Sec. 2).  The u_l
+// cells beside f then gain lam (div u) (bulk viscosity, Sec. "Preconditioners").  The u_l
 // values the shear terms load are exactly the cells' tangential faces, so the
 // cell divergences cost no extra velocity loads.
 // Z != 0 (first sweep from a zero iterate): the components l > k have not
@@ -265,7 +265,7 @@ __device__ __forceinline__ void a_row_nb(const Geo &g, int k, const int i[3], T 
                      al, lam != nullptr, lr, ll, Au, diag);
 }
 
-// A = alpha - L_mu at one face (paper Sec. 3.1, eq. div_stress), all values
+// A = alpha - L_mu at one face (paper Sec. "Staggered-grid Discretization", eq. div_stress), all values
 // from the concatenated velocity buffer u.  Returns (A u)_f and the diagonal
 // of A at f.  Tangential no-slip walls use the ghost value -u_f, which equals
 // the one-sided wall difference (u_f - 0)/(h/2).
@@ -314,7 +314,7 @@ __device__ __forceinline__ bool low_wall(const Geo &g, int k, const int i[3]) {
 }
 
 // ------------------------------------------------------------------------
-// coefficient setup (Sec. 3.1 averages, Sec. 3.3 rescaling)
+// coefficient setup (Sec. "Staggered-grid Discretization" averages, Sec. "Rescaling of the Linear System" rescaling)
 // ------------------------------------------------------------------------
 
 __global__ void k_setup_faces(Geo g, const double *__restrict__ rho, double theta, double c,
@@ -466,7 +466,7 @@ __global__ void k_check_coefs(const double *__restrict__ rho, const double *__re
   if (!ok) atomicOr(flag, 1);
 }
 
-// bulk coefficient of the stress, lam = c (gamma - 2/3 mu) per cell (Sec. 2);
+// bulk coefficient of the stress, lam = c (gamma - 2/3 mu) per cell (Sec. "Preconditioners");
 // sig = c mu + lam / 2 = c (gamma + 4/3 mu) / 2 is what the Schur
 // approximation multiplies by 2 (eq. Schur_app_bulk)
 __global__ void k_setup_bulk(const double *__restrict__ gamma, const double *__restrict__ mu,
@@ -2006,7 +2006,7 @@ template void launch_tail_p<float>(const TailLevels<float> &, hipStream_t);
 template void launch_tail_p<double>(const TailLevels<double> &, hipStream_t);
 
 // ------------------------------------------------------------------------
-// preconditioner glue (Sec. 2: P1..P5 compositions)
+// preconditioner glue (Sec. "Preconditioners": P1..P5 compositions)
 // ------------------------------------------------------------------------
 
 template <typename T, int DIM>
@@ -2638,7 +2638,7 @@ void launch_norm2(const double *a, i64 n, double *partials, double *nrm2, hipStr
 }
 
 
-// sum of log(mu) over mu > 0 and the count of such cells (rescaling, Sec. 3.3)
+// sum of log(mu) over mu > 0 and the count of such cells (rescaling, Sec. "Rescaling of the Linear System")
 __global__ void k_logsum_partial(const double *__restrict__ mu, i64 n, double *__restrict__ partials) {
   __shared__ double sh[kBlock / 64];
   double acc = 0.0, cnt = 0.0;

@@ -5,7 +5,7 @@ fields) and describes the array layout of the C ABI.  It holds none of the
 solver's arithmetic: no face/edge averaging, no operators, no rescaling.  Both
 the GPU path and the CPU oracle receive exactly these bytes.
 
-The workloads follow the paper's own kind of test problems (Sec. 4: smooth
+The workloads follow the paper's own kind of test problems (Sec. "Results": smooth
 variable coefficients, viscosity/density contrasts, random right-hand sides on
 no-slip or periodic unit domains) at the five sizes the benchmark and the tests
 use.  Seeds: workload k uses base seed 1000*k; sub-streams +1 coefficients,
@@ -440,7 +440,7 @@ def fd_directions(seed, lay: Layout, count):
 
 
 def bubble(dim=3, n=32, r_mu=100.0, r_rho=100.0, theta=0.0, seed=6000):
-    """The paper's bubble test problem (Sec. 4, eq. varcoeff_def): a sphere
+    """The paper's bubble test problem (Sec. "Results", eq. varcoeff_def): a sphere
     (disk in 2D) of radius L/4 at the centre of the unit cube (square) with
     no-slip walls; mu = f(x; r_mu), rho = f(x; r_rho) with
     f(x; r) = (r+1)/2 + (r-1)/2 tanh(d/eps) + 0.1 R, d the signed distance to

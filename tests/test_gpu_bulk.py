@@ -1,4 +1,4 @@
-"""Bulk viscosity on the GPU (Sec. 2: the stress (gamma - 2/3 mu)(div u) I for
+"""Bulk viscosity on the GPU (Sec. "Preconditioners": the stress (gamma - 2/3 mu)(div u) I for
 div u = g != 0; eq. Schur_app_bulk: gamma + 4/3 mu in the Schur approximation)
 against the oracle on identical seeded inputs: the operator, the boundary
 terms and the gradient contraction at 1e-12, the FP64 subsolver and

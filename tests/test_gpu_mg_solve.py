@@ -1,5 +1,5 @@
 """The stand-alone multigrid solvers on the GPU (the velocity and pressure
-V-cycle run to convergence, Sec. 4.3.1) against the oracle: FP64 cycle counts
+V-cycle run to convergence, Sec. "The effect of the number of multigrid cycles") against the oracle: FP64 cycle counts
 equal the oracle's (+-1) and the solutions agree to the tolerance; the FP32
 hierarchy, used as iterative refinement under FP64 residuals, reaches the same
 FP64 tolerances; and the coupled solver costs at most three split solves in

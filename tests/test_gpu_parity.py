@@ -229,7 +229,7 @@ FREESLIP = [
                                               (W.MG_FP32, W.FGMRES)])
 def test_solve_parity_freeslip(dim, n, bc, theta, precond, precision, krylov):
     """Free-slip walls (zero normal velocity, no tangential momentum flux),
-    variable coefficients, b = M x for a seeded x (Sec. 4 protocol)."""
+    variable coefficients, b = M x for a seeded x (Sec. "Results" protocol)."""
     print(f"free-slip solve {dim} {n} {bc} theta={theta} P{precond} prec={precision} kry={krylov}",
           flush=True)
     p, lay = params(dim, n, bc, theta, precond=precond, precision=precision, krylov=krylov)

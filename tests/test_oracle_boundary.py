@@ -1,4 +1,4 @@
-"""Prescribed wall velocities (Sec. 3.2: the viscous operator is affine when
+"""Prescribed wall velocities (Sec. "Krylov Solver": the viscous operator is affine when
 the velocity boundary values are non-zero; the Krylov solver works on the
 homogeneous problem after the boundary terms are moved to the right-hand
 side).  The oracle's boundary terms are pinned by Couette flow, whose

@@ -1,4 +1,4 @@
-"""Bulk viscosity (Sec. 2: for div u = g != 0 the stress gains
+"""Bulk viscosity (Sec. "Preconditioners": for div u = g != 0 the stress gains
 (gamma - 2/3 mu)(div u) I; eq. Schur_app_bulk: the Schur approximation uses
 gamma + 4/3 mu in place of 2 mu; Appendix A: the constant-coefficient symbol).
 The oracle's bulk term is pinned by the grad-div operator it must reduce to

@@ -1,5 +1,5 @@
 """The oracle's stand-alone multigrid solvers (the velocity and pressure
-V-cycle run to convergence, Sec. 4.3.1) pinned against dense direct solves of
+V-cycle run to convergence, Sec. "The effect of the number of multigrid cycles") pinned against dense direct solves of
 the operators assembled from the oracle's own M by unit vectors, against the
 V-cycle contraction bounds, and against the paper's statement that the coupled
 solver costs at most 2-3 times the scalar V-cycles of a split (projection)

@@ -1,4 +1,4 @@
-"""Walls of one axis with different conditions (Sec. 3.1: a condition is
+"""Walls of one axis with different conditions (Sec. "Staggered-grid Discretization": a condition is
 specified at each domain boundary): no-slip at one end, free-slip at the
 other.  Pinned by the open channel, whose discrete solution is known in
 closed form (the shear stress falls linearly from zero at the free surface,

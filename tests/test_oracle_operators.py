@@ -1,5 +1,5 @@
 """Pins of the oracle's discrete operators against facts the paper and the
-mathematics fix (Sec. 2, Sec. 3.1, Appendix A of arXiv:1308.4605)."""
+mathematics fix (Sec. "Preconditioners", Sec. "Staggered-grid Discretization", Appendix A of arXiv:1308.4605)."""
 import numpy as np
 import pytest
 
@@ -44,7 +44,7 @@ def _oracle(dim, n, bc, theta=0.0, seed=0, const=None, **kw):
 
 @pytest.mark.parametrize("dim,n,bc", CASES)
 def test_divergence_is_minus_gradient_transpose(dim, n, bc):
-    """D = -G^T exactly (Sec. 3.1: the staggered D and G are negative adjoints
+    """D = -G^T exactly (Sec. "Staggered-grid Discretization": the staggered D and G are negative adjoints
     for periodic and no-slip boundaries); entries are +-1/h, exact in FP64."""
     o, lay, h, *_ = _oracle(dim, n, bc)
     M, nv = assemble(o, lay)
@@ -57,7 +57,7 @@ def test_divergence_is_minus_gradient_transpose(dim, n, bc):
 
 @pytest.mark.parametrize("dim,n,bc", CASES)
 def test_div_grad_is_textbook_laplacian(dim, n, bc):
-    """D G = L_p, the standard 5/7-point cell Laplacian (Sec. 3.1), built here
+    """D G = L_p, the standard 5/7-point cell Laplacian (Sec. "Staggered-grid Discretization"), built here
     independently as a Kronecker sum (zero-flux walls, periodic wrap)."""
     o, lay, h, *_ = _oracle(dim, n, bc)
     M, nv = assemble(o, lay)
@@ -68,7 +68,7 @@ def test_div_grad_is_textbook_laplacian(dim, n, bc):
 
 @pytest.mark.parametrize("dim,n,bc", CASES)
 def test_saddle_operator_symmetric_and_viscous_semidefinite(dim, n, bc):
-    """M = M^T for variable rho, mu (Sec. 2: G = (-D)^*), and -L_mu is
+    """M = M^T for variable rho, mu (Sec. "Preconditioners": G = (-D)^*), and -L_mu is
     symmetric positive semidefinite (a viscous dissipation)."""
     o, lay, h, *_ = _oracle(dim, n, bc, theta=3.0, seed=7)
     M, nv = assemble(o, lay)
@@ -83,7 +83,7 @@ def test_saddle_operator_symmetric_and_viscous_semidefinite(dim, n, bc):
 @pytest.mark.parametrize("dim,n,bc", CASES)
 def test_constant_viscosity_stress_form_identity(dim, n, bc):
     """For constant mu0 the stress-form operator equals mu0 (L + G D), L the
-    Laplace-form vector Laplacian with the no-slip wall rule (Sec. 3.1: the
+    Laplace-form vector Laplacian with the no-slip wall rule (Sec. "Staggered-grid Discretization": the
     stress form degenerates to mu0 L on divergence-free fields).  Pins the
     one-sided wall shear and the cross terms."""
     mu0 = 1.7
@@ -97,7 +97,7 @@ def test_constant_viscosity_stress_form_identity(dim, n, bc):
 
 def test_alpha_term_is_face_averaged_density():
     """A = theta rho_f - L_mu with rho_f the mean of the two cells sharing the
-    face (Sec. 3.1): A(theta) - A(0) = theta diag(rho_f)."""
+    face (Sec. "Staggered-grid Discretization"): A(theta) - A(0) = theta diag(rho_f)."""
     dim, n, bc = 2, (8, 8), (0, 1)
     o1, lay, h, rho, mu = _oracle(dim, n, bc, theta=5.0, seed=3)
     o0, *_ = _oracle(dim, n, bc, theta=0.0, seed=3)

@@ -1,5 +1,5 @@
 """The oracle against the iteration counts the paper states for its own
-bubble test problem (Sec. 4.2-4.3; values in tests/golden/paper_claims.json).
+bubble test problem (Secs. "Comparison of Preconditioners" and "Robustness"; values in tests/golden/paper_claims.json).
 These are soft pins (upper bounds and orderings read from the text; the
 figures themselves are not available)."""
 import json
@@ -16,7 +16,7 @@ GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_c
 
 def _solve(w, **kw):
     o = oracle.Oracle.from_workload(w, **kw)
-    bu, bp = o.apply(w.extra["x_u"], w.extra["x_p"])  # b = M x, x random (Sec. 4)
+    bu, bp = o.apply(w.extra["x_u"], w.extra["x_p"])  # b = M x, x random (Sec. "Results")
     xu, xp, st, rc = o.solve(bu, bp - bp.mean(), tol=1e-10, max_iter=400)
     return st
 
@@ -103,7 +103,7 @@ def check_restart_claims(res):
 
 
 def test_restart_claims_128():
-    """Sec. 4.2.2 at 128^2 (the GPU test runs the paper's 512^2)."""
+    """Sec. "The effect of restarts" at 128^2 (the GPU test runs the paper's 512^2)."""
     res = restart_study(2, 128, lambda w, P, m: _solve(w, precond=P, restart=m)["iters"])
     check_restart_claims(res)
 
@@ -144,7 +144,7 @@ def _oracle_mg(lay, nu, vel):
 
 @pytest.mark.parametrize("dim,n", [(2, 128), (3, 32)])
 def test_smoothing_sweeps_claims(dim, n):
-    """Sec. 4.1.1 at 128^2 / 32^3 (the GPU test runs 512^2 / 128^3)."""
+    """Sec. "The effect of the number of smoothing sweeps" at 128^2 / 32^3 (the GPU test runs 512^2 / 128^3)."""
     check_sweep_claims(sweep_study(dim, n, _oracle_mg))
 
 
@@ -173,7 +173,7 @@ def check_vcycle_claims(sv):
 
 
 def test_vcycles_per_application_claims_128():
-    """Sec. 4.1.2 at 128^2 (the GPU test runs 512^2 and 128^3)."""
+    """Sec. "The effect of the number of multigrid cycles" at 128^2 (the GPU test runs 512^2 and 128^3)."""
     sv = vcycle_study(2, 128, lambda w, v: _solve(w, precond=W.P1, vcycles=v,
                                                   restart=60)["scalar_vcycles"])
     check_vcycle_claims(sv)

@@ -1,6 +1,6 @@
 """Pins of the oracle's solver path (multigrid subsolvers, preconditioners,
 GMRES/FGMRES) against exact solutions, closed forms and the paper's stated
-properties (arXiv:1308.4605, Sec. 2, Sec. 4.1, Appendices A-C)."""
+properties (arXiv:1308.4605, Sec. "Preconditioners", Sec. "Multigrid Subsolvers", Appendices A-C)."""
 import numpy as np
 import pytest
 
@@ -117,7 +117,7 @@ def test_gmres_matches_dense_direct_solve(dim, n, bc, theta, precond, krylov):
 
 
 # ---------------------------------------------------------------------------
-# manufactured solutions: global second order (Sec. 3.1)
+# manufactured solutions: global second order (Sec. "Staggered-grid Discretization")
 # ---------------------------------------------------------------------------
 
 def _mms_fields(dim, periodic, freeslip=False):
@@ -218,7 +218,7 @@ def test_manufactured_solution_second_order(dim, ns, periodic, theta, freeslip):
 
 
 # ---------------------------------------------------------------------------
-# multigrid subsolvers (Sec. 4.1, Appendix C)
+# multigrid subsolvers (Sec. "Multigrid Subsolvers", Appendix C)
 # ---------------------------------------------------------------------------
 
 def _vel_op(o, lay, u):
@@ -261,7 +261,7 @@ RATE = {2: 0.105, 3: 0.15}
 @pytest.mark.parametrize("dim,n", [(2, 128), (3, 32)])
 def test_velocity_vcycle_contracts_tenfold(dim, n):
     """Constant-coefficient steady no-slip stress-form velocity problem
-    (Sec. 4.1.1): per-cycle residual reduction and 12 cycles to 1e-10."""
+    (Sec. "The effect of the number of smoothing sweeps"): per-cycle residual reduction and 12 cycles to 1e-10."""
     lay = W.make_layout(dim, (n,) * dim, (1,) * dim)
     o, lay, h = _mk(dim, lay.n, lay.bc, 0.0, np.ones(lay.ncell), np.ones(lay.ncell), rescale_c=1.0)
     r = W.random_velocity(1, lay)
@@ -289,7 +289,7 @@ def test_pressure_vcycle_contracts_tenfold(dim, n, bc):
 
 def test_vcycle_is_linear():
     """A fixed number of V-cycles is a constant linear operator (needed for
-    left-preconditioned GMRES, Sec. 4)."""
+    left-preconditioned GMRES, Sec. "Results")."""
     dim, n, bc = 3, (8, 8, 8), (1, 0, 1)
     lay = W.make_layout(dim, n, bc)
     rho, mu = W.random_coefficients(2, lay)
@@ -328,7 +328,7 @@ def test_coarse_coefficients_of_linear_fields():
 
 
 # ---------------------------------------------------------------------------
-# preconditioners with (near-)exact subsolvers (Sec. 2, Appendix B)
+# preconditioners with (near-)exact subsolvers (Sec. "Preconditioners", Appendix B)
 # ---------------------------------------------------------------------------
 
 EXACT = dict(vcycles=40)
@@ -453,7 +453,7 @@ def test_bubble_schur_spectrum_32():
 
 
 # ---------------------------------------------------------------------------
-# adjoint (M = M^T, Sec. 2)
+# adjoint (M = M^T, Sec. "Preconditioners")
 # ---------------------------------------------------------------------------
 
 def _loss_and_grad(dim, n, bc, theta, s, f, target, tol):
