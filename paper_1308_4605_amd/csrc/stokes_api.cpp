@@ -105,6 +105,12 @@ struct stokes_ctx {
   int vsplit = 0;
   void *vrs = nullptr, *ves = nullptr, *alpha_v = nullptr;
   int tail_l = -1;  // first level of the single-workgroup coarse tail (-1: none)
+  // the velocity tail as its matrix B (tail_nv x tail_nv, row-major, precision
+  // of the hierarchy), built at create; tail_dense = 0 (STOKES_TAIL_DENSE=0 in
+  // the environment at create time): the tail's own sweeps every time
+  void *tail_B = nullptr;
+  int tail_nv = 0;
+  int tail_dense = 1;
   double c = 1.0;
   Level lev[kMaxLev];
   i64 nvel = 0, ncell = 0, nedge = 0, n = 0;
@@ -207,6 +213,17 @@ bool use_vsplit(const stokes_params *p) {
   return p->precision == STOKES_MG_FP32 && p->n[0] >= 128 && cells > kTailCells;
 }
 
+// first level of the single-workgroup coarse tail: the first of the last
+// kTailMax levels with at most kTailCells cells (-1: none)
+int tail_level_of(const stokes_params *p, int nlev) {
+  for (int l = std::max(0, nlev - kTailMax); l < nlev; l++) {
+    i64 cells = 1;
+    for (int a = 0; a < p->dim; a++) cells *= (i64)(p->n[a] >> l);
+    if (cells <= kTailCells) return l;
+  }
+  return -1;
+}
+
 void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
   const int d = p->dim;
   const size_t tb = (p->precision == STOKES_MG_FP32) ? sizeof(float) : sizeof(double);
@@ -236,6 +253,19 @@ void carve_all(const stokes_params *p, int nlev, Carver &cv, stokes_ctx *X) {
     L.rhs_p = cv.take(g.ncell * tb);
     L.res_p = cv.take(g.ncell * tb);
     if (X) X->lev[l] = L;
+  }
+  // matrix of the velocity tail's linear map (first tail level's velocity
+  // count squared)
+  const int tl = tail_level_of(p, nlev);
+  if (tl >= 0) {
+    int nt[3];
+    for (int a = 0; a < 3; a++) nt[a] = (a < d) ? (n[a] >> tl) : 1;
+    const Geo gt = make_geo(d, nt, ns, p->h * (double)(1 << tl));
+    void *B = cv.take((size_t)gt.nvel * (size_t)gt.nvel * tb);
+    if (X) {
+      X->tail_B = B;
+      X->tail_nv = (int)gt.nvel;
+    }
   }
   // FP64 fine coefficients of M (rescaled)
   double *ma = (double *)cv.take(nv * 8);
@@ -418,12 +448,18 @@ void split_alpha(stokes_ctx *X) {
 // components already written in that sweep (on its second colour, the half
 // of component k its first colour wrote).  Pressure alike with beta on the
 // faces and red-black passes over the cells (half of rhs read and half of
-// phi written per pass).
+// phi written per pass).  A velocity tail applied as its matrix counts the
+// matrix, its input and its output instead of the tail levels' kernels.
 double vcycle_alg_bytes(const stokes_ctx *X, bool vel) {
   const double s = X->mg32 ? 4.0 : 8.0;
   const bool th = X->p.theta != 0.0;
   double total = 0.0;
   for (int l = 0; l < X->nlev; l++) {
+    if (vel && X->tail_dense && l >= X->tail_l) {
+      const double nt = (double)X->tail_nv;
+      total += s * (nt * nt + 2.0 * nt);
+      break;
+    }
     const Geo &g = X->lev[l].g;
     const double nv = (double)g.nvel, nc = (double)g.ncell, ne = (double)g.nedge;
     const bool coarsest = (l == X->nlev - 1);
@@ -560,12 +596,26 @@ TailLevels<T> tail_levels(stokes_ctx *X, int l0, const T *rhs, T *phi, bool vel)
   return t;
 }
 
+// B of the velocity tail: one workgroup per column, each running the tail on
+// a unit vector with its own vectors in LDS.  False (tail_dense off) when
+// the vectors do not fit.
+template <typename T>
+bool build_tail_matrix(stokes_ctx *X) {
+  TailLevels<T> t = tail_levels<T>(X, X->tail_l, nullptr, nullptr, true);
+  if (!tail_plan_lds<T>(t, true, true)) return false;
+  launch_tail_vel_columns<T>(t, P<T>(X->tail_B), X->tail_nv, X->s);
+  return true;
+}
+
 // velocity V-cycle on level l from zero (Appendix C)
 template <typename T>
 void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
   Level &L = X->lev[l];
   if (l == X->tail_l) {
-    launch_tail_vel<T>(tail_levels<T>(X, l, rhs, phi, true), X->s);
+    if (X->tail_dense)
+      launch_tail_matvec<T>(P<T>(X->tail_B), X->tail_nv, rhs, phi, X->s);
+    else
+      launch_tail_vel<T>(tail_levels<T>(X, l, rhs, phi, true), X->s);
     return;
   }
   const bool coarsest = l == X->nlev - 1;
@@ -1407,11 +1457,8 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
   for (int l = 0; l < nlev; l++) X->lev[l].g.sing = X->lev[l].gv.sing = X->vel_singular;
   X->vsplit = use_vsplit(p) ? 1 : 0;
   // coarse tail: the levels small enough for one workgroup (at most kTailMax)
-  for (int l = std::max(0, nlev - kTailMax); l < nlev; l++)
-    if (X->lev[l].g.ncell <= kTailCells) {
-      X->tail_l = l;
-      break;
-    }
+  X->tail_l = tail_level_of(p, nlev);
+  if (const char *e = std::getenv("STOKES_TAIL_DENSE")) X->tail_dense = (e[0] != '0');
   // colour-split storage for the velocity levels below the coarse tail
   if (X->vsplit)
     for (int l = 0; l < nlev && (X->tail_l < 0 || l < X->tail_l); l++) X->lev[l].gv.split = 1;
@@ -1500,6 +1547,9 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
     else
       split_alpha<double>(X);
   }
+  if (X->tail_l < 0 || !X->tail_B) X->tail_dense = 0;
+  if (X->tail_dense && !(X->mg32 ? build_tail_matrix<float>(X) : build_tail_matrix<double>(X)))
+    X->tail_dense = 0;
   if (X->sdiag) {
     // diagonal scaling from the FP64 coefficients of M'; X->t is still zero
     launch_fill<int>(X->dflag, 0, 1, s);

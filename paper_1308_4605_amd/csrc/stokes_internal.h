@@ -153,13 +153,28 @@ struct TailLevels {
   int lds0;
   unsigned lds_bytes;
   unsigned off[kTailMax][7];
+  // vec0: the first level's phi, rhs and res live in LDS too (at off[0][3..5];
+  // its coefficients stay in global memory); set for the column launches
+  int vec0;
 };
 constexpr unsigned kTailLds = 60 * 1024;  // dynamic LDS budget of a tail launch
-// fills lds0 / off / lds_bytes for the velocity (vel) or pressure tail
+// fills lds0 / off / lds_bytes for the velocity (vel) or pressure tail;
+// vec0: also place the first level's vectors in LDS (reserved first).
+// Returns false when vec0 is asked for and not every level's vectors fit.
 template <typename T>
-void tail_plan_lds(TailLevels<T> &L, bool vel);
+bool tail_plan_lds(TailLevels<T> &L, bool vel, bool vec0 = false);
 template <typename T>
 void launch_tail_vel(const TailLevels<T> &L, hipStream_t s);
+// The velocity tail from a zero iterate is a fixed linear map B of its
+// right-hand side (nv = the first tail level's velocity count).  Column
+// launch: workgroup j runs the tail on the unit vector e_j with all vectors
+// in LDS (L planned with vec0) and stores the result as column j of the
+// row-major nv x nv matrix B.  Apply: phi = B rhs, one wave per row, FP64
+// accumulation.
+template <typename T>
+void launch_tail_vel_columns(const TailLevels<T> &L, T *B, int nv, hipStream_t s);
+template <typename T>
+void launch_tail_matvec(const T *B, int nv, const T *rhs, T *phi, hipStream_t s);
 template <typename T>
 void launch_tail_p(const TailLevels<T> &L, hipStream_t s);
 

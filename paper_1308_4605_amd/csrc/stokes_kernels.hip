@@ -1838,9 +1838,10 @@ __device__ void tail_stage(const TailLevels<T> &L, unsigned char *lds, TailPtrs<
       P.mc[l] = in ? (const T *)(lds + L.off[l][1]) : L.mc[l];
       P.me[l] = in ? (const T *)(lds + L.off[l][2]) : L.me[l];
       P.lam[l] = (in && L.lam[l]) ? (const T *)(lds + L.off[l][6]) : L.lam[l];
-      P.phi[l] = in ? (T *)(lds + L.off[l][3]) : L.phi[l];
-      P.rhs[l] = in ? (T *)(lds + L.off[l][4]) : L.rhs[l];
-      P.res[l] = in ? (T *)(lds + L.off[l][5]) : L.res[l];
+      const bool vin = in || (l == 0 && L.vec0);
+      P.phi[l] = vin ? (T *)(lds + L.off[l][3]) : L.phi[l];
+      P.rhs[l] = vin ? (T *)(lds + L.off[l][4]) : L.rhs[l];
+      P.res[l] = vin ? (T *)(lds + L.off[l][5]) : L.res[l];
     }
   }
   for (int l = L.lds0; l < L.nl; l++) {
@@ -1863,11 +1864,9 @@ __device__ void tail_stage(const TailLevels<T> &L, unsigned char *lds, TailPtrs<
   __syncthreads();
 }
 
+// the velocity tail cycle on staged levels (ends with a barrier)
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kTailBlock) k_tail_vel(TailLevels<T> L) {
-  extern __shared__ __align__(16) unsigned char tail_lds[];
-  __shared__ TailPtrs<T> P;
-  tail_stage<T>(L, tail_lds, P, true);
+__device__ __forceinline__ void tail_vel_run(const TailLevels<T> &L, const TailPtrs<T> &P) {
   const int nl = L.nl;
   for (int l = 0; l < nl - 1; l++) {
     const Geo &g = L.g[l];
@@ -1906,6 +1905,42 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_vel(TailLevels<T> L) {
     tail_vel_smooth<T, DIM>(g, P.a[l], P.mc[l], P.me[l], P.lam[l], P.rhs[l], P.phi[l],
                             L.nu_post);
   }
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kTailBlock) k_tail_vel(TailLevels<T> L) {
+  extern __shared__ __align__(16) unsigned char tail_lds[];
+  __shared__ TailPtrs<T> P;
+  tail_stage<T>(L, tail_lds, P, true);
+  tail_vel_run<T, DIM>(L, P);
+}
+
+// column blockIdx.x of the tail's matrix: the tail on the unit vector
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kTailBlock) k_tail_vel_columns(TailLevels<T> L,
+                                                                 T *__restrict__ B, int nv) {
+  extern __shared__ __align__(16) unsigned char tail_lds[];
+  __shared__ TailPtrs<T> P;
+  tail_stage<T>(L, tail_lds, P, true);
+  const int j = (int)blockIdx.x;
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) P.rhs[0][t] = (t == j) ? (T)1 : (T)0;
+  __syncthreads();
+  tail_vel_run<T, DIM>(L, P);
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) B[(i64)t * nv + j] = P.phi[0][t];
+}
+
+// phi = B rhs: wave w of the launch takes row w
+template <typename T>
+__global__ void k_tail_matvec(const T *__restrict__ B, int nv, const T *__restrict__ rhs,
+                              T *__restrict__ phi) {
+  const int row = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  if (row >= nv) return;  // the whole wave
+  const T *__restrict__ b = B + (i64)row * nv;
+  double acc = 0.0;
+  for (int c = lane; c < nv; c += 64) acc += (double)b[c] * (double)rhs[c];
+  acc = wave_sum(acc);
+  if (lane == 0) phi[row] = (T)acc;
 }
 
 template <typename T, int DIM>
@@ -1954,13 +1989,22 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_p(TailLevels<T> L) {
 }
 
 template <typename T>
-void tail_plan_lds(TailLevels<T> &L, bool vel) {
+bool tail_plan_lds(TailLevels<T> &L, bool vel, bool vec0) {
   auto up = [](unsigned x) { return (x + 15u) & ~15u; };
   L.lds0 = L.nl;
   L.lds_bytes = 0;
+  L.vec0 = vec0 ? 1 : 0;
   for (int l = 0; l < kTailMax; l++)
     for (int q = 0; q < 7; q++) L.off[l][q] = 0;
   unsigned total = 0;
+  if (vec0) {
+    const unsigned v = up((unsigned)(vel ? L.g[0].nvel : L.g[0].ncell) * sizeof(T));
+    for (int q = 3; q < 6; q++) {
+      L.off[0][q] = total;
+      total += v;
+    }
+    if (total > kTailLds) return false;
+  }
   // from the coarsest level up; the first tail level keeps the caller's
   // buffers in global memory
   for (int l = L.nl - 1; l >= 1; l--) {
@@ -1982,9 +2026,10 @@ void tail_plan_lds(TailLevels<T> &L, bool vel) {
     L.lds0 = l;
   }
   L.lds_bytes = total;
+  return !vec0 || L.lds0 <= 1;
 }
-template void tail_plan_lds<float>(TailLevels<float> &, bool);
-template void tail_plan_lds<double>(TailLevels<double> &, bool);
+template bool tail_plan_lds<float>(TailLevels<float> &, bool, bool);
+template bool tail_plan_lds<double>(TailLevels<double> &, bool, bool);
 
 template <typename T>
 void launch_tail_vel(const TailLevels<T> &L, hipStream_t s) {
@@ -2000,6 +2045,26 @@ void launch_tail_p(const TailLevels<T> &L, hipStream_t s) {
   else
     hipLaunchKernelGGL((k_tail_p<T, 2>), dim3(1), dim3(kTailBlock), L.lds_bytes, s, L);
 }
+template <typename T>
+void launch_tail_vel_columns(const TailLevels<T> &L, T *B, int nv, hipStream_t s) {
+  if (L.g[0].d == 3)
+    hipLaunchKernelGGL((k_tail_vel_columns<T, 3>), dim3(nv), dim3(kTailBlock), L.lds_bytes, s, L,
+                       B, nv);
+  else
+    hipLaunchKernelGGL((k_tail_vel_columns<T, 2>), dim3(nv), dim3(kTailBlock), L.lds_bytes, s, L,
+                       B, nv);
+}
+template <typename T>
+void launch_tail_matvec(const T *B, int nv, const T *rhs, T *phi, hipStream_t s) {
+  const unsigned nb = (unsigned)((nv + 3) / 4);  // four waves (rows) per workgroup
+  hipLaunchKernelGGL(k_tail_matvec<T>, dim3(nb), dim3(256), 0, s, B, nv, rhs, phi);
+}
+template void launch_tail_vel_columns<float>(const TailLevels<float> &, float *, int, hipStream_t);
+template void launch_tail_vel_columns<double>(const TailLevels<double> &, double *, int,
+                                              hipStream_t);
+template void launch_tail_matvec<float>(const float *, int, const float *, float *, hipStream_t);
+template void launch_tail_matvec<double>(const double *, int, const double *, double *,
+                                         hipStream_t);
 template void launch_tail_vel<float>(const TailLevels<float> &, hipStream_t);
 template void launch_tail_vel<double>(const TailLevels<double> &, hipStream_t);
 template void launch_tail_p<float>(const TailLevels<float> &, hipStream_t);
