@@ -340,7 +340,11 @@ double stokes_rescale(const stokes_ctx *ctx);
    (each value the pass needs counted once: every velocity component, the
    cell and edge viscosities in full, the pass's own colour half of the
    right-hand side and of the mass coefficient, and the half of the
-   component it writes).  Reading the totals synchronises the stream. */
+   component it writes).  Reading the totals synchronises the stream.
+   enable: 0 off, 1 per-launch and per-V-cycle events (every V-cycle then runs
+   kernel by kernel), 2 per-V-cycle events only (the finest-level V-cycle
+   replays its recorded graph as in untimed runs); other values EINVAL.
+   Enabling resets the totals. */
 int stokes_set_timing(stokes_ctx *ctx, int enable);
 int stokes_kernel_time(stokes_ctx *ctx, double *ms_total, long *launches, double *bytes_total);
 /* With timing enabled, every V-cycle started from the finest level (in the

@@ -111,6 +111,13 @@ struct stokes_ctx {
   void *tail_B = nullptr;
   int tail_nv = 0;
   int tail_dense = 1;
+  // the finest-level velocity V-cycle of a colour-split hierarchy (fixed
+  // buffers vrs -> ves) recorded once at create as a HIP graph and replayed
+  // on the caller's stream (STOKES_VGRAPH=0 in the environment at create
+  // time: launched kernel by kernel)
+  hipStream_t gstream = nullptr;
+  hipGraph_t vgraph = nullptr;
+  hipGraphExec_t vgexec = nullptr;
   double c = 1.0;
   Level lev[kMaxLev];
   i64 nvel = 0, ncell = 0, nedge = 0, n = 0;
@@ -538,7 +545,7 @@ void smooth_vel(stokes_ctx *X, int l, const T *rhs, T *phi, int nsweeps, bool fr
       for (int colour = 0; colour < 2; colour++) {
         const int first = from_zero && s == 0;
         // the timed passes are the full ones (the first sweep reads less)
-        const bool tm = X->timing && l == 0 && !first;
+        const bool tm = X->timing == 1 && l == 0 && !first;
         if (tm) {
           if (X->ev_used == kEventPool) fold_events(X);
           (void)hipEventRecord(X->ev[2 * X->ev_used], X->s);
@@ -644,6 +651,41 @@ void vcycle_vel(stokes_ctx *X, int l, const T *rhs, T *phi) {
   smooth_vel<T>(X, l, rhs, phi, X->p.nu_post);
 }
 
+// Records the colour-split finest-level V-cycle (vrs -> ves) on a private
+// stream into vgraph / vgexec.  Nothing runs during the capture.
+template <typename T>
+bool capture_vcycle(stokes_ctx *X) {
+  if (hipStreamCreateWithFlags(&X->gstream, hipStreamNonBlocking) != hipSuccess) {
+    X->gstream = nullptr;
+    return false;
+  }
+  if (hipStreamBeginCapture(X->gstream, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
+  hipStream_t user = X->s;
+  const int tm = X->timing;
+  X->timing = 0;
+  X->s = X->gstream;
+  vcycle_vel<T>(X, 0, P<T>(X->vrs), P<T>(X->ves));
+  X->s = user;
+  X->timing = tm;
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(X->gstream, &g) != hipSuccess || !g) return false;
+  X->vgraph = g;
+  if (hipGraphInstantiate(&X->vgexec, g, nullptr, nullptr, 0) != hipSuccess) {
+    X->vgexec = nullptr;
+    return false;
+  }
+  return true;
+}
+
+void release_vgraph(stokes_ctx *X) {
+  if (X->vgexec) (void)hipGraphExecDestroy(X->vgexec);
+  if (X->vgraph) (void)hipGraphDestroy(X->vgraph);
+  if (X->gstream) (void)hipStreamDestroy(X->gstream);
+  X->vgexec = nullptr;
+  X->vgraph = nullptr;
+  X->gstream = nullptr;
+}
+
 // pressure V-cycle; singular operator: consistent coarsest problem by mean
 // removal
 template <typename T>
@@ -693,7 +735,10 @@ void vcycle_top(stokes_ctx *X, bool vel, const T *rhs, T *phi, bool means_in = f
     double *sums = X->dsc + 8;
     if (means_in) launch_vel_sums<T>(L0.g, rhs, X->part, sums, X->s);
     launch_vel_permute<T>(L0.g, L0.gv, rhs, P<T>(X->vrs), means_in ? sums : nullptr, X->s);
-    vcycle_vel<T>(X, 0, P<T>(X->vrs), P<T>(X->ves));
+    if (X->vgexec && X->timing != 1)
+      hip_ok(X, hipGraphLaunch(X->vgexec, X->s));
+    else
+      vcycle_vel<T>(X, 0, P<T>(X->vrs), P<T>(X->ves));
     if (means_out) launch_vel_sums<T>(L0.gv, P<T>(X->ves), X->part, sums, X->s);
     launch_vel_permute<T>(L0.gv, L0.g, P<T>(X->ves), phi, means_out ? sums : nullptr, X->s);
   } else if (vel) {
@@ -1588,7 +1633,14 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
   }
   X->vc_cycle_bytes[0] = vcycle_alg_bytes(X, true);
   X->vc_cycle_bytes[1] = vcycle_alg_bytes(X, false);
+  const char *vg = std::getenv("STOKES_VGRAPH");
+  if (X->vsplit && !(vg && vg[0] == '0') &&
+      !(X->mg32 ? capture_vcycle<float>(X) : capture_vcycle<double>(X))) {
+    release_vgraph(X);  // the V-cycle then runs kernel by kernel
+    (void)hipGetLastError();
+  }
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
+    release_vgraph(X);
     (void)hipHostFree(X->host);
     delete X;
     return STOKES_EDEVICE;
@@ -1608,6 +1660,7 @@ void stokes_destroy(stokes_ctx *X) {
   for (auto e : X->vev) (void)hipEventDestroy(e);
   for (auto e : X->pev)
     if (e) (void)hipEventDestroy(e);
+  release_vgraph(X);
   if (X->host) (void)hipHostFree(X->host);
   delete X;
 }
@@ -1817,7 +1870,8 @@ int stokes_set_timing(stokes_ctx *X, int enable) {
   }
   fold_events(X);
   fold_vevents(X);
-  X->timing = enable ? 1 : 0;
+  if (enable < 0 || enable > 2) return STOKES_EINVAL;
+  X->timing = enable;
   X->t_ms = 0.0;
   X->launches = 0;
   X->bytes = 0.0;

@@ -341,8 +341,10 @@ class Stokes:
             out["dgamma_cell"] = dg
         return out
 
-    def set_timing(self, enable: bool):
-        rc = lib().stokes_set_timing(self._h, 1 if enable else 0)
+    def set_timing(self, enable):
+        """0 / False: off; 1 / True: per-launch and per-V-cycle events (the
+        V-cycles run kernel by kernel); 2: per-V-cycle events only."""
+        rc = lib().stokes_set_timing(self._h, int(enable))
         if rc:
             raise StokesError(rc, "stokes_set_timing")
 

@@ -81,10 +81,14 @@ def _vcycle_bytes_model(dim, n, bc, theta, vel, s=8, nu=(2, 2, 8)):
         sweeps = nu[2] if coarsest else nu[0] + nu[1]
         edges = {m_: int(np.prod(lay.edge_dims(m_)[:dim])) for m_ in lay.edge_families}
         if vel:
-            # levels of at most 512 cells run in the single-workgroup tail, which
-            # clears phi; above it the first sweep starts from uncleared memory
-            # (every extent even) and reads only the components it has written
-            in_tail = nc <= 512
+            # levels of at most 512 cells form the coarse tail, applied as its
+            # matrix (first tail level's nv squared, plus its input and output)
+            if nc <= 512:
+                total += s * (nv * nv + 2.0 * nv)
+                break
+            # above it the first sweep starts from uncleared memory (every
+            # extent even) and reads only the components it has written
+            in_tail = False
             zf = (not in_tail) and all(x % 2 == 0 for x in dims[l]) and \
                 (nu[2] if coarsest else nu[0]) > 0
             b = 0 if zf else nv
@@ -121,14 +125,16 @@ def _vcycle_bytes_model(dim, n, bc, theta, vel, s=8, nu=(2, 2, 8)):
     (3, (516, 8, 8), (1, 0, 0)),   # no tail; odd coarsest extent (129), which keeps the fill
     (2, (256, 256), (0, 0)),       # periodic 2D, tail from 16^2
 ])
-def test_vcycle_timing_counts_and_bytes(dim, n, bc):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_vcycle_timing_counts_and_bytes(dim, n, bc, mode):
     """The V-cycle timer counts one velocity and one pressure cycle per P1
-    application and reports the bytes of the documented cycle model."""
+    application and reports the bytes of the documented cycle model, with
+    per-launch events (mode 1) and with per-V-cycle events only (mode 2)."""
     p, lay = params(dim, n, bc, 10.0, precond=W.P1)
     rho, mu = W.random_coefficients(98, lay)
     g, _ = pair(p, rho, mu)
     bu = W.random_velocity(99, lay)
-    g.set_timing(True)
+    g.set_timing(mode)
     g.precond(T(bu), T(np.zeros(lay.ncell)))
     g.precond(T(bu), T(np.zeros(lay.ncell)))
     msv, cv, bv = g.vcycle_time(False)
