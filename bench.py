@@ -211,6 +211,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="only one FP32-multigrid solve of the workload (then the calibration "
+                         "copy if asked), no JSON line: the program the counter runs profile")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -234,6 +237,16 @@ def main():
     lay = w.layout
     T = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
     rho, mu, bu, bp = T(w.rho), T(w.mu), T(w.bu), T(w.bp)
+
+    if args.profile_solve:
+        S = Stokes(w.params(precision=W.MG_FP32, krylov=W.FGMRES), rho, mu)
+        _, _, st, rc = S.solve(bu, bp, tol=args.tol, max_iter=3000)
+        torch.cuda.synchronize()
+        _log(f"profiled solve: rc {rc}, iters {st['iters']}, rel_res {st['rel_res_true']:.2e}")
+        S.close()
+        if args.calib_copy:
+            _calibration_copy(torch, dev)
+        return
 
     def timed_solves(params, steps, warmup, timing):
         S = Stokes(params, rho, mu)
@@ -389,11 +402,15 @@ def main():
     }
     print(json.dumps(line), flush=True)
     if args.calib_copy:
-        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        _log("calibration copy: 1 GiB read + 1 GiB write")
+        _calibration_copy(torch, dev)
+
+
+def _calibration_copy(torch, dev):
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    _log("calibration copy: 1 GiB read + 1 GiB write")
 
 
 if __name__ == "__main__":

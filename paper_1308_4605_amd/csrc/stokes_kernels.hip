@@ -2514,10 +2514,10 @@ __global__ void __launch_bounds__(kArnBlock) k_dcgs_update(const double *__restr
                                                            float *__restrict__ out32,
                                                            double *__restrict__ coef_out,
                                                            double *__restrict__ partials) {
-  // T(l, i), l <= i
-  auto T = [&](int l, int i) -> double {
-    return tm ? tm[l * ld + i] : tp.t[i * (i + 1) / 2 + l];
-  };
+  // T(l, i), l <= i, read straight from the argument (no reference to tp
+  // is taken, which would give it a private copy in every lane)
+#define TRI(l, i) \
+  (tm ? tm[(l) * ld + (i)] : ((i) < kTriDim ? tp.t[(i) * ((i) + 1) / 2 + (l)] : 0.0))
   // coefficients (the same few values in every thread), over compile-time
   // register indices
   double d[MAXV], g[MAXV];
@@ -2527,7 +2527,7 @@ __global__ void __launch_bounds__(kArnBlock) k_dcgs_update(const double *__restr
     double acc = 0.0;
 #pragma unroll
     for (int l = 0; l < MAXV; l++)
-      if (l <= i && i <= j) acc += T(l, i) * dots[l];
+      if (l <= i && i <= j) acc += TRI(l, i) * dots[l];
     d[i] = (i <= j) ? acc : 0.0;
     dd2 += d[i] * d[i];
   }
@@ -2537,9 +2537,10 @@ __global__ void __launch_bounds__(kArnBlock) k_dcgs_update(const double *__restr
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < MAXV; i++)
-      if (i >= l && i <= j) acc += T(l, i) * d[i];
+      if (i >= l && i <= j) acc += TRI(l, i) * d[i];
     g[l] = (l <= j) ? acc : 0.0;
   }
+#undef TRI
   const double q = dots[j + 1];
   const double nu2 = q - dd2;
   const double floor2 = q * 0x1p-60;
