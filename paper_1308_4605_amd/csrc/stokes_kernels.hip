@@ -2200,14 +2200,20 @@ __global__ void k_sum_partial(const T *__restrict__ a, i64 n, double *__restrict
 }
 
 // out[j] = sum_b partials[b * stride + j] for j < nout, fixed order
-__global__ void k_finish(const double *__restrict__ partials, int nblocks, int stride, int nout,
-                         double *__restrict__ out) {
-  __shared__ double sh[kBlock / 64];
-  for (int j = 0; j < nout; j++) {
+// out[j] = sum over the blocks of partials[b * stride + j], j < nout: wave w
+// takes the outputs w, w + (waves), ...; its lanes sum blocks lane, lane +
+// 64, ... and the wave's butterfly adds the lanes (a fixed order: the result
+// does not depend on timing)
+constexpr int kFinishBlock = 1024;
+__global__ void __launch_bounds__(kFinishBlock)
+    k_finish(const double *__restrict__ partials, int nblocks, int stride, int nout,
+             double *__restrict__ out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = wid; j < nout; j += nw) {
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += partials[(i64)b * stride + j];
-    const double r = block_sum(acc, sh);
-    if (threadIdx.x == 0) out[j] = r;
+    for (int b = lane; b < nblocks; b += 64) acc += partials[(i64)b * stride + j];
+    acc = wave_sum(acc);
+    if (lane == 0) out[j] = acc;
   }
 }
 
@@ -2221,7 +2227,7 @@ template <typename T>
 void launch_sum(const T *a, i64 n, double *partials, double *out, hipStream_t s) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_sum_partial<T>, dim3(nb), dim3(kBlock), 0, s, a, n, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, out);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nb, 1, 1, out);
 }
 
 template <typename T>
@@ -2305,7 +2311,7 @@ void launch_vel_sums(const Geo &g, const T *in, double *partials, double *sums, 
   const i64 nbx = (nmax + 4 * kBlock - 1) / (4 * kBlock);
   const int nr = (int)(nbx < kRedBlocks ? (nbx < 1 ? 1 : nbx) : kRedBlocks);
   hipLaunchKernelGGL(k_vel_sums_partial<T>, dim3(nr, g.d), dim3(kBlock), 0, s, g, in, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nr, 3, g.d, sums);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nr, 3, g.d, sums);
 }
 template void launch_vel_sums<float>(const Geo &, const float *, double *, double *, hipStream_t);
 template void launch_vel_sums<double>(const Geo &, const double *, double *, double *,
@@ -2614,7 +2620,7 @@ void launch_cgs_dots(const double *w, const double *const *v, int nv, i64 n, dou
   const int nb = arn_blocks(n);
   const int nout = nv + (with_norm ? 1 : 0);
   ARN_DISPATCH(k_cgs_dots, nv, w, pk, nv, n, nout, with_norm ? 1 : 0, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, nout, nout, h);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nb, nout, nout, h);
 }
 
 void launch_cgs_proj(const double *w, const double *const *v, const double *h, int nv, i64 n,
@@ -2623,7 +2629,8 @@ void launch_cgs_proj(const double *w, const double *const *v, const double *h, i
   for (int j = 0; j < nv; j++) pk.p[j] = v[j];
   const int nb = arn_blocks(n);
   ARN_DISPATCH(k_cgs_proj, nv, w, pk, h, nv, n, nv + 1, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, nv + 1, nv + 1, h2s2);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nb, nv + 1, nv + 1,
+                     h2s2);
 }
 
 void launch_cgs_next(const double *w, const double *const *v, const double *h1, const double *h2,
@@ -2639,7 +2646,8 @@ void launch_cgs_next(const double *w, const double *const *v, const double *h1, 
   const int nb = nrm2 ? arn_blocks(n) : (int)std::min<i64>(pairs, 0x7fffffff);
   ARN_DISPATCH(k_cgs_next, nv, w, pk, h1, h2, nv, inv_nu, n, out, out32,
                nrm2 ? partials : nullptr);
-  if (nrm2) hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, nrm2);
+  if (nrm2)
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nb, 1, 1, nrm2);
 }
 void launch_dcgs_update(const double *w, const double *const *v, int j, const double *dots,
                         const double *tm_host, const double *tm_dev, int ld, i64 n,
@@ -2659,7 +2667,7 @@ void launch_dcgs_update(const double *w, const double *const *v, int j, const do
   const int nb = arn_blocks(n);
   ARN_DISPATCH(k_dcgs_update, j + 1, w, pk, j, dots, tp, tm, ld, n, vnext, out32, coef_out,
                partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, j + 2, j + 2, red);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nb, j + 2, j + 2, red);
 }
 #undef ARN_DISPATCH
 
@@ -2700,7 +2708,7 @@ __global__ void k_norm2_partial(const double *__restrict__ a, i64 n, double *__r
 void launch_norm2(const double *a, i64 n, double *partials, double *nrm2, hipStream_t s) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kBlock), 0, s, a, n, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 1, 1, nrm2);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nb, 1, 1, nrm2);
 }
 
 
@@ -2725,7 +2733,7 @@ __global__ void k_logsum_partial(const double *__restrict__ mu, i64 n, double *_
 void launch_logsum(const double *mu, i64 n, double *partials, double *out2, hipStream_t s) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_logsum_partial, dim3(nb), dim3(kBlock), 0, s, mu, n, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, partials, nb, 2, 2, out2);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nb, 2, 2, out2);
 }
 
 // ------------------------------------------------------------------------
