@@ -167,8 +167,13 @@ struct stokes_ctx {
   int vev_used = 0;
   double vc_ms[2] = {0, 0}, vc_bytes[2] = {0, 0}, vc_cycle_bytes[2] = {0, 0};
   long vc_count[2] = {0, 0};
-  // preconditioner timing for stokes_stats (two events around each application)
-  hipEvent_t pev[2] = {nullptr, nullptr};
+  // preconditioner timing for stokes_stats: two pairs of events around the
+  // applications (the pairs alternate, so that one application can still be
+  // running when the next is recorded)
+  hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // marks the end of an Arnoldi step's reads to the host, which the host
+  // waits for while the next preconditioner application already runs
+  hipEvent_t sev = nullptr;
   double *hist = nullptr;  // residual history (caller's host buffer)
   int hist_cap = 0;
   int err = 0;
@@ -911,21 +916,31 @@ double fetch(stokes_ctx *X, const double *dev, int count, double *dst) {
 struct PrecClock {
   stokes_ctx *X;
   double ms = 0.0;
-  bool open = false;
+  int cur = 0;
+  bool open[2] = {false, false};
   void start() {
-    if (X->pev[0]) (void)hipEventRecord(X->pev[0], X->s);
+    if (!X->pev[0]) return;
+    if (open[cur]) fold_pair(cur, true);  // two applications back: long done
+    (void)hipEventRecord(X->pev[2 * cur], X->s);
   }
   void stop() {
-    if (X->pev[0]) {
-      (void)hipEventRecord(X->pev[1], X->s);
-      open = true;
-    }
+    if (!X->pev[0]) return;
+    (void)hipEventRecord(X->pev[2 * cur + 1], X->s);
+    open[cur] = true;
+    cur ^= 1;
   }
-  void fold() {  // call after the stream has reached the stop event
-    if (!open) return;
+  void fold_pair(int q, bool wait) {
+    if (!open[q]) return;
+    if (wait) (void)hipEventSynchronize(X->pev[2 * q + 1]);
+    else if (hipEventQuery(X->pev[2 * q + 1]) != hipSuccess) return;
     float t = 0.f;
-    if (hipEventElapsedTime(&t, X->pev[0], X->pev[1]) == hipSuccess) ms += t;
-    open = false;
+    if (hipEventElapsedTime(&t, X->pev[2 * q], X->pev[2 * q + 1]) == hipSuccess) ms += t;
+    open[q] = false;
+  }
+  // the applications that have finished (wait: all of them)
+  void fold(bool wait = false) {
+    fold_pair(cur ^ 1, wait);
+    fold_pair(cur, wait);
   }
 };
 
@@ -979,7 +994,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     PrecClock &pc;
     std::chrono::steady_clock::time_point t0;
     ~Finish() {
-      pc.fold();
+      pc.fold(true);
       st->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       st->t_precond = pc.ms * 1e-3;
       st->t_krylov = st->t_total - st->t_precond;
@@ -1046,10 +1061,14 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jj = 0;
+    // the preconditioner application of V[j] was already queued at the end
+    // of step j - 1 (flexible FP32 steps; see below)
+    bool queued = false;
     for (int j = 0; j < m; j++) {
       if (j + 1 > 12) {
         // the basis transform outgrows the kernel arguments: stage it in
-        // device memory now, while the stream is idle after the last step
+        // device memory (the copy is ordered after the last step's reads of
+        // the host buffer)
         const int ld = m + 1;
         double *tpin = hb + 2048;
         for (int r = 0; r <= j; r++)
@@ -1058,14 +1077,17 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
                                  hipMemcpyHostToDevice, X->s));
       }
       if (flexible) {
-        pc.start();
-        if (S) {
-          launch_mul_scaling(X->V[j], S, 1, n, X->t, X->s);
-          precond_from64(X, X->t, X->Z[j], false);
-        } else {
-          precond_from64(X, X->V[j], X->Z[j], j > 0);
+        if (!queued) {
+          pc.start();
+          if (S) {
+            launch_mul_scaling(X->V[j], S, 1, n, X->t, X->s);
+            precond_from64(X, X->t, X->Z[j], false);
+          } else {
+            precond_from64(X, X->V[j], X->Z[j], j > 0);
+          }
+          pc.stop();
         }
-        pc.stop();
+        queued = false;
         if (X->mg32)
           launch_apply_m<float>(X->lev[0].g, m_alpha_of(X), X->m_muc, X->m_mue, X->m_lam,
                                 P<float>(X->Z[j]),
@@ -1103,7 +1125,22 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
                                hipMemcpyDeviceToHost, X->s));
       hip_ok(X, hipMemcpyAsync(hb + 72, X->dsc + 72, (j + 2) * sizeof(double),
                                hipMemcpyDeviceToHost, X->s));
-      hip_ok(X, hipStreamSynchronize(X->s));
+      // A flexible FP32 step whose successor exists queues the next
+      // preconditioner application (on the FP32 copy of v_{j+1} just
+      // written) before the host waits for the step's numbers, so the GPU
+      // keeps working through the host's Hessenberg update.  When the
+      // correction below rewrites v_{j+1}, the application is repeated;
+      // when the cycle ends here, its result is not used.
+      if (flexible && X->mg32 && !S && X->sev && j + 1 < m && it < max_iter) {
+        hip_ok(X, hipEventRecord(X->sev, X->s));
+        pc.start();
+        precond_from64(X, X->V[j + 1], X->Z[j + 1], true);
+        pc.stop();
+        queued = true;
+        hip_ok(X, hipEventSynchronize(X->sev));
+      } else {
+        hip_ok(X, hipStreamSynchronize(X->s));
+      }
       if (X->err) return STOKES_EDEVICE;
       pc.fold();
       const double nu = hb[110 + j + 1];
@@ -1166,6 +1203,7 @@ int krylov(stokes_ctx *X, double tol, int max_iter, stokes_stats *st) {
         Tm[(j + 1) * ld + j + 1] = 1.0;
         // the operator of the next left-GMRES step sees the final vector
         ianext = 1.0;
+        queued = false;  // the queued application saw the uncorrected vector
       }
       // either way v_{j+1} = alpha u_{j+1} + U c': the column gains sc c'
       for (int i = 0; i <= j; i++) col[i] += sc * cnext[i];
@@ -1645,10 +1683,15 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
     delete X;
     return STOKES_EDEVICE;
   }
-  if (hipEventCreate(&X->pev[0]) != hipSuccess || hipEventCreate(&X->pev[1]) != hipSuccess) {
-    if (X->pev[0]) (void)hipEventDestroy(X->pev[0]);
-    X->pev[0] = X->pev[1] = nullptr;  // statistics then report no preconditioner time
+  bool evs = true;
+  for (auto &e : X->pev) evs = evs && hipEventCreate(&e) == hipSuccess;
+  if (!evs) {
+    for (auto &e : X->pev) {
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;  // statistics then report no preconditioner time
+    }
   }
+  if (hipEventCreateWithFlags(&X->sev, hipEventDisableTiming) != hipSuccess) X->sev = nullptr;
   *out = X;
   return STOKES_OK;
 }
@@ -1660,6 +1703,7 @@ void stokes_destroy(stokes_ctx *X) {
   for (auto e : X->vev) (void)hipEventDestroy(e);
   for (auto e : X->pev)
     if (e) (void)hipEventDestroy(e);
+  if (X->sev) (void)hipEventDestroy(X->sev);
   release_vgraph(X);
   if (X->host) (void)hipHostFree(X->host);
   delete X;

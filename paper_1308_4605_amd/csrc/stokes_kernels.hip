@@ -2200,20 +2200,29 @@ __global__ void k_sum_partial(const T *__restrict__ a, i64 n, double *__restrict
 }
 
 // out[j] = sum_b partials[b * stride + j] for j < nout, fixed order
-// out[j] = sum over the blocks of partials[b * stride + j], j < nout: wave w
-// takes the outputs w, w + (waves), ...; its lanes sum blocks lane, lane +
-// 64, ... and the wave's butterfly adds the lanes (a fixed order: the result
-// does not depend on timing)
+// out[j] = sum over the blocks of partials[b * stride + j], j < nout <=
+// kFinishMax: every thread adds its blocks b = t, t + blockDim, ... for all
+// outputs (independent loads, no barrier between the outputs), each wave
+// adds its lanes, and thread j adds the waves' sums of output j (a fixed
+// order: the result does not depend on timing)
 constexpr int kFinishBlock = 1024;
+constexpr int kFinishMax = 34;
 __global__ void __launch_bounds__(kFinishBlock)
     k_finish(const double *__restrict__ partials, int nblocks, int stride, int nout,
              double *__restrict__ out) {
+  __shared__ double sh[kFinishMax][kFinishBlock / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int j = wid; j < nout; j += nw) {
+  for (int j = 0; j < nout; j++) {
     double acc = 0.0;
-    for (int b = lane; b < nblocks; b += 64) acc += partials[(i64)b * stride + j];
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += partials[(i64)b * stride + j];
     acc = wave_sum(acc);
-    if (lane == 0) out[j] = acc;
+    if (lane == 0) sh[j][wid] = acc;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nout) {
+    double r = 0.0;
+    for (int w = 0; w < nw; w++) r += sh[threadIdx.x][w];
+    out[threadIdx.x] = r;
   }
 }
 
