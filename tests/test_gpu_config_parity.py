@@ -3,6 +3,7 @@
   - the 1e6-contrast periodic steady field (the headline workload's
     coefficients) at 32^3: iteration counts within +-1 for left GMRES and
     FGMRES in FP64, and the FP32-multigrid form's iteration penalty and error;
+    at 64^3 the same for FGMRES;
   - the headline workload itself at 256^3: the FP64 FGMRES iterate after a
     fixed number of Arnoldi steps, element for element;
   - the two-layer unsteady workload at 128^3, both forms solved to 1e-8 and
@@ -51,6 +52,33 @@ def test_contrast_1e6_iteration_parity_32(krylov):
         assert scaled_residual(o, o.c, w.bu, w.bp, N(yu), N(yp)) <= 1e-8 * (1 + 1e-6)
         assert st32["iters"] <= 1.05 * ost["iters"] + 3
         assert e32u <= 1e-5 and e32p <= 1e-5
+
+
+@pytest.mark.timeout(900)
+def test_contrast_1e6_iteration_parity_64():
+    """The same field at 64^3 with FGMRES(10): the FP64 GPU solve within +-1
+    iteration of the oracle, and both GPU forms' errors against the oracle's
+    solution."""
+    print("contrast 1e6 64^3 FGMRES", flush=True)
+    w = W.contrast_periodic_3d(n=64, contrast=1e6, precision=W.FP64)
+    p = w.params(krylov=W.FGMRES, precision=W.FP64)
+    g, o = pair(p, w.rho, w.mu)
+    xu, xp, st, rc = g.solve(T(w.bu), T(w.bp), tol=1e-8, max_iter=3000)
+    ou, op, ost, orc = o.solve(w.bu, w.bp, tol=1e-8, max_iter=3000)
+    eu, ep = rel(N(xu), ou), rel(N(xp), op)
+    print(f"  gpu iters {st['iters']} oracle iters {ost['iters']} err u {eu:.2e} p {ep:.2e}",
+          flush=True)
+    assert rc == 0 and orc == 0
+    assert abs(st["iters"] - ost["iters"]) <= 1
+    assert eu <= 1e-6 and ep <= 1e-6
+    g32, _ = pair(dict(p, precision=W.MG_FP32), w.rho, w.mu)
+    yu, yp, st32, rc32 = g32.solve(T(w.bu), T(w.bp), tol=1e-8, max_iter=3000)
+    e32u, e32p = rel(N(yu), ou), rel(N(yp), op)
+    print(f"  fp32-mg iters {st32['iters']} err u {e32u:.2e} p {e32p:.2e}", flush=True)
+    assert rc32 == 0
+    assert scaled_residual(o, o.c, w.bu, w.bp, N(yu), N(yp)) <= 1e-8 * (1 + 1e-6)
+    assert st32["iters"] <= 1.05 * ost["iters"] + 3
+    assert e32u <= 1e-5 and e32p <= 1e-5
 
 
 @pytest.mark.timeout(900)
