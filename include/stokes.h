@@ -193,7 +193,17 @@ size_t stokes_workspace_bytes(const stokes_params *p);
    workspace: device buffer of ws_bytes >= stokes_workspace_bytes(p);
    hip_stream: a hipStream_t (NULL = the default stream).
    The coefficient fields are checked for sign and finiteness on the device
-   (one synchronisation); rho, mu and gamma are not retained. */
+   (one synchronisation); rho, mu and gamma are not retained.
+   Create also prepares two forms of the velocity V-cycle that compute the
+   same map as its kernel-by-kernel form, up to rounding: the coarse levels of
+   at most 512 cells (Appendix C's smoothing and coarsest-level relaxations
+   from a zero iterate, a fixed linear map of their right-hand side) are run
+   once per unit vector and stored as a matrix in the workspace, applied by
+   one matrix-vector product per V-cycle; and on a colour-split FP32
+   hierarchy the finest-level V-cycle is recorded as a HIP graph (on a
+   private stream; nothing runs) and replayed on hip_stream.  The environment
+   variables STOKES_TAIL_DENSE=0 and STOKES_VGRAPH=0, read here, turn either
+   off for this context (comparisons and tests). */
 int stokes_create(const stokes_params *p, const double *rho_cell, const double *mu_cell,
                   const double *mu_edges, const double *gamma_cell, void *workspace,
                   size_t ws_bytes, void *hip_stream, stokes_ctx **out);
