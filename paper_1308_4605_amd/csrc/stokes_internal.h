@@ -209,18 +209,16 @@ void launch_vel_remove_means(const Geo &g, const T *in, T *out, double *partials
 
 // Krylov (FP64)
 constexpr int kRedBlocks = 2048;
-// Arnoldi by classical Gram-Schmidt applied twice (CGS2), three passes:
+// Arnoldi passes (classical Gram-Schmidt, the second pass lagged into the
+// basis transform; see launch_dcgs_update):
 //   h[i] = (w, v_i), i < nv
 //   (with_norm: h[nv] = (w, w))
 void launch_cgs_dots(const double *w, const double *const *v, int nv, i64 n, double *partials,
                      double *h, hipStream_t s, bool with_norm = false);
-//   w' = w - sum_i h_i v_i (not stored); h2s2[i] = (w', v_i) for i < nv,
-//   h2s2[nv] = (w', w')
-void launch_cgs_proj(const double *w, const double *const *v, const double *h, int nv, i64 n,
-                     double *partials, double *h2s2, hipStream_t s);
-//   out = (w - sum_i (h1_i + h2_i) v_i) * inv_nu (nv = 0: plain scale), also
-//   cast to out32 when out32 != nullptr; nrm2 = (out, out) when nrm2 !=
-//   nullptr.  out may alias w.
+//   the explicit second pass when the lagged one would remove half or more
+//   of a vector: out = (w - sum_i (h1_i + h2_i) v_i) * inv_nu (nv = 0: plain
+//   scale), also cast to out32 when out32 != nullptr; nrm2 = (out, out) when
+//   nrm2 != nullptr.  out may alias w.
 void launch_cgs_next(const double *w, const double *const *v, const double *h1, const double *h2,
                      int nv, double inv_nu, i64 n, double *out, float *out32, double *partials,
                      double *nrm2, hipStream_t s);

@@ -2350,14 +2350,16 @@ struct CoefPack {
 };
 
 
-// ---- Arnoldi by classical Gram-Schmidt applied twice (CGS2) -------------
-// Three streaming passes over [w, v_0..v_j] with double2 loads, a fixed grid
-// and per-block partial sums (bitwise reproducible); pass C without a norm to
-// reduce runs one double2 per thread instead:
-//   A: h1 = V^T w
-//   B: w' = w - V h1 formed on the fly (not stored): h2 = V^T w', s2 = (w', w')
-//   C: v_next = (w - V (h1 + h2)) * inv_nu, optionally also as FP32 (the
-//      next flexible preconditioner input), or a plain scale when w is final
+// ---- Arnoldi: classical Gram-Schmidt, second pass lagged -----------------
+// Streaming passes over [w, v_0..v_j] with double2 loads, a fixed grid and
+// per-block partial sums (bitwise reproducible):
+//   R (k_cgs_dots): V^T w and (w, w)
+//   U (k_dcgs_update): the projections on the orthonormal basis V T, the next
+//      stored vector (and its FP32 copy, the next flexible preconditioner
+//      input) and its dots with the stored vectors
+//   k_cgs_next: the explicit second pass applied to a stored vector when the
+//      lagged one would remove half or more of it (and a plain scale); it
+//      runs one double2 per thread when there is no norm to reduce
 
 constexpr int kArnBlock = 256;
 constexpr int kArnGrid = 2048;
@@ -2414,45 +2416,6 @@ __global__ void __launch_bounds__(kArnBlock) k_cgs_dots(const double *__restrict
     if (with_norm) acc[MAXV] += a * a;
   }
   block_store<MAXV>(acc, nv, with_norm != 0, stride, partials);
-}
-
-template <int MAXV>
-__global__ void __launch_bounds__(kArnBlock) k_cgs_proj(const double *__restrict__ w, PtrPack v,
-                                                        const double *__restrict__ h, int nv,
-                                                        i64 n, int stride,
-                                                        double *__restrict__ partials) {
-  double acc[MAXV + 1];
-  double hh[MAXV];
-#pragma unroll
-  for (int i = 0; i <= MAXV; i++) acc[i] = 0.0;
-#pragma unroll
-  for (int i = 0; i < MAXV; i++) hh[i] = (i < nv) ? h[i] : 0.0;
-  const i64 n2 = n >> 1;
-  const double2 *__restrict__ w2 = (const double2 *)w;
-  for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n2; t += (i64)gridDim.x * blockDim.x) {
-    double2 a = w2[t];
-    double2 b[MAXV];
-#pragma unroll
-    for (int i = 0; i < MAXV; i++) {
-      if (i < nv) {
-        b[i] = ((const double2 *)v.p[i])[t];
-        a.x -= hh[i] * b[i].x;
-        a.y -= hh[i] * b[i].y;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < MAXV; i++)
-      if (i < nv) acc[i] += a.x * b[i].x + a.y * b[i].y;
-    acc[MAXV] += a.x * a.x + a.y * a.y;
-  }
-  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-    double a = w[n - 1];
-    for (int i = 0; i < nv; i++) a -= hh[i] * ((const double *)v.p[i])[n - 1];
-    for (int i = 0; i < nv; i++) acc[i] += a * ((const double *)v.p[i])[n - 1];
-    acc[MAXV] += a * a;
-  }
-  // slot nv receives (w', w')
-  block_store<MAXV>(acc, nv, true, stride, partials);
 }
 
 // out may equal w (the norm-forming call runs in place): each element is
@@ -2630,16 +2593,6 @@ void launch_cgs_dots(const double *w, const double *const *v, int nv, i64 n, dou
   const int nout = nv + (with_norm ? 1 : 0);
   ARN_DISPATCH(k_cgs_dots, nv, w, pk, nv, n, nout, with_norm ? 1 : 0, partials);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nb, nout, nout, h);
-}
-
-void launch_cgs_proj(const double *w, const double *const *v, const double *h, int nv, i64 n,
-                     double *partials, double *h2s2, hipStream_t s) {
-  PtrPack pk;
-  for (int j = 0; j < nv; j++) pk.p[j] = v[j];
-  const int nb = arn_blocks(n);
-  ARN_DISPATCH(k_cgs_proj, nv, w, pk, h, nv, n, nv + 1, partials);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nb, nv + 1, nv + 1,
-                     h2s2);
 }
 
 void launch_cgs_next(const double *w, const double *const *v, const double *h1, const double *h2,
