@@ -1200,8 +1200,10 @@ void launch_vel_gs(const Geo &g, int k, int colour, int first, const T *alpha, c
 // loaded once: per component c the value at i, at i +- e_a for every axis a,
 // and at i + e_c - e_k for k != c (27 loads in 3D instead of 45), and the
 // cell and edge viscosities around i likewise.  Each row then runs the
-// arithmetic of a_row_core, as the smoother does.
-template <typename T, int DIM>
+// arithmetic of a_row_core, as the smoother does.  HA, HL, HP: alpha, the
+// bulk coefficient and p are given (compile-time, so that no load sits in
+// a branch and every load issues before the first row is evaluated).
+template <typename T, int DIM, bool HA, bool HL, bool HP>
 __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i64 t,
                                                 const T *__restrict__ alpha,
                                                 const T *__restrict__ muc,
@@ -1247,14 +1249,14 @@ __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i6
   // cell viscosity (and bulk coefficient) at i and at i - e_k
   T mc[1 + DIM], lc[1 + DIM];
   mc[0] = muc[t];
-  lc[0] = lam ? lam[t] : (T)0;
+  lc[0] = HL ? lam[t] : (T)0;
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
     int q[3] = {i[0], i[1], i[2]};
     q[k] = im[k];
     const i64 cq = cidx3(g, q);
     mc[1 + k] = muc[cq];
-    lc[1 + k] = lam ? lam[cq] : (T)0;
+    lc[1 + k] = HL ? lam[cq] : (T)0;
   }
   // edge family m at i (E0) and at i + e_a for the axes a != m (E1)
   T E0[3] = {0, 0, 0}, E1[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -1267,6 +1269,21 @@ __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i6
       int q[3] = {i[0], i[1], i[2]};
       q[a] = ip[a];
       E1[m][a] = mue[eidx3(g, m, q)];
+    }
+  }
+  // the right-hand side and alpha of the d rows (and the pressures), loaded
+  // with the rest before the first row is evaluated and stored
+  T rh[DIM], alr[DIM], pg[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    const i64 fq = fidx3(g, k, i);
+    rh[k] = rhs[fq];
+    alr[k] = HA ? alpha[fq] : (T)0;  // no alpha array: theta = 0
+    pg[k] = (T)0;
+    if (HP) {
+      int l[3] = {i[0], i[1], i[2]};
+      l[k] = im[k];
+      pg[k] = (p[t] - p[cidx3(g, l)]) * (T)g.ih;
     }
   }
 #pragma unroll
@@ -1293,17 +1310,12 @@ __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i6
       mlo[l] = E0[m];
     }
     const i64 fq = fidx3(g, k, i);
-    const T al = alpha ? alpha[fq] : (T)0;  // no alpha array: theta = 0
     T Au, dg;
     a_row_core<T, DIM>(g, k, i, uf, V[k][1 + 2 * k], V[k][2 + 2 * k], ua, ub, ulh_r, ulh_l, ull_r,
-                       ull_l, mhi, mlo, mc[0], mc[1 + k], al, lam != nullptr, lc[0], lc[1 + k],
-                       Au, dg);
-    T r = rhs[fq] - Au;
-    if (p) {
-      int l[3] = {i[0], i[1], i[2]};
-      l[k] = im[k];
-      r -= (p[t] - p[cidx3(g, l)]) * (T)g.ih;
-    }
+                       ull_l, mhi, mlo, mc[0], mc[1 + k], alr[k], HL, lc[0], lc[1 + k], Au,
+                       dg);
+    T r = rh[k] - Au;
+    if (HP) r -= pg[k];
     res[fq] = r;
   }
 }
@@ -1350,7 +1362,7 @@ __device__ __forceinline__ void vel_residual_elem(const Geo &g, i64 t, const T *
   vel_residual_rows_at<T, DIM>(g, i, t, alpha, muc, mue, lam, rhs, phi, p, res);
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool HA, bool HL, bool HP>
 __global__ void k_vel_residual(Geo g, const T *__restrict__ alpha, const T *__restrict__ muc,
                                const T *__restrict__ mue, const T *__restrict__ lam,
                                const T *__restrict__ rhs, const T *__restrict__ phi,
@@ -1358,18 +1370,42 @@ __global__ void k_vel_residual(Geo g, const T *__restrict__ alpha, const T *__re
   int w, i[3];
   if (!box_thread(g, g.n[0], w, i[1], i[2])) return;
   i[0] = split_x(g, w);
-  vel_residual_at<T, DIM>(g, i, cidx3(g, i), alpha, muc, mue, lam, rhs, phi, p, res);
+  vel_residual_at<T, DIM, HA, HL, HP>(g, i, cidx3(g, i), alpha, muc, mue, lam, rhs, phi, p, res);
+}
+
+template <typename T, int DIM, bool HA, bool HL>
+static void launch_vel_residual_hp(const Geo &g, const T *alpha, const T *muc, const T *mue,
+                                   const T *lam, const T *rhs, const T *phi, const T *p, T *res,
+                                   hipStream_t s) {
+  if (p)
+    hipLaunchKernelGGL((k_vel_residual<T, DIM, HA, HL, true>), box_blocks(g, g.n[0]),
+                       dim3(kBlock), 0, s, g, alpha, muc, mue, lam, rhs, phi, p, res);
+  else
+    hipLaunchKernelGGL((k_vel_residual<T, DIM, HA, HL, false>), box_blocks(g, g.n[0]),
+                       dim3(kBlock), 0, s, g, alpha, muc, mue, lam, rhs, phi, p, res);
+}
+
+template <typename T, int DIM>
+static void launch_vel_residual_d(const Geo &g, const T *alpha, const T *muc, const T *mue,
+                                  const T *lam, const T *rhs, const T *phi, const T *p, T *res,
+                                  hipStream_t s) {
+  if (alpha && lam)
+    launch_vel_residual_hp<T, DIM, true, true>(g, alpha, muc, mue, lam, rhs, phi, p, res, s);
+  else if (alpha)
+    launch_vel_residual_hp<T, DIM, true, false>(g, alpha, muc, mue, lam, rhs, phi, p, res, s);
+  else if (lam)
+    launch_vel_residual_hp<T, DIM, false, true>(g, alpha, muc, mue, lam, rhs, phi, p, res, s);
+  else
+    launch_vel_residual_hp<T, DIM, false, false>(g, alpha, muc, mue, lam, rhs, phi, p, res, s);
 }
 
 template <typename T>
 void launch_vel_residual(const Geo &g, const T *alpha, const T *muc, const T *mue, const T *lam,
                          const T *rhs, const T *phi, const T *p, T *res, hipStream_t s) {
   if (g.d == 3)
-    hipLaunchKernelGGL((k_vel_residual<T, 3>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
-                       alpha, muc, mue, lam, rhs, phi, p, res);
+    launch_vel_residual_d<T, 3>(g, alpha, muc, mue, lam, rhs, phi, p, res, s);
   else
-    hipLaunchKernelGGL((k_vel_residual<T, 2>), box_blocks(g, g.n[0]), dim3(kBlock), 0, s, g,
-                       alpha, muc, mue, lam, rhs, phi, p, res);
+    launch_vel_residual_d<T, 2>(g, alpha, muc, mue, lam, rhs, phi, p, res, s);
 }
 
 // face restriction (Appendix C): normal weights 1/4, 1/2, 1/4 at fine faces
@@ -1518,11 +1554,17 @@ __global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
   int C[3];
   if (!box_thread(gc, gc.n[0], C[0], C[1], C[2])) return;
   constexpr int NB = (DIM == 3) ? 3 : 1;
-#pragma unroll
-  for (int k = 0; k < DIM; k++) {
+  constexpr int NF = (DIM == 3) ? 8 : 4;
+  // Loads (coarse taps and the fine values the thread updates) before the
+  // stores: a store to phif would otherwise order every later load of phif
+  // after it.  FP32: all components' loads first; FP64 (twice the
+  // registers): component by component.
+  constexpr bool kHoist = sizeof(T) == 4;
+  T cv[DIM][2][3][NB];
+  T old[DIM][NF];
+  auto load = [&](int k) {
     const int ta = (k == 0) ? 1 : 0;
     const int tb = (k == 2) ? 1 : 2;
-    T cv[2][3][NB];
     int cf[3] = {0, 0, 0};
 #pragma unroll
     for (int n = 0; n < 2; n++) {
@@ -1534,10 +1576,26 @@ __global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
 #pragma unroll
         for (int s1 = 0; s1 < NB; s1++) {
           if (DIM == 3) cf[tb] = tap_index(gc, tb, C[tb] + s1 - 1);
-          cv[n][s0][s1] = ec[fidx3(gc, k, cf)];
+          cv[k][n][s0][s1] = ec[fidx3(gc, k, cf)];
         }
       }
     }
+#pragma unroll
+    for (int q = 0; q < NF; q++) {
+      int f[3] = {2 * C[0] + (q & 1), 2 * C[1] + ((q >> 1) & 1),
+                  (DIM == 3) ? 2 * C[2] + ((q >> 2) & 1) : 0};
+      old[k][q] = low_wall(gf, k, f) ? (T)0 : phif[fidx3(gf, k, f)];
+    }
+  };
+  if (kHoist) {
+#pragma unroll
+    for (int k = 0; k < DIM; k++) load(k);
+  }
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    if (!kHoist) load(k);
+    const int ta = (k == 0) ? 1 : 0;
+    const int tb = (k == 2) ? 1 : 2;
     // wall ghosts, axis ta then tb (a corner takes both signs)
     if (gc.ns[ta]) {
       const T slo = (gc.fs[ta] & 1) ? (T)1 : (T)-1, shi = (gc.fs[ta] & 2) ? (T)1 : (T)-1;
@@ -1546,8 +1604,8 @@ __global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
       for (int n = 0; n < 2; n++)
 #pragma unroll
         for (int s1 = 0; s1 < NB; s1++) {
-          if (lo) cv[n][0][s1] = slo * cv[n][1][s1];
-          if (hi) cv[n][2][s1] = shi * cv[n][1][s1];
+          if (lo) cv[k][n][0][s1] = slo * cv[k][n][1][s1];
+          if (hi) cv[k][n][2][s1] = shi * cv[k][n][1][s1];
         }
     }
     if (DIM == 3 && gc.ns[tb]) {
@@ -1557,8 +1615,8 @@ __global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
       for (int n = 0; n < 2; n++)
 #pragma unroll
         for (int s0 = 0; s0 < 3; s0++) {
-          if (lo) cv[n][s0][0] = slo * cv[n][s0][1];
-          if (hi) cv[n][s0][NB - 1] = shi * cv[n][s0][1];
+          if (lo) cv[k][n][s0][0] = slo * cv[k][n][s0][1];
+          if (hi) cv[k][n][s0][NB - 1] = shi * cv[k][n][s0][1];
         }
     }
 #pragma unroll
@@ -1584,8 +1642,8 @@ __global__ void k_face_prolong_add(Geo gc, Geo gf, const T *__restrict__ ec,
             for (int b0 = 0; b0 < 2; b0++)
 #pragma unroll
               for (int b1 = 0; b1 < (DIM == 3 ? 2 : 1); b1++)
-                sum += nw[a] * (T)w0[b0] * (T)w1[b1] * cv[ns[a]][s0i[b0]][s1i[b1]];
-          phif[fidx3(gf, k, f)] += sum;
+                sum += nw[a] * (T)w0[b0] * (T)w1[b1] * cv[k][ns[a]][s0i[b0]][s1i[b1]];
+          phif[fidx3(gf, k, f)] = old[k][o0 + 2 * o1 + 4 * o2] + sum;
         }
   }
 }
