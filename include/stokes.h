@@ -203,7 +203,10 @@ size_t stokes_workspace_bytes(const stokes_params *p);
    hierarchy the finest-level V-cycle is recorded as a HIP graph (on a
    private stream; nothing runs) and replayed on hip_stream.  The environment
    variables STOKES_TAIL_DENSE=0 and STOKES_VGRAPH=0, read here, turn either
-   off for this context (comparisons and tests). */
+   off for this context (comparisons and tests).  On 3D FP32 levels of at
+   least 2^21 cells the velocity residual runs by columns of 8 cells along z
+   (bitwise the same result); STOKES_RESIDUAL_COLUMNS=n sets the column
+   length for this context, and n = 0 runs it by cells. */
 int stokes_create(const stokes_params *p, const double *rho_cell, const double *mu_cell,
                   const double *mu_edges, const double *gamma_cell, void *workspace,
                   size_t ws_bytes, void *hip_stream, stokes_ctx **out);

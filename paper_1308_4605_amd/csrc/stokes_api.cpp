@@ -26,6 +26,10 @@ constexpr int kMaxLev = 24;
 constexpr int kMaxRestart = 32;
 constexpr size_t kAlign = 256;
 constexpr int kEventPool = 2048;
+// 3D velocity residual by columns (Geo::col): cells per column thread, and
+// the smallest level that takes it
+constexpr int kResidualColumn = 8;
+constexpr i64 kResidualColumnCells = (i64)1 << 21;
 
 struct Level {
   Geo g;
@@ -1545,6 +1549,17 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
   // colour-split storage for the velocity levels below the coarse tail
   if (X->vsplit)
     for (int l = 0; l < nlev && (X->tail_l < 0 || l < X->tail_l); l++) X->lev[l].gv.split = 1;
+  // the 3D velocity residual by columns of kResidualColumn cells along z on
+  // the levels with at least kResidualColumnCells cells
+  // (STOKES_RESIDUAL_COLUMNS=n in the environment at create time: columns of
+  // n cells, or by cells for n = 0)
+  {
+    int col = kResidualColumn;
+    if (const char *e = std::getenv("STOKES_RESIDUAL_COLUMNS")) col = std::max(0, std::atoi(e));
+    if (p->dim == 3 && col > 0)
+      for (int l = 0; l < nlev; l++)
+        if (X->lev[l].gv.ncell >= kResidualColumnCells) X->lev[l].g.col = X->lev[l].gv.col = col;
+  }
   if (hipHostMalloc((void **)&X->host, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete X;
     return STOKES_EDEVICE;

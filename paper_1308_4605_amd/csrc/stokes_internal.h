@@ -36,6 +36,9 @@ struct Geo {
   // x index (even positions of a row first, then odd), so that the faces of
   // one Gauss-Seidel colour lie contiguously in every row
   int split;
+  // velocity residual (3D): 0 one thread per cell; > 0 one thread per column
+  // of this many cells along z, carrying the values two planes share
+  int col;
 };
 
 // bc[a]: STOKES_PERIODIC, STOKES_NOSLIP or STOKES_FREESLIP per axis

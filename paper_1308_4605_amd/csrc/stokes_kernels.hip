@@ -49,6 +49,7 @@ Geo make_geo(int d, const int n[3], const int bc[3], double h) {
   g.ncell = (i64)g.n[0] * g.n[1] * g.n[2];
   g.xcd = 1;
   g.split = 0;
+  g.col = 0;
   i64 off = 0;
   for (int k = 0; k < 3; k++) {
     for (int a = 0; a < 3; a++) g.fd[k][a] = g.n[a] + ((a == k && k < d) ? g.ns[a] : 0);
@@ -1195,12 +1196,58 @@ void launch_vel_gs(const Geo &g, int k, int colour, int first, const T *alpha, c
 #undef GS_CASE
 }
 
+// The velocity rows of all components at cell i from their loaded values:
+// V[c][0] = u_c at i, V[c][1 + 2a] at i + e_a, V[c][2 + 2a] at i - e_a
+// (wall clamps applied), X[c][k] = u_c at i + e_c - e_k, mc / lc = mu / lam
+// at i and at i - e_k, E0[m] = edge family m at i and E1[m][a] at i + e_a,
+// rh / alr = rhs and alpha of the rows, pg = the pressure gradients, fq = the
+// rows' face indices; each row runs the arithmetic of a_row_core, as the
+// smoother does, and res = rh - A u (- pg) is stored at the low faces of i
+// that are not wall faces.
+template <typename T, int DIM, bool HL, bool HP>
+__device__ __forceinline__ void vel_residual_rows(
+    const Geo &g, const int i[3], const T (&V)[DIM][1 + 2 * DIM], const T (&X)[DIM][DIM],
+    const T (&mc)[1 + DIM], const T (&lc)[1 + DIM], const T (&E0)[3], const T (&E1)[3][3],
+    const T (&rh)[DIM], const T (&alr)[DIM], const T (&pg)[DIM], const int (&fq)[DIM],
+    T *__restrict__ res) {
+#pragma unroll
+  for (int k = 0; k < DIM; k++) {
+    if (low_wall(g, k, i)) continue;
+    const T uf = V[k][0];
+    T ua[3] = {0, 0, 0}, ub[3] = {0, 0, 0};
+    T ulh_r[3] = {0, 0, 0}, ulh_l[3] = {0, 0, 0}, ull_r[3] = {0, 0, 0}, ull_l[3] = {0, 0, 0};
+    T mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0};
+#pragma unroll
+    for (int l = 0; l < DIM; l++) {
+      if (l == k) continue;
+      const int m = 3 - k - l;
+      const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
+      const bool bot = g.ns[l] && (i[l] == 0);
+      // no-slip: odd ghost (zero wall value); free-slip: even ghost (no shear)
+      ua[l] = top ? ((g.fs[l] & 2) ? uf : -uf) : V[k][1 + 2 * l];
+      ub[l] = bot ? ((g.fs[l] & 1) ? uf : -uf) : V[k][2 + 2 * l];
+      ulh_r[l] = V[l][1 + 2 * l];
+      ulh_l[l] = X[l][k];
+      ull_r[l] = V[l][0];
+      ull_l[l] = V[l][2 + 2 * k];
+      mhi[l] = E1[m][l];
+      mlo[l] = E0[m];
+    }
+    T Au, dg;
+    a_row_core<T, DIM>(g, k, i, uf, V[k][1 + 2 * k], V[k][2 + 2 * k], ua, ub, ulh_r, ulh_l, ull_r,
+                       ull_l, mhi, mlo, mc[0], mc[1 + k], alr[k], HL, lc[0], lc[1 + k], Au,
+                       dg);
+    T r = rh[k] - Au;
+    if (HP) r -= pg[k];
+    res[fq[k]] = r;
+  }
+}
+
 // res = rhs - A phi - G p (p may be null) at the low faces of cell i, all
 // components.  The rows share most of their velocity values, so those are
 // loaded once: per component c the value at i, at i +- e_a for every axis a,
 // and at i + e_c - e_k for k != c (27 loads in 3D instead of 45), and the
-// cell and edge viscosities around i likewise.  Each row then runs the
-// arithmetic of a_row_core, as the smoother does.  HA, HL, HP: alpha, the
+// cell and edge viscosities around i likewise.  HA, HL, HP: alpha, the
 // bulk coefficient and p are given (compile-time, so that no load sits in
 // a branch and every load issues before the first row is evaluated).
 template <typename T, int DIM, bool HA, bool HL, bool HP>
@@ -1218,9 +1265,8 @@ __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i6
     ip[a] = up1(g, a, i[a]);
     im[a] = dn1(g, a, i[a]);
   }
-  // V[c][0] at i, V[c][1 + 2a] at i + e_a, V[c][2 + 2a] at i - e_a;
-  // X[c][k] at i + e_c - e_k.  Component c has no face at index n[a] along a
-  // wall axis a != c: that load is clamped to i (the wall ghost replaces it).
+  // Component c has no face at index n[a] along a wall axis a != c: that
+  // load is clamped to i (the wall ghost replaces it).
   T V[DIM][1 + 2 * DIM], X[DIM][DIM];
 #pragma unroll
   for (int c = 0; c < DIM; c++) {
@@ -1274,11 +1320,12 @@ __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i6
   // the right-hand side and alpha of the d rows (and the pressures), loaded
   // with the rest before the first row is evaluated and stored
   T rh[DIM], alr[DIM], pg[DIM];
+  int fq[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; k++) {
-    const i64 fq = fidx3(g, k, i);
-    rh[k] = rhs[fq];
-    alr[k] = HA ? alpha[fq] : (T)0;  // no alpha array: theta = 0
+    fq[k] = fidx3(g, k, i);
+    rh[k] = rhs[fq[k]];
+    alr[k] = HA ? alpha[fq[k]] : (T)0;  // no alpha array: theta = 0
     pg[k] = (T)0;
     if (HP) {
       int l[3] = {i[0], i[1], i[2]};
@@ -1286,37 +1333,153 @@ __device__ __forceinline__ void vel_residual_at(const Geo &g, const int i[3], i6
       pg[k] = (p[t] - p[cidx3(g, l)]) * (T)g.ih;
     }
   }
+  vel_residual_rows<T, DIM, HL, HP>(g, i, V, X, mc, lc, E0, E1, rh, alr, pg, fq, res);
+}
+
+// Loads at (x, y, z) of a face, cell or edge array.  PER (every axis
+// periodic): every array has the cells' extents, so the in-plane part of the
+// index is written once for all of them and shared by the compiler.
+template <bool PER, typename T>
+__device__ __forceinline__ T face_at(const Geo &g, const T *__restrict__ u, int c, int x, int y,
+                                     int z) {
+  if (PER) return u[(int)g.foff[c] + (z * g.n[1] + y) * g.n[0] + xpos(g, g.n[0], x)];
+  const int q[3] = {x, y, z};
+  return u[fidx3(g, c, q)];
+}
+template <bool PER, typename T>
+__device__ __forceinline__ T cell_at(const Geo &g, const T *__restrict__ u, int x, int y, int z) {
+  const int q[3] = {x, y, z};
+  return u[cidx3(g, q)];
+}
+template <bool PER, typename T>
+__device__ __forceinline__ T edge_at(const Geo &g, const T *__restrict__ u, int m, int x, int y,
+                                     int z) {
+  if (PER) return u[(int)g.eoff[m] + (z * g.n[1] + y) * g.n[0] + x];
+  const int q[3] = {x, y, z};
+  return u[eidx3(g, m, q)];
+}
+
+// The 3D residual by columns: a thread takes the cells (x, y, z0 .. z0+nz-1)
+// and carries from one plane to the next what the two share: u_c at z and
+// z - 1, the diagonal values u_0(i + e_0 - e_2) and u_1(i + e_1 - e_2) (the
+// x and y neighbours one plane down), u_2 at i - e_0 and i - e_1 (the
+// diagonal values i + e_2 - e_k one plane up), mu and lam at z - 1, the
+// edges of families 0 and 1 at z, and p at z - 1.  A cell then loads 30 values
+// instead of 43; each value and each row is the one vel_residual_at forms, so
+// the result is bitwise the same.
+template <typename T, bool HA, bool HL, bool HP, bool PER>
+__global__ void k_vel_residual_col(Geo g, int nz, const T *__restrict__ alpha,
+                                   const T *__restrict__ muc, const T *__restrict__ mue,
+                                   const T *__restrict__ lam, const T *__restrict__ rhs,
+                                   const T *__restrict__ phi, const T *__restrict__ p,
+                                   T *__restrict__ res) {
+  int w, i[3], zb;
+  if (!box_thread(g, g.n[0], w, i[1], zb)) return;
+  i[0] = split_x(g, w);
+  const int x = i[0], y = i[1];
+  const int z0 = zb * nz, z1 = min(z0 + nz, g.n[2]);
+  const int xp = up1(g, 0, x), xm = dn1(g, 0, x), yp = up1(g, 1, y), ym = dn1(g, 1, y);
+  // upper neighbours of the components without a face at n along a wall axis
+  const int xpc = (!PER && g.ns[0] && x + 1 == g.n[0]) ? x : xp;  // components 1, 2 along x
+  const int ypc = (!PER && g.ns[1] && y + 1 == g.n[1]) ? y : yp;  // components 0, 2 along y
+  const T ih = (T)g.ih;
+  // carried values, primed for z0
+  const int zm0 = dn1(g, 2, z0);
+  T cu[3], cum[3];
 #pragma unroll
-  for (int k = 0; k < DIM; k++) {
-    if (low_wall(g, k, i)) continue;
-    const T uf = V[k][0];
-    T ua[3] = {0, 0, 0}, ub[3] = {0, 0, 0};
-    T ulh_r[3] = {0, 0, 0}, ulh_l[3] = {0, 0, 0}, ull_r[3] = {0, 0, 0}, ull_l[3] = {0, 0, 0};
-    T mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0};
-#pragma unroll
-    for (int l = 0; l < DIM; l++) {
-      if (l == k) continue;
-      const int m = 3 - k - l;
-      const bool top = g.ns[l] && (i[l] + 1 == g.n[l]);
-      const bool bot = g.ns[l] && (i[l] == 0);
-      // no-slip: odd ghost (zero wall value); free-slip: even ghost (no shear)
-      ua[l] = top ? ((g.fs[l] & 2) ? uf : -uf) : V[k][1 + 2 * l];
-      ub[l] = bot ? ((g.fs[l] & 1) ? uf : -uf) : V[k][2 + 2 * l];
-      ulh_r[l] = V[l][1 + 2 * l];
-      ulh_l[l] = X[l][k];
-      ull_r[l] = V[l][0];
-      ull_l[l] = V[l][2 + 2 * k];
-      mhi[l] = E1[m][l];
-      mlo[l] = E0[m];
+  for (int c = 0; c < 3; c++) {
+    cu[c] = face_at<PER>(g, phi, c, x, y, z0);
+    cum[c] = face_at<PER>(g, phi, c, x, y, zm0);
+  }
+  T cx02 = face_at<PER>(g, phi, 0, xp, y, zm0), cx12 = face_at<PER>(g, phi, 1, x, yp, zm0);
+  T cv22 = face_at<PER>(g, phi, 2, xm, y, z0), cv24 = face_at<PER>(g, phi, 2, x, ym, z0);
+  T cmz = cell_at<PER>(g, muc, x, y, zm0), clz = HL ? cell_at<PER>(g, lam, x, y, zm0) : (T)0;
+  T ce0 = edge_at<PER>(g, mue, 0, x, y, z0), ce1 = edge_at<PER>(g, mue, 1, x, y, z0);
+  T cpz = HP ? cell_at<PER>(g, p, x, y, zm0) : (T)0;
+  for (int z = z0; z < z1; z++) {
+    i[2] = z;
+    const int zp = up1(g, 2, z);
+    const int zpc = (!PER && g.ns[2] && z + 1 == g.n[2]) ? z : zp;  // components 0, 1 along z
+    T V[3][7], X[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    V[0][1] = face_at<PER>(g, phi, 0, xp, y, z);
+    V[0][2] = face_at<PER>(g, phi, 0, xm, y, z);
+    V[0][3] = face_at<PER>(g, phi, 0, x, ypc, z);
+    V[0][4] = face_at<PER>(g, phi, 0, x, ym, z);
+    V[0][5] = face_at<PER>(g, phi, 0, x, y, zpc);
+    V[1][1] = face_at<PER>(g, phi, 1, xpc, y, z);
+    V[1][2] = face_at<PER>(g, phi, 1, xm, y, z);
+    V[1][3] = face_at<PER>(g, phi, 1, x, yp, z);
+    V[1][4] = face_at<PER>(g, phi, 1, x, ym, z);
+    V[1][5] = face_at<PER>(g, phi, 1, x, y, zpc);
+    V[2][1] = face_at<PER>(g, phi, 2, xpc, y, z);
+    V[2][3] = face_at<PER>(g, phi, 2, x, ypc, z);
+    V[2][5] = face_at<PER>(g, phi, 2, x, y, zp);
+    X[0][1] = face_at<PER>(g, phi, 0, xp, ym, z);
+    X[1][0] = face_at<PER>(g, phi, 1, xm, yp, z);
+    X[2][0] = face_at<PER>(g, phi, 2, xm, y, zp);
+    X[2][1] = face_at<PER>(g, phi, 2, x, ym, zp);
+    T mc[4], lc[4] = {0, 0, 0, 0};
+    mc[0] = cell_at<PER>(g, muc, x, y, z);
+    mc[1] = cell_at<PER>(g, muc, xm, y, z);
+    mc[2] = cell_at<PER>(g, muc, x, ym, z);
+    if (HL) {
+      lc[0] = cell_at<PER>(g, lam, x, y, z);
+      lc[1] = cell_at<PER>(g, lam, xm, y, z);
+      lc[2] = cell_at<PER>(g, lam, x, ym, z);
     }
-    const i64 fq = fidx3(g, k, i);
-    T Au, dg;
-    a_row_core<T, DIM>(g, k, i, uf, V[k][1 + 2 * k], V[k][2 + 2 * k], ua, ub, ulh_r, ulh_l, ull_r,
-                       ull_l, mhi, mlo, mc[0], mc[1 + k], alr[k], HL, lc[0], lc[1 + k], Au,
-                       dg);
-    T r = rh[k] - Au;
-    if (HP) r -= pg[k];
-    res[fq] = r;
+    T E0[3], E1[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    E0[2] = edge_at<PER>(g, mue, 2, x, y, z);
+    E1[0][1] = edge_at<PER>(g, mue, 0, x, yp, z);
+    E1[0][2] = edge_at<PER>(g, mue, 0, x, y, zp);
+    E1[1][0] = edge_at<PER>(g, mue, 1, xp, y, z);
+    E1[1][2] = edge_at<PER>(g, mue, 1, x, y, zp);
+    E1[2][0] = edge_at<PER>(g, mue, 2, xp, y, z);
+    E1[2][1] = edge_at<PER>(g, mue, 2, x, yp, z);
+    T rh[3], alr[3], pg[3] = {0, 0, 0};
+    int fq[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      fq[k] = PER ? (int)g.foff[k] + (z * g.n[1] + y) * g.n[0] + xpos(g, g.n[0], x)
+                  : fidx3(g, k, i);
+      rh[k] = rhs[fq[k]];
+      alr[k] = HA ? alpha[fq[k]] : (T)0;
+    }
+    T pc0 = (T)0;
+    if (HP) {
+      pc0 = cell_at<PER>(g, p, x, y, z);
+      pg[0] = (pc0 - cell_at<PER>(g, p, xm, y, z)) * ih;
+      pg[1] = (pc0 - cell_at<PER>(g, p, x, ym, z)) * ih;
+      pg[2] = (pc0 - cpz) * ih;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      V[c][0] = cu[c];
+      V[c][6] = cum[c];
+    }
+    X[0][2] = cx02;
+    X[1][2] = cx12;
+    V[2][2] = cv22;
+    V[2][4] = cv24;
+    mc[3] = cmz;
+    lc[3] = clz;
+    E0[0] = ce0;
+    E0[1] = ce1;
+    vel_residual_rows<T, 3, HL, HP>(g, i, V, X, mc, lc, E0, E1, rh, alr, pg, fq, res);
+    // what plane z + 1 shares with this one (the last plane's values go unused)
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      cum[c] = V[c][0];
+      cu[c] = V[c][5];
+    }
+    cx02 = V[0][1];
+    cx12 = V[1][3];
+    cv22 = X[2][0];
+    cv24 = X[2][1];
+    cmz = mc[0];
+    clz = lc[0];
+    ce0 = E1[0][2];
+    ce1 = E1[1][2];
+    cpz = pc0;
   }
 }
 
@@ -1377,6 +1540,26 @@ template <typename T, int DIM, bool HA, bool HL>
 static void launch_vel_residual_hp(const Geo &g, const T *alpha, const T *muc, const T *mue,
                                    const T *lam, const T *rhs, const T *phi, const T *p, T *res,
                                    hipStream_t s) {
+  // by columns in FP32 only: the FP64 column kernel exceeds the register file
+  if constexpr (DIM == 3 && sizeof(T) == 4) {
+    if (g.col > 0) {
+      dim3 nb = box_blocks(g, g.n[0]);
+      nb.y = (unsigned)((g.n[2] + g.col - 1) / g.col);
+      const bool per = !g.ns[0] && !g.ns[1] && !g.ns[2];
+#define COL_CASE(HPV, PERV)                                                                     \
+  hipLaunchKernelGGL((k_vel_residual_col<T, HA, HL, HPV, PERV>), nb, dim3(kBlock), 0, s, g, g.col, \
+                     alpha, muc, mue, lam, rhs, phi, p, res)
+      if (p) {
+        if (per) COL_CASE(true, true);
+        else COL_CASE(true, false);
+      } else {
+        if (per) COL_CASE(false, true);
+        else COL_CASE(false, false);
+      }
+#undef COL_CASE
+      return;
+    }
+  }
   if (p)
     hipLaunchKernelGGL((k_vel_residual<T, DIM, HA, HL, true>), box_blocks(g, g.n[0]),
                        dim3(kBlock), 0, s, g, alpha, muc, mue, lam, rhs, phi, p, res);

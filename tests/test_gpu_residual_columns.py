@@ -1,0 +1,72 @@
+"""The 3D FP32 velocity residual by columns along z (a thread carries the
+values two planes share) against the residual by cells
+(STOKES_RESIDUAL_COLUMNS=0 at create time).
+
+Both forms load the same values and run the same row arithmetic, so every
+result must agree bit for bit: the V-cycle (its residual before the
+restriction), two V-cycles per subsolve (the residual between them), and P5
+(the residual with the pressure gradient).  The grids have at least 2^21
+cells, where the columns are used: periodic, every wall kind, alpha, the bulk
+term, and z extents that are not a multiple of the column length (one
+partial column that wraps; a partial last column against a wall), with the
+default column length and with columns of 3 cells.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import N, T, params
+from paper_1308_4605_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(p, rho, mu, gamma, columns):
+    """columns: None for the library's default column length, else the value
+    of STOKES_RESIDUAL_COLUMNS at create time ("0": by cells)."""
+    from paper_1308_4605_amd.stokes import Stokes
+
+    old = os.environ.pop("STOKES_RESIDUAL_COLUMNS", None)
+    if columns is not None:
+        os.environ["STOKES_RESIDUAL_COLUMNS"] = columns
+    try:
+        return Stokes(p, T(rho), T(mu), gamma=None if gamma is None else T(gamma))
+    finally:
+        os.environ.pop("STOKES_RESIDUAL_COLUMNS", None)
+        if old is not None:
+            os.environ["STOKES_RESIDUAL_COLUMNS"] = old
+
+
+# (n, bc, theta, bulk, precond, vcycles)
+CASES = [((128, 128, 128), (0, 0, 0), 0.0, False, W.P2, 1),
+         ((128, 128, 128), (1, 0, 2), 30.0, False, W.P2, 1),
+         ((128, 128, 128), (0, 1, 0), 10.0, True, W.P1, 2),
+         ((1024, 512, 4), (0, 0, 0), 0.0, False, W.P2, 1),
+         ((8, 512, 516), (0, 0, 1), 0.0, False, W.P5, 1),
+         ((256, 128, 64), (3, 4, 0), 5.0, True, W.P5, 2)]
+
+
+@pytest.mark.parametrize("n,bc,theta,bulk,precond,vcycles", CASES)
+@pytest.mark.parametrize("columns", [None, "3"])
+def test_columns_equal_cells(n, bc, theta, bulk, precond, vcycles, columns):
+    print(f"residual columns {columns or 'default'} {n} {bc} theta={theta} bulk={bulk} "
+          f"P{precond} vcycles={vcycles}", flush=True)
+    lay = W.make_layout(3, n, bc)
+    rho, mu = W.random_coefficients(91, lay, mu_range=(0.1, 10.0))
+    gamma = W.random_bulk_viscosity(92, lay) if bulk else None
+    p, _ = params(3, n, bc, theta, precision=W.MG_FP32, krylov=W.FGMRES, precond=precond,
+                  vcycles=vcycles)
+    a = _ctx(p, rho, mu, gamma, columns)
+    b = _ctx(p, rho, mu, gamma, "0")
+    r = W.random_velocity(93, lay, remove_mean=lay.singular_components(theta))
+    ea, eb = N(a.vel_subsolve(T(r))), N(b.vel_subsolve(T(r)))
+    print(f"  subsolve: max |columns - cells| = {np.abs(ea - eb).max():.3e}", flush=True)
+    assert np.all(np.isfinite(ea))
+    assert np.array_equal(ea, eb)
+    bu, bp = T(W.random_velocity(94, lay)), T(W.random_cells(95, lay))
+    (ua, pa), (ub, pb) = a.precond(bu, bp), b.precond(bu, bp)
+    print(f"  precond: max |columns - cells| = {np.abs(N(ua) - N(ub)).max():.3e}", flush=True)
+    assert np.array_equal(N(ua), N(ub)) and np.array_equal(N(pa), N(pb))
+    a.close()
+    b.close()
