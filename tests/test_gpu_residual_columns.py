@@ -4,12 +4,12 @@ values two planes share) against the residual by cells
 
 Both forms load the same values and run the same row arithmetic, so every
 result must agree bit for bit: the V-cycle (its residual before the
-restriction), two V-cycles per subsolve (the residual between them), and P5
-(the residual with the pressure gradient).  The grids have at least 2^21
-cells, where the columns are used: periodic, every wall kind, alpha, the bulk
-term, and z extents that are not a multiple of the column length (one
-partial column that wraps; a partial last column against a wall), with the
-default column length and with columns of 3 cells.
+restriction), two V-cycles per subsolve (the residual between them), P5 (the
+residual with the pressure gradient), and whole FGMRES solves.  The grids have at least 2^21 cells, where the columns are used:
+periodic, every wall kind, alpha, the bulk term, and z extents that are not a
+multiple of the column length (one partial column that wraps; a partial last
+column against a wall), with the default column length and with columns of
+3 cells.
 """
 import os
 
@@ -68,5 +68,26 @@ def test_columns_equal_cells(n, bc, theta, bulk, precond, vcycles, columns):
     (ua, pa), (ub, pb) = a.precond(bu, bp), b.precond(bu, bp)
     print(f"  precond: max |columns - cells| = {np.abs(N(ua) - N(ub)).max():.3e}", flush=True)
     assert np.array_equal(N(ua), N(ub)) and np.array_equal(N(pa), N(pb))
+    a.close()
+    b.close()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision", [W.MG_FP32, W.FP64])
+def test_columns_solve_equal_cells(precision):
+    """FGMRES(10) with P2 on the contrast-1e6 periodic field at 128^3: the
+    same iterates and solution with either form (the FP64 form keeps the
+    residual by cells, so its solve checks that the switch leaves it alone)."""
+    print(f"residual columns solve contrast 1e6 128^3 precision={precision}", flush=True)
+    w = W.contrast_periodic_3d(n=128, contrast=1e6, precision=precision)
+    p = w.params(krylov=W.FGMRES)
+    a = _ctx(p, w.rho, w.mu, None, None)
+    b = _ctx(p, w.rho, w.mu, None, "0")
+    xa, pa, sa, ra = a.solve(T(w.bu), T(w.bp), tol=1e-8, max_iter=500)
+    xb, pb, sb, rb = b.solve(T(w.bu), T(w.bp), tol=1e-8, max_iter=500)
+    print(f"  iters columns {sa['iters']} cells {sb['iters']}", flush=True)
+    assert ra == 0 and rb == 0
+    assert sa["iters"] == sb["iters"]
+    assert np.array_equal(N(xa), N(xb)) and np.array_equal(N(pa), N(pb))
     a.close()
     b.close()
