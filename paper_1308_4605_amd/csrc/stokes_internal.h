@@ -36,8 +36,9 @@ struct Geo {
   // x index (even positions of a row first, then odd), so that the faces of
   // one Gauss-Seidel colour lie contiguously in every row
   int split;
-  // velocity residual (3D): 0 one thread per cell; > 0 one thread per column
-  // of this many cells along z, carrying the values two planes share
+  // velocity residual (3D, FP32 arrays): 0 one thread per cell; > 0 one
+  // thread per column of this many cells along z, carrying the values two
+  // planes share (FP64 residuals run by cells whatever its value)
   int col;
 };
 

@@ -8,8 +8,8 @@ restriction), two V-cycles per subsolve (the residual between them), P5 (the
 residual with the pressure gradient), and whole FGMRES solves.  The grids have at least 2^21 cells, where the columns are used:
 periodic, every wall kind, alpha, the bulk term, and z extents that are not a
 multiple of the column length (one partial column that wraps; a partial last
-column against a wall), with the default column length and with columns of
-3 cells.
+column against a wall), a y extent that is not a multiple of 8 (threads not
+banded by XCD), with the default column length and with columns of 3 cells.
 """
 import os
 
@@ -44,7 +44,8 @@ CASES = [((128, 128, 128), (0, 0, 0), 0.0, False, W.P2, 1),
          ((128, 128, 128), (0, 1, 0), 10.0, True, W.P1, 2),
          ((1024, 512, 4), (0, 0, 0), 0.0, False, W.P2, 1),
          ((8, 512, 516), (0, 0, 1), 0.0, False, W.P5, 1),
-         ((256, 128, 64), (3, 4, 0), 5.0, True, W.P5, 2)]
+         ((256, 128, 64), (3, 4, 0), 5.0, True, W.P5, 2),
+         ((1024, 4, 512), (0, 0, 0), 0.0, False, W.P2, 1)]
 
 
 @pytest.mark.parametrize("n,bc,theta,bulk,precond,vcycles", CASES)
