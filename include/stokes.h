@@ -206,7 +206,8 @@ size_t stokes_workspace_bytes(const stokes_params *p);
    off for this context (comparisons and tests).  On 3D FP32 levels of at
    least 2^21 cells the velocity residual runs by columns of 8 cells along z
    (bitwise the same result); STOKES_RESIDUAL_COLUMNS=n sets the column
-   length for this context, and n = 0 runs it by cells. */
+   length for this context (clamped to each level's z extent), and n = 0
+   runs it by cells. */
 int stokes_create(const stokes_params *p, const double *rho_cell, const double *mu_cell,
                   const double *mu_edges, const double *gamma_cell, void *workspace,
                   size_t ws_bytes, void *hip_stream, stokes_ctx **out);

@@ -1555,10 +1555,12 @@ int stokes_create(const stokes_params *p, const double *rho, const double *mu,
   // n cells, or by cells for n = 0)
   {
     int col = kResidualColumn;
-    if (const char *e = std::getenv("STOKES_RESIDUAL_COLUMNS")) col = std::max(0, std::atoi(e));
+    if (const char *e = std::getenv("STOKES_RESIDUAL_COLUMNS"))
+      col = (int)std::max(0L, std::min(std::strtol(e, nullptr, 10), 1L << 20));
     if (p->dim == 3 && col > 0)
       for (int l = 0; l < nlev; l++)
-        if (X->lev[l].gv.ncell >= kResidualColumnCells) X->lev[l].g.col = X->lev[l].gv.col = col;
+        if (X->lev[l].gv.ncell >= kResidualColumnCells)  // a column never exceeds the z extent
+          X->lev[l].g.col = X->lev[l].gv.col = std::min(col, X->lev[l].gv.n[2]);
   }
   if (hipHostMalloc((void **)&X->host, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete X;

@@ -9,7 +9,8 @@ residual with the pressure gradient), and whole FGMRES solves.  The grids have a
 periodic, every wall kind, alpha, the bulk term, and z extents that are not a
 multiple of the column length (one partial column that wraps; a partial last
 column against a wall), a y extent that is not a multiple of 8 (threads not
-banded by XCD), with the default column length and with columns of 3 cells.
+banded by XCD), with the default column length, with columns of 3 cells, and
+with a length beyond every z extent (one column per thread, the whole axis).
 """
 import os
 
@@ -49,7 +50,7 @@ CASES = [((128, 128, 128), (0, 0, 0), 0.0, False, W.P2, 1),
 
 
 @pytest.mark.parametrize("n,bc,theta,bulk,precond,vcycles", CASES)
-@pytest.mark.parametrize("columns", [None, "3"])
+@pytest.mark.parametrize("columns", [None, "3", "99999999999"])
 def test_columns_equal_cells(n, bc, theta, bulk, precond, vcycles, columns):
     print(f"residual columns {columns or 'default'} {n} {bc} theta={theta} bulk={bulk} "
           f"P{precond} vcycles={vcycles}", flush=True)
